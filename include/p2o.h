@@ -1,0 +1,190 @@
+/*
+ * p2o.h -- C ABI of the FFT-based block-Toeplitz parameter-to-observable
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The operator.  A linear time-invariant system stepped with a single-step
+ * explicit scheme, w_{k+1} = A w_k + C m_k, d_{k+1} = B w_{k+1} (paper,
+ * section 2, "Discrete LTI system"), maps a parameter series m (Nt blocks of
+ * Nm values) to observations d (Nt blocks of Nd values) through the block
+ * lower-triangular Toeplitz matrix of its time-domain blocks
+ *
+ *     d_t = sum_{k=0}^{t} F_k m_{t-k},   F_k = B A^k C,   t = 0..Nt-1
+ *
+ * (equations LTI-time-discrete, ShiftInvariance and p2o; time index 0-based,
+ * F_k is the paper's first-column block F_{k+1,1}).  Section 4 ("FFT-based
+ * GPU-accelerated p2o and p2q matvecs") applies it by embedding the Toeplitz
+ * matrix in a block circulant of length L, transforming the blocks once,
+ * and doing one independent Nd x Nm complex matrix-vector product per
+ * frequency; the adjoint uses the conjugate-transposed Fourier blocks of the
+ * same stored spectrum.
+ *
+ * Conventions shared by every call.
+ *  - Time series are time-major and row-major: m is [nrhs][Nt][Nm], d is
+ *    [nrhs][Nt][Nd], contiguous, on the device.  Element type ("I/O type")
+ *    is double for P2O_FP64 plans and float for every other precision.
+ *  - L = 2 * S(Nt), where S(n) is the smallest 7-smooth integer >= n; the
+ *    spectrum keeps the L/2 + 1 non-redundant bins of the real transform.
+ *  - The caller owns all device memory (see p2o_required_bytes and
+ *    p2o_bind_storage); the plan holds host metadata only.  The apply calls
+ *    never allocate and never synchronise; they enqueue on the plan's stream.
+ *  - Arguments and plan state are checked before anything is enqueued.  On
+ *    error nothing is enqueued, outputs are untouched, a negative status is
+ *    returned and p2o_last_error() describes it.  No C++ exception crosses
+ *    this interface.
+ *  - Calls on one plan are not thread safe; distinct plans are independent.
+ */
+#ifndef P2O_H
+#define P2O_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct p2o_plan p2o_plan;
+
+/* Storage precision of the spectrum.  BF16 and FP16 store one power-of-two
+ * scale per (frequency, 4096-column block) and accumulate in FP32. */
+typedef enum {
+    P2O_FP64 = 0,
+    P2O_FP32 = 1,
+    P2O_BF16 = 2,
+    P2O_FP16 = 3
+} p2o_precision;
+
+/* Element type of the time-domain blocks handed to p2o_load_blocks. */
+typedef enum {
+    P2O_SRC_F64 = 0,
+    P2O_SRC_F32 = 1
+} p2o_src_dtype;
+
+typedef enum {
+    P2O_OK = 0,
+    P2O_ERR_ARG = -1,        /* bad shape, pointer, size or enum value      */
+    P2O_ERR_STATE = -2,      /* call out of order (e.g. apply before load)  */
+    P2O_ERR_DTYPE = -3,      /* precision / element type not supported here */
+    P2O_ERR_STORAGE = -4,    /* bound memory smaller than required          */
+    P2O_ERR_NONFINITE = -5,  /* NaN or Inf found in the loaded blocks       */
+    P2O_ERR_HIP = -6,        /* a HIP runtime call failed                   */
+    P2O_ERR_NO_DEVICE = -7   /* no usable GPU                               */
+} p2o_status;
+
+/* Describe an operator with Nd sensors, Nm parameters per step and Nt steps
+ * (section 2, dimensions of m, d and F after equation p2o), stored in
+ * `precision`, applied to at most `max_rhs` right-hand sides per call.
+ * Host-only: works without a GPU.  *out receives a new plan. */
+p2o_status p2o_create(p2o_plan** out, int64_t Nd, int64_t Nm, int64_t Nt,
+                      int32_t precision, int64_t max_rhs);
+
+/* Free the plan's host state (never the caller's device memory). */
+p2o_status p2o_destroy(p2o_plan* plan);
+
+/* Derived sizes: circulant length L, number of stored frequencies L/2+1,
+ * row pitch of the stored spectrum in complex elements (Nm rounded up to 8),
+ * and the number of 4096-column scale blocks.  Any pointer may be NULL. */
+p2o_status p2o_get_layout(const p2o_plan* plan, int64_t* L, int64_t* nfreq,
+                          int64_t* pitch, int64_t* nscale_blocks);
+
+/* Device bytes the caller must provide: the spectrum store (persistent:
+ * spectrum, scales, twiddles) and the workspace (scratch for apply calls
+ * with up to max_rhs right-hand sides, and for loading). */
+p2o_status p2o_required_bytes(const p2o_plan* plan, size_t* fhat_bytes,
+                              size_t* workspace_bytes);
+
+/* Attach caller-owned device memory (256-byte aligned).  The plan keeps the
+ * pointers; the caller keeps ownership and must keep them alive until
+ * p2o_destroy.  Rebinding resets the plan to "not loaded". */
+p2o_status p2o_bind_storage(p2o_plan* plan, void* fhat, size_t fhat_bytes,
+                            void* workspace, size_t workspace_bytes);
+
+/* Stream (a hipStream_t, NULL = default stream) on which all later calls
+ * enqueue their work. */
+p2o_status p2o_set_stream(p2o_plan* plan, void* stream);
+
+/* Transform and store columns [col0, col0+ncols) of the time-domain blocks
+ * ("the DFT only needs to be done once for each matrix", section 4):
+ * F_chunk is a device array [Nt][Nd][ncols] of element type src_dtype,
+ * holding F_k[:, col0:col0+ncols] for k = 0..Nt-1.  For BF16/FP16 plans col0
+ * must be a multiple of 4096 and ncols a multiple of 4096 unless the chunk
+ * ends at Nm, so every scale block is loaded whole.  The transform runs in
+ * FP64; the result is rounded to nearest-even into the storage precision.
+ * Asynchronous; the caller keeps F_chunk alive until the stream reaches it. */
+p2o_status p2o_load_blocks(p2o_plan* plan, const void* F_chunk, int64_t col0,
+                           int64_t ncols, int32_t src_dtype);
+
+/* Finish loading: synchronises the stream, checks that every column was
+ * loaded and that no NaN/Inf was seen (P2O_ERR_NONFINITE), and marks the
+ * plan ready for the apply calls. */
+p2o_status p2o_load_finalize(p2o_plan* plan);
+
+/* d = F m  (equation p2o) for nrhs right-hand sides.  m: [nrhs][Nt][Nm],
+ * d: [nrhs][Nt][Nd].  nt_active (device int32[nrhs], or NULL) restricts
+ * right-hand side b to its leading nt_active[b] steps: inputs past it count
+ * as zero and outputs past it are written as zero (the leading block
+ * principal submatrix of a lower-triangular Toeplitz matrix is the operator
+ * of the shorter problem).  1 <= nrhs <= max_rhs. */
+p2o_status p2o_apply_F(p2o_plan* plan, const void* m, void* d, int64_t nrhs,
+                       const int32_t* nt_active);
+
+/* m = F^* d, the adjoint (section 2, F^* in equation mmap-problem; section 4,
+ * conjugate-transposed Fourier blocks).  d: [nrhs][Nt][Nd] in,
+ * m: [nrhs][Nt][Nm] out.  nt_active as for p2o_apply_F. */
+p2o_status p2o_apply_Ft(p2o_plan* plan, const void* d, void* m, int64_t nrhs,
+                        const int32_t* nt_active);
+
+/* Data-space operator columns h = F F^* e (F Gamma F^* with Gamma = I, the
+ * products that assemble K = Gamma_noise + F Gamma_prior F^* column by
+ * column, section 4, Phase 2).  e, h: [nrhs][Nt][Nd].  The intermediate
+ * parameter series is truncated to Nt steps between the two passes and never
+ * leaves the workspace.  nt_active as for p2o_apply_F. */
+p2o_status p2o_apply_FFt(p2o_plan* plan, const void* e, void* h, int64_t nrhs,
+                         const int32_t* nt_active);
+
+/* Data misfit and gradient with diagonal noise covariance (section 2, MAP
+ * objective and equation mmap-problem; section 4, diagonal Gamma_noise):
+ *   r = F m - d_obs,  misfit[b] = 1/2 r^T Gamma_noise^{-1} r,
+ *   grad = F^* Gamma_noise^{-1} r.
+ * m, grad: [nrhs][Nt][Nm]; d_obs: [nrhs][Nt][Nd]; noise_var: device double
+ * array of length noise_var_len in {1, Nd, Nt*Nd} (one variance, one per
+ * sensor, or one per step and sensor); misfit: device double[nrhs], reduced
+ * in FP64 in a fixed order (bitwise reproducible).  nt_active as for
+ * p2o_apply_F (steps past it carry no data). */
+p2o_status p2o_misfit_grad(p2o_plan* plan, const void* m, const void* d_obs,
+                           const double* noise_var, int64_t noise_var_len,
+                           void* grad, double* misfit, int64_t nrhs,
+                           const int32_t* nt_active);
+
+/* Stages of the calls above, for per-stage timing. */
+typedef enum {
+    P2O_STAGE_R2C = 0,       /* zero-padded real FFT along time              */
+    P2O_STAGE_GEMV_FWD = 1,  /* per-frequency products with Fhat_w          */
+    P2O_STAGE_GEMV_ADJ = 2,  /* per-frequency products with Fhat_w^H        */
+    P2O_STAGE_C2R = 3,       /* inverse FFT and truncation (misfit fused)    */
+    P2O_STAGE_PROJECT = 4,   /* truncate and re-pad between F^* and F        */
+    P2O_STAGE_REDUCE = 5,    /* fixed-order FP64 misfit reduction            */
+    P2O_STAGE_LOAD = 6,      /* spectrum load (FFT along k, rounding)        */
+    P2O_STAGE_COUNT = 7
+} p2o_stage;
+
+/* Per-stage timing with HIP events recorded on the plan's stream around
+ * every launch (enable = 1) or not (enable = 0).  Either call resets the
+ * totals.  Recording adds one event pair per launch and never synchronises. */
+p2o_status p2o_profile_enable(p2o_plan* plan, int32_t enable);
+
+/* Total device time in milliseconds and number of launches of `stage` since
+ * profiling was enabled.  Waits for the recorded events (synchronising). */
+p2o_status p2o_profile_read(p2o_plan* plan, int32_t stage, double* total_ms, int64_t* launches);
+
+/* Human-readable name of a status code (static storage). */
+const char* p2o_status_string(int32_t status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* p2o_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2O_H */

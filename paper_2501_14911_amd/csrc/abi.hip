@@ -1,0 +1,573 @@
+// C ABI of the p2o library: plan state, argument checks, memory carving and
+// the launch sequences of each call.  See include/p2o.h for the contract.
+#include "p2o.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace p2o;
+
+namespace {
+
+thread_local std::string g_err;
+
+p2o_status fail(p2o_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum PlanState { kCreated = 0, kBound = 1, kLoading = 2, kReady = 3 };
+
+int64_t smooth7_at_least(int64_t n) {
+    for (int64_t c = n < 1 ? 1 : n;; ++c) {
+        int64_t m = c;
+        for (int64_t p : {2, 3, 5, 7})
+            while (m % p == 0) m /= p;
+        if (m == 1) return c;
+    }
+}
+
+bool have_device() {
+    static bool found = false;        // a device, once seen, stays for the process
+    if (found) return true;
+    int n = 0;
+    found = hipGetDeviceCount(&n) == hipSuccess && n > 0;
+    if (!found) (void)hipGetLastError();
+    return found;
+}
+
+}  // namespace
+
+struct p2o_plan {
+    int64_t Nd = 0, Nm = 0, Nt = 0, max_rhs = 0;
+    int prec = 0;
+    FftPlan fft{};
+    int64_t L = 0, nfreq = 0, pitch = 0, nblk = 0;
+    int elem_bytes = 0;        // stored complex entry
+    int cbytes = 0;            // compute complex (16 FP64, 8 otherwise)
+    int io_bytes = 0;          // element of m and d
+    // spectrum store layout (bytes)
+    size_t off_scales = 0, off_tw64 = 0, off_tw32 = 0, off_flag = 0, fhat_total = 0;
+    // workspace layout (bytes)
+    size_t off_X = 0, off_Y = 0, off_D = 0, off_P = 0, ws_total = 0;
+    // kernel configuration
+    int fwd_rows = 64, fwd_nslab = 1, fwd_chunks = 1;
+    int adj_rows = 1, adj_nslab = 1;
+    int c2r_nd_blocks = 1;
+    // bound memory
+    char* fhat = nullptr;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int state = kCreated;
+    bool aux_ready = false;
+    std::vector<uint8_t> loaded;   // per column
+    // per-stage timing
+    bool prof = false;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double tot_ms[P2O_STAGE_COUNT] = {};
+    int64_t launches[P2O_STAGE_COUNT] = {};
+    ~p2o_plan() {
+        for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+p2o_status check_hip(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(P2O_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return P2O_OK;
+}
+
+hipEvent_t take_event(p2o_plan* p) {
+    if (!p->pool.empty()) { hipEvent_t e = p->pool.back(); p->pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    return e;
+}
+
+// Run one launcher; with profiling on, bracket it with events on the stream.
+template <class Fn>
+p2o_status staged(p2o_plan* p, int stage, const char* what, Fn&& launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (p->prof) {
+        a = take_event(p);
+        b = take_event(p);
+        if (a && b) (void)hipEventRecord(a, p->stream);
+    }
+    const hipError_t e = launch();
+    if (p->prof && a && b) {
+        (void)hipEventRecord(b, p->stream);
+        p->pending.push_back({stage, a, b});
+    } else {
+        if (a) p->pool.push_back(a);
+        if (b) p->pool.push_back(b);
+    }
+    return check_hip(e, what);
+}
+
+p2o_status drain_profile(p2o_plan* p) {
+    for (auto& r : p->pending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return check_hip(e, "profile events");
+        p->tot_ms[r.stage] += ms;
+        p->launches[r.stage] += 1;
+        p->pool.push_back(r.a);
+        p->pool.push_back(r.b);
+    }
+    p->pending.clear();
+    return P2O_OK;
+}
+
+bool f64_plan(const p2o_plan* p) { return p->prec == kFP64; }
+const void* tw_of(const p2o_plan* p) { return p->fhat + (f64_plan(p) ? p->off_tw64 : p->off_tw32); }
+const float* scales_of(const p2o_plan* p) { return reinterpret_cast<const float*>(p->fhat + p->off_scales); }
+
+void layout(p2o_plan* p) {
+    const size_t nfreq = (size_t)p->nfreq;
+    const size_t spec = nfreq * (size_t)p->Nd * (size_t)p->pitch * (size_t)p->elem_bytes;
+    p->off_scales = align_up(spec);
+    p->off_tw64 = align_up(p->off_scales + nfreq * (size_t)p->nblk * sizeof(float));
+    p->off_tw32 = align_up(p->off_tw64 + (size_t)p->L * 16);
+    p->off_flag = align_up(p->off_tw32 + (size_t)p->L * 8);
+    p->fhat_total = align_up(p->off_flag + sizeof(unsigned));
+
+    const size_t R = (size_t)p->max_rhs;
+    const size_t xparts = (size_t)(p->adj_nslab > 1 ? p->adj_nslab : 1);
+    const size_t yparts = (size_t)(p->fwd_chunks > 1 ? p->fwd_chunks : 1);
+    p->off_X = 0;
+    p->off_Y = align_up(p->off_X + xparts * nfreq * R * (size_t)p->pitch * p->cbytes);
+    p->off_D = align_up(p->off_Y + yparts * nfreq * R * (size_t)p->Nd * p->cbytes);
+    p->off_P = align_up(p->off_D + R * (size_t)p->Nt * (size_t)p->Nd * p->io_bytes);
+    p->ws_total = align_up(p->off_P + R * (size_t)p->c2r_nd_blocks * sizeof(double));
+}
+
+p2o_status ready_for_apply(const p2o_plan* p, const void* a, const void* b, int64_t nrhs) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (!a || !b) return fail(P2O_ERR_ARG, "input or output pointer is NULL");
+    if (nrhs < 1 || nrhs > p->max_rhs)
+        return fail(P2O_ERR_ARG, "nrhs=%lld outside [1, max_rhs=%lld]", (long long)nrhs, (long long)p->max_rhs);
+    if (p->state != kReady) return fail(P2O_ERR_STATE, "spectrum not loaded (call p2o_load_blocks and p2o_load_finalize)");
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return P2O_OK;
+}
+
+// descriptors --------------------------------------------------------------
+// parameter-side series: time [b][t][Nm]  <->  spectrum [w][b][pitch] (+ partials)
+SeriesIO io_param(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active, int nparts) {
+    SeriesIO io{};
+    io.t_stride = p->Nm;
+    io.t_outer = p->Nt * p->Nm;
+    io.f_stride = nrhs * p->pitch;
+    io.f_outer = p->pitch;
+    io.f_part = p->nfreq * nrhs * p->pitch;
+    io.nparts = nparts;
+    io.S = (int)p->Nm;
+    io.S_pad = (int)p->pitch;
+    io.Nt = (int)p->Nt;
+    io.outer_count = (int)nrhs;
+    io.nt_active = nt_active;
+    return io;
+}
+
+// data-side series: time [b][t][Nd]  <->  spectrum [w][b][Nd] (+ partials)
+SeriesIO io_data(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active, int nparts) {
+    SeriesIO io{};
+    io.t_stride = p->Nd;
+    io.t_outer = p->Nt * p->Nd;
+    io.f_stride = nrhs * p->Nd;
+    io.f_outer = p->Nd;
+    io.f_part = p->nfreq * nrhs * p->Nd;
+    io.nparts = nparts;
+    io.S = (int)p->Nd;
+    io.S_pad = (int)p->Nd;
+    io.Nt = (int)p->Nt;
+    io.outer_count = (int)nrhs;
+    io.nt_active = nt_active;
+    return io;
+}
+
+GemvArgs gemv_args(const p2o_plan* p, int64_t nrhs, bool fwd) {
+    GemvArgs ga{};
+    ga.Nd = (int)p->Nd;
+    ga.pitch = (int)p->pitch;
+    ga.nfreq = (int)p->nfreq;
+    ga.nrhs = (int)nrhs;
+    ga.nblk = (int)p->nblk;
+    ga.nslab = fwd ? p->fwd_nslab : p->adj_nslab;
+    ga.rows_per_wg = fwd ? p->fwd_rows : p->adj_rows;
+    ga.part_stride = fwd ? p->nfreq * nrhs * p->Nd : p->nfreq * nrhs * p->pitch;
+    return ga;
+}
+
+// enqueue sequences ----------------------------------------------------------
+p2o_status enqueue_forward_to_Y(p2o_plan* p, const void* m, int64_t nrhs, const int32_t* nt) {
+    void* X = p->ws + p->off_X;
+    void* Y = p->ws + p->off_Y;
+    p2o_status s = staged(p, P2O_STAGE_R2C, "r2c (parameters)", [&] {
+        return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_param(p, nrhs, nt, 1), m, X, tw_of(p), p->stream);
+    });
+    if (s) return s;
+    return staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
+        return launch_gemv_fwd(p->prec, gemv_args(p, nrhs, true), p->fhat, scales_of(p), X, Y, p->stream);
+    });
+}
+
+p2o_status enqueue_adjoint_to_X(p2o_plan* p, const void* d, int64_t nrhs, const int32_t* nt) {
+    void* X = p->ws + p->off_X;
+    void* Y = p->ws + p->off_Y;
+    p2o_status s = staged(p, P2O_STAGE_R2C, "r2c (data)", [&] {
+        return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_data(p, nrhs, nt, 1), d, Y, tw_of(p), p->stream);
+    });
+    if (s) return s;
+    return staged(p, P2O_STAGE_GEMV_ADJ, "adjoint per-frequency products", [&] {
+        return launch_gemv_adj(p->prec, gemv_args(p, nrhs, false), p->fhat, scales_of(p), Y, X, p->stream);
+    });
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* p2o_status_string(int32_t st) {
+    switch (st) {
+        case P2O_OK: return "P2O_OK";
+        case P2O_ERR_ARG: return "P2O_ERR_ARG";
+        case P2O_ERR_STATE: return "P2O_ERR_STATE";
+        case P2O_ERR_DTYPE: return "P2O_ERR_DTYPE";
+        case P2O_ERR_STORAGE: return "P2O_ERR_STORAGE";
+        case P2O_ERR_NONFINITE: return "P2O_ERR_NONFINITE";
+        case P2O_ERR_HIP: return "P2O_ERR_HIP";
+        case P2O_ERR_NO_DEVICE: return "P2O_ERR_NO_DEVICE";
+        default: return "P2O_UNKNOWN_STATUS";
+    }
+}
+
+const char* p2o_last_error(void) { return g_err.c_str(); }
+
+p2o_status p2o_create(p2o_plan** out, int64_t Nd, int64_t Nm, int64_t Nt, int32_t precision, int64_t max_rhs) {
+    try {
+        if (!out) return fail(P2O_ERR_ARG, "out is NULL");
+        if (Nd < 1 || Nm < 1 || Nt < 1)
+            return fail(P2O_ERR_ARG, "shape Nd=%lld Nm=%lld Nt=%lld must be positive", (long long)Nd, (long long)Nm,
+                        (long long)Nt);
+        if (max_rhs < 1 || max_rhs > 65535) return fail(P2O_ERR_ARG, "max_rhs=%lld outside [1, 65535]", (long long)max_rhs);
+        if (precision < P2O_FP64 || precision > P2O_FP16)
+            return fail(P2O_ERR_DTYPE, "unknown precision %d", (int)precision);
+        if (Nd > (1 << 24) || Nm > (1LL << 30))
+            return fail(P2O_ERR_ARG, "Nd=%lld or Nm=%lld too large", (long long)Nd, (long long)Nm);
+        const int64_t M = smooth7_at_least(Nt);
+        FftPlan fp{};
+        fp.M = (int)M;
+        fp.L = (int)(2 * M);
+        int64_t m = M;
+        int np = 0;
+        for (int r : {8, 4, 2, 3, 5, 7})
+            while (m % r == 0 && np < kMaxPasses) { fp.radix[np++] = r; m /= r; }
+        fp.npass = np;
+        if (m != 1 || fft_tile_shift((int)M, true) < 0 || fft_tile_shift((int)M, false) < 0 || load_tile_shift((int)M) < 0)
+            return fail(P2O_ERR_ARG, "Nt=%lld too long (transform length %lld exceeds the LDS tile)", (long long)Nt,
+                        (long long)(2 * M));
+
+        p2o_plan* p = new (std::nothrow) p2o_plan();
+        if (!p) return fail(P2O_ERR_ARG, "out of host memory");
+        p->Nd = Nd; p->Nm = Nm; p->Nt = Nt; p->max_rhs = max_rhs; p->prec = precision;
+        p->fft = fp;
+        p->L = 2 * M;
+        p->nfreq = M + 1;
+        p->pitch = (Nm + 7) / 8 * 8;
+        p->nblk = (Nm + kScaleBlock - 1) / kScaleBlock;
+        p->elem_bytes = precision == P2O_FP64 ? 16 : precision == P2O_FP32 ? 8 : 4;
+        p->cbytes = precision == P2O_FP64 ? 16 : 8;
+        p->io_bytes = precision == P2O_FP64 ? 8 : 4;
+        p->fwd_rows = 64;
+        p->fwd_nslab = (int)((Nd + p->fwd_rows - 1) / p->fwd_rows);
+        p->fwd_chunks = gemv_fwd_chunks(precision, (int)p->pitch);
+        p->adj_nslab = 1;
+        p->adj_rows = (int)Nd;
+        p->c2r_nd_blocks = c2r_grid_x(fp, precision == P2O_FP64, (int)Nd);
+        layout(p);
+        p->loaded.assign((size_t)Nm, 0);
+        *out = p;
+        return P2O_OK;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_create");
+    }
+}
+
+p2o_status p2o_profile_enable(p2o_plan* p, int32_t enable) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (enable != 0 && enable != 1) return fail(P2O_ERR_ARG, "enable must be 0 or 1");
+    if (!p->pending.empty()) {
+        if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+        p2o_status s = drain_profile(p);
+        if (s) return s;
+    }
+    for (int i = 0; i < P2O_STAGE_COUNT; ++i) { p->tot_ms[i] = 0.0; p->launches[i] = 0; }
+    p->prof = enable != 0;
+    return P2O_OK;
+}
+
+p2o_status p2o_profile_read(p2o_plan* p, int32_t stage, double* total_ms, int64_t* launches) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (stage < 0 || stage >= P2O_STAGE_COUNT) return fail(P2O_ERR_ARG, "unknown stage %d", (int)stage);
+    if (!total_ms && !launches) return fail(P2O_ERR_ARG, "both outputs are NULL");
+    if (!p->pending.empty()) {
+        if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+        p2o_status s = drain_profile(p);
+        if (s) return s;
+    }
+    if (total_ms) *total_ms = p->tot_ms[stage];
+    if (launches) *launches = p->launches[stage];
+    return P2O_OK;
+}
+
+p2o_status p2o_destroy(p2o_plan* plan) {
+    if (!plan) return fail(P2O_ERR_ARG, "plan is NULL");
+    delete plan;
+    return P2O_OK;
+}
+
+p2o_status p2o_get_layout(const p2o_plan* p, int64_t* L, int64_t* nfreq, int64_t* pitch, int64_t* nscale_blocks) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (L) *L = p->L;
+    if (nfreq) *nfreq = p->nfreq;
+    if (pitch) *pitch = p->pitch;
+    if (nscale_blocks) *nscale_blocks = p->nblk;
+    return P2O_OK;
+}
+
+p2o_status p2o_required_bytes(const p2o_plan* p, size_t* fhat_bytes, size_t* workspace_bytes) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (!fhat_bytes && !workspace_bytes) return fail(P2O_ERR_ARG, "both outputs are NULL");
+    if (fhat_bytes) *fhat_bytes = p->fhat_total;
+    if (workspace_bytes) *workspace_bytes = p->ws_total;
+    return P2O_OK;
+}
+
+p2o_status p2o_bind_storage(p2o_plan* p, void* fhat, size_t fhat_bytes, void* workspace, size_t workspace_bytes) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (!fhat || !workspace) return fail(P2O_ERR_ARG, "storage pointer is NULL");
+        if ((reinterpret_cast<uintptr_t>(fhat) | reinterpret_cast<uintptr_t>(workspace)) % kAlign)
+            return fail(P2O_ERR_ARG, "storage must be %zu-byte aligned", kAlign);
+        if (fhat_bytes < p->fhat_total || workspace_bytes < p->ws_total)
+            return fail(P2O_ERR_STORAGE, "storage too small: spectrum %zu < %zu or workspace %zu < %zu", fhat_bytes,
+                        p->fhat_total, workspace_bytes, p->ws_total);
+        if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+        for (void* ptr : {fhat, workspace}) {
+            hipPointerAttribute_t at;
+            if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice) {
+                (void)hipGetLastError();
+                return fail(P2O_ERR_ARG, "storage pointer %p is not device memory", ptr);
+            }
+        }
+        p->fhat = static_cast<char*>(fhat);
+        p->ws = static_cast<char*>(workspace);
+        p->state = kBound;
+        p->aux_ready = false;
+        std::fill(p->loaded.begin(), p->loaded.end(), 0);
+        return P2O_OK;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_bind_storage");
+    }
+}
+
+p2o_status p2o_set_stream(p2o_plan* p, void* stream) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    p->stream = static_cast<hipStream_t>(stream);
+    return P2O_OK;
+}
+
+p2o_status p2o_load_blocks(p2o_plan* p, const void* F_chunk, int64_t col0, int64_t ncols, int32_t src_dtype) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (!F_chunk) return fail(P2O_ERR_ARG, "F_chunk is NULL");
+        if (src_dtype != P2O_SRC_F64 && src_dtype != P2O_SRC_F32)
+            return fail(P2O_ERR_DTYPE, "unknown source dtype %d", (int)src_dtype);
+        if (col0 < 0 || ncols < 1 || col0 + ncols > p->Nm)
+            return fail(P2O_ERR_ARG, "columns [%lld, %lld) outside [0, Nm=%lld)", (long long)col0,
+                        (long long)(col0 + ncols), (long long)p->Nm);
+        if (ncols > (1LL << 30)) return fail(P2O_ERR_ARG, "ncols too large");
+        const bool scaled = p->prec == P2O_BF16 || p->prec == P2O_FP16;
+        if (scaled && (col0 % kScaleBlock != 0 || (ncols % kScaleBlock != 0 && col0 + ncols != p->Nm)))
+            return fail(P2O_ERR_ARG, "BF16/FP16 loads need whole %d-column scale blocks (col0=%lld ncols=%lld)",
+                        kScaleBlock, (long long)col0, (long long)ncols);
+        if (p->state == kCreated) return fail(P2O_ERR_STATE, "bind storage before loading");
+        if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+        p2o_status s;
+        if (!p->aux_ready) {
+            s = check_hip(launch_twiddle(p->fhat + p->off_tw64, p->fhat + p->off_tw32, (int)p->L, p->stream), "twiddles");
+            if (s) return s;
+            s = check_hip(hipMemsetAsync(p->fhat + p->off_flag, 0, sizeof(unsigned), p->stream), "flag reset");
+            if (s) return s;
+            s = check_hip(launch_zero_pad(p->fhat, p->nfreq * p->Nd, (int)p->pitch, (int)p->Nm, p->elem_bytes, p->stream),
+                          "spectrum padding");
+            if (s) return s;
+            p->aux_ready = true;
+        }
+        LoadArgs la{};
+        la.fhat = p->fhat;
+        la.scales = reinterpret_cast<float*>(p->fhat + p->off_scales);
+        la.flag = reinterpret_cast<unsigned*>(p->fhat + p->off_flag);
+        la.col0 = col0;
+        la.ncols = (int)ncols;
+        la.Nd = (int)p->Nd;
+        la.Nt = (int)p->Nt;
+        la.t_stride = p->Nd * ncols;
+        la.pitch = p->pitch;
+        la.nblk = (int)p->nblk;
+        la.rows_per_wg = (int)(p->Nd < 32 ? p->Nd : 32);
+        s = staged(p, P2O_STAGE_LOAD, "spectrum load", [&] {
+            return launch_load(p->prec, src_dtype == P2O_SRC_F64, p->fft, la, F_chunk, p->fhat + p->off_tw64, p->stream);
+        });
+        if (s) return s;
+        std::fill(p->loaded.begin() + col0, p->loaded.begin() + col0 + ncols, 1);
+        p->state = kLoading;
+        return P2O_OK;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_load_blocks");
+    }
+}
+
+p2o_status p2o_load_finalize(p2o_plan* p) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (p->state != kLoading && p->state != kReady) return fail(P2O_ERR_STATE, "nothing loaded");
+        for (size_t j = 0; j < p->loaded.size(); ++j)
+            if (!p->loaded[j]) return fail(P2O_ERR_STATE, "column %zu of the blocks was never loaded", j);
+        if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+        unsigned flag = 0;
+        p2o_status s = check_hip(hipMemcpyAsync(&flag, p->fhat + p->off_flag, sizeof(flag), hipMemcpyDeviceToHost,
+                                                p->stream), "flag readback");
+        if (s) return s;
+        s = check_hip(hipStreamSynchronize(p->stream), "load synchronisation");
+        if (s) return s;
+        if (flag) {
+            p->state = kBound;
+            p->aux_ready = false;
+            std::fill(p->loaded.begin(), p->loaded.end(), 0);
+            return fail(P2O_ERR_NONFINITE, "NaN or Inf in the time-domain blocks");
+        }
+        p->state = kReady;
+        return P2O_OK;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_load_finalize");
+    }
+}
+
+p2o_status p2o_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const int32_t* nt_active) {
+    try {
+        p2o_status s = ready_for_apply(p, m, d, nrhs);
+        if (s) return s;
+        s = enqueue_forward_to_Y(p, m, nrhs, nt_active);
+        if (s) return s;
+        return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
+            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, p->fwd_chunks), p->ws + p->off_Y, d,
+                              tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
+        });
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_apply_F");
+    }
+}
+
+p2o_status p2o_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, const int32_t* nt_active) {
+    try {
+        p2o_status s = ready_for_apply(p, d, m, nrhs);
+        if (s) return s;
+        s = enqueue_adjoint_to_X(p, d, nrhs, nt_active);
+        if (s) return s;
+        return staged(p, P2O_STAGE_C2R, "c2r (parameters)", [&] {
+            return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, p->adj_nslab), p->ws + p->off_X, m,
+                              tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
+        });
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_apply_Ft");
+    }
+}
+
+p2o_status p2o_apply_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, const int32_t* nt_active) {
+    try {
+        p2o_status s = ready_for_apply(p, e, h, nrhs);
+        if (s) return s;
+        s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
+        if (s) return s;
+        s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
+            return launch_project(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, p->adj_nslab), p->ws + p->off_X,
+                                  tw_of(p), p->stream);
+        });
+        if (s) return s;
+        s = staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
+            return launch_gemv_fwd(p->prec, gemv_args(p, nrhs, true), p->fhat, scales_of(p), p->ws + p->off_X,
+                                   p->ws + p->off_Y, p->stream);
+        });
+        if (s) return s;
+        return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
+            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, p->fwd_chunks), p->ws + p->off_Y, h,
+                              tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
+        });
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_apply_FFt");
+    }
+}
+
+p2o_status p2o_misfit_grad(p2o_plan* p, const void* m, const void* d_obs, const double* noise_var,
+                           int64_t noise_var_len, void* grad, double* misfit, int64_t nrhs, const int32_t* nt_active) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (!d_obs || !noise_var || !misfit) return fail(P2O_ERR_ARG, "d_obs, noise_var or misfit is NULL");
+        int var_mode;
+        if (noise_var_len == 1) var_mode = 0;
+        else if (noise_var_len == p->Nd) var_mode = 1;
+        else if (noise_var_len == p->Nd * p->Nt) var_mode = 2;
+        else
+            return fail(P2O_ERR_ARG, "noise_var_len=%lld must be 1, Nd=%lld or Nt*Nd=%lld", (long long)noise_var_len,
+                        (long long)p->Nd, (long long)(p->Nd * p->Nt));
+        p2o_status s = ready_for_apply(p, m, grad, nrhs);
+        if (s) return s;
+        s = enqueue_forward_to_Y(p, m, nrhs, nt_active);
+        if (s) return s;
+        void* D = p->ws + p->off_D;
+        double* P = reinterpret_cast<double*>(p->ws + p->off_P);
+        s = staged(p, P2O_STAGE_C2R, "c2r with misfit", [&] {
+            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, p->fwd_chunks), p->ws + p->off_Y, D,
+                              tw_of(p), d_obs, noise_var, var_mode, P, p->stream);
+        });
+        if (s) return s;
+        s = staged(p, P2O_STAGE_REDUCE, "misfit reduction", [&] {
+            return launch_misfit_reduce(P, p->c2r_nd_blocks, misfit, (int)nrhs, p->stream);
+        });
+        if (s) return s;
+        s = enqueue_adjoint_to_X(p, D, nrhs, nt_active);
+        if (s) return s;
+        return staged(p, P2O_STAGE_C2R, "c2r (gradient)", [&] {
+            return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, p->adj_nslab), p->ws + p->off_X, grad,
+                              tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
+        });
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_misfit_grad");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,644 @@
+// Batched real FFTs along time for the block-Toeplitz matvec.
+//
+// Section 4 of the paper embeds the block lower-triangular Toeplitz matrix
+// in a block circulant of length L and diagonalises it with the DFT: every
+// time series (one per parameter or sensor) is zero-padded to L, transformed,
+// multiplied per frequency, transformed back and truncated to Nt steps.
+//
+// Design for gfx950.  Series are the contiguous dimension of time-major
+// arrays, so a workgroup takes a tile of TW adjacent series and all time
+// steps: every global access is a run of TW consecutive elements.  The tile
+// lives in LDS as [bin][series].  A real series x of even length L is
+// transformed as one complex series z[n] = x[2n] + i x[2n+1] of length
+// M = L/2 (half the work and LDS), followed by the usual split into the
+// spectra of the even and odd samples.  The complex transform is a
+// Stockham autosort FFT (Govindaraju et al., "High performance discrete
+// Fourier transforms on graphics processors", SC'08) with radices
+// 8, 4, 2, 3, 5, 7, run in place: each pass stages its butterflies' inputs
+// in registers, synchronises, then writes.  Twiddles come from a table
+// e^{-2 pi i n / L} generated once per plan in FP64 with sincospi.
+//
+// Zero padding (inputs past Nt, or past a right-hand side's active length)
+// and truncation (outputs past Nt) are fused into the loads and stores.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace p2o {
+
+constexpr int kFftThreads = 256;
+
+template <typename T> struct FftCap;
+template <> struct FftCap<float> { static constexpr int cap = 8192; };   // complex entries of LDS
+template <> struct FftCap<double> { static constexpr int cap = 4096; };
+
+// ---------------------------------------------------------------- butterflies
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_small(cplx<T>* a, const cplx<T>* w) {
+    using Z = cplx<T>;
+    if constexpr (R == 2) {
+        Z t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    } else if constexpr (R == 4) {
+        Z t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        Z t2 = cadd(a[1], a[3]), t3 = csub(a[1], a[3]);
+        a[0] = cadd(t0, t2);
+        a[2] = csub(t0, t2);
+        if constexpr (!INV) {   // multiply t3 by -i
+            a[1] = cmk<T>(t1.x + t3.y, t1.y - t3.x);
+            a[3] = cmk<T>(t1.x - t3.y, t1.y + t3.x);
+        } else {                // multiply t3 by +i
+            a[1] = cmk<T>(t1.x - t3.y, t1.y + t3.x);
+            a[3] = cmk<T>(t1.x + t3.y, t1.y - t3.x);
+        }
+    } else if constexpr (R == 8) {
+        Z e[4] = {a[0], a[2], a[4], a[6]};
+        Z o[4] = {a[1], a[3], a[5], a[7]};
+        dft_small<T, 4, INV>(e, w);
+        dft_small<T, 4, INV>(o, w);
+        const T c = T(0.70710678118654752440084436210485);   // sqrt(2)/2
+        Z o1, o2, o3;
+        if constexpr (!INV) {   // e^{-i pi p / 4} o_p
+            o1 = cmk<T>(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+            o2 = cmk<T>(o[2].y, -o[2].x);
+            o3 = cmk<T>(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+        } else {                // e^{+i pi p / 4} o_p
+            o1 = cmk<T>(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y));
+            o2 = cmk<T>(-o[2].y, o[2].x);
+            o3 = cmk<T>(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y));
+        }
+        a[0] = cadd(e[0], o[0]); a[4] = csub(e[0], o[0]);
+        a[1] = cadd(e[1], o1);   a[5] = csub(e[1], o1);
+        a[2] = cadd(e[2], o2);   a[6] = csub(e[2], o2);
+        a[3] = cadd(e[3], o3);   a[7] = csub(e[3], o3);
+    } else {
+        // odd prime radix: direct DFT with the R-th roots w[m] = e^{-+2 pi i m / R}
+        Z out[R];
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            Z acc = a[0];
+#pragma unroll
+            for (int q = 1; q < R; ++q) acc = cadd(acc, cmul(a[q], w[(p * q) % R]));
+            out[p] = acc;
+        }
+#pragma unroll
+        for (int p = 0; p < R; ++p) a[p] = out[p];
+    }
+}
+
+// One Stockham pass of radix R over a [M][TW] tile: butterfly j (of M/R)
+// reads z[j + q M/R], applies twiddles e^{-2 pi i q k / (Ns R)} with
+// k = j mod Ns, transforms, and writes z[(j / Ns) Ns R + k + p Ns].
+template <typename T, int R, bool INV, int MAXV>
+__device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
+                                         const cplx<T>* __restrict__ tw, int L) {
+    using Z = cplx<T>;
+    constexpr int MAXBF = (MAXV + R - 1) / R;
+    const int TWm = (1 << twsh) - 1;
+    const int MR = M / R;
+    const int nbf = MR << twsh;
+    const int tstep = L / (Ns * R);
+    Z w[R];
+    if constexpr (R == 3 || R == 5 || R == 7) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            Z t = tw[m * (L / R)];
+            w[m] = INV ? cconj(t) : t;
+        }
+    }
+    Z v[MAXBF][R];
+#pragma unroll
+    for (int u = 0; u < MAXBF; ++u) {
+        const int bf = threadIdx.x + u * kFftThreads;
+        if (bf < nbf) {
+            const int s = bf & TWm;
+            const int j = bf >> twsh;
+            const int k = j % Ns;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                Z a = buf[((j + q * MR) << twsh) + s];
+                if (q > 0 && k > 0) {
+                    Z t = tw[q * k * tstep];
+                    a = cmul(a, INV ? cconj(t) : t);
+                }
+                v[u][q] = a;
+            }
+            dft_small<T, R, INV>(v[u], w);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXBF; ++u) {
+        const int bf = threadIdx.x + u * kFftThreads;
+        if (bf < nbf) {
+            const int s = bf & TWm;
+            const int j = bf >> twsh;
+            const int k = j % Ns;
+            const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int p = 0; p < R; ++p) buf[((base + p * Ns) << twsh) + s] = v[u][p];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, bool INV>
+__device__ void fft_tile(cplx<T>* buf, int twsh, const FftPlan& pl, const cplx<T>* __restrict__ tw) {
+    constexpr int MAXV = FftCap<T>::cap / kFftThreads;
+    int Ns = 1;
+    for (int p = 0; p < pl.npass; ++p) {
+        const int R = pl.radix[p];
+        switch (R) {
+            case 2: fft_pass<T, 2, INV, MAXV>(buf, twsh, pl.M, Ns, tw, pl.L); break;
+            case 3: fft_pass<T, 3, INV, MAXV>(buf, twsh, pl.M, Ns, tw, pl.L); break;
+            case 4: fft_pass<T, 4, INV, MAXV>(buf, twsh, pl.M, Ns, tw, pl.L); break;
+            case 5: fft_pass<T, 5, INV, MAXV>(buf, twsh, pl.M, Ns, tw, pl.L); break;
+            case 7: fft_pass<T, 7, INV, MAXV>(buf, twsh, pl.M, Ns, tw, pl.L); break;
+            default: fft_pass<T, 8, INV, MAXV>(buf, twsh, pl.M, Ns, tw, pl.L); break;
+        }
+        Ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------- real <-> half spectrum
+// X[k] = (Z[k] + conj Z[M-k]) / 2 - (i/2) W^k (Z[k] - conj Z[M-k]), W = e^{-2 pi i / L},
+// k = 0..M (Z is M-periodic).  Calls store(k, s, X).
+template <typename T, typename Store>
+__device__ __forceinline__ void r2c_post(const cplx<T>* buf, int twsh, int M,
+                                         const cplx<T>* __restrict__ tw, Store&& store) {
+    using Z = cplx<T>;
+    const int TWm = (1 << twsh) - 1;
+    for (int e = threadIdx.x; e < ((M + 1) << twsh); e += kFftThreads) {
+        const int k = e >> twsh, s = e & TWm;
+        const int k1 = (k == M) ? 0 : k;
+        const int k2 = (k == 0) ? 0 : M - k;
+        const Z a = buf[(k1 << twsh) + s];
+        const Z b = cconj(buf[(k2 << twsh) + s]);
+        const Z sum = cadd(a, b);
+        const Z t = cmul(tw[k], csub(a, b));
+        store(k, s, cmk<T>(T(0.5) * (sum.x + t.y), T(0.5) * (sum.y - t.x)));
+    }
+}
+
+// Inverse of r2c_post on a tile holding X[0..M]: leaves Z[0..M-1] with
+// Z[k] = E[k] + i O[k], E = (X[k] + conj X[M-k]) / 2,
+// O = conj(W^k) (X[k] - conj X[M-k]) / 2.  Bins 0 and M are taken as real.
+template <typename T>
+__device__ __forceinline__ void c2r_pre(cplx<T>* buf, int twsh, int M, const cplx<T>* __restrict__ tw) {
+    using Z = cplx<T>;
+    const int TWm = (1 << twsh) - 1;
+    auto one = [&](Z xa, Z xb, Z w) {
+        const Z cb = cconj(xb);
+        const Z E = cscale(cadd(xa, cb), T(0.5));
+        const Z O = cscale(cmul(cconj(w), csub(xa, cb)), T(0.5));
+        return cmk<T>(E.x - O.y, E.y + O.x);
+    };
+    for (int e = threadIdx.x; e < ((M / 2 + 1) << twsh); e += kFftThreads) {
+        const int k = e >> twsh, s = e & TWm;
+        const int kk = M - k;
+        Z xk = buf[(k << twsh) + s];
+        Z xkk = buf[(kk << twsh) + s];
+        if (k == 0) { xk.y = T(0); xkk.y = T(0); }
+        const Z zk = one(xk, xkk, tw[k]);
+        if (k != 0 && kk != k) {
+            const Z zkk = one(xkk, xk, tw[kk]);
+            buf[(kk << twsh) + s] = zkk;
+        }
+        buf[(k << twsh) + s] = zk;
+    }
+}
+
+__device__ __forceinline__ int active_len(const SeriesIO& io, int outer) {
+    int nt = io.Nt;
+    if (io.nt_active) {
+        const int a = io.nt_active[outer];
+        nt = a < 0 ? 0 : (a < nt ? a : nt);
+    }
+    return nt;
+}
+
+// Load real series (zero past the active length) as z[n] = x[2n] + i x[2n+1].
+template <typename T, typename TIN>
+__device__ __forceinline__ void load_time(cplx<T>* buf, int twsh, int M, const TIN* __restrict__ src,
+                                          long long t_stride, int S, int s0, int nt) {
+    const int TWm = (1 << twsh) - 1;
+    for (int e = threadIdx.x; e < (M << twsh); e += kFftThreads) {
+        const int n = e >> twsh, s = e & TWm;
+        const int col = s0 + s;
+        T x0 = T(0), x1 = T(0);
+        if (col < S) {
+            const int t0 = 2 * n;
+            if (t0 < nt) x0 = (T)src[(long long)t0 * t_stride + col];
+            if (t0 + 1 < nt) x1 = (T)src[(long long)(t0 + 1) * t_stride + col];
+        }
+        buf[e] = cmk<T>(x0, x1);
+    }
+}
+
+// Load a half spectrum X[0..M], summing `nparts` partial spectra in order.
+template <typename T>
+__device__ __forceinline__ void load_spec(cplx<T>* buf, int twsh, int M, const cplx<T>* __restrict__ src,
+                                          long long f_stride, long long f_part, int nparts, int S, int s0) {
+    using Z = cplx<T>;
+    const int TWm = (1 << twsh) - 1;
+    for (int e = threadIdx.x; e < ((M + 1) << twsh); e += kFftThreads) {
+        const int k = e >> twsh, s = e & TWm;
+        const int col = s0 + s;
+        Z acc = cmk<T>(T(0), T(0));
+        if (col < S) {
+            const Z* p = src + (long long)k * f_stride + col;
+            for (int q = 0; q < nparts; ++q) acc = cadd(acc, p[(long long)q * f_part]);
+        }
+        buf[e] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+// r2c: time series [outer][t][col] -> half spectra [outer][k][col] (cols >= S zero-filled up to S_pad)
+template <typename T, typename TIN>
+__global__ __launch_bounds__(kFftThreads) void k_r2c(FftPlan pl, SeriesIO io, const TIN* __restrict__ in,
+                                                     cplx<T>* __restrict__ out, const cplx<T>* __restrict__ tw,
+                                                     int twsh) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    using Z = cplx<T>;
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    const int outer = blockIdx.y;
+    const int s0 = blockIdx.x << twsh;
+    const int nt = active_len(io, outer);
+    load_time<T, TIN>(buf, twsh, pl.M, in + (long long)outer * io.t_outer, io.t_stride, io.S, s0, nt);
+    __syncthreads();
+    fft_tile<T, false>(buf, twsh, pl, tw);
+    Z* dst = out + (long long)outer * io.f_outer + s0;
+    r2c_post<T>(buf, twsh, pl.M, tw, [&](int k, int s, Z X) {
+        if (s0 + s < io.S_pad) dst[(long long)k * io.f_stride + s] = X;
+    });
+}
+
+// c2r: half spectra (sum of nparts partials) -> time series, truncated to Nt
+// (and to the active length, zeros past it).  With EPI_MISFIT the stored
+// value is w = (y - d_obs) / var and the FP64 block sum of r * w goes to
+// `partials[outer * gridDim.x + blockIdx.x]`.
+struct MisfitArgs {
+    const void* d_obs;       // [outer][t][col], I/O type
+    const double* var;       // noise variances
+    int var_mode;            // 0: scalar, 1: per column (sensor), 2: per (t, col)
+    double* partials;
+};
+
+enum { EPI_PLAIN = 0, EPI_MISFIT = 1 };
+
+template <typename T, typename TOUT, int EPI>
+__global__ __launch_bounds__(kFftThreads) void k_c2r(FftPlan pl, SeriesIO io, const cplx<T>* __restrict__ in,
+                                                     TOUT* __restrict__ out, const cplx<T>* __restrict__ tw,
+                                                     int twsh, MisfitArgs ma) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    using Z = cplx<T>;
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    const int outer = blockIdx.y;
+    const int s0 = blockIdx.x << twsh;
+    const int TWm = (1 << twsh) - 1;
+    const int nt = active_len(io, outer);
+    load_spec<T>(buf, twsh, pl.M, in + (long long)outer * io.f_outer, io.f_stride, io.f_part, io.nparts, io.S, s0);
+    __syncthreads();
+    c2r_pre<T>(buf, twsh, pl.M, tw);
+    __syncthreads();
+    fft_tile<T, true>(buf, twsh, pl, tw);
+    const T inv = T(1) / T(pl.M);
+    TOUT* dst = out + (long long)outer * io.t_outer;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < (pl.M << twsh); e += kFftThreads) {
+        const int n = e >> twsh, s = e & TWm;
+        const int col = s0 + s;
+        if (col >= io.S) continue;
+        const Z z = buf[e];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = 2 * n + h;
+            if (t >= io.Nt) break;
+            const T y = (h == 0 ? z.x : z.y) * inv;
+            const long long off = (long long)t * io.t_stride + col;
+            if constexpr (EPI == EPI_PLAIN) {
+                dst[off] = (t < nt) ? (TOUT)y : TOUT(0);
+            } else {
+                const TOUT* dob = reinterpret_cast<const TOUT*>(ma.d_obs) + (long long)outer * io.t_outer;
+                double r = 0.0, wv = 0.0;
+                if (t < nt) {
+                    const double var = ma.var_mode == 0 ? ma.var[0]
+                                     : ma.var_mode == 1 ? ma.var[col]
+                                                        : ma.var[(long long)t * io.S + col];
+                    r = (double)y - (double)dob[off];
+                    wv = r / var;
+                    acc += r * wv;
+                }
+                dst[off] = (TOUT)wv;
+            }
+        }
+    }
+    if constexpr (EPI == EPI_MISFIT) {
+        __syncthreads();                       // LDS tile is free now
+        double* red = reinterpret_cast<double*>(smem_raw);
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = kFftThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ma.partials[(long long)outer * gridDim.x + blockIdx.x] = red[0];
+    }
+}
+
+// Truncate-and-repad between the adjoint and forward passes of F F^*:
+// half spectra (sum of partials) -> time series -> keep t < active length
+// -> half spectra again, written over partial 0 of the input (every
+// workgroup reads its whole tile before it writes).
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_project(FftPlan pl, SeriesIO io, cplx<T>* in_out,
+                                                         const cplx<T>* __restrict__ tw, int twsh) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    using Z = cplx<T>;
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    const int outer = blockIdx.y;
+    const int s0 = blockIdx.x << twsh;
+    const int TWm = (1 << twsh) - 1;
+    const int nt = active_len(io, outer);
+    Z* base = in_out + (long long)outer * io.f_outer;
+    load_spec<T>(buf, twsh, pl.M, base, io.f_stride, io.f_part, io.nparts, io.S, s0);
+    __syncthreads();
+    c2r_pre<T>(buf, twsh, pl.M, tw);
+    __syncthreads();
+    fft_tile<T, true>(buf, twsh, pl, tw);
+    const T inv = T(1) / T(pl.M);
+    for (int e = threadIdx.x; e < (pl.M << twsh); e += kFftThreads) {
+        const int n = e >> twsh;
+        Z z = buf[e];
+        z.x = (2 * n < nt) ? z.x * inv : T(0);
+        z.y = (2 * n + 1 < nt) ? z.y * inv : T(0);
+        buf[e] = z;
+    }
+    __syncthreads();
+    fft_tile<T, false>(buf, twsh, pl, tw);
+    Z* dst = base + s0;
+    r2c_post<T>(buf, twsh, pl.M, tw, [&](int k, int s, Z X) {
+        if (s0 + s < io.S_pad) dst[(long long)k * io.f_stride + s] = X;
+    });
+}
+
+// Fixed-order sum of the misfit partials: misfit[b] = 1/2 sum_x partials[b][x].
+__global__ void k_misfit_reduce(const double* __restrict__ partials, int nper, double* __restrict__ misfit,
+                                int nrhs) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    if (b >= nrhs) return;
+    double acc = 0.0;
+    for (int x = threadIdx.x; x < nper; x += 256) acc += partials[(long long)b * nper + x];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) misfit[b] = 0.5 * red[0];
+}
+
+// ---------------------------------------------------------------- loading the spectrum
+// Twiddles e^{-2 pi i n / L}, n < L, in FP64 (sincospi takes the angle in
+// units of pi, so the only rounding before it is that of 2n/L), also
+// rounded to FP32.
+__global__ void k_twiddle(double2* __restrict__ tw64, float2* __restrict__ tw32, int L) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= L) return;
+    double s, c;
+    sincospi(-(2.0 * (double)n) / (double)L, &s, &c);
+    tw64[n] = make_double2(c, s);
+    tw32[n] = make_float2((float)c, (float)s);
+}
+
+__device__ __forceinline__ int quant_exponent(float amax, int prec) {
+    if (!(amax > 0.0f)) return 0;
+    int ex;
+    const float f = frexpf(amax, &ex);          // amax = f 2^ex, f in [1/2, 1)
+    const int clog2 = (f == 0.5f) ? ex - 1 : ex; // ceil(log2 amax)
+    int e = (prec == kFP16 ? 15 : 0) - clog2;
+    e = e < -126 ? -126 : (e > 126 ? 126 : e);
+    return e;
+}
+
+// Transform columns of the time-domain blocks, all rows in [row0, row0+rows).
+// PASS 0: per-(bin, scale block) maximum magnitude of real and imaginary
+// parts, accumulated as float bits with atomicMax into `amax` (exact and
+// order independent), and a non-finite flag.  PASS 1: round and store.
+template <typename TIN, int P, int PASS>
+__global__ __launch_bounds__(kFftThreads) void k_load(FftPlan pl, LoadArgs la, const TIN* __restrict__ in,
+                                                      const double2* __restrict__ tw, int twsh) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    using Z = double2;
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    unsigned* lmax = reinterpret_cast<unsigned*>(buf + ((pl.M + 1) << twsh));
+    const int s0 = blockIdx.x << twsh;
+    const int TWm = (1 << twsh) - 1;
+    const int blk = (int)((la.col0 + s0) / kScaleBlock);
+    bool bad = false;
+    if constexpr (PASS == 0) {
+        for (int k = threadIdx.x; k <= pl.M; k += kFftThreads) lmax[k] = 0u;
+    }
+    const int r0 = blockIdx.y * la.rows_per_wg;
+    const int r1 = min(la.Nd, r0 + la.rows_per_wg);
+    for (int row = r0; row < r1; ++row) {
+        const TIN* src = in + (long long)row * la.ncols;
+        for (int e = threadIdx.x; e < (pl.M << twsh); e += kFftThreads) {
+            const int n = e >> twsh, s = e & TWm;
+            const int col = s0 + s;
+            double x0 = 0.0, x1 = 0.0;
+            if (col < la.ncols) {
+                const int t0 = 2 * n;
+                if (t0 < la.Nt) x0 = (double)src[(long long)t0 * la.t_stride + col];
+                if (t0 + 1 < la.Nt) x1 = (double)src[(long long)(t0 + 1) * la.t_stride + col];
+                if constexpr (PASS == 0 || !Fmt<P>::scaled) bad |= !isfinite(x0) || !isfinite(x1);
+            }
+            buf[e] = make_double2(x0, x1);
+        }
+        __syncthreads();
+        fft_tile<double, false>(buf, twsh, pl, tw);
+        r2c_post<double>(buf, twsh, pl.M, tw, [&](int k, int s, Z X) {
+            const long long col = la.col0 + s0 + s;
+            if constexpr (PASS == 0) {
+                if (s0 + s < la.ncols) {
+                    const float m = (float)fmax(fabs(X.x), fabs(X.y));
+                    atomicMax(&lmax[k], __float_as_uint(m));
+                }
+            } else {
+                if (s0 + s >= la.ncols) return;
+                const long long off = ((long long)k * la.Nd + row) * la.pitch + col;
+                if constexpr (P == kFP64) {
+                    reinterpret_cast<double2*>(la.fhat)[off] = X;
+                } else if constexpr (P == kFP32) {
+                    reinterpret_cast<float2*>(la.fhat)[off] = make_float2((float)X.x, (float)X.y);
+                } else {
+                    const float am = __uint_as_float(reinterpret_cast<const unsigned*>(la.scales)[k * la.nblk + blk]);
+                    const int ex = quant_exponent(am, P);
+                    const float re = f64_to_f32_odd(ldexp(X.x, ex));
+                    const float im = f64_to_f32_odd(ldexp(X.y, ex));
+                    uint32_t q;
+                    if constexpr (P == kBF16) q = f32_to_bf16_rne(re) | (f32_to_bf16_rne(im) << 16);
+                    else q = f32_to_f16_rne(re) | (f32_to_f16_rne(im) << 16);
+                    reinterpret_cast<uint32_t*>(la.fhat)[off] = q;
+                }
+            }
+        });
+        __syncthreads();
+    }
+    if constexpr (PASS == 0) {
+        for (int k = threadIdx.x; k <= pl.M; k += kFftThreads)
+            atomicMax(reinterpret_cast<unsigned*>(la.scales) + k * la.nblk + blk, lmax[k]);
+    }
+    if (bad) atomicOr(la.flag, 1u);
+}
+
+// Zero (PASS 0 start) the amax slots of scale blocks [blk0, blk1), or turn
+// them into dequantisation multipliers 2^-e, or set multipliers to 1.
+__global__ void k_scales(float* __restrict__ scales, int nfreq, int nblk, int blk0, int blk1, int mode, int prec) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = blk1 - blk0;
+    if (i >= nfreq * nb) return;
+    const int k = i / nb, b = blk0 + i % nb;
+    float* p = scales + (long long)k * nblk + b;
+    if (mode == 0) *p = 0.0f;
+    else if (mode == 1) *p = ldexpf(1.0f, -quant_exponent(*p, prec));
+    else *p = 1.0f;
+}
+
+// Zero-fill of the padding columns [Nm, pitch) of every stored row.
+__global__ void k_zero_pad(uint8_t* __restrict__ fhat, long long rows, int pitch, int Nm, int bytes) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = (pitch - Nm) * bytes;
+    if (w <= 0 || i >= rows * w) return;
+    const long long r = i / w;
+    fhat[r * (long long)pitch * bytes + (long long)Nm * bytes + (i % w)] = 0;
+}
+
+// ---------------------------------------------------------------- host launchers
+int fft_tile_shift(int M, bool f64) {
+    const int cap = f64 ? FftCap<double>::cap : FftCap<float>::cap;
+    int tw = 64;
+    while (tw > 1 && tw * (M + 1) > cap) tw >>= 1;
+    if (tw * (M + 1) > cap) return -1;
+    int sh = 0;
+    while ((1 << sh) < tw) ++sh;
+    return sh;
+}
+
+static size_t fft_lds(int M, int twsh, size_t zbytes) { return (size_t)(M + 1) * ((size_t)1 << twsh) * zbytes; }
+
+// The loader also keeps one running maximum per bin in LDS; stay within 64 KiB.
+int load_tile_shift(int M) {
+    int sh = fft_tile_shift(M, true);
+    while (sh > 0 && fft_lds(M, sh, sizeof(double2)) + (size_t)(M + 1) * sizeof(unsigned) > 65536) --sh;
+    if (sh < 0 || fft_lds(M, sh, sizeof(double2)) + (size_t)(M + 1) * sizeof(unsigned) > 65536) return -1;
+    return sh;
+}
+
+hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st) {
+    hipLaunchKernelGGL(k_twiddle, dim3((L + 255) / 256), dim3(256), 0, st,
+                       (double2*)tw64, (float2*)tw32, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
+                      const void* tw, hipStream_t st) {
+    const int sh = fft_tile_shift(pl.M, f64);
+    dim3 grid((io.S_pad + (1 << sh) - 1) >> sh, io.outer_count);
+    if (f64) {
+        const size_t lds = fft_lds(pl.M, sh, sizeof(double2));
+        if (in_f64) hipLaunchKernelGGL((k_r2c<double, double>), grid, dim3(kFftThreads), lds, st, pl, io, (const double*)in, (double2*)out, (const double2*)tw, sh);
+        else hipLaunchKernelGGL((k_r2c<double, float>), grid, dim3(kFftThreads), lds, st, pl, io, (const float*)in, (double2*)out, (const double2*)tw, sh);
+    } else {
+        const size_t lds = fft_lds(pl.M, sh, sizeof(float2));
+        hipLaunchKernelGGL((k_r2c<float, float>), grid, dim3(kFftThreads), lds, st, pl, io, (const float*)in, (float2*)out, (const float2*)tw, sh);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
+                      const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st) {
+    const int sh = fft_tile_shift(pl.M, f64);
+    dim3 grid((io.S + (1 << sh) - 1) >> sh, io.outer_count);
+    MisfitArgs ma{d_obs, var, var_mode, partials};
+    const bool mis = d_obs != nullptr;
+    if (f64) {
+        size_t lds = fft_lds(pl.M, sh, sizeof(double2));
+        if (lds < kFftThreads * sizeof(double)) lds = kFftThreads * sizeof(double);
+        if (mis) hipLaunchKernelGGL((k_c2r<double, double, EPI_MISFIT>), grid, dim3(kFftThreads), lds, st, pl, io, (const double2*)in, (double*)out, (const double2*)tw, sh, ma);
+        else hipLaunchKernelGGL((k_c2r<double, double, EPI_PLAIN>), grid, dim3(kFftThreads), lds, st, pl, io, (const double2*)in, (double*)out, (const double2*)tw, sh, ma);
+    } else {
+        size_t lds = fft_lds(pl.M, sh, sizeof(float2));
+        if (lds < kFftThreads * sizeof(double)) lds = kFftThreads * sizeof(double);
+        if (mis) hipLaunchKernelGGL((k_c2r<float, float, EPI_MISFIT>), grid, dim3(kFftThreads), lds, st, pl, io, (const float2*)in, (float*)out, (const float2*)tw, sh, ma);
+        else hipLaunchKernelGGL((k_c2r<float, float, EPI_PLAIN>), grid, dim3(kFftThreads), lds, st, pl, io, (const float2*)in, (float*)out, (const float2*)tw, sh, ma);
+    }
+    return hipGetLastError();
+}
+
+int c2r_grid_x(const FftPlan& pl, bool f64, int S) {
+    const int sh = fft_tile_shift(pl.M, f64);
+    return (S + (1 << sh) - 1) >> sh;
+}
+
+hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
+                          hipStream_t st) {
+    const int sh = fft_tile_shift(pl.M, f64);
+    dim3 grid((io.S_pad + (1 << sh) - 1) >> sh, io.outer_count);
+    if (f64) hipLaunchKernelGGL((k_project<double>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(double2)), st, pl, io, (double2*)in_out, (const double2*)tw, sh);
+    else hipLaunchKernelGGL((k_project<float>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(float2)), st, pl, io, (float2*)in_out, (const float2*)tw, sh);
+    return hipGetLastError();
+}
+
+hipError_t launch_misfit_reduce(const double* partials, int nper, double* misfit, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_misfit_reduce, dim3(nrhs), dim3(256), 0, st, partials, nper, misfit, nrhs);
+    return hipGetLastError();
+}
+
+template <typename TIN, int P>
+static void load_pass(int pass, dim3 grid, size_t lds, hipStream_t st, const FftPlan& pl, const LoadArgs& la,
+                      const void* in, const void* tw, int sh) {
+    if (pass == 0) hipLaunchKernelGGL((k_load<TIN, P, 0>), grid, dim3(kFftThreads), lds, st, pl, la, (const TIN*)in, (const double2*)tw, sh);
+    else hipLaunchKernelGGL((k_load<TIN, P, 1>), grid, dim3(kFftThreads), lds, st, pl, la, (const TIN*)in, (const double2*)tw, sh);
+}
+
+hipError_t launch_load(int prec, bool in_f64, const FftPlan& pl, const LoadArgs& la, const void* in,
+                       const void* tw64, hipStream_t st) {
+    const int sh = load_tile_shift(pl.M);
+    if (sh < 0) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((la.ncols + (1 << sh) - 1) >> sh), (unsigned)((la.Nd + la.rows_per_wg - 1) / la.rows_per_wg));
+    const size_t lds = fft_lds(pl.M, sh, sizeof(double2)) + (size_t)(pl.M + 1) * sizeof(unsigned);
+    const int nb0 = (int)(la.col0 / kScaleBlock);
+    const int nb1 = (int)((la.col0 + la.ncols + kScaleBlock - 1) / kScaleBlock);
+    const int nfreq = pl.M + 1;
+    const int ns = nfreq * (nb1 - nb0);
+    const bool scaled = prec == kBF16 || prec == kFP16;
+    if (scaled) {
+        hipLaunchKernelGGL(k_scales, dim3((ns + 255) / 256), dim3(256), 0, st, la.scales, nfreq, la.nblk, nb0, nb1, 0, prec);
+    } else {
+        hipLaunchKernelGGL(k_scales, dim3((ns + 255) / 256), dim3(256), 0, st, la.scales, nfreq, la.nblk, nb0, nb1, 2, prec);
+    }
+    for (int pass = scaled ? 0 : 1; pass < 2; ++pass) {
+        switch (prec) {
+            case kFP64: in_f64 ? load_pass<double, kFP64>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kFP64>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
+            case kFP32: in_f64 ? load_pass<double, kFP32>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kFP32>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
+            case kBF16: in_f64 ? load_pass<double, kBF16>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kBF16>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
+            default: in_f64 ? load_pass<double, kFP16>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kFP16>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
+        }
+    }
+    if (scaled) {
+        hipLaunchKernelGGL(k_scales, dim3((ns + 255) / 256), dim3(256), 0, st, la.scales, nfreq, la.nblk, nb0, nb1, 1, prec);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_pad(void* fhat, long long rows, int pitch, int Nm, int bytes, hipStream_t st) {
+    const long long n = rows * (long long)(pitch - Nm) * bytes;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint8_t*)fhat, rows, pitch, Nm, bytes);
+    return hipGetLastError();
+}
+
+}  // namespace p2o

@@ -1,0 +1,58 @@
+// Internal launchers between the plan (abi.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include "common.hpp"
+
+namespace p2o {
+
+struct GemvArgs {
+    int Nd;
+    int pitch;            // complex entries per stored row (>= Nm, multiple of 8)
+    int nfreq;
+    int nrhs;
+    int nblk;             // scale blocks per row
+    int nslab;            // row slabs (adjoint: partial outputs; forward: row tiling)
+    int rows_per_wg;      // rows per slab
+    long long part_stride;  // complex elements between partial outputs
+};
+
+struct LoadArgs {
+    void* fhat;
+    float* scales;        // [nfreq][nblk]
+    unsigned* flag;       // non-finite flag
+    long long col0;
+    int ncols;
+    int Nd;
+    int Nt;
+    long long t_stride;   // elements between time steps of the source chunk (Nd * ncols)
+    long long pitch;
+    int nblk;
+    int rows_per_wg;
+};
+
+// fft.hip
+int fft_tile_shift(int M, bool f64);
+int c2r_grid_x(const FftPlan& pl, bool f64, int S);
+hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st);
+hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
+                      const void* tw, hipStream_t st);
+hipError_t launch_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
+                      const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st);
+hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
+                          hipStream_t st);
+hipError_t launch_misfit_reduce(const double* partials, int nper, double* misfit, int nrhs, hipStream_t st);
+hipError_t launch_load(int prec, bool in_f64, const FftPlan& pl, const LoadArgs& la, const void* in,
+                       const void* tw64, hipStream_t st);
+hipError_t launch_zero_pad(void* fhat, long long rows, int pitch, int Nm, int bytes, hipStream_t st);
+int load_tile_shift(int M);
+
+// gemv.hip
+int gemv_cols_per_lane(int prec);
+int gemv_fwd_chunks(int prec, int pitch);
+hipError_t launch_gemv_fwd(int prec, const GemvArgs& ga, const void* fhat, const float* scales, const void* X,
+                           void* Yp, hipStream_t st);
+hipError_t launch_gemv_adj(int prec, const GemvArgs& ga, const void* fhat, const float* scales, const void* Y,
+                           void* Xp, hipStream_t st);
+
+}  // namespace p2o

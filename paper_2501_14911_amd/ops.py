@@ -1,0 +1,251 @@
+"""Python face of the p2o library: a plan bound to torch-owned device memory,
+and autograd functions whose backward passes are the hand-written adjoint.
+
+Every step of a matvec runs in libp2o's HIP kernels; this module only
+allocates memory with torch, passes pointers and the current HIP stream,
+and checks shapes and dtypes.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_int64, c_size_t, c_void_p
+from typing import Callable, Optional
+
+import torch
+
+from ._lib import (P2O_FP64, P2O_SRC_F32, P2O_SRC_F64, PRECISIONS, STAGES, check, lib)
+
+SCALE_BLOCK = 4096
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+class P2OOperator:
+    """The block lower-triangular Toeplitz map F (Nd sensors, Nm parameters,
+    Nt steps) held as its stored spectrum on one GPU.
+
+    ``precision`` is the storage of the spectrum: "fp64", "fp32", "bf16" or
+    "fp16" (the last two accumulate in FP32).  Series are float64 for fp64
+    plans and float32 otherwise, shaped [nrhs, Nt, Nm] / [nrhs, Nt, Nd]
+    (a leading nrhs may be omitted).
+    """
+
+    def __init__(self, Nd: int, Nm: int, Nt: int, precision: str = "bf16", max_rhs: int = 1,
+                 device="cuda"):
+        self.Nd, self.Nm, self.Nt = int(Nd), int(Nm), int(Nt)
+        self.precision = precision
+        self.max_rhs = int(max_rhs)
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the p2o operator lives on a GPU (device 'cuda')")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        plan = c_void_p()
+        check(lib.p2o_create(byref(plan), self.Nd, self.Nm, self.Nt, PRECISIONS[precision], self.max_rhs))
+        self._plan = plan
+        L, nf, pitch, nblk = c_int64(), c_int64(), c_int64(), c_int64()
+        check(lib.p2o_get_layout(plan, byref(L), byref(nf), byref(pitch), byref(nblk)))
+        self.L, self.nfreq, self.pitch, self.nblk = L.value, nf.value, pitch.value, nblk.value
+        fb, wb = c_size_t(), c_size_t()
+        check(lib.p2o_required_bytes(plan, byref(fb), byref(wb)))
+        self.fhat_bytes, self.ws_bytes = fb.value, wb.value
+        self.fhat = torch.empty(self.fhat_bytes, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        check(lib.p2o_bind_storage(plan, _ptr(self.fhat), self.fhat_bytes, _ptr(self.workspace), self.ws_bytes))
+        self.ready = False
+
+    # ------------------------------------------------------------------ plumbing
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device)
+        check(lib.p2o_set_stream(self._plan, c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            lib.p2o_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def elem_bytes(self) -> int:
+        return {"fp64": 16, "fp32": 8, "bf16": 4, "fp16": 4}[self.precision]
+
+    def spectrum_view(self) -> torch.Tensor:
+        """Raw stored spectrum bytes as [nfreq, Nd, pitch * elem_bytes] (read-only use)."""
+        n = self.nfreq * self.Nd * self.pitch * self.elem_bytes
+        return self.fhat[:n].view(self.nfreq, self.Nd, self.pitch * self.elem_bytes)
+
+    def scales_view(self) -> torch.Tensor:
+        """Per-(frequency, 4096-column block) dequantisation multipliers."""
+        n = self.nfreq * self.Nd * self.pitch * self.elem_bytes
+        off = (n + 255) // 256 * 256
+        return self.fhat[off: off + 4 * self.nfreq * self.nblk].view(torch.float32).view(self.nfreq, self.nblk)
+
+    # ------------------------------------------------------------------ timing
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-stage HIP-event timing; resets the totals."""
+        check(lib.p2o_profile_enable(self._plan, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        """{stage: (total_ms, launches)} since profiling was enabled (synchronises)."""
+        out = {}
+        for name, sid in STAGES.items():
+            ms, n = ctypes.c_double(), c_int64()
+            check(lib.p2o_profile_read(self._plan, sid, byref(ms), byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    # ------------------------------------------------------------------ loading
+    def load_blocks(self, F_chunk: torch.Tensor, col0: int = 0):
+        """Transform and store F_k[:, col0:col0+ncols] given as [Nt, Nd, ncols]
+        (float64 or float32, on this device)."""
+        if F_chunk.device != self.device or F_chunk.dim() != 3:
+            raise ValueError("F_chunk must be a [Nt, Nd, ncols] tensor on the operator's device")
+        if F_chunk.shape[0] != self.Nt or F_chunk.shape[1] != self.Nd:
+            raise ValueError(f"F_chunk shape {tuple(F_chunk.shape)} does not match Nt={self.Nt}, Nd={self.Nd}")
+        if F_chunk.dtype not in (torch.float64, torch.float32):
+            raise ValueError("F_chunk must be float64 or float32")
+        F_chunk = F_chunk.contiguous()
+        src = P2O_SRC_F64 if F_chunk.dtype == torch.float64 else P2O_SRC_F32
+        self._stream()
+        check(lib.p2o_load_blocks(self._plan, _ptr(F_chunk), int(col0), int(F_chunk.shape[2]), src))
+        # keep the chunk alive until the stream has consumed it
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def finalize(self):
+        self._stream()
+        check(lib.p2o_load_finalize(self._plan))
+        self.ready = True
+
+    def load(self, blocks: Callable[[int, int], torch.Tensor], chunk_cols: int = SCALE_BLOCK):
+        """Load every column with ``blocks(col0, ncols) -> [Nt, Nd, ncols]``."""
+        for c0 in range(0, self.Nm, chunk_cols):
+            n = min(chunk_cols, self.Nm - c0)
+            self.load_blocks(blocks(c0, n), c0)
+        self.finalize()
+
+    # ------------------------------------------------------------------ applies
+    def _series(self, x: torch.Tensor, last: int, name: str):
+        if x.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+        if x.dtype != self.dtype:
+            raise ValueError(f"{name} must be {self.dtype} for a {self.precision} operator")
+        squeeze = x.dim() == 2
+        xb = x.unsqueeze(0) if squeeze else x
+        if xb.dim() != 3 or xb.shape[1] != self.Nt or xb.shape[2] != last:
+            raise ValueError(f"{name} shape {tuple(x.shape)} must be [nrhs, {self.Nt}, {last}]")
+        return xb.contiguous(), squeeze
+
+    def _nt(self, nt_active, nrhs: int):
+        if nt_active is None:
+            return None
+        n = torch.as_tensor(nt_active, dtype=torch.int32, device=self.device).contiguous()
+        if n.numel() != nrhs:
+            raise ValueError("nt_active needs one length per right-hand side")
+        return n
+
+    def apply_F(self, m: torch.Tensor, nt_active=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """d = F m."""
+        mb, sq = self._series(m, self.Nm, "m")
+        nrhs = mb.shape[0]
+        nt = self._nt(nt_active, nrhs)
+        d = out if out is not None else torch.empty((nrhs, self.Nt, self.Nd), dtype=self.dtype, device=self.device)
+        self._stream()
+        check(lib.p2o_apply_F(self._plan, _ptr(mb), _ptr(d), nrhs, _ptr(nt)))
+        return d[0] if sq and out is None else d
+
+    def apply_Ft(self, d: torch.Tensor, nt_active=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """m = F^* d."""
+        db, sq = self._series(d, self.Nd, "d")
+        nrhs = db.shape[0]
+        nt = self._nt(nt_active, nrhs)
+        m = out if out is not None else torch.empty((nrhs, self.Nt, self.Nm), dtype=self.dtype, device=self.device)
+        self._stream()
+        check(lib.p2o_apply_Ft(self._plan, _ptr(db), _ptr(m), nrhs, _ptr(nt)))
+        return m[0] if sq and out is None else m
+
+    def apply_FFt(self, e: torch.Tensor, nt_active=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """h = F F^* e (data-space operator columns)."""
+        eb, sq = self._series(e, self.Nd, "e")
+        nrhs = eb.shape[0]
+        nt = self._nt(nt_active, nrhs)
+        h = out if out is not None else torch.empty((nrhs, self.Nt, self.Nd), dtype=self.dtype, device=self.device)
+        self._stream()
+        check(lib.p2o_apply_FFt(self._plan, _ptr(eb), _ptr(h), nrhs, _ptr(nt)))
+        return h[0] if sq and out is None else h
+
+    def misfit_grad(self, m: torch.Tensor, d_obs: torch.Tensor, noise_var, nt_active=None):
+        """(Phi, grad): Phi = 1/2 (Fm - d_obs)^T Gamma^-1 (Fm - d_obs) per
+        right-hand side (float64), grad = F^* Gamma^-1 (Fm - d_obs)."""
+        mb, sq = self._series(m, self.Nm, "m")
+        db, _ = self._series(d_obs, self.Nd, "d_obs")
+        nrhs = mb.shape[0]
+        if db.shape[0] != nrhs:
+            raise ValueError("m and d_obs need the same number of right-hand sides")
+        var = torch.as_tensor(noise_var, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+        nt = self._nt(nt_active, nrhs)
+        grad = torch.empty_like(mb)
+        phi = torch.empty(nrhs, dtype=torch.float64, device=self.device)
+        self._stream()
+        check(lib.p2o_misfit_grad(self._plan, _ptr(mb), _ptr(db), _ptr(var), var.numel(), _ptr(grad), _ptr(phi),
+                                  nrhs, _ptr(nt)))
+        if sq:
+            return phi[0], grad[0]
+        return phi, grad
+
+
+# ---------------------------------------------------------------------- autograd
+class P2O(torch.autograd.Function):
+    """d = F m with backward m_bar = F^* d_bar (the hand-written adjoint)."""
+
+    @staticmethod
+    def forward(ctx, m, op: P2OOperator, nt_active=None):
+        ctx.op = op
+        ctx.nt_active = nt_active
+        return op.apply_F(m, nt_active)
+
+    @staticmethod
+    def backward(ctx, g):
+        return P2OT.apply(g.contiguous(), ctx.op, ctx.nt_active), None, None
+
+
+class P2OT(torch.autograd.Function):
+    """m = F^* d with backward d_bar = F m_bar."""
+
+    @staticmethod
+    def forward(ctx, d, op: P2OOperator, nt_active=None):
+        ctx.op = op
+        ctx.nt_active = nt_active
+        return op.apply_Ft(d, nt_active)
+
+    @staticmethod
+    def backward(ctx, g):
+        return P2O.apply(g.contiguous(), ctx.op, ctx.nt_active), None, None
+
+
+class _Misfit(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, m, op: P2OOperator, d_obs, noise_var, nt_active):
+        phi, grad = op.misfit_grad(m, d_obs, noise_var, nt_active)
+        ctx.save_for_backward(grad)
+        return phi
+
+    @staticmethod
+    def backward(ctx, gphi):
+        (grad,) = ctx.saved_tensors
+        if grad.dim() == 2:
+            return (gphi.to(grad.dtype) * grad), None, None, None, None
+        return gphi.to(grad.dtype)[:, None, None] * grad, None, None, None, None
+
+
+def misfit(m: torch.Tensor, op: P2OOperator, d_obs: torch.Tensor, noise_var, nt_active=None) -> torch.Tensor:
+    """Phi(m) = 1/2 ||F m - d_obs||^2_{Gamma_noise^-1} (float64, per right-hand
+    side) with the fused gradient kernel as its backward."""
+    return _Misfit.apply(m, op, d_obs, noise_var, nt_active)

@@ -1,0 +1,142 @@
+"""Host-side checks of the C ABI with the real libp2o.so (no GPU needed):
+every declared symbol is exported, argument and state checks return the
+documented status without touching a device, and layout arithmetic matches
+the header's contract."""
+import ctypes
+import os
+import re
+from ctypes import byref, c_int64, c_size_t, c_void_p
+
+import pytest
+
+from conftest import ROOT, ensure_built, gpu_available
+
+ensure_built()
+import paper_2501_14911_amd as p2o  # noqa: E402
+from paper_2501_14911_amd._lib import lib  # noqa: E402
+
+HEADER = os.path.join(ROOT, "include", "p2o.h")
+OK, ARG, STATE, DTYPE, STORAGE, NONFINITE, HIP, NODEV = 0, -1, -2, -3, -4, -5, -6, -7
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(p2o_[a-zA-Z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 14, names
+    raw = ctypes.CDLL(p2o.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), f"{n} declared in p2o.h but not exported"
+
+
+def create(Nd=600, Nm=16384, Nt=420, prec=2, max_rhs=1):
+    plan = c_void_p()
+    st = lib.p2o_create(byref(plan), Nd, Nm, Nt, prec, max_rhs)
+    return st, plan
+
+
+def test_status_strings():
+    for code, name in [(OK, "P2O_OK"), (ARG, "P2O_ERR_ARG"), (STATE, "P2O_ERR_STATE"), (DTYPE, "P2O_ERR_DTYPE"),
+                       (STORAGE, "P2O_ERR_STORAGE"), (NONFINITE, "P2O_ERR_NONFINITE"), (HIP, "P2O_ERR_HIP"),
+                       (NODEV, "P2O_ERR_NO_DEVICE")]:
+        assert p2o.status_name(code) == name
+    assert p2o.status_name(12345) == "P2O_UNKNOWN_STATUS"
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 10, 10, 0, 1), ARG), ((4, 0, 10, 0, 1), ARG), ((4, 10, 0, 0, 1), ARG),
+    ((4, 10, 10, 0, 0), ARG), ((4, 10, 10, 7, 1), DTYPE), ((4, 10, 10, -1, 1), DTYPE),
+    ((4, 10, 100000, 0, 1), ARG),
+])
+def test_create_rejects_bad_arguments(args, code):
+    st, plan = create(*args)
+    assert st == code
+    assert p2o.last_error() != ""
+    assert not plan.value
+
+
+def test_create_null_out():
+    assert lib.p2o_create(None, 4, 4, 4, 0, 1) == ARG
+
+
+@pytest.mark.parametrize("Nt,L", [(1, 2), (2, 4), (13, 28), (16, 32), (21, 42), (128, 256), (420, 840), (500, 1000),
+                                  (419, 840), (11, 24)])
+def test_transform_length_is_twice_7smooth(Nt, L):
+    st, plan = create(Nd=3, Nm=5, Nt=Nt, prec=0)
+    assert st == OK
+    Lv, nf, pitch, nblk = c_int64(), c_int64(), c_int64(), c_int64()
+    assert lib.p2o_get_layout(plan, byref(Lv), byref(nf), byref(pitch), byref(nblk)) == OK
+    assert Lv.value == L and nf.value == L // 2 + 1 and Lv.value >= 2 * Nt - 1
+    assert pitch.value == 8 and nblk.value == 1
+    lib.p2o_destroy(plan)
+
+
+@pytest.mark.parametrize("prec,elem", [(0, 16), (1, 8), (2, 4), (3, 4)])
+def test_required_bytes_cover_the_spectrum(prec, elem):
+    st, plan = create(Nd=600, Nm=16384, Nt=420, prec=prec)
+    assert st == OK
+    fb, wb = c_size_t(), c_size_t()
+    assert lib.p2o_required_bytes(plan, byref(fb), byref(wb)) == OK
+    spec = 421 * 600 * 16384 * elem
+    assert spec <= fb.value <= spec + 421 * 4 * 4 + 840 * 24 + 4096
+    # workspace: one spectrum of the parameter series at least
+    assert wb.value >= 421 * 16384 * (16 if prec == 0 else 8)
+    lib.p2o_destroy(plan)
+
+
+def test_bind_checks():
+    st, plan = create(Nd=4, Nm=64, Nt=16, prec=0)
+    fb, wb = c_size_t(), c_size_t()
+    lib.p2o_required_bytes(plan, byref(fb), byref(wb))
+    assert lib.p2o_bind_storage(plan, None, fb.value, c_void_p(4096), wb.value) == ARG
+    assert lib.p2o_bind_storage(plan, c_void_p(4096 + 8), fb.value, c_void_p(8192), wb.value) == ARG
+    assert lib.p2o_bind_storage(plan, c_void_p(4096), fb.value - 1, c_void_p(8192), wb.value) == STORAGE
+    st = lib.p2o_bind_storage(plan, c_void_p(4096), fb.value, c_void_p(8192), wb.value)
+    # host addresses: no device here, or not device memory on a GPU host
+    assert st == (ARG if gpu_available() else NODEV)
+    lib.p2o_destroy(plan)
+
+
+def test_calls_out_of_order_and_bad_arguments():
+    st, plan = create(Nd=4, Nm=64, Nt=16, prec=2, max_rhs=2)
+    dummy = c_void_p(4096)
+    assert lib.p2o_load_blocks(plan, dummy, 0, 64, 0) == STATE          # not bound
+    assert lib.p2o_load_blocks(plan, dummy, 0, 64, 9) == DTYPE
+    assert lib.p2o_load_blocks(plan, dummy, 0, 65, 0) == ARG
+    assert lib.p2o_load_blocks(plan, None, 0, 64, 0) == ARG
+    assert lib.p2o_load_finalize(plan) == STATE
+    assert lib.p2o_apply_F(plan, dummy, dummy, 1, None) == STATE
+    assert lib.p2o_apply_Ft(plan, dummy, dummy, 1, None) == STATE
+    assert lib.p2o_apply_FFt(plan, dummy, dummy, 1, None) == STATE
+    assert lib.p2o_apply_F(plan, dummy, dummy, 3, None) == ARG          # nrhs > max_rhs
+    assert lib.p2o_apply_F(plan, dummy, dummy, 0, None) == ARG
+    assert lib.p2o_apply_F(plan, None, dummy, 1, None) == ARG
+    assert lib.p2o_apply_F(None, dummy, dummy, 1, None) == ARG
+    assert lib.p2o_misfit_grad(plan, dummy, dummy, dummy, 5, dummy, dummy, 1, None) == ARG   # var length
+    assert "noise_var_len" in p2o.last_error()
+    assert lib.p2o_misfit_grad(plan, dummy, dummy, dummy, 4, dummy, dummy, 1, None) == STATE
+    assert lib.p2o_misfit_grad(plan, dummy, None, dummy, 4, dummy, dummy, 1, None) == ARG
+    assert lib.p2o_set_stream(plan, None) == OK
+    assert lib.p2o_destroy(plan) == OK
+    assert lib.p2o_destroy(None) == ARG
+
+
+def test_scaled_loads_need_whole_blocks():
+    st, plan = create(Nd=2, Nm=9000, Nt=8, prec=3)
+    dummy = c_void_p(4096)
+    assert lib.p2o_load_blocks(plan, dummy, 100, 4096, 0) == ARG
+    assert lib.p2o_load_blocks(plan, dummy, 0, 1000, 0) == ARG
+    assert "scale blocks" in p2o.last_error()
+    # whole blocks and the ragged last block pass the argument checks (then fail on state)
+    assert lib.p2o_load_blocks(plan, dummy, 0, 4096, 0) == STATE
+    assert lib.p2o_load_blocks(plan, dummy, 8192, 808, 0) == STATE
+    lib.p2o_destroy(plan)
+
+
+def test_python_operator_requires_a_gpu_device():
+    with pytest.raises(ValueError):
+        p2o.P2OOperator(4, 64, 16, "fp64", device="cpu")
