@@ -1,11 +1,22 @@
 """Benchmark of the FFT-based block-Toeplitz p2o path on one MI355X.
 
-One step is one data-misfit gradient evaluation, the whole single
-right-hand-side hot path: zero-padded r2c FFT of m, per-frequency products
-with the stored spectrum, inverse FFT + truncation fused with the residual,
-FP64 misfit reduction, r2c of the weighted residual, conjugate-transposed
-per-frequency products, inverse FFT -> gradient.  That is one F and one F^*
-matvec, so ``value`` = 2 * steps / seconds (matvecs/s).
+Workload: Nd = 600 sensors, Nm = 16384 parameters per step, Nt = 420 steps
+(circulant length 840), BF16 spectrum with FP32 accumulation, synthetic
+blocks F_k = exp(-k/100) N(0,1)/sqrt(Nm).
+
+One step is one pass over every use of the hot path:
+  1. a data-misfit gradient on one right-hand side (r2c FFT of m, streaming
+     forward products, inverse FFT fused with the residual and the FP64
+     misfit reduction, r2c, streaming adjoint products, inverse FFT):
+     one F and one F^* matvec;
+  2. 64 data-space operator columns h_j = F F^* e_j in one call (batched
+     adjoint and forward products on the matrix cores, truncate-and-repad
+     between them): 128 matvecs;
+  3. F and F^* on 32 right-hand sides whose active lengths are drawn from
+     U{64..420} (batched, ragged): 64 matvecs.
+``value`` = matvecs per second over the step (194 per step).  The plain FP64
+single-right-hand-side path on an FP64 spectrum of the same operator is timed
+beside it for the batched-mixed-precision speedup.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build targets one
 GPU (the operator's column share on that GPU).
@@ -14,7 +25,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -23,6 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+N_HESS = 64
+N_RAGGED = 32
 
 
 def parse():
@@ -31,10 +44,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_time")
-    ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
     ap.add_argument("--cpu-sample-cols", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
     return ap.parse_args()
 
 
@@ -68,55 +81,103 @@ def main():
     w = synth.CONFIGS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"[bench] workload {w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt} precision={args.precision}")
+    log(f"[bench] workload {w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt}")
 
-    op = P2OOperator(w.Nd, w.Nm, w.Nt, args.precision, max_rhs=1, device=dev)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=N_HESS, device=dev)
     t0 = time.perf_counter()
     op.profile(True)
     op.load(lambda c0, n: gpu_blocks(w, c0, n, dev, torch, synth))
     load_ms = op.stage_times()["load"][0]
     op.profile(False)
-    log(f"[bench] spectrum loaded ({op.fhat_bytes / 1e9:.2f} GB) in {time.perf_counter() - t0:.1f} s "
+    log(f"[bench] BF16 spectrum loaded ({op.fhat_bytes / 1e9:.2f} GB) in {time.perf_counter() - t0:.1f} s "
         f"(load kernels {load_ms:.1f} ms)")
 
-    m = synth.param_series(w, 1, backend="torch", device=dev, smooth=(w.name == "largest"))[0].to(op.dtype)
-    d_obs = (synth.data_series(w, 1, backend="torch", device=dev)[0]).to(op.dtype)
+    # inputs
+    m = synth.param_series(w, 1, backend="torch", device=dev, smooth=(w.name == "largest"))[0].float()
+    d_obs = synth.data_series(w, 1, backend="torch", device=dev)[0].float()
     var = torch.tensor([w.sigma ** 2], dtype=torch.float64, device=dev)
+    hidx = synth.hessian_column_indices(w, N_HESS)
+    E = torch.from_numpy(synth.unit_data_vectors(w, hidx)).to(dev, torch.float32)
+    nt_r = synth.ragged_lengths(w, N_RAGGED)
+    nt_r_dev = torch.from_numpy(nt_r).to(dev)
+    m_r = synth.param_series(w, N_RAGGED, seed_offset=21, backend="torch", device=dev).float()
+    d_r = synth.data_series(w, N_RAGGED, tag=synth.TAG_D + 16, backend="torch", device=dev).float()
+    H = torch.empty((N_HESS, w.Nt, w.Nd), dtype=torch.float32, device=dev)
+    Y_r = torch.empty((N_RAGGED, w.Nt, w.Nd), dtype=torch.float32, device=dev)
+    S_r = torch.empty((N_RAGGED, w.Nt, w.Nm), dtype=torch.float32, device=dev)
+
+    def step(evs=None):
+        if evs:
+            evs[0].record()
+        op.misfit_grad(m, d_obs, var)
+        if evs:
+            evs[1].record()
+        op.apply_FFt(E, out=H)
+        if evs:
+            evs[2].record()
+        op.apply_F(m_r, nt_active=nt_r_dev, out=Y_r)
+        op.apply_Ft(d_r, nt_active=nt_r_dev, out=S_r)
+        if evs:
+            evs[3].record()
 
     for _ in range(args.warmup):
-        op.misfit_grad(m, d_obs, var)
+        step()
     torch.cuda.synchronize()
     op.profile(True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ev0.record()
-    for _ in range(args.steps):
-        op.misfit_grad(m, d_obs, var)
+    for k in range(args.steps):
+        step(evs[k])
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    part_ms = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps for i in range(3)]
     stages = op.stage_times()
     op.profile(False)
-    log(f"[bench] {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f} ms/step)")
+    matvecs = 2 + 2 * N_HESS + 2 * N_RAGGED
+    log(f"[bench] {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}): single-RHS gradient "
+        f"{part_ms[0]:.3f} ms, 64 F F* columns {part_ms[1]:.3f} ms, 32 ragged F + F* {part_ms[2]:.3f} ms")
     for k, (tot, n) in stages.items():
         if n:
-            log(f"[bench]   {k:9s} {tot / n * 1e3:9.1f} us x {n // args.steps}/step")
+            log(f"[bench]   {k:9s} {tot / n * 1e3:9.1f} us x {n / args.steps:.0f}/step")
 
-    elem = op.elem_bytes
-    cbytes = 16 if args.precision == "fp64" else 8
-    spec_bytes = op.nfreq * w.Nd * w.Nm * elem
-    vec_bytes = op.nfreq * (w.Nm + w.Nd) * cbytes
-    algo_bytes = spec_bytes + vec_bytes
-    fwd_us = stages["gemv_fwd"][0] / max(1, stages["gemv_fwd"][1]) * 1e3
-    adj_us = stages["gemv_adj"][0] / max(1, stages["gemv_adj"][1]) * 1e3
-    dom, dom_us = ("gemv_adj", adj_us) if adj_us >= fwd_us else ("gemv_fwd", fwd_us)
-    achieved = algo_bytes / (dom_us * 1e-6) / 1e9
+    # roofline bookkeeping (algorithmic bytes: spectrum once + series spectra in/out)
+    spec_bytes = op.nfreq * w.Nd * w.Nm * op.elem_bytes
+
+    def avg_us(k):
+        tot, n = stages[k]
+        return tot / n * 1e3 if n else 0.0
+
+    gemv_bytes = spec_bytes + op.nfreq * (w.Nm + w.Nd) * 8
+    gemm_bytes = spec_bytes + op.nfreq * N_HESS * (w.Nm + w.Nd) * 8
+    gemm_flop = 2.0 * op.nfreq * w.Nd * (2 * w.Nm) * (2 * N_HESS)      # real-equivalent, one BF16 pass
+    kern = {
+        "gemv_fwd": {"us": avg_us("gemv_fwd"), "bytes": gemv_bytes},
+        "gemv_adj": {"us": avg_us("gemv_adj"), "bytes": gemv_bytes},
+        "gemm_fwd": {"us": avg_us("gemm_fwd"), "bytes": gemm_bytes, "flop": gemm_flop},
+        "gemm_adj": {"us": avg_us("gemm_adj"), "bytes": gemm_bytes, "flop": gemm_flop},
+    }
+    # the 64-column launches only (the ragged 32-RHS launches use fewer columns)
+    for k in ("gemm_fwd", "gemm_adj"):
+        kern[k]["note"] = "average over the 64-column and the 32-column launches of a step"
+    for k, v in kern.items():
+        v["GBs"] = v["bytes"] / (v["us"] * 1e-6) / 1e9 if v["us"] else 0.0
+        if "flop" in v and v["us"]:
+            v["TFLOPs"] = v["flop"] / (v["us"] * 1e-6) / 1e12
+    totals = {k: stages[k][0] for k in kern}
+    dom = max(totals, key=totals.get)
+    dk = kern[dom]
+    roof = {"bound": "hbm", "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dk["GBs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+            "algorithmic_bytes_per_launch": dk["bytes"], "avg_launch_us": dk["us"]}
 
     result = {
         "metric": "F/F* matvecs/s + HBM GB/s vs peak",
-        "value": 2.0 / (ms_step * 1e-3),
+        "value": matvecs / (ms_step * 1e-3),
         "unit": "matvecs/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -125,46 +186,111 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16-storage/f32" if args.precision in ("bf16", "fp16") else args.precision.replace("fp", "f"),
+        "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt} L={op.L} {args.precision} spectrum, "
-                               f"single right-hand side, misfit gradient (one F + one F*)",
-                   "Nd": w.Nd, "Nm": w.Nm, "Nt": w.Nt, "precision": args.precision, "nrhs": 1},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
-                     "algorithmic_bytes_per_launch": algo_bytes, "avg_launch_us": dom_us},
-        "kernels_us": {k: (tot / n * 1e3 if n else 0.0) for k, (tot, n) in stages.items()},
-        "gemv_fwd_GBs": algo_bytes / (fwd_us * 1e-6) / 1e9,
-        "gemv_adj_GBs": algo_bytes / (adj_us * 1e-6) / 1e9,
+        "config": {"workload": f"{w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt} L={op.L}, BF16 spectrum + FP32 "
+                               f"accumulation; step = misfit gradient on 1 RHS + 64 F F* columns + F and F* "
+                               f"on 32 ragged RHS ({matvecs} matvecs)",
+                   "Nd": w.Nd, "Nm": w.Nm, "Nt": w.Nt, "spectrum": "bf16", "matvecs_per_step": matvecs},
+        "roofline": roof,
+        "parts_ms": {"single_rhs_gradient": part_ms[0], "hessian_64_columns": part_ms[1],
+                     "ragged_32_F_and_Ft": part_ms[2]},
+        "single_rhs_matvecs_per_s": 2.0 / (part_ms[0] * 1e-3),
+        "batched_matvecs_per_s": 2.0 * N_HESS / (part_ms[1] * 1e-3),
+        "kernels": kern,
+        "kernels_us": {k: avg_us(k) for k in stages},
+        "load_ms": load_ms,
     }
 
     if not args.no_accuracy:
-        result["accuracy"] = accuracy_sample(op, w, m, dev, torch, np)
+        result["accuracy"] = accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np)
+    if not args.no_fp64:
+        result["fp64_plain"] = fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var,
+                                          args.no_accuracy, result)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_cols, np, torch)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_cols, np)
     print(json.dumps(result), flush=True)
 
 
-def accuracy_sample(op, w, m, dev, torch, np):
-    """rel-L2 of F m on 8 sensor rows and of F^* d on 64 parameter columns,
-    against the FP64 oracle on the same rows / columns of every block."""
+def accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np):
+    """rel-L2 against the FP64 oracle on sampled sensor rows / parameter
+    columns of the same outputs (the oracle regenerates those rows or
+    columns of every block)."""
     import oracle
     import synth
     rng = np.random.default_rng(1)
     rows = np.sort(rng.choice(w.Nd, 8, replace=False))
     cols = np.sort(rng.choice(w.Nm, 64, replace=False))
+    out = {}
     d = op.apply_F(m).double().cpu().numpy()
     Fr = synth.operator_rows_cols(w, range(w.Nt), rows=rows, backend="torch").numpy()
-    e_f = oracle.rel_l2(d[:, rows], oracle.apply_F(Fr, m.double().cpu().numpy()))
+    out["single_F_8rows"] = oracle.rel_l2(d[:, rows], oracle.apply_F(Fr, m.double().cpu().numpy()))
     din = synth.data_series(w, 1)[0]
-    s = op.apply_Ft(torch.from_numpy(din).to(dev, op.dtype)).double().cpu().numpy()
+    s = op.apply_Ft(torch.from_numpy(din).to(dev, torch.float32)).double().cpu().numpy()
     Fc = synth.operator_rows_cols(w, range(w.Nt), cols=cols, backend="torch").numpy()
-    e_t = oracle.rel_l2(s[:, cols], oracle.apply_Ft(Fc, din))
-    log(f"[bench] sampled rel-L2 vs FP64 oracle: F {e_f:.2e} (8 rows), F* {e_t:.2e} (64 columns)")
-    return {"rel_l2_F_8rows": e_f, "rel_l2_Ft_64cols": e_t}
+    out["single_Ft_64cols"] = oracle.rel_l2(s[:, cols], oracle.apply_Ft(Fc, din))
+    # data-space columns: F^T e_(t0, s) needs sensor row s of the blocks only
+    h = H.double().cpu().numpy()
+    errs = []
+    for c in range(4):
+        j = int(hidx[c])
+        t0, sidx = divmod(j, w.Nd)
+        rs = np.unique(np.concatenate([rows, [sidx]]))
+        Frs = synth.operator_rows_cols(w, range(w.Nt), rows=rs, backend="torch").numpy()
+        e = np.zeros((w.Nt, len(rs)))
+        e[t0, np.searchsorted(rs, sidx)] = 1.0
+        mt = oracle.apply_Ft(Frs, e)
+        href = oracle.apply_F(Frs, mt)
+        errs.append(oracle.rel_l2(h[c][:, rs], href))
+    out["hessian_columns_4x_rows"] = max(errs)
+    y = Y_r.double().cpu().numpy()
+    mr = m_r.double().cpu().numpy()
+    errs = []
+    for b in range(4):
+        yo = oracle.apply_F(Fr, mr[b:b + 1], nt_r[b:b + 1])[0]
+        errs.append(oracle.rel_l2(y[b][:, rows], yo))
+    out["ragged_F_4x_8rows"] = max(errs)
+    log("[bench] sampled rel-L2 vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
+    out["tolerance"] = 2e-3
+    return out
 
 
-def cpu_baseline(w, cols, np, torch):
+def fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var, no_acc, result, steps=5):
+    """The plain path: FP64 spectrum, one right-hand side, F then F^*."""
+    import oracle
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp64", max_rhs=1, device=dev)
+    op.load(lambda c0, n: gpu_blocks(w, c0, n, dev, torch, synth))
+    m64, d64 = m.double(), d_obs.double()
+    op.misfit_grad(m64, d64, var)
+    torch.cuda.synchronize()
+    op.profile(True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        op.misfit_grad(m64, d64, var)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    st = op.stage_times()
+    out = {"ms_per_F_plus_Ft": ms, "matvecs_per_s": 2.0 / (ms * 1e-3),
+           "gemv_fwd_us": st["gemv_fwd"][0] / max(1, st["gemv_fwd"][1]) * 1e3,
+           "gemv_adj_us": st["gemv_adj"][0] / max(1, st["gemv_adj"][1]) * 1e3}
+    out["batched_bf16_speedup_per_matvec"] = result["batched_matvecs_per_s"] / out["matvecs_per_s"]
+    out["single_bf16_speedup"] = result["single_rhs_matvecs_per_s"] / out["matvecs_per_s"]
+    if not no_acc:
+        rows = np.sort(np.random.default_rng(1).choice(w.Nd, 8, replace=False))
+        d = op.apply_F(m64).cpu().numpy()
+        Fr = synth.operator_rows_cols(w, range(w.Nt), rows=rows, backend="torch").numpy()
+        out["rel_l2_F_8rows"] = oracle.rel_l2(d[:, rows], oracle.apply_F(Fr, m64.cpu().numpy()))
+    log(f"[bench] FP64 plain: {ms:.3f} ms per F + F* ({out['matvecs_per_s']:.1f} matvecs/s); batched BF16 "
+        f"speedup per matvec {out['batched_bf16_speedup_per_matvec']:.1f}x")
+    op.close()
+    del op
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(w, cols, np):
     """The FP64 oracle (direct block-Toeplitz sums with BLAS) on the host
     cores, on the first ``cols`` parameter columns of the same workload; its
     time is scaled by Nm / cols to a full-size matvec rate."""

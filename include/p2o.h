@@ -165,8 +165,30 @@ typedef enum {
     P2O_STAGE_PROJECT = 4,   /* truncate and re-pad between F^* and F        */
     P2O_STAGE_REDUCE = 5,    /* fixed-order FP64 misfit reduction            */
     P2O_STAGE_LOAD = 6,      /* spectrum load (FFT along k, rounding)        */
-    P2O_STAGE_COUNT = 7
+    P2O_STAGE_GEMM_FWD = 7,  /* batched products with Fhat_w on matrix cores */
+    P2O_STAGE_GEMM_ADJ = 8,  /* batched products with Fhat_w^H, matrix cores */
+    P2O_STAGE_COUNT = 9
 } p2o_stage;
+
+/* Plan options (p2o_set_option). */
+typedef enum {
+    P2O_OPT_BATCHED = 0      /* value: p2o_batched_mode                      */
+} p2o_option;
+
+/* How calls with several right-hand sides do the per-frequency products.
+ * AUTO: matrix cores (one launch for up to 64 right-hand sides per group,
+ * BF16 spectrum x BF16 hi+lo split of the FP32 right-hand sides, FP32
+ * accumulation) when the spectrum is BF16 and nrhs >= 2, otherwise one
+ * streaming matrix-vector pass per right-hand side.  GEMV forces the latter;
+ * MFMA forces the former (BF16 plans only, P2O_ERR_DTYPE otherwise). */
+typedef enum {
+    P2O_BATCHED_AUTO = 0,
+    P2O_BATCHED_GEMV = 1,
+    P2O_BATCHED_MFMA = 2
+} p2o_batched_mode;
+
+/* Set a plan option; takes effect for later calls. */
+p2o_status p2o_set_option(p2o_plan* plan, int32_t option, int64_t value);
 
 /* Per-stage timing with HIP events recorded on the plan's stream around
  * every launch (enable = 1) or not (enable = 0).  Either call resets the

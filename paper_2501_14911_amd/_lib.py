@@ -16,7 +16,9 @@ P2O_FP64, P2O_FP32, P2O_BF16, P2O_FP16 = 0, 1, 2, 3
 P2O_SRC_F64, P2O_SRC_F32 = 0, 1
 PRECISIONS = {"fp64": P2O_FP64, "fp32": P2O_FP32, "bf16": P2O_BF16, "fp16": P2O_FP16}
 
-STAGES = {"r2c": 0, "gemv_fwd": 1, "gemv_adj": 2, "c2r": 3, "project": 4, "reduce": 5, "load": 6}
+STAGES = {"r2c": 0, "gemv_fwd": 1, "gemv_adj": 2, "c2r": 3, "project": 4, "reduce": 5, "load": 6,
+          "gemm_fwd": 7, "gemm_adj": 8}
+BATCHED = {"auto": 0, "gemv": 1, "mfma": 2}
 
 STATUS = {
     0: "P2O_OK", -1: "P2O_ERR_ARG", -2: "P2O_ERR_STATE", -3: "P2O_ERR_DTYPE",
@@ -56,6 +58,7 @@ def _load():
         "p2o_apply_FFt": [pv, pv, pv, c_int64, pv],
         "p2o_misfit_grad": [pv, pv, pv, pv, c_int64, pv, pv, c_int64, pv],
         "p2o_profile_enable": [pv, c_int32],
+        "p2o_set_option": [pv, c_int32, c_int64],
         "p2o_profile_read": [pv, c_int32, POINTER(c_double), POINTER(c_int64)],
     }
     for name, args in sigs.items():
@@ -85,6 +88,6 @@ def last_error() -> str:
     return lib.p2o_last_error().decode(errors="replace")
 
 
-__all__ = ["STAGES", "lib", "check", "P2OError", "PRECISIONS", "P2O_FP64", "P2O_FP32", "P2O_BF16", "P2O_FP16",
+__all__ = ["BATCHED", "STAGES", "lib", "check", "P2OError", "PRECISIONS", "P2O_FP64", "P2O_FP32", "P2O_BF16", "P2O_FP16",
            "P2O_SRC_F64", "P2O_SRC_F32", "status_name", "last_error", "LIB_PATH",
            "c_double", "c_int64", "c_size_t", "c_void_p"]

@@ -70,6 +70,7 @@ struct p2o_plan {
     int fwd_rows = 64, fwd_nslab = 1, fwd_chunks = 1;
     int adj_rows = 1, adj_nslab = 1;
     int c2r_nd_blocks = 1;
+    int batched_mode = P2O_BATCHED_AUTO;
     // bound memory
     char* fhat = nullptr;
     char* ws = nullptr;
@@ -154,7 +155,8 @@ void layout(p2o_plan* p) {
 
     const size_t R = (size_t)p->max_rhs;
     const size_t xparts = (size_t)(p->adj_nslab > 1 ? p->adj_nslab : 1);
-    const size_t yparts = (size_t)(p->fwd_chunks > 1 ? p->fwd_chunks : 1);
+    size_t yparts = (size_t)(p->fwd_chunks > 1 ? p->fwd_chunks : 1);
+    if (p->prec == kBF16 && (size_t)gemm_fwd_kchunks((int)p->pitch) > yparts) yparts = (size_t)gemm_fwd_kchunks((int)p->pitch);
     p->off_X = 0;
     p->off_Y = align_up(p->off_X + xparts * nfreq * R * (size_t)p->pitch * p->cbytes);
     p->off_D = align_up(p->off_Y + yparts * nfreq * R * (size_t)p->Nd * p->cbytes);
@@ -221,6 +223,53 @@ GemvArgs gemv_args(const p2o_plan* p, int64_t nrhs, bool fwd) {
 }
 
 // enqueue sequences ----------------------------------------------------------
+// Several right-hand sides with a BF16 spectrum go to the matrix cores.
+bool mfma_on(const p2o_plan* p, int64_t nrhs) {
+    if (p->prec != kBF16) return false;
+    if (p->batched_mode == P2O_BATCHED_MFMA) return true;
+    if (p->batched_mode == P2O_BATCHED_GEMV) return false;
+    return nrhs >= 2;
+}
+
+int fwd_parts(const p2o_plan* p, int64_t nrhs) {
+    return mfma_on(p, nrhs) ? gemm_fwd_kchunks((int)p->pitch) : p->fwd_chunks;
+}
+
+int adj_parts(const p2o_plan* p, int64_t nrhs) { return mfma_on(p, nrhs) ? 1 : p->adj_nslab; }
+
+GemmArgs gemm_args(const p2o_plan* p, int64_t nrhs) {
+    GemmArgs ga{};
+    ga.Nd = (int)p->Nd;
+    ga.pitch = (int)p->pitch;
+    ga.nfreq = (int)p->nfreq;
+    ga.nrhs = (int)nrhs;
+    ga.nblk = (int)p->nblk;
+    ga.part_stride = p->nfreq * nrhs * p->Nd;
+    return ga;
+}
+
+// X (parameter spectra) -> Y partial products
+p2o_status enqueue_fwd_products(p2o_plan* p, const void* X, void* Y, int64_t nrhs) {
+    if (mfma_on(p, nrhs))
+        return staged(p, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores)", [&] {
+            return launch_gemm_fwd(gemm_args(p, nrhs), p->fhat, scales_of(p), X, Y, p->stream);
+        });
+    return staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
+        return launch_gemv_fwd(p->prec, gemv_args(p, nrhs, true), p->fhat, scales_of(p), X, Y, p->stream);
+    });
+}
+
+// Y (data spectra) -> X partial products
+p2o_status enqueue_adj_products(p2o_plan* p, const void* Y, void* X, int64_t nrhs) {
+    if (mfma_on(p, nrhs))
+        return staged(p, P2O_STAGE_GEMM_ADJ, "adjoint per-frequency products (matrix cores)", [&] {
+            return launch_gemm_adj(gemm_args(p, nrhs), p->fhat, scales_of(p), Y, X, p->stream);
+        });
+    return staged(p, P2O_STAGE_GEMV_ADJ, "adjoint per-frequency products", [&] {
+        return launch_gemv_adj(p->prec, gemv_args(p, nrhs, false), p->fhat, scales_of(p), Y, X, p->stream);
+    });
+}
+
 p2o_status enqueue_forward_to_Y(p2o_plan* p, const void* m, int64_t nrhs, const int32_t* nt) {
     void* X = p->ws + p->off_X;
     void* Y = p->ws + p->off_Y;
@@ -228,9 +277,7 @@ p2o_status enqueue_forward_to_Y(p2o_plan* p, const void* m, int64_t nrhs, const 
         return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_param(p, nrhs, nt, 1), m, X, tw_of(p), p->stream);
     });
     if (s) return s;
-    return staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
-        return launch_gemv_fwd(p->prec, gemv_args(p, nrhs, true), p->fhat, scales_of(p), X, Y, p->stream);
-    });
+    return enqueue_fwd_products(p, X, Y, nrhs);
 }
 
 p2o_status enqueue_adjoint_to_X(p2o_plan* p, const void* d, int64_t nrhs, const int32_t* nt) {
@@ -240,9 +287,7 @@ p2o_status enqueue_adjoint_to_X(p2o_plan* p, const void* d, int64_t nrhs, const 
         return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_data(p, nrhs, nt, 1), d, Y, tw_of(p), p->stream);
     });
     if (s) return s;
-    return staged(p, P2O_STAGE_GEMV_ADJ, "adjoint per-frequency products", [&] {
-        return launch_gemv_adj(p->prec, gemv_args(p, nrhs, false), p->fhat, scales_of(p), Y, X, p->stream);
-    });
+    return enqueue_adj_products(p, Y, X, nrhs);
 }
 
 }  // namespace
@@ -314,6 +359,19 @@ p2o_status p2o_create(p2o_plan** out, int64_t Nd, int64_t Nm, int64_t Nt, int32_
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_create");
     }
+}
+
+p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (option == P2O_OPT_BATCHED) {
+        if (value < P2O_BATCHED_AUTO || value > P2O_BATCHED_MFMA)
+            return fail(P2O_ERR_ARG, "batched mode %lld unknown", (long long)value);
+        if (value == P2O_BATCHED_MFMA && p->prec != kBF16)
+            return fail(P2O_ERR_DTYPE, "the matrix-core path needs a BF16 spectrum");
+        p->batched_mode = (int)value;
+        return P2O_OK;
+    }
+    return fail(P2O_ERR_ARG, "unknown option %d", (int)option);
 }
 
 p2o_status p2o_profile_enable(p2o_plan* p, int32_t enable) {
@@ -484,7 +542,7 @@ p2o_status p2o_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const 
         s = enqueue_forward_to_Y(p, m, nrhs, nt_active);
         if (s) return s;
         return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, p->fwd_chunks), p->ws + p->off_Y, d,
+            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, d,
                               tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
         });
     } catch (...) {
@@ -499,7 +557,7 @@ p2o_status p2o_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, const
         s = enqueue_adjoint_to_X(p, d, nrhs, nt_active);
         if (s) return s;
         return staged(p, P2O_STAGE_C2R, "c2r (parameters)", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, p->adj_nslab), p->ws + p->off_X, m,
+            return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, adj_parts(p, nrhs)), p->ws + p->off_X, m,
                               tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
         });
     } catch (...) {
@@ -514,17 +572,14 @@ p2o_status p2o_apply_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, cons
         s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
         if (s) return s;
         s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
-            return launch_project(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, p->adj_nslab), p->ws + p->off_X,
+            return launch_project(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, adj_parts(p, nrhs)), p->ws + p->off_X,
                                   tw_of(p), p->stream);
         });
         if (s) return s;
-        s = staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
-            return launch_gemv_fwd(p->prec, gemv_args(p, nrhs, true), p->fhat, scales_of(p), p->ws + p->off_X,
-                                   p->ws + p->off_Y, p->stream);
-        });
+        s = enqueue_fwd_products(p, p->ws + p->off_X, p->ws + p->off_Y, nrhs);
         if (s) return s;
         return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, p->fwd_chunks), p->ws + p->off_Y, h,
+            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, h,
                               tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
         });
     } catch (...) {
@@ -551,7 +606,7 @@ p2o_status p2o_misfit_grad(p2o_plan* p, const void* m, const void* d_obs, const 
         void* D = p->ws + p->off_D;
         double* P = reinterpret_cast<double*>(p->ws + p->off_P);
         s = staged(p, P2O_STAGE_C2R, "c2r with misfit", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, p->fwd_chunks), p->ws + p->off_Y, D,
+            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, D,
                               tw_of(p), d_obs, noise_var, var_mode, P, p->stream);
         });
         if (s) return s;
@@ -562,7 +617,7 @@ p2o_status p2o_misfit_grad(p2o_plan* p, const void* m, const void* d_obs, const 
         s = enqueue_adjoint_to_X(p, D, nrhs, nt_active);
         if (s) return s;
         return staged(p, P2O_STAGE_C2R, "c2r (gradient)", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, p->adj_nslab), p->ws + p->off_X, grad,
+            return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, adj_parts(p, nrhs)), p->ws + p->off_X, grad,
                               tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
         });
     } catch (...) {

@@ -1,0 +1,335 @@
+// Batched per-frequency products on the matrix cores (many right-hand sides
+// per launch): Y_w = Fhat_w X_w and X'_w = Fhat_w^H Y_w for a BF16 spectrum.
+//
+// With B right-hand sides the per-frequency matvecs of section 4 become one
+// complex GEMM per frequency.  Written over the reals with the spectrum in
+// its stored interleaved form (re, im, re, im, ... along the parameter
+// index), the forward product is a real GEMM of size Nd x 2Nm x 2B: each
+// complex right-hand side x contributes the two real columns
+// (x_r, -x_i, ...) and (x_i, x_r, ...), whose products with a row are the
+// real and imaginary parts of F x.  The adjoint contracts over sensors: with
+// K = (sensor, re/im) it is a real GEMM of size Nm x 2Nd x 2B whose two
+// columns per right-hand side are (y_r, y_i, ...) and (y_i, -y_r, ...).
+//
+// Operands.  The spectrum is BF16 and goes to v_mfma_f32_16x16x32_bf16
+// as is.  Right-hand sides are FP32 spectra; each value is split into a BF16
+// pair hi + lo (hi = RNE(x), lo = RNE(x - hi)), so two MFMAs per tile give
+// about 16 significant bits of the right-hand side while accumulating in
+// FP32.  The per-(frequency, 4096-column block) power-of-two scale of the
+// stored spectrum is folded into x (forward) or the finished columns
+// (adjoint); both are exact.
+//
+// Work.  Every spectrum byte is read once per launch.  Forward workgroups
+// own (frequency, 4096-column chunk, 320-row tile, right-hand-side group):
+// A fragments stream from HBM straight into registers (each lane loads 32
+// contiguous bytes of one row, covering two MFMA K steps), while the right-
+// hand sides of the chunk are staged through LDS, double buffered, already
+// in fragment order.  The chunk's partial products go to their own slot
+// (summed in fixed order by the inverse FFT).  Adjoint workgroups own
+// (frequency, 256-column tile): the spectrum tile of 16 sensors x 256
+// columns is loaded coalesced and transposed into LDS (rows padded to 20
+// words: conflict-free writes, 16-byte fragment reads).  Workgroup ids are
+// mapped so that consecutive ids on one XCD share the same frequency (and
+// forward column chunk): the right-hand-side spectra they all read stay in
+// that XCD's L2.
+//
+// Any permutation of K inside a lane's 8 values is harmless as long as A
+// and B use the same one; both sides below order a lane's values as
+// (re, im) pairs of consecutive complex entries.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace p2o {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGemmThreads = 256;
+constexpr int kFwdMB = 5;          // 16-row blocks per wavefront (forward): 320 rows per workgroup
+constexpr int kAdjMB = 4;          // 16-column blocks per wavefront (adjoint): 256 columns per workgroup
+constexpr int kAdjAW = 20;         // LDS words per transposed column (16 sensors + 4 pad)
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ f32x4 mfma(uint4 a, uint4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+}
+
+// x = hi + lo with hi, lo BF16 (round to nearest even); returns the raw 16-bit codes.
+__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
+    hi = f32_to_bf16_rne(x);
+    lo = f32_to_bf16_rne(x - __uint_as_float(hi << 16));
+}
+
+__device__ __forceinline__ int xcd_item(int id, int Q) { return (id & 7) * Q + (id >> 3); }
+
+// ---------------------------------------------------------------- forward
+template <int NB>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* __restrict__ fhat,
+                                                           const float* __restrict__ scales,
+                                                           const float2* __restrict__ X,
+                                                           float2* __restrict__ Yp, GemmArgs ga) {
+    constexpr int MB = kFwdMB;
+    constexpr int RB = 8 * NB;                 // right-hand sides per group (16 real columns per block)
+    constexpr int ROWS = 4 * MB * 16;
+    __shared__ uint4 bs[2][NB][2][2][64];      // [buffer][n block][K half][hi/lo][lane]
+
+    const int q = xcd_item(blockIdx.x, ga.Q);
+    if (q >= ga.items) return;
+    int t = q;
+    const int mt = t % ga.n_mt; t /= ga.n_mt;
+    const int bg = t % ga.n_bg; t /= ga.n_bg;
+    const int kc = t % ga.n_kc; t /= ga.n_kc;
+    const int w = t;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int b0 = bg * RB;
+    const int jbeg = kc * ga.kchunk;
+    const int jend = min(ga.pitch, jbeg + ga.kchunk);
+    const int nsteps = (jend - jbeg + 31) >> 5;
+    const float sc = scales[(long long)w * ga.nblk + jbeg / kScaleBlock];
+
+    const int rowbase = mt * ROWS + wave * MB * 16;
+    const uint8_t* arow[MB];
+    bool rok[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const int row = rowbase + mb * 16 + lr;
+        rok[mb] = row < ga.Nd;
+        arow[mb] = fhat + (((long long)w * ga.Nd + (rok[mb] ? row : 0)) * ga.pitch + jbeg + 8 * lg) * 4;
+    }
+    auto load_a = [&](Raw32 (&a)[MB], int s) {
+        const int j = jbeg + 32 * s + 8 * lg;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            if (rok[mb] && j < jend) a[mb] = load32(arow[mb] + (long long)s * 128);
+            else a[mb] = Raw32{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+        }
+    };
+
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    Raw32 acur[MB], anxt[MB];
+    load_a(acur, 0);
+    const float2* Xw = X + (long long)w * ga.nrhs * ga.pitch;
+
+    for (int s = 0; s < nsteps; ++s) {
+        const int buf = s & 1;
+        // stage 32 complex columns of the group's right-hand sides as BF16 hi/lo fragments
+        for (int e = tid; e < 32 * RB; e += kGemmThreads) {
+            const int c = e & 31, bl = e >> 5;
+            const int b = b0 + bl, j = jbeg + 32 * s + c;
+            float2 x = make_float2(0.f, 0.f);
+            if (b < ga.nrhs && j < jend) x = Xw[(long long)b * ga.pitch + j];
+            uint32_t rh, rl, ih, il;
+            split_bf16(x.x * sc, rh, rl);
+            split_bf16(x.y * sc, ih, il);
+            const int g = c >> 3, h = (c >> 2) & 1, cc = c & 3;
+            const int nre = 2 * bl, nim = 2 * bl + 1;
+            // real-part column: (x_r, -x_i); imaginary-part column: (x_i, x_r)
+            uint32_t* pre_h = reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][0][g * 16 + (nre & 15)]);
+            uint32_t* pre_l = reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][1][g * 16 + (nre & 15)]);
+            uint32_t* pim_h = reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][0][g * 16 + (nim & 15)]);
+            uint32_t* pim_l = reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][1][g * 16 + (nim & 15)]);
+            pre_h[cc] = rh | ((ih ^ 0x8000u) << 16);
+            pre_l[cc] = rl | ((il ^ 0x8000u) << 16);
+            pim_h[cc] = ih | (rh << 16);
+            pim_l[cc] = il | (rl << 16);
+        }
+        if (s + 1 < nsteps) load_a(anxt, s + 1);
+        __syncthreads();
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const uint4 f0h = bs[buf][nb][0][0][lane], f0l = bs[buf][nb][0][1][lane];
+            const uint4 f1h = bs[buf][nb][1][0][lane], f1l = bs[buf][nb][1][1][lane];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                acc[mb][nb] = mfma(acur[mb].a, f0h, acc[mb][nb]);
+                acc[mb][nb] = mfma(acur[mb].a, f0l, acc[mb][nb]);
+                acc[mb][nb] = mfma(acur[mb].b, f1h, acc[mb][nb]);
+                acc[mb][nb] = mfma(acur[mb].b, f1l, acc[mb][nb]);
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acur[mb] = anxt[mb];
+    }
+
+    // partial sums of this column chunk: Yp[kc][w][b][row], row-block lanes hold rows 4 lg + r
+    float* out = reinterpret_cast<float*>(Yp + (long long)kc * ga.part_stride + (long long)w * ga.nrhs * ga.Nd);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int ncol = nb * 16 + lr;
+        const int b = b0 + (ncol >> 1), comp = ncol & 1;
+        if (b >= ga.nrhs) continue;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rowbase + mb * 16 + 4 * lg + r;
+                if (row < ga.Nd) out[2 * ((long long)b * ga.Nd + row) + comp] = acc[mb][nb][r];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+template <int NB>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __restrict__ fhat,
+                                                           const float* __restrict__ scales,
+                                                           const float2* __restrict__ Y,
+                                                           float2* __restrict__ Xp, GemmArgs ga) {
+    constexpr int MB = kAdjMB;
+    constexpr int RB = 8 * NB;
+    constexpr int COLS = 4 * MB * 16;
+    __shared__ uint32_t as[2][COLS * kAdjAW];  // [buffer][column][sensor + pad]
+    __shared__ uint4 bs[2][NB][2][64];         // [buffer][n block][hi/lo][lane]
+
+    const int q = xcd_item(blockIdx.x, ga.Q);
+    if (q >= ga.items) return;
+    int t = q;
+    const int jt = t % ga.n_mt; t /= ga.n_mt;
+    const int bg = t % ga.n_bg; t /= ga.n_bg;
+    const int w = t;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int b0 = bg * RB;
+    const int j0 = jt * COLS;
+    const int nsteps = (ga.Nd + 15) >> 4;
+    const uint8_t* Fw = fhat + (long long)w * ga.Nd * ga.pitch * 4;
+    const float2* Yw = Y + (long long)w * ga.nrhs * ga.Nd;
+
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int s = 0; s < nsteps; ++s) {
+        const int buf = s & 1;
+        const int i0 = 16 * s;
+        // spectrum tile: 16 sensors x COLS columns, transposed to [column][sensor]
+        for (int e = tid; e < 16 * (COLS / 4); e += kGemmThreads) {
+            const int r = e & 15, ch = e >> 4;
+            const int i = i0 + r, j = j0 + 4 * ch;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (i < ga.Nd && j < ga.pitch) {
+                const u32x4 raw = __builtin_nontemporal_load(
+                    reinterpret_cast<const u32x4*>(Fw + ((long long)i * ga.pitch + j) * 4));
+                v = make_uint4(raw.x, raw.y, raw.z, raw.w);
+            }
+            uint32_t* dst = &as[buf][(4 * ch) * kAdjAW + r];
+            dst[0] = v.x;
+            dst[kAdjAW] = v.y;
+            dst[2 * kAdjAW] = v.z;
+            dst[3 * kAdjAW] = v.w;
+        }
+        // right-hand sides: 16 sensors x RB, as BF16 hi/lo fragments
+        for (int e = tid; e < 16 * RB; e += kGemmThreads) {
+            const int r = e & 15, bl = e >> 4;
+            const int b = b0 + bl, i = i0 + r;
+            float2 y = make_float2(0.f, 0.f);
+            if (b < ga.nrhs && i < ga.Nd) y = Yw[(long long)b * ga.Nd + i];
+            uint32_t rh, rl, ih, il;
+            split_bf16(y.x, rh, rl);
+            split_bf16(y.y, ih, il);
+            const int g = r >> 2, rho = r & 3;
+            const int nre = 2 * bl, nim = 2 * bl + 1;
+            // real-part column: (y_r, y_i); imaginary-part column: (y_i, -y_r)
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][0][g * 16 + (nre & 15)])[rho] = rh | (ih << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][1][g * 16 + (nre & 15)])[rho] = rl | (il << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][0][g * 16 + (nim & 15)])[rho] = ih | ((rh ^ 0x8000u) << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][1][g * 16 + (nim & 15)])[rho] = il | ((rl ^ 0x8000u) << 16);
+        }
+        __syncthreads();
+        uint4 afr[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int col = wave * MB * 16 + mb * 16 + lr;
+            afr[mb] = *reinterpret_cast<const uint4*>(&as[buf][col * kAdjAW + 4 * lg]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const uint4 fh = bs[buf][nb][0][lane], fl = bs[buf][nb][1][lane];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                acc[mb][nb] = mfma(afr[mb], fh, acc[mb][nb]);
+                acc[mb][nb] = mfma(afr[mb], fl, acc[mb][nb]);
+            }
+        }
+    }
+
+    const float sc = scales[(long long)w * ga.nblk + j0 / kScaleBlock];
+    float* out = reinterpret_cast<float*>(Xp + (long long)w * ga.nrhs * ga.pitch);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int ncol = nb * 16 + lr;
+        const int b = b0 + (ncol >> 1), comp = ncol & 1;
+        if (b >= ga.nrhs) continue;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + wave * MB * 16 + mb * 16 + 4 * lg + r;
+                if (j < ga.pitch) out[2 * ((long long)b * ga.pitch + j) + comp] = acc[mb][nb][r] * sc;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host launchers
+static int gemm_nb(int nrhs) { return nrhs > 32 ? 8 : nrhs > 16 ? 4 : nrhs > 8 ? 2 : 1; }
+
+int gemm_fwd_kchunks(int pitch) { return (pitch + kScaleBlock - 1) / kScaleBlock; }
+
+hipError_t launch_gemm_fwd(const GemmArgs& in, const void* fhat, const float* scales, const void* X, void* Yp,
+                           hipStream_t st) {
+    GemmArgs ga = in;
+    const int NB = gemm_nb(ga.nrhs);
+    ga.kchunk = kScaleBlock;
+    ga.n_kc = gemm_fwd_kchunks(ga.pitch);
+    ga.n_mt = (ga.Nd + 4 * kFwdMB * 16 - 1) / (4 * kFwdMB * 16);
+    ga.n_bg = (ga.nrhs + 8 * NB - 1) / (8 * NB);
+    ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
+    ga.Q = (ga.items + 7) / 8;
+    dim3 grid(8 * ga.Q);
+    const uint8_t* F = (const uint8_t*)fhat;
+    const float2* x = (const float2*)X;
+    float2* y = (float2*)Yp;
+    switch (NB) {
+        case 8: hipLaunchKernelGGL((k_gemm_fwd<8>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
+        case 4: hipLaunchKernelGGL((k_gemm_fwd<4>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
+        case 2: hipLaunchKernelGGL((k_gemm_fwd<2>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
+        default: hipLaunchKernelGGL((k_gemm_fwd<1>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_adj(const GemmArgs& in, const void* fhat, const float* scales, const void* Y, void* Xp,
+                           hipStream_t st) {
+    GemmArgs ga = in;
+    const int NB = gemm_nb(ga.nrhs);
+    ga.n_mt = (ga.pitch + 4 * kAdjMB * 16 - 1) / (4 * kAdjMB * 16);
+    ga.n_kc = 1;
+    ga.n_bg = (ga.nrhs + 8 * NB - 1) / (8 * NB);
+    ga.items = ga.nfreq * ga.n_bg * ga.n_mt;
+    ga.Q = (ga.items + 7) / 8;
+    dim3 grid(8 * ga.Q);
+    const uint8_t* F = (const uint8_t*)fhat;
+    const float2* y = (const float2*)Y;
+    float2* x = (float2*)Xp;
+    switch (NB) {
+        case 8: hipLaunchKernelGGL((k_gemm_adj<8>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
+        case 4: hipLaunchKernelGGL((k_gemm_adj<4>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
+        case 2: hipLaunchKernelGGL((k_gemm_adj<2>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
+        default: hipLaunchKernelGGL((k_gemm_adj<1>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace p2o

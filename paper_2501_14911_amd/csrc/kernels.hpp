@@ -17,6 +17,19 @@ struct GemvArgs {
     long long part_stride;  // complex elements between partial outputs
 };
 
+struct GemmArgs {
+    int Nd;
+    int pitch;
+    int nfreq;
+    int nrhs;
+    int nblk;
+    long long part_stride;  // complex elements between forward partial outputs
+    // filled in by the launcher
+    int kchunk;             // complex columns per forward K chunk
+    int n_kc, n_mt, n_bg;   // K chunks, row (or column) tiles, right-hand-side groups
+    int items, Q;           // work items and items per XCD
+};
+
 struct LoadArgs {
     void* fhat;
     float* scales;        // [nfreq][nblk]
@@ -54,5 +67,12 @@ hipError_t launch_gemv_fwd(int prec, const GemvArgs& ga, const void* fhat, const
                            void* Yp, hipStream_t st);
 hipError_t launch_gemv_adj(int prec, const GemvArgs& ga, const void* fhat, const float* scales, const void* Y,
                            void* Xp, hipStream_t st);
+
+// gemm_mfma.hip
+int gemm_fwd_kchunks(int pitch);
+hipError_t launch_gemm_fwd(const GemmArgs& ga, const void* fhat, const float* scales, const void* X, void* Yp,
+                           hipStream_t st);
+hipError_t launch_gemm_adj(const GemmArgs& ga, const void* fhat, const float* scales, const void* Y, void* Xp,
+                           hipStream_t st);
 
 }  // namespace p2o

@@ -13,7 +13,7 @@ from typing import Callable, Optional
 
 import torch
 
-from ._lib import (P2O_FP64, P2O_SRC_F32, P2O_SRC_F64, PRECISIONS, STAGES, check, lib)
+from ._lib import (BATCHED, P2O_FP64, P2O_SRC_F32, P2O_SRC_F64, PRECISIONS, STAGES, check, lib)
 
 SCALE_BLOCK = 4096
 
@@ -87,6 +87,12 @@ class P2OOperator:
         n = self.nfreq * self.Nd * self.pitch * self.elem_bytes
         off = (n + 255) // 256 * 256
         return self.fhat[off: off + 4 * self.nfreq * self.nblk].view(torch.float32).view(self.nfreq, self.nblk)
+
+    def set_batched(self, mode: str = "auto"):
+        """Per-frequency products for several right-hand sides: "auto",
+        "gemv" (one streaming pass per right-hand side) or "mfma" (matrix
+        cores, BF16 spectra only)."""
+        check(lib.p2o_set_option(self._plan, 0, BATCHED[mode]))
 
     # ------------------------------------------------------------------ timing
     def profile(self, enable: bool = True):

@@ -1,0 +1,121 @@
+"""GPU parity of the batched (many right-hand sides) path on the matrix
+cores against the FP64 oracle, and against the per-right-hand-side streaming
+path on the same plan.  BF16 spectrum; right-hand sides enter the MFMA as a
+BF16 hi + lo pair, so the batched and streaming results differ only by
+that split (relative 2^-16) and by summation order."""
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ensure_built()
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from paper_2501_14911_amd import P2OOperator  # noqa: E402
+
+DEV = "cuda"
+TOL_BF16 = 2e-3
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def build(w, max_rhs):
+    F = synth.operator_blocks(w)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=max_rhs, device=DEV)
+    Ft = torch.from_numpy(F).to(DEV)
+    op.load(lambda c0, n: Ft[:, :, c0:c0 + n])
+    return op, F
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV, torch.float32)
+
+
+def host(x):
+    torch.cuda.synchronize()
+    return x.double().cpu().numpy()
+
+
+SHAPES = [
+    synth.Workload("odd", Nd=70, Nm=1003, Nt=21, tau=6.0),        # 70 rows, pitch 1008 (partial column tiles)
+    synth.Workload("blocks", Nd=37, Nm=9000, Nt=13, tau=5.0),     # three scale blocks / K chunks, ragged last
+]
+
+
+@pytest.mark.parametrize("nrhs", [2, 9, 17, 40, 70])
+@pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
+def test_batched_forward_adjoint(w, nrhs):
+    note(f"[batched] {w.name} nrhs={nrhs}")
+    op, F = build(w, nrhs)
+    m = synth.param_series(w, nrhs)
+    d = synth.data_series(w, nrhs)
+    y = host(op.apply_F(dev(m)))
+    s = host(op.apply_Ft(dev(d)))
+    yo, so = oracle.apply_F(F, m), oracle.apply_Ft(F, d)
+    worst = max(max(oracle.rel_l2(y[b], yo[b]), oracle.rel_l2(s[b], so[b])) for b in range(nrhs))
+    note(f"  worst rel-L2 vs oracle {worst:.3e}")
+    assert worst <= TOL_BF16
+    op.set_batched("gemv")
+    y2 = host(op.apply_F(dev(m)))
+    s2 = host(op.apply_Ft(dev(d)))
+    assert oracle.rel_l2(y, y2) <= 5e-5 and oracle.rel_l2(s, s2) <= 5e-5
+
+
+def test_batched_medium_64_and_ragged():
+    w = synth.CONFIGS["medium"]
+    note("[batched] medium 64 rhs + ragged")
+    op, F = build(w, 64)
+    m = synth.param_series(w, 64)
+    n = synth.ragged_lengths(w, 64, lo=1)
+    y = host(op.apply_F(dev(m), nt_active=n))
+    yo = oracle.apply_F(F, m, n)
+    for b in range(64):
+        assert np.all(y[b, n[b]:] == 0.0)
+        assert oracle.rel_l2(y[b], yo[b]) <= TOL_BF16
+    d = synth.data_series(w, 64)
+    s = host(op.apply_Ft(dev(d), nt_active=n))
+    so = oracle.apply_Ft(F, d, n)
+    for b in range(64):
+        assert np.all(s[b, n[b]:] == 0.0)
+        assert oracle.rel_l2(s[b], so[b]) <= TOL_BF16
+
+
+def test_batched_data_space_columns():
+    w = synth.CONFIGS["medium"]
+    idx = synth.hessian_column_indices(w, 64)
+    e = synth.unit_data_vectors(w, idx)
+    op, F = build(w, 64)
+    h = host(op.apply_FFt(dev(e)))
+    ho = oracle.data_space_hessian(F, e)
+    worst = max(oracle.rel_l2(h[b], ho[b]) for b in range(64))
+    note(f"[batched] F F* columns worst rel-L2 {worst:.3e}")
+    assert worst <= TOL_BF16
+
+
+def test_batched_misfit_gradient():
+    w = synth.CONFIGS["medium"]
+    op, F = build(w, 16)
+    m = synth.param_series(w, 16)
+    d_obs = oracle.apply_F(F, synth.param_series(w, 16, seed_offset=5)) + synth.noise(w, 16)
+    phi, g = op.misfit_grad(dev(m), dev(d_obs), torch.tensor([w.sigma ** 2], dtype=torch.float64, device=DEV))
+    phi_o, g_o = oracle.misfit_and_grad(F, m, d_obs, w.sigma ** 2)
+    phi, g = host(phi), host(g)
+    for b in range(16):
+        assert abs(phi[b] - phi_o[b]) <= TOL_BF16 * phi_o[b]
+        assert oracle.rel_l2(g[b], g_o[b]) <= TOL_BF16
+
+
+def test_mfma_option_needs_bf16():
+    w = synth.CONFIGS["tiny"]
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp32", max_rhs=2, device=DEV)
+    from paper_2501_14911_amd import P2OError
+    with pytest.raises(P2OError):
+        op.set_batched("mfma")
