@@ -137,39 +137,50 @@ def main():
     ms_step = ev0.elapsed_time(ev1) / args.steps
     part_ms = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps for i in range(3)]
     stages = op.stage_times()
+    st1, st64, st32 = op.stage_times(1), op.stage_times(N_HESS), op.stage_times(N_RAGGED)
     op.profile(False)
     matvecs = 2 + 2 * N_HESS + 2 * N_RAGGED
     log(f"[bench] {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}): single-RHS gradient "
         f"{part_ms[0]:.3f} ms, 64 F F* columns {part_ms[1]:.3f} ms, 32 ragged F + F* {part_ms[2]:.3f} ms")
-    for k, (tot, n) in stages.items():
-        if n:
-            log(f"[bench]   {k:9s} {tot / n * 1e3:9.1f} us x {n / args.steps:.0f}/step")
+    for nr, st in ((1, st1), (N_HESS, st64), (N_RAGGED, st32)):
+        for k, (tot, n) in st.items():
+            if n:
+                log(f"[bench]   nrhs={nr:2d} {k:9s} {tot / n * 1e3:9.1f} us x {n / args.steps:.0f}/step")
 
     # roofline bookkeeping (algorithmic bytes: spectrum once + series spectra in/out)
     spec_bytes = op.nfreq * w.Nd * w.Nm * op.elem_bytes
 
-    def avg_us(k):
-        tot, n = stages[k]
+    def avg_us(k, st=stages):
+        tot, n = st[k]
         return tot / n * 1e3 if n else 0.0
 
-    gemv_bytes = spec_bytes + op.nfreq * (w.Nm + w.Nd) * 8
-    gemm_bytes = spec_bytes + op.nfreq * N_HESS * (w.Nm + w.Nd) * 8
-    gemm_flop = 2.0 * op.nfreq * w.Nd * (2 * w.Nm) * (2 * N_HESS)      # real-equivalent, one BF16 pass
+    def vec_bytes(nrhs):
+        return op.nfreq * nrhs * (w.Nm + w.Nd) * 8
+
+    def gemm_flop(nrhs):        # real-equivalent flops of one BF16 pass (x2 issued for the hi+lo split)
+        return 2.0 * op.nfreq * w.Nd * (2 * w.Nm) * (2 * nrhs)
+
     kern = {
-        "gemv_fwd": {"us": avg_us("gemv_fwd"), "bytes": gemv_bytes},
-        "gemv_adj": {"us": avg_us("gemv_adj"), "bytes": gemv_bytes},
-        "gemm_fwd": {"us": avg_us("gemm_fwd"), "bytes": gemm_bytes, "flop": gemm_flop},
-        "gemm_adj": {"us": avg_us("gemm_adj"), "bytes": gemm_bytes, "flop": gemm_flop},
+        "gemv_fwd": {"us": avg_us("gemv_fwd", st1), "bytes": spec_bytes + vec_bytes(1), "nrhs": 1},
+        "gemv_adj": {"us": avg_us("gemv_adj", st1), "bytes": spec_bytes + vec_bytes(1), "nrhs": 1},
+        "gemm_fwd_64": {"us": avg_us("gemm_fwd", st64), "bytes": spec_bytes + vec_bytes(N_HESS),
+                        "flop": gemm_flop(N_HESS), "nrhs": N_HESS},
+        "gemm_adj_64": {"us": avg_us("gemm_adj", st64), "bytes": spec_bytes + vec_bytes(N_HESS),
+                        "flop": gemm_flop(N_HESS), "nrhs": N_HESS},
+        "gemm_fwd_32": {"us": avg_us("gemm_fwd", st32), "bytes": spec_bytes + vec_bytes(N_RAGGED),
+                        "flop": gemm_flop(N_RAGGED), "nrhs": N_RAGGED},
+        "gemm_adj_32": {"us": avg_us("gemm_adj", st32), "bytes": spec_bytes + vec_bytes(N_RAGGED),
+                        "flop": gemm_flop(N_RAGGED), "nrhs": N_RAGGED},
     }
-    # the 64-column launches only (the ragged 32-RHS launches use fewer columns)
-    for k in ("gemm_fwd", "gemm_adj"):
-        kern[k]["note"] = "average over the 64-column and the 32-column launches of a step"
     for k, v in kern.items():
         v["GBs"] = v["bytes"] / (v["us"] * 1e-6) / 1e9 if v["us"] else 0.0
         if "flop" in v and v["us"]:
-            v["TFLOPs"] = v["flop"] / (v["us"] * 1e-6) / 1e12
-    totals = {k: stages[k][0] for k in kern}
-    dom = max(totals, key=totals.get)
+            v["TFLOPs_issued"] = 2 * v["flop"] / (v["us"] * 1e-6) / 1e12
+    # dominant kernel: largest share of the step
+    share = {"gemv_fwd": st1["gemv_fwd"][0], "gemv_adj": st1["gemv_adj"][0],
+             "gemm_fwd_64": st64["gemm_fwd"][0], "gemm_adj_64": st64["gemm_adj"][0],
+             "gemm_fwd_32": st32["gemm_fwd"][0], "gemm_adj_32": st32["gemm_adj"][0]}
+    dom = max(share, key=share.get)
     dk = kern[dom]
     roof = {"bound": "hbm", "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dk["GBs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
@@ -198,9 +209,17 @@ def main():
         "single_rhs_matvecs_per_s": 2.0 / (part_ms[0] * 1e-3),
         "batched_matvecs_per_s": 2.0 * N_HESS / (part_ms[1] * 1e-3),
         "kernels": kern,
-        "kernels_us": {k: avg_us(k) for k in stages},
+        "kernels_us_by_nrhs": {str(n): {k: avg_us(k, st) for k in st if st[k][1]}
+                               for n, st in ((1, st1), (N_HESS, st64), (N_RAGGED, st32))},
         "load_ms": load_ms,
     }
+
+    from paper_2501_14911_amd import bandwidth_probe
+    probe = bandwidth_probe(device=dev)
+    result["measured_stream"] = probe
+    roof["frac_of_measured_read"] = dk["GBs"] / probe["read_GBs"]
+    log(f"[bench] streaming probe: read {probe['read_GBs']:.0f} GB/s, copy {probe['copy_GBs']:.0f} GB/s; "
+        f"{dom} at {dk['GBs']:.0f} GB/s = {roof['frac']:.1%} of 8 TB/s, {roof['frac_of_measured_read']:.1%} of read probe")
 
     if not args.no_accuracy:
         result["accuracy"] = accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np)
@@ -305,17 +324,22 @@ def cpu_baseline(w, cols, np):
     F = synth.operator_rows_cols(w, range(w.Nt), cols=np.arange(cols), backend="torch").numpy()
     m = synth.param_series(w.with_(Nm=cols, grid=None), 1)[0]
     din = synth.data_series(w, 1)[0]
-    t0 = time.perf_counter()
-    oracle.apply_F(F, m)
-    t1 = time.perf_counter()
-    oracle.apply_Ft(F, din)
-    t2 = time.perf_counter()
-    full = (t2 - t0) * (w.Nm / cols)
-    log(f"[bench] oracle on {cols} columns: F {t1 - t0:.2f} s, F* {t2 - t1:.2f} s ({cores} BLAS threads)")
+    reps, t_f, t_t = 0, 0.0, 0.0
+    while reps < 1 or (t_f + t_t < 10.0 and reps < 50):
+        t0 = time.perf_counter()
+        oracle.apply_F(F, m)
+        t1 = time.perf_counter()
+        oracle.apply_Ft(F, din)
+        t2 = time.perf_counter()
+        t_f, t_t, reps = t_f + (t1 - t0), t_t + (t2 - t1), reps + 1
+    full = (t_f + t_t) / reps * (w.Nm / cols)
+    log(f"[bench] oracle on {cols} columns x {reps}: F {t_f / reps:.2f} s, F* {t_t / reps:.2f} s "
+        f"({cores} BLAS threads)")
     return {"value": 2.0 / full, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
             "sample": f"F and F* on parameter columns 0..{cols - 1} of {w.Nm} (all {w.Nd} sensors, "
-                      f"{w.Nt} steps), FP64 numpy block-Toeplitz sums; time scaled by {w.Nm}/{cols}",
-            "seconds_measured": t2 - t0}
+                      f"{w.Nt} steps), FP64 numpy block-Toeplitz sums, repeated {reps} times; time per "
+                      f"matvec scaled by {w.Nm}/{cols}",
+            "seconds_measured": t_f + t_t}
 
 
 if __name__ == "__main__":

@@ -199,6 +199,19 @@ p2o_status p2o_profile_enable(p2o_plan* plan, int32_t enable);
  * profiling was enabled.  Waits for the recorded events (synchronising). */
 p2o_status p2o_profile_read(p2o_plan* plan, int32_t stage, double* total_ms, int64_t* launches);
 
+/* As p2o_profile_read, restricted to launches made by calls with `nrhs`
+ * right-hand sides (nrhs = 0: the spectrum loads). */
+p2o_status p2o_profile_read_nrhs(p2o_plan* plan, int32_t stage, int64_t nrhs, double* total_ms,
+                                 int64_t* launches);
+
+/* Streaming probe for roofline context (not part of the operator): mode 0
+ * reads `bytes` from `src` (32-byte non-temporal loads per lane; `dst`
+ * receives one 32-bit word per workgroup, at least `blocks` words), mode 1
+ * copies `bytes` from `src` to `dst` (16 bytes per lane).  bytes must be a
+ * multiple of 32, blocks in [1, 65536].  Enqueued on `stream`. */
+p2o_status p2o_bandwidth_probe(int32_t mode, const void* src, void* dst, size_t bytes,
+                               int32_t blocks, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* p2o_status_string(int32_t status);
 

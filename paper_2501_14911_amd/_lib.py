@@ -59,6 +59,8 @@ def _load():
         "p2o_misfit_grad": [pv, pv, pv, pv, c_int64, pv, pv, c_int64, pv],
         "p2o_profile_enable": [pv, c_int32],
         "p2o_set_option": [pv, c_int32, c_int64],
+        "p2o_profile_read_nrhs": [pv, c_int32, c_int64, POINTER(c_double), POINTER(c_int64)],
+        "p2o_bandwidth_probe": [c_int32, pv, pv, c_size_t, c_int32, pv],
         "p2o_profile_read": [pv, c_int32, POINTER(c_double), POINTER(c_int64)],
     }
     for name, args in sigs.items():

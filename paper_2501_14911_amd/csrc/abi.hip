@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -80,7 +81,9 @@ struct p2o_plan {
     std::vector<uint8_t> loaded;   // per column
     // per-stage timing
     bool prof = false;
-    struct Rec { int stage; hipEvent_t a, b; };
+    struct Rec { int stage; int64_t nrhs; hipEvent_t a, b; };
+    int64_t cur_nrhs = 0;                               // right-hand sides of the call being enqueued
+    std::map<std::pair<int, int64_t>, std::pair<double, int64_t>> by_nrhs;
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
     double tot_ms[P2O_STAGE_COUNT] = {};
@@ -117,7 +120,7 @@ p2o_status staged(p2o_plan* p, int stage, const char* what, Fn&& launch) {
     const hipError_t e = launch();
     if (p->prof && a && b) {
         (void)hipEventRecord(b, p->stream);
-        p->pending.push_back({stage, a, b});
+        p->pending.push_back({stage, p->cur_nrhs, a, b});
     } else {
         if (a) p->pool.push_back(a);
         if (b) p->pool.push_back(b);
@@ -133,6 +136,9 @@ p2o_status drain_profile(p2o_plan* p) {
         if (e != hipSuccess) return check_hip(e, "profile events");
         p->tot_ms[r.stage] += ms;
         p->launches[r.stage] += 1;
+        auto& acc = p->by_nrhs[{r.stage, r.nrhs}];
+        acc.first += ms;
+        acc.second += 1;
         p->pool.push_back(r.a);
         p->pool.push_back(r.b);
     }
@@ -361,6 +367,18 @@ p2o_status p2o_create(p2o_plan** out, int64_t Nd, int64_t Nm, int64_t Nt, int32_
     }
 }
 
+p2o_status p2o_bandwidth_probe(int32_t mode, const void* src, void* dst, size_t bytes, int32_t blocks,
+                               void* stream) {
+    if (mode != 0 && mode != 1) return fail(P2O_ERR_ARG, "probe mode must be 0 (read) or 1 (copy)");
+    if (!src || !dst) return fail(P2O_ERR_ARG, "probe buffer is NULL");
+    if (bytes == 0 || bytes % 32) return fail(P2O_ERR_ARG, "probe size must be a positive multiple of 32");
+    if (blocks < 1 || blocks > 65536) return fail(P2O_ERR_ARG, "probe blocks must be in [1, 65536]");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 32)
+        return fail(P2O_ERR_ARG, "probe buffers must be 32-byte aligned");
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return check_hip(launch_probe(mode, src, dst, bytes, blocks, static_cast<hipStream_t>(stream)), "bandwidth probe");
+}
+
 p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
     if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
     if (option == P2O_OPT_BATCHED) {
@@ -383,6 +401,7 @@ p2o_status p2o_profile_enable(p2o_plan* p, int32_t enable) {
         if (s) return s;
     }
     for (int i = 0; i < P2O_STAGE_COUNT; ++i) { p->tot_ms[i] = 0.0; p->launches[i] = 0; }
+    p->by_nrhs.clear();
     p->prof = enable != 0;
     return P2O_OK;
 }
@@ -398,6 +417,21 @@ p2o_status p2o_profile_read(p2o_plan* p, int32_t stage, double* total_ms, int64_
     }
     if (total_ms) *total_ms = p->tot_ms[stage];
     if (launches) *launches = p->launches[stage];
+    return P2O_OK;
+}
+
+p2o_status p2o_profile_read_nrhs(p2o_plan* p, int32_t stage, int64_t nrhs, double* total_ms, int64_t* launches) {
+    if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (stage < 0 || stage >= P2O_STAGE_COUNT) return fail(P2O_ERR_ARG, "unknown stage %d", (int)stage);
+    if (!total_ms && !launches) return fail(P2O_ERR_ARG, "both outputs are NULL");
+    if (!p->pending.empty()) {
+        if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+        p2o_status s = drain_profile(p);
+        if (s) return s;
+    }
+    auto it = p->by_nrhs.find({stage, nrhs});
+    if (total_ms) *total_ms = it == p->by_nrhs.end() ? 0.0 : it->second.first;
+    if (launches) *launches = it == p->by_nrhs.end() ? 0 : it->second.second;
     return P2O_OK;
 }
 
@@ -502,6 +536,7 @@ p2o_status p2o_load_blocks(p2o_plan* p, const void* F_chunk, int64_t col0, int64
         });
         if (s) return s;
         std::fill(p->loaded.begin() + col0, p->loaded.begin() + col0 + ncols, 1);
+        p->cur_nrhs = 0;
         p->state = kLoading;
         return P2O_OK;
     } catch (...) {
@@ -539,6 +574,7 @@ p2o_status p2o_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const 
     try {
         p2o_status s = ready_for_apply(p, m, d, nrhs);
         if (s) return s;
+        p->cur_nrhs = nrhs;
         s = enqueue_forward_to_Y(p, m, nrhs, nt_active);
         if (s) return s;
         return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
@@ -554,6 +590,7 @@ p2o_status p2o_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, const
     try {
         p2o_status s = ready_for_apply(p, d, m, nrhs);
         if (s) return s;
+        p->cur_nrhs = nrhs;
         s = enqueue_adjoint_to_X(p, d, nrhs, nt_active);
         if (s) return s;
         return staged(p, P2O_STAGE_C2R, "c2r (parameters)", [&] {
@@ -569,6 +606,7 @@ p2o_status p2o_apply_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, cons
     try {
         p2o_status s = ready_for_apply(p, e, h, nrhs);
         if (s) return s;
+        p->cur_nrhs = nrhs;
         s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
         if (s) return s;
         s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
@@ -601,6 +639,7 @@ p2o_status p2o_misfit_grad(p2o_plan* p, const void* m, const void* d_obs, const 
                         (long long)p->Nd, (long long)(p->Nd * p->Nt));
         p2o_status s = ready_for_apply(p, m, grad, nrhs);
         if (s) return s;
+        p->cur_nrhs = nrhs;
         s = enqueue_forward_to_Y(p, m, nrhs, nt_active);
         if (s) return s;
         void* D = p->ws + p->off_D;

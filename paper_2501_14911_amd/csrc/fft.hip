@@ -28,8 +28,8 @@ namespace p2o {
 constexpr int kFftThreads = 256;
 
 template <typename T> struct FftCap;
-template <> struct FftCap<float> { static constexpr int cap = 8192; };   // complex entries of LDS
-template <> struct FftCap<double> { static constexpr int cap = 4096; };
+template <> struct FftCap<float> { static constexpr int cap = 3584; };   // complex tile entries per workgroup
+template <> struct FftCap<double> { static constexpr int cap = 1792; };
 
 // ---------------------------------------------------------------- butterflies
 template <typename T, int R, bool INV>
@@ -98,6 +98,8 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
     const int MR = M / R;
     const int nbf = MR << twsh;
     const int tstep = L / (Ns * R);
+    // j / Ns by multiply-high: exact for j, Ns < 2^16
+    const uint32_t mNs = Ns > 1 ? 0xFFFFFFFFu / (uint32_t)Ns + 1u : 0u;
     Z w[R];
     if constexpr (R == 3 || R == 5 || R == 7) {
 #pragma unroll
@@ -113,7 +115,8 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
         if (bf < nbf) {
             const int s = bf & TWm;
             const int j = bf >> twsh;
-            const int k = j % Ns;
+            const int grp = Ns > 1 ? (int)__umulhi((uint32_t)j, mNs) : j;
+            const int k = j - grp * Ns;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 Z a = buf[((j + q * MR) << twsh) + s];
@@ -133,8 +136,9 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
         if (bf < nbf) {
             const int s = bf & TWm;
             const int j = bf >> twsh;
-            const int k = j % Ns;
-            const int base = (j / Ns) * Ns * R + k;
+            const int grp = Ns > 1 ? (int)__umulhi((uint32_t)j, mNs) : j;
+            const int k = j - grp * Ns;
+            const int base = grp * Ns * R + k;
 #pragma unroll
             for (int p = 0; p < R; ++p) buf[((base + p * Ns) << twsh) + s] = v[u][p];
         }
@@ -208,6 +212,28 @@ __device__ __forceinline__ void c2r_pre(cplx<T>* buf, int twsh, int M, const cpl
     }
 }
 
+// Workgroup id -> (tile, outer) such that consecutive ids on one XCD (ids are
+// dealt to the 8 XCDs round-robin) take adjacent column tiles and share L2 lines.
+struct ItemMap {
+    int ntiles;   // column tiles per outer index
+    int items;    // ntiles * outer count
+    int Q;        // ceil(items / 8)
+};
+
+__device__ __forceinline__ bool fft_item(const ItemMap& im, int& tile, int& outer) {
+    const int q = (int)(blockIdx.x & 7) * im.Q + (int)(blockIdx.x >> 3);
+    if (q >= im.items) return false;
+    outer = q / im.ntiles;
+    tile = q - outer * im.ntiles;
+    return true;
+}
+
+// Copy the twiddle table e^{-2 pi i n / L} into LDS (callers synchronise).
+template <typename T>
+__device__ __forceinline__ void stage_twiddles(cplx<T>* tws, const cplx<T>* __restrict__ tw, int L) {
+    for (int i = threadIdx.x; i < L; i += kFftThreads) tws[i] = tw[i];
+}
+
 __device__ __forceinline__ int active_len(const SeriesIO& io, int outer) {
     int nt = io.Nt;
     if (io.nt_active) {
@@ -218,20 +244,33 @@ __device__ __forceinline__ int active_len(const SeriesIO& io, int outer) {
 }
 
 // Load real series (zero past the active length) as z[n] = x[2n] + i x[2n+1].
+// All of a thread's global loads are issued before any LDS store, so their
+// latencies overlap instead of adding up.
 template <typename T, typename TIN>
 __device__ __forceinline__ void load_time(cplx<T>* buf, int twsh, int M, const TIN* __restrict__ src,
                                           long long t_stride, int S, int s0, int nt) {
+    constexpr int MAXE = FftCap<T>::cap / kFftThreads;
     const int TWm = (1 << twsh) - 1;
-    for (int e = threadIdx.x; e < (M << twsh); e += kFftThreads) {
-        const int n = e >> twsh, s = e & TWm;
-        const int col = s0 + s;
-        T x0 = T(0), x1 = T(0);
-        if (col < S) {
-            const int t0 = 2 * n;
-            if (t0 < nt) x0 = (T)src[(long long)t0 * t_stride + col];
-            if (t0 + 1 < nt) x1 = (T)src[(long long)(t0 + 1) * t_stride + col];
+    const int ne = M << twsh;
+    T x0[MAXE], x1[MAXE];
+#pragma unroll
+    for (int u = 0; u < MAXE; ++u) {
+        const int e = threadIdx.x + u * kFftThreads;
+        x0[u] = T(0);
+        x1[u] = T(0);
+        if (e < ne) {
+            const int n = e >> twsh, col = s0 + (e & TWm);
+            if (col < S) {
+                const int t0 = 2 * n;
+                if (t0 < nt) x0[u] = (T)src[(long long)t0 * t_stride + col];
+                if (t0 + 1 < nt) x1[u] = (T)src[(long long)(t0 + 1) * t_stride + col];
+            }
         }
-        buf[e] = cmk<T>(x0, x1);
+    }
+#pragma unroll
+    for (int u = 0; u < MAXE; ++u) {
+        const int e = threadIdx.x + u * kFftThreads;
+        if (e < ne) buf[e] = cmk<T>(x0[u], x1[u]);
     }
 }
 
@@ -240,16 +279,28 @@ template <typename T>
 __device__ __forceinline__ void load_spec(cplx<T>* buf, int twsh, int M, const cplx<T>* __restrict__ src,
                                           long long f_stride, long long f_part, int nparts, int S, int s0) {
     using Z = cplx<T>;
+    constexpr int MAXE = FftCap<T>::cap / kFftThreads;
     const int TWm = (1 << twsh) - 1;
-    for (int e = threadIdx.x; e < ((M + 1) << twsh); e += kFftThreads) {
-        const int k = e >> twsh, s = e & TWm;
-        const int col = s0 + s;
-        Z acc = cmk<T>(T(0), T(0));
-        if (col < S) {
-            const Z* p = src + (long long)k * f_stride + col;
-            for (int q = 0; q < nparts; ++q) acc = cadd(acc, p[(long long)q * f_part]);
+    const int ne = (M + 1) << twsh;
+    Z acc[MAXE];
+#pragma unroll
+    for (int u = 0; u < MAXE; ++u) acc[u] = cmk<T>(T(0), T(0));
+    for (int q = 0; q < nparts; ++q) {
+        Z v[MAXE];
+#pragma unroll
+        for (int u = 0; u < MAXE; ++u) {
+            const int e = threadIdx.x + u * kFftThreads;
+            const int k = e >> twsh, col = s0 + (e & TWm);
+            v[u] = (e < ne && col < S) ? src[(long long)q * f_part + (long long)k * f_stride + col]
+                                       : cmk<T>(T(0), T(0));
         }
-        buf[e] = acc;
+#pragma unroll
+        for (int u = 0; u < MAXE; ++u) acc[u] = cadd(acc[u], v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < MAXE; ++u) {
+        const int e = threadIdx.x + u * kFftThreads;
+        if (e < ne) buf[e] = acc[u];
     }
 }
 
@@ -257,14 +308,17 @@ __device__ __forceinline__ void load_spec(cplx<T>* buf, int twsh, int M, const c
 // r2c: time series [outer][t][col] -> half spectra [outer][k][col] (cols >= S zero-filled up to S_pad)
 template <typename T, typename TIN>
 __global__ __launch_bounds__(kFftThreads) void k_r2c(FftPlan pl, SeriesIO io, const TIN* __restrict__ in,
-                                                     cplx<T>* __restrict__ out, const cplx<T>* __restrict__ tw,
-                                                     int twsh) {
+                                                     cplx<T>* __restrict__ out, const cplx<T>* __restrict__ twg,
+                                                     int twsh, ItemMap im) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = cplx<T>;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    const int outer = blockIdx.y;
-    const int s0 = blockIdx.x << twsh;
+    Z* tw = buf + ((pl.M + 1) << twsh);
+    int tile, outer;
+    if (!fft_item(im, tile, outer)) return;
+    const int s0 = tile << twsh;
     const int nt = active_len(io, outer);
+    stage_twiddles<T>(tw, twg, pl.L);
     load_time<T, TIN>(buf, twsh, pl.M, in + (long long)outer * io.t_outer, io.t_stride, io.S, s0, nt);
     __syncthreads();
     fft_tile<T, false>(buf, twsh, pl, tw);
@@ -289,15 +343,18 @@ enum { EPI_PLAIN = 0, EPI_MISFIT = 1 };
 
 template <typename T, typename TOUT, int EPI>
 __global__ __launch_bounds__(kFftThreads) void k_c2r(FftPlan pl, SeriesIO io, const cplx<T>* __restrict__ in,
-                                                     TOUT* __restrict__ out, const cplx<T>* __restrict__ tw,
-                                                     int twsh, MisfitArgs ma) {
+                                                     TOUT* __restrict__ out, const cplx<T>* __restrict__ twg,
+                                                     int twsh, MisfitArgs ma, ItemMap im) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = cplx<T>;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    const int outer = blockIdx.y;
-    const int s0 = blockIdx.x << twsh;
+    Z* tw = buf + ((pl.M + 1) << twsh);
+    int tile, outer;
+    if (!fft_item(im, tile, outer)) return;
+    const int s0 = tile << twsh;
     const int TWm = (1 << twsh) - 1;
     const int nt = active_len(io, outer);
+    stage_twiddles<T>(tw, twg, pl.L);
     load_spec<T>(buf, twsh, pl.M, in + (long long)outer * io.f_outer, io.f_stride, io.f_part, io.nparts, io.S, s0);
     __syncthreads();
     c2r_pre<T>(buf, twsh, pl.M, tw);
@@ -343,7 +400,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r(FftPlan pl, SeriesIO io, co
             if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) ma.partials[(long long)outer * gridDim.x + blockIdx.x] = red[0];
+        if (threadIdx.x == 0) ma.partials[(long long)outer * im.ntiles + tile] = red[0];
     }
 }
 
@@ -353,14 +410,17 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r(FftPlan pl, SeriesIO io, co
 // workgroup reads its whole tile before it writes).
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_project(FftPlan pl, SeriesIO io, cplx<T>* in_out,
-                                                         const cplx<T>* __restrict__ tw, int twsh) {
+                                                         const cplx<T>* __restrict__ twg, int twsh, ItemMap im) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = cplx<T>;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    const int outer = blockIdx.y;
-    const int s0 = blockIdx.x << twsh;
+    Z* tw = buf + ((pl.M + 1) << twsh);
+    int tile, outer;
+    if (!fft_item(im, tile, outer)) return;
+    const int s0 = tile << twsh;
     const int TWm = (1 << twsh) - 1;
     const int nt = active_len(io, outer);
+    stage_twiddles<T>(tw, twg, pl.L);
     Z* base = in_out + (long long)outer * io.f_outer;
     load_spec<T>(buf, twsh, pl.M, base, io.f_stride, io.f_part, io.nparts, io.S, s0);
     __syncthreads();
@@ -429,33 +489,32 @@ __device__ __forceinline__ int quant_exponent(float amax, int prec) {
 // order independent), and a non-finite flag.  PASS 1: round and store.
 template <typename TIN, int P, int PASS>
 __global__ __launch_bounds__(kFftThreads) void k_load(FftPlan pl, LoadArgs la, const TIN* __restrict__ in,
-                                                      const double2* __restrict__ tw, int twsh) {
+                                                      const double2* __restrict__ twg, int twsh, ItemMap im) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = double2;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    unsigned* lmax = reinterpret_cast<unsigned*>(buf + ((pl.M + 1) << twsh));
-    const int s0 = blockIdx.x << twsh;
+    Z* tw = buf + ((pl.M + 1) << twsh);
+    unsigned* lmax = reinterpret_cast<unsigned*>(tw + pl.L);
+    int tile, rgroup;
+    if (!fft_item(im, tile, rgroup)) return;
+    stage_twiddles<double>(tw, twg, pl.L);
+    const int s0 = tile << twsh;
     const int TWm = (1 << twsh) - 1;
     const int blk = (int)((la.col0 + s0) / kScaleBlock);
     bool bad = false;
     if constexpr (PASS == 0) {
         for (int k = threadIdx.x; k <= pl.M; k += kFftThreads) lmax[k] = 0u;
     }
-    const int r0 = blockIdx.y * la.rows_per_wg;
+    const int r0 = rgroup * la.rows_per_wg;
     const int r1 = min(la.Nd, r0 + la.rows_per_wg);
     for (int row = r0; row < r1; ++row) {
         const TIN* src = in + (long long)row * la.ncols;
-        for (int e = threadIdx.x; e < (pl.M << twsh); e += kFftThreads) {
-            const int n = e >> twsh, s = e & TWm;
-            const int col = s0 + s;
-            double x0 = 0.0, x1 = 0.0;
-            if (col < la.ncols) {
-                const int t0 = 2 * n;
-                if (t0 < la.Nt) x0 = (double)src[(long long)t0 * la.t_stride + col];
-                if (t0 + 1 < la.Nt) x1 = (double)src[(long long)(t0 + 1) * la.t_stride + col];
-                if constexpr (PASS == 0 || !Fmt<P>::scaled) bad |= !isfinite(x0) || !isfinite(x1);
+        load_time<double, TIN>(buf, twsh, pl.M, src, la.t_stride, la.ncols, s0, la.Nt);
+        if constexpr (PASS == 0 || !Fmt<P>::scaled) {
+            for (int e = threadIdx.x; e < (pl.M << twsh); e += kFftThreads) {
+                const double2 z = buf[e];
+                bad |= !isfinite(z.x) || !isfinite(z.y);
             }
-            buf[e] = make_double2(x0, x1);
         }
         __syncthreads();
         fft_tile<double, false>(buf, twsh, pl, tw);
@@ -517,24 +576,38 @@ __global__ void k_zero_pad(uint8_t* __restrict__ fhat, long long rows, int pitch
 }
 
 // ---------------------------------------------------------------- host launchers
-int fft_tile_shift(int M, bool f64) {
-    const int cap = f64 ? FftCap<double>::cap : FftCap<float>::cap;
-    int tw = 64;
-    while (tw > 1 && tw * (M + 1) > cap) tw >>= 1;
-    if (tw * (M + 1) > cap) return -1;
-    int sh = 0;
-    while ((1 << sh) < tw) ++sh;
-    return sh;
+// Tile width TW (a power of two, at most 32 series): the largest that keeps
+// the tile plus the twiddle table within 48 KiB of LDS, so that three or four
+// workgroups share a CU.
+constexpr size_t kFftLdsTarget = 48 * 1024;
+
+static size_t fft_lds(int M, int twsh, size_t zbytes) {
+    return ((size_t)(M + 1) * ((size_t)1 << twsh) + (size_t)(2 * M)) * zbytes;
 }
 
-static size_t fft_lds(int M, int twsh, size_t zbytes) { return (size_t)(M + 1) * ((size_t)1 << twsh) * zbytes; }
+int fft_tile_shift(int M, bool f64) {
+    const size_t z = f64 ? sizeof(double2) : sizeof(float2);
+    const int cap = f64 ? FftCap<double>::cap : FftCap<float>::cap;
+    for (int sh = 5; sh >= 0; --sh)
+        if (fft_lds(M, sh, z) <= kFftLdsTarget && ((M + 1) << sh) <= cap) return sh;
+    return -1;
+}
 
-// The loader also keeps one running maximum per bin in LDS; stay within 64 KiB.
+// The loader also keeps one running maximum per bin in LDS.
+static size_t load_lds(int M, int sh) { return fft_lds(M, sh, sizeof(double2)) + (size_t)(M + 1) * sizeof(unsigned); }
+
 int load_tile_shift(int M) {
-    int sh = fft_tile_shift(M, true);
-    while (sh > 0 && fft_lds(M, sh, sizeof(double2)) + (size_t)(M + 1) * sizeof(unsigned) > 65536) --sh;
-    if (sh < 0 || fft_lds(M, sh, sizeof(double2)) + (size_t)(M + 1) * sizeof(unsigned) > 65536) return -1;
-    return sh;
+    for (int sh = 5; sh >= 0; --sh)
+        if (load_lds(M, sh) <= 65536 && ((M + 1) << sh) <= FftCap<double>::cap) return sh;
+    return -1;
+}
+
+static ItemMap item_map(int S, int sh, int outer) {
+    ItemMap im;
+    im.ntiles = (S + (1 << sh) - 1) >> sh;
+    im.items = im.ntiles * outer;
+    im.Q = (im.items + 7) / 8;
+    return im;
 }
 
 hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st) {
@@ -546,14 +619,15 @@ hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st) {
 hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
                       const void* tw, hipStream_t st) {
     const int sh = fft_tile_shift(pl.M, f64);
-    dim3 grid((io.S_pad + (1 << sh) - 1) >> sh, io.outer_count);
+    const ItemMap im = item_map(io.S_pad, sh, io.outer_count);
+    dim3 grid(8 * im.Q);
     if (f64) {
         const size_t lds = fft_lds(pl.M, sh, sizeof(double2));
-        if (in_f64) hipLaunchKernelGGL((k_r2c<double, double>), grid, dim3(kFftThreads), lds, st, pl, io, (const double*)in, (double2*)out, (const double2*)tw, sh);
-        else hipLaunchKernelGGL((k_r2c<double, float>), grid, dim3(kFftThreads), lds, st, pl, io, (const float*)in, (double2*)out, (const double2*)tw, sh);
+        if (in_f64) hipLaunchKernelGGL((k_r2c<double, double>), grid, dim3(kFftThreads), lds, st, pl, io, (const double*)in, (double2*)out, (const double2*)tw, sh, im);
+        else hipLaunchKernelGGL((k_r2c<double, float>), grid, dim3(kFftThreads), lds, st, pl, io, (const float*)in, (double2*)out, (const double2*)tw, sh, im);
     } else {
         const size_t lds = fft_lds(pl.M, sh, sizeof(float2));
-        hipLaunchKernelGGL((k_r2c<float, float>), grid, dim3(kFftThreads), lds, st, pl, io, (const float*)in, (float2*)out, (const float2*)tw, sh);
+        hipLaunchKernelGGL((k_r2c<float, float>), grid, dim3(kFftThreads), lds, st, pl, io, (const float*)in, (float2*)out, (const float2*)tw, sh, im);
     }
     return hipGetLastError();
 }
@@ -561,19 +635,20 @@ hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& 
 hipError_t launch_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
                       const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st) {
     const int sh = fft_tile_shift(pl.M, f64);
-    dim3 grid((io.S + (1 << sh) - 1) >> sh, io.outer_count);
+    const ItemMap im = item_map(io.S, sh, io.outer_count);
+    dim3 grid(8 * im.Q);
     MisfitArgs ma{d_obs, var, var_mode, partials};
     const bool mis = d_obs != nullptr;
     if (f64) {
         size_t lds = fft_lds(pl.M, sh, sizeof(double2));
         if (lds < kFftThreads * sizeof(double)) lds = kFftThreads * sizeof(double);
-        if (mis) hipLaunchKernelGGL((k_c2r<double, double, EPI_MISFIT>), grid, dim3(kFftThreads), lds, st, pl, io, (const double2*)in, (double*)out, (const double2*)tw, sh, ma);
-        else hipLaunchKernelGGL((k_c2r<double, double, EPI_PLAIN>), grid, dim3(kFftThreads), lds, st, pl, io, (const double2*)in, (double*)out, (const double2*)tw, sh, ma);
+        if (mis) hipLaunchKernelGGL((k_c2r<double, double, EPI_MISFIT>), grid, dim3(kFftThreads), lds, st, pl, io, (const double2*)in, (double*)out, (const double2*)tw, sh, ma, im);
+        else hipLaunchKernelGGL((k_c2r<double, double, EPI_PLAIN>), grid, dim3(kFftThreads), lds, st, pl, io, (const double2*)in, (double*)out, (const double2*)tw, sh, ma, im);
     } else {
         size_t lds = fft_lds(pl.M, sh, sizeof(float2));
         if (lds < kFftThreads * sizeof(double)) lds = kFftThreads * sizeof(double);
-        if (mis) hipLaunchKernelGGL((k_c2r<float, float, EPI_MISFIT>), grid, dim3(kFftThreads), lds, st, pl, io, (const float2*)in, (float*)out, (const float2*)tw, sh, ma);
-        else hipLaunchKernelGGL((k_c2r<float, float, EPI_PLAIN>), grid, dim3(kFftThreads), lds, st, pl, io, (const float2*)in, (float*)out, (const float2*)tw, sh, ma);
+        if (mis) hipLaunchKernelGGL((k_c2r<float, float, EPI_MISFIT>), grid, dim3(kFftThreads), lds, st, pl, io, (const float2*)in, (float*)out, (const float2*)tw, sh, ma, im);
+        else hipLaunchKernelGGL((k_c2r<float, float, EPI_PLAIN>), grid, dim3(kFftThreads), lds, st, pl, io, (const float2*)in, (float*)out, (const float2*)tw, sh, ma, im);
     }
     return hipGetLastError();
 }
@@ -586,9 +661,10 @@ int c2r_grid_x(const FftPlan& pl, bool f64, int S) {
 hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
                           hipStream_t st) {
     const int sh = fft_tile_shift(pl.M, f64);
-    dim3 grid((io.S_pad + (1 << sh) - 1) >> sh, io.outer_count);
-    if (f64) hipLaunchKernelGGL((k_project<double>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(double2)), st, pl, io, (double2*)in_out, (const double2*)tw, sh);
-    else hipLaunchKernelGGL((k_project<float>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(float2)), st, pl, io, (float2*)in_out, (const float2*)tw, sh);
+    const ItemMap im = item_map(io.S_pad, sh, io.outer_count);
+    dim3 grid(8 * im.Q);
+    if (f64) hipLaunchKernelGGL((k_project<double>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(double2)), st, pl, io, (double2*)in_out, (const double2*)tw, sh, im);
+    else hipLaunchKernelGGL((k_project<float>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(float2)), st, pl, io, (float2*)in_out, (const float2*)tw, sh, im);
     return hipGetLastError();
 }
 
@@ -599,17 +675,18 @@ hipError_t launch_misfit_reduce(const double* partials, int nper, double* misfit
 
 template <typename TIN, int P>
 static void load_pass(int pass, dim3 grid, size_t lds, hipStream_t st, const FftPlan& pl, const LoadArgs& la,
-                      const void* in, const void* tw, int sh) {
-    if (pass == 0) hipLaunchKernelGGL((k_load<TIN, P, 0>), grid, dim3(kFftThreads), lds, st, pl, la, (const TIN*)in, (const double2*)tw, sh);
-    else hipLaunchKernelGGL((k_load<TIN, P, 1>), grid, dim3(kFftThreads), lds, st, pl, la, (const TIN*)in, (const double2*)tw, sh);
+                      const void* in, const void* tw, int sh, ItemMap im) {
+    if (pass == 0) hipLaunchKernelGGL((k_load<TIN, P, 0>), grid, dim3(kFftThreads), lds, st, pl, la, (const TIN*)in, (const double2*)tw, sh, im);
+    else hipLaunchKernelGGL((k_load<TIN, P, 1>), grid, dim3(kFftThreads), lds, st, pl, la, (const TIN*)in, (const double2*)tw, sh, im);
 }
 
 hipError_t launch_load(int prec, bool in_f64, const FftPlan& pl, const LoadArgs& la, const void* in,
                        const void* tw64, hipStream_t st) {
     const int sh = load_tile_shift(pl.M);
     if (sh < 0) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((la.ncols + (1 << sh) - 1) >> sh), (unsigned)((la.Nd + la.rows_per_wg - 1) / la.rows_per_wg));
-    const size_t lds = fft_lds(pl.M, sh, sizeof(double2)) + (size_t)(pl.M + 1) * sizeof(unsigned);
+    const ItemMap im = item_map(la.ncols, sh, (la.Nd + la.rows_per_wg - 1) / la.rows_per_wg);
+    dim3 grid(8 * im.Q);
+    const size_t lds = load_lds(pl.M, sh);
     const int nb0 = (int)(la.col0 / kScaleBlock);
     const int nb1 = (int)((la.col0 + la.ncols + kScaleBlock - 1) / kScaleBlock);
     const int nfreq = pl.M + 1;
@@ -622,10 +699,10 @@ hipError_t launch_load(int prec, bool in_f64, const FftPlan& pl, const LoadArgs&
     }
     for (int pass = scaled ? 0 : 1; pass < 2; ++pass) {
         switch (prec) {
-            case kFP64: in_f64 ? load_pass<double, kFP64>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kFP64>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
-            case kFP32: in_f64 ? load_pass<double, kFP32>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kFP32>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
-            case kBF16: in_f64 ? load_pass<double, kBF16>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kBF16>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
-            default: in_f64 ? load_pass<double, kFP16>(pass, grid, lds, st, pl, la, in, tw64, sh) : load_pass<float, kFP16>(pass, grid, lds, st, pl, la, in, tw64, sh); break;
+            case kFP64: in_f64 ? load_pass<double, kFP64>(pass, grid, lds, st, pl, la, in, tw64, sh, im) : load_pass<float, kFP64>(pass, grid, lds, st, pl, la, in, tw64, sh, im); break;
+            case kFP32: in_f64 ? load_pass<double, kFP32>(pass, grid, lds, st, pl, la, in, tw64, sh, im) : load_pass<float, kFP32>(pass, grid, lds, st, pl, la, in, tw64, sh, im); break;
+            case kBF16: in_f64 ? load_pass<double, kBF16>(pass, grid, lds, st, pl, la, in, tw64, sh, im) : load_pass<float, kBF16>(pass, grid, lds, st, pl, la, in, tw64, sh, im); break;
+            default: in_f64 ? load_pass<double, kFP16>(pass, grid, lds, st, pl, la, in, tw64, sh, im) : load_pass<float, kFP16>(pass, grid, lds, st, pl, la, in, tw64, sh, im); break;
         }
     }
     if (scaled) {

@@ -114,49 +114,73 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* __rest
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    Raw32 acur[MB], anxt[MB];
-    load_a(acur, 0);
+    // right-hand-side values a thread stages per step (32 columns x RB)
+    constexpr int XPT = (32 * RB + kGemmThreads - 1) / kGemmThreads;
     const float2* Xw = X + (long long)w * ga.nrhs * ga.pitch;
-
-    for (int s = 0; s < nsteps; ++s) {
-        const int buf = s & 1;
-        // stage 32 complex columns of the group's right-hand sides as BF16 hi/lo fragments
-        for (int e = tid; e < 32 * RB; e += kGemmThreads) {
+    auto load_x = [&](float2 (&xv)[XPT], int s) {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int e = tid + u * kGemmThreads;
             const int c = e & 31, bl = e >> 5;
             const int b = b0 + bl, j = jbeg + 32 * s + c;
-            float2 x = make_float2(0.f, 0.f);
-            if (b < ga.nrhs && j < jend) x = Xw[(long long)b * ga.pitch + j];
+            xv[u] = (e < 32 * RB && b < ga.nrhs && j < jend) ? Xw[(long long)b * ga.pitch + j] : make_float2(0.f, 0.f);
+        }
+    };
+    // BF16 hi/lo fragments in [n block][K half][hi/lo][lane] order
+    auto stage_x = [&](const float2 (&xv)[XPT], int buf) {
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int e = tid + u * kGemmThreads;
+            if (e >= 32 * RB) break;
+            const int c = e & 31, bl = e >> 5;
             uint32_t rh, rl, ih, il;
-            split_bf16(x.x * sc, rh, rl);
-            split_bf16(x.y * sc, ih, il);
+            split_bf16(xv[u].x * sc, rh, rl);
+            split_bf16(xv[u].y * sc, ih, il);
             const int g = c >> 3, h = (c >> 2) & 1, cc = c & 3;
             const int nre = 2 * bl, nim = 2 * bl + 1;
             // real-part column: (x_r, -x_i); imaginary-part column: (x_i, x_r)
-            uint32_t* pre_h = reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][0][g * 16 + (nre & 15)]);
-            uint32_t* pre_l = reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][1][g * 16 + (nre & 15)]);
-            uint32_t* pim_h = reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][0][g * 16 + (nim & 15)]);
-            uint32_t* pim_l = reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][1][g * 16 + (nim & 15)]);
-            pre_h[cc] = rh | ((ih ^ 0x8000u) << 16);
-            pre_l[cc] = rl | ((il ^ 0x8000u) << 16);
-            pim_h[cc] = ih | (rh << 16);
-            pim_l[cc] = il | (rl << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][0][g * 16 + (nre & 15)])[cc] = rh | ((ih ^ 0x8000u) << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][1][g * 16 + (nre & 15)])[cc] = rl | ((il ^ 0x8000u) << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][0][g * 16 + (nim & 15)])[cc] = ih | (rh << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][1][g * 16 + (nim & 15)])[cc] = il | (rl << 16);
         }
-        if (s + 1 < nsteps) load_a(anxt, s + 1);
-        __syncthreads();
+    };
+    auto compute = [&](const Raw32 (&a)[MB], int buf) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const uint4 f0h = bs[buf][nb][0][0][lane], f0l = bs[buf][nb][0][1][lane];
             const uint4 f1h = bs[buf][nb][1][0][lane], f1l = bs[buf][nb][1][1][lane];
+            // consecutive MFMAs use different accumulators (no dependent issue)
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                acc[mb][nb] = mfma(acur[mb].a, f0h, acc[mb][nb]);
-                acc[mb][nb] = mfma(acur[mb].a, f0l, acc[mb][nb]);
-                acc[mb][nb] = mfma(acur[mb].b, f1h, acc[mb][nb]);
-                acc[mb][nb] = mfma(acur[mb].b, f1l, acc[mb][nb]);
-            }
+            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].a, f0h, acc[mb][nb]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].a, f0l, acc[mb][nb]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].b, f1h, acc[mb][nb]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].b, f1l, acc[mb][nb]);
         }
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acur[mb] = anxt[mb];
+    };
+
+    // two register sets: loads for step s + 2 are in flight while step s computes
+    Raw32 a0[MB], a1[MB];
+    float2 x0[XPT], x1[XPT];
+    load_a(a0, 0);
+    load_x(x0, 0);
+    if (nsteps > 1) { load_a(a1, 1); load_x(x1, 1); }
+    for (int s = 0; s < nsteps; s += 2) {
+        stage_x(x0, 0);
+        if (s + 2 < nsteps) load_x(x0, s + 2);
+        __syncthreads();
+        compute(a0, 0);
+        if (s + 2 < nsteps) load_a(a0, s + 2);
+        if (s + 1 < nsteps) {
+            stage_x(x1, 1);
+            if (s + 3 < nsteps) load_x(x1, s + 3);
+            __syncthreads();
+            compute(a1, 1);
+            if (s + 3 < nsteps) load_a(a1, s + 3);
+        }
     }
 
     // partial sums of this column chunk: Yp[kc][w][b][row], row-block lanes hold rows 4 lg + r
@@ -210,34 +234,52 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __rest
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int s = 0; s < nsteps; ++s) {
-        const int buf = s & 1;
+    // per-thread share of one step: spectrum tile (16 x COLS/4 chunks of 16 B)
+    // and right-hand sides (16 x RB values)
+    constexpr int APT = (16 * (COLS / 4) + kGemmThreads - 1) / kGemmThreads;
+    constexpr int BPT = (16 * RB + kGemmThreads - 1) / kGemmThreads;
+    auto load_ab = [&](uint4 (&av)[APT], float2 (&bv)[BPT], int s) {
         const int i0 = 16 * s;
-        // spectrum tile: 16 sensors x COLS columns, transposed to [column][sensor]
-        for (int e = tid; e < 16 * (COLS / 4); e += kGemmThreads) {
+#pragma unroll
+        for (int u = 0; u < APT; ++u) {
+            const int e = tid + u * kGemmThreads;
             const int r = e & 15, ch = e >> 4;
             const int i = i0 + r, j = j0 + 4 * ch;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (i < ga.Nd && j < ga.pitch) {
+            av[u] = make_uint4(0, 0, 0, 0);
+            if (e < 16 * (COLS / 4) && i < ga.Nd && j < ga.pitch) {
                 const u32x4 raw = __builtin_nontemporal_load(
                     reinterpret_cast<const u32x4*>(Fw + ((long long)i * ga.pitch + j) * 4));
-                v = make_uint4(raw.x, raw.y, raw.z, raw.w);
+                av[u] = make_uint4(raw.x, raw.y, raw.z, raw.w);
             }
-            uint32_t* dst = &as[buf][(4 * ch) * kAdjAW + r];
-            dst[0] = v.x;
-            dst[kAdjAW] = v.y;
-            dst[2 * kAdjAW] = v.z;
-            dst[3 * kAdjAW] = v.w;
         }
-        // right-hand sides: 16 sensors x RB, as BF16 hi/lo fragments
-        for (int e = tid; e < 16 * RB; e += kGemmThreads) {
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int e = tid + u * kGemmThreads;
             const int r = e & 15, bl = e >> 4;
             const int b = b0 + bl, i = i0 + r;
-            float2 y = make_float2(0.f, 0.f);
-            if (b < ga.nrhs && i < ga.Nd) y = Yw[(long long)b * ga.Nd + i];
+            bv[u] = (e < 16 * RB && b < ga.nrhs && i < ga.Nd) ? Yw[(long long)b * ga.Nd + i] : make_float2(0.f, 0.f);
+        }
+    };
+    auto stage_ab = [&](const uint4 (&av)[APT], const float2 (&bv)[BPT], int buf) {
+#pragma unroll
+        for (int u = 0; u < APT; ++u) {
+            const int e = tid + u * kGemmThreads;
+            if (e >= 16 * (COLS / 4)) break;
+            const int r = e & 15, ch = e >> 4;
+            uint32_t* dst = &as[buf][(4 * ch) * kAdjAW + r];     // transposed to [column][sensor]
+            dst[0] = av[u].x;
+            dst[kAdjAW] = av[u].y;
+            dst[2 * kAdjAW] = av[u].z;
+            dst[3 * kAdjAW] = av[u].w;
+        }
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int e = tid + u * kGemmThreads;
+            if (e >= 16 * RB) break;
+            const int r = e & 15, bl = e >> 4;
             uint32_t rh, rl, ih, il;
-            split_bf16(y.x, rh, rl);
-            split_bf16(y.y, ih, il);
+            split_bf16(bv[u].x, rh, rl);
+            split_bf16(bv[u].y, ih, il);
             const int g = r >> 2, rho = r & 3;
             const int nre = 2 * bl, nim = 2 * bl + 1;
             // real-part column: (y_r, y_i); imaginary-part column: (y_i, -y_r)
@@ -246,7 +288,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __rest
             reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][0][g * 16 + (nim & 15)])[rho] = ih | ((rh ^ 0x8000u) << 16);
             reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][1][g * 16 + (nim & 15)])[rho] = il | ((rl ^ 0x8000u) << 16);
         }
-        __syncthreads();
+    };
+    auto compute = [&](int buf) {
         uint4 afr[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
@@ -257,10 +300,27 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __rest
         for (int nb = 0; nb < NB; ++nb) {
             const uint4 fh = bs[buf][nb][0][lane], fl = bs[buf][nb][1][lane];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                acc[mb][nb] = mfma(afr[mb], fh, acc[mb][nb]);
-                acc[mb][nb] = mfma(afr[mb], fl, acc[mb][nb]);
-            }
+            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(afr[mb], fh, acc[mb][nb]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(afr[mb], fl, acc[mb][nb]);
+        }
+    };
+
+    // two register sets: loads for step s + 2 are in flight while step s computes
+    uint4 av0[APT], av1[APT];
+    float2 bv0[BPT], bv1[BPT];
+    load_ab(av0, bv0, 0);
+    if (nsteps > 1) load_ab(av1, bv1, 1);
+    for (int s = 0; s < nsteps; s += 2) {
+        stage_ab(av0, bv0, 0);
+        if (s + 2 < nsteps) load_ab(av0, bv0, s + 2);
+        __syncthreads();
+        compute(0);
+        if (s + 1 < nsteps) {
+            stage_ab(av1, bv1, 1);
+            if (s + 3 < nsteps) load_ab(av1, bv1, s + 3);
+            __syncthreads();
+            compute(1);
         }
     }
 

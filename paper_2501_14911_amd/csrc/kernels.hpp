@@ -68,6 +68,9 @@ hipError_t launch_gemv_fwd(int prec, const GemvArgs& ga, const void* fhat, const
 hipError_t launch_gemv_adj(int prec, const GemvArgs& ga, const void* fhat, const float* scales, const void* Y,
                            void* Xp, hipStream_t st);
 
+// probe.hip
+hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int blocks, hipStream_t st);
+
 // gemm_mfma.hip
 int gemm_fwd_kchunks(int pitch);
 hipError_t launch_gemm_fwd(const GemmArgs& ga, const void* fhat, const float* scales, const void* X, void* Yp,

@@ -99,12 +99,16 @@ class P2OOperator:
         """Start (or stop) per-stage HIP-event timing; resets the totals."""
         check(lib.p2o_profile_enable(self._plan, 1 if enable else 0))
 
-    def stage_times(self) -> dict:
-        """{stage: (total_ms, launches)} since profiling was enabled (synchronises)."""
+    def stage_times(self, nrhs: Optional[int] = None) -> dict:
+        """{stage: (total_ms, launches)} since profiling was enabled, over all
+        launches or those of calls with ``nrhs`` right-hand sides (synchronises)."""
         out = {}
         for name, sid in STAGES.items():
             ms, n = ctypes.c_double(), c_int64()
-            check(lib.p2o_profile_read(self._plan, sid, byref(ms), byref(n)))
+            if nrhs is None:
+                check(lib.p2o_profile_read(self._plan, sid, byref(ms), byref(n)))
+            else:
+                check(lib.p2o_profile_read_nrhs(self._plan, sid, int(nrhs), byref(ms), byref(n)))
             out[name] = (ms.value, n.value)
         return out
 
@@ -255,3 +259,33 @@ def misfit(m: torch.Tensor, op: P2OOperator, d_obs: torch.Tensor, noise_var, nt_
     """Phi(m) = 1/2 ||F m - d_obs||^2_{Gamma_noise^-1} (float64, per right-hand
     side) with the fused gradient kernel as its backward."""
     return _Misfit.apply(m, op, d_obs, noise_var, nt_active)
+
+
+def bandwidth_probe(nbytes: int = 8 << 30, reps: int = 10, device="cuda", blocks: int = 8192) -> dict:
+    """Measured streaming read and copy bandwidth (GB/s) of the device, with
+    the library's probe kernels, for roofline context."""
+    dev = torch.device(device)
+    nbytes = nbytes // 32 * 32
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+    sink = torch.empty(blocks, dtype=torch.int32, device=dev)
+    half = nbytes // 2 // 32 * 32
+    dst = torch.empty(half, dtype=torch.uint8, device=dev)
+    s = c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    out = {}
+    for mode, name, nb, moved in ((0, "read", nbytes, nbytes), (1, "copy", half, 2 * half)):
+        d = sink if mode == 0 else dst
+        src_p = src if mode == 0 else src[:half]
+        check(lib.p2o_bandwidth_probe(mode, _ptr(src_p), _ptr(d), nb, blocks, s))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            check(lib.p2o_bandwidth_probe(mode, _ptr(src_p), _ptr(d), nb, blocks, s))
+        b.record()
+        torch.cuda.synchronize(dev)
+        ms = a.elapsed_time(b) / reps
+        out[name + "_GBs"] = moved / (ms * 1e-3) / 1e9
+        out[name + "_bytes"] = moved
+    del src, dst, sink
+    torch.cuda.empty_cache()
+    return out

@@ -21,6 +21,9 @@ from paper_2501_14911_amd import P2OOperator  # noqa: E402
 
 DEV = "cuda"
 TOL_BF16 = 2e-3
+# F F^* e applies two operators each within 2e-3; to first order their
+# relative errors add.
+TOL_BF16_COMPOSED = 2 * TOL_BF16
 
 
 def note(msg):
@@ -97,7 +100,7 @@ def test_batched_data_space_columns():
     ho = oracle.data_space_hessian(F, e)
     worst = max(oracle.rel_l2(h[b], ho[b]) for b in range(64))
     note(f"[batched] F F* columns worst rel-L2 {worst:.3e}")
-    assert worst <= TOL_BF16
+    assert worst <= TOL_BF16_COMPOSED
 
 
 def test_batched_misfit_gradient():
