@@ -31,6 +31,11 @@ template <typename T> struct FftCap;
 template <> struct FftCap<float> { static constexpr int cap = 3584; };   // complex tile entries per workgroup
 template <> struct FftCap<double> { static constexpr int cap = 1792; };
 
+// Tile element (bin n, series s) in LDS.  Rows are padded by one element:
+// an odd row stride keeps the strided writes of the first Stockham passes
+// (stride R rows) on distinct banks.
+__device__ __forceinline__ int tix(int n, int s, int twsh) { return n * ((1 << twsh) + 1) + s; }
+
 // ---------------------------------------------------------------- butterflies
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_small(cplx<T>* a, const cplx<T>* w) {
@@ -119,7 +124,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
             const int k = j - grp * Ns;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                Z a = buf[((j + q * MR) << twsh) + s];
+                Z a = buf[tix(j + q * MR, s, twsh)];
                 if (q > 0 && k > 0) {
                     Z t = tw[q * k * tstep];
                     a = cmul(a, INV ? cconj(t) : t);
@@ -140,7 +145,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
             const int k = j - grp * Ns;
             const int base = grp * Ns * R + k;
 #pragma unroll
-            for (int p = 0; p < R; ++p) buf[((base + p * Ns) << twsh) + s] = v[u][p];
+            for (int p = 0; p < R; ++p) buf[tix(base + p * Ns, s, twsh)] = v[u][p];
         }
     }
     __syncthreads();
@@ -176,8 +181,8 @@ __device__ __forceinline__ void r2c_post(const cplx<T>* buf, int twsh, int M,
         const int k = e >> twsh, s = e & TWm;
         const int k1 = (k == M) ? 0 : k;
         const int k2 = (k == 0) ? 0 : M - k;
-        const Z a = buf[(k1 << twsh) + s];
-        const Z b = cconj(buf[(k2 << twsh) + s]);
+        const Z a = buf[tix(k1, s, twsh)];
+        const Z b = cconj(buf[tix(k2, s, twsh)]);
         const Z sum = cadd(a, b);
         const Z t = cmul(tw[k], csub(a, b));
         store(k, s, cmk<T>(T(0.5) * (sum.x + t.y), T(0.5) * (sum.y - t.x)));
@@ -200,15 +205,15 @@ __device__ __forceinline__ void c2r_pre(cplx<T>* buf, int twsh, int M, const cpl
     for (int e = threadIdx.x; e < ((M / 2 + 1) << twsh); e += kFftThreads) {
         const int k = e >> twsh, s = e & TWm;
         const int kk = M - k;
-        Z xk = buf[(k << twsh) + s];
-        Z xkk = buf[(kk << twsh) + s];
+        Z xk = buf[tix(k, s, twsh)];
+        Z xkk = buf[tix(kk, s, twsh)];
         if (k == 0) { xk.y = T(0); xkk.y = T(0); }
         const Z zk = one(xk, xkk, tw[k]);
         if (k != 0 && kk != k) {
             const Z zkk = one(xkk, xk, tw[kk]);
-            buf[(kk << twsh) + s] = zkk;
+            buf[tix(kk, s, twsh)] = zkk;
         }
-        buf[(k << twsh) + s] = zk;
+        buf[tix(k, s, twsh)] = zk;
     }
 }
 
@@ -244,37 +249,26 @@ __device__ __forceinline__ int active_len(const SeriesIO& io, int outer) {
 }
 
 // Load real series (zero past the active length) as z[n] = x[2n] + i x[2n+1].
-// All of a thread's global loads are issued before any LDS store, so their
-// latencies overlap instead of adding up.
 template <typename T, typename TIN>
 __device__ __forceinline__ void load_time(cplx<T>* buf, int twsh, int M, const TIN* __restrict__ src,
                                           long long t_stride, int S, int s0, int nt) {
-    constexpr int MAXE = FftCap<T>::cap / kFftThreads;
     const int TWm = (1 << twsh) - 1;
-    const int ne = M << twsh;
-    T x0[MAXE], x1[MAXE];
-#pragma unroll
-    for (int u = 0; u < MAXE; ++u) {
-        const int e = threadIdx.x + u * kFftThreads;
-        x0[u] = T(0);
-        x1[u] = T(0);
-        if (e < ne) {
-            const int n = e >> twsh, col = s0 + (e & TWm);
-            if (col < S) {
-                const int t0 = 2 * n;
-                if (t0 < nt) x0[u] = (T)src[(long long)t0 * t_stride + col];
-                if (t0 + 1 < nt) x1[u] = (T)src[(long long)(t0 + 1) * t_stride + col];
-            }
+    for (int e = threadIdx.x; e < (M << twsh); e += kFftThreads) {
+        const int n = e >> twsh, s = e & TWm;
+        const int col = s0 + s;
+        T x0 = T(0), x1 = T(0);
+        if (col < S) {
+            const int t0 = 2 * n;
+            if (t0 < nt) x0 = (T)src[(long long)t0 * t_stride + col];
+            if (t0 + 1 < nt) x1 = (T)src[(long long)(t0 + 1) * t_stride + col];
         }
-    }
-#pragma unroll
-    for (int u = 0; u < MAXE; ++u) {
-        const int e = threadIdx.x + u * kFftThreads;
-        if (e < ne) buf[e] = cmk<T>(x0[u], x1[u]);
+        buf[tix(n, s, twsh)] = cmk<T>(x0, x1);
     }
 }
 
 // Load a half spectrum X[0..M], summing `nparts` partial spectra in order.
+// All of a thread's global loads of one partial are issued before any LDS
+// store, so their latencies overlap instead of adding up.
 template <typename T>
 __device__ __forceinline__ void load_spec(cplx<T>* buf, int twsh, int M, const cplx<T>* __restrict__ src,
                                           long long f_stride, long long f_part, int nparts, int S, int s0) {
@@ -300,7 +294,7 @@ __device__ __forceinline__ void load_spec(cplx<T>* buf, int twsh, int M, const c
 #pragma unroll
     for (int u = 0; u < MAXE; ++u) {
         const int e = threadIdx.x + u * kFftThreads;
-        if (e < ne) buf[e] = acc[u];
+        if (e < ne) buf[tix(e >> twsh, e & TWm, twsh)] = acc[u];
     }
 }
 
@@ -313,7 +307,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c(FftPlan pl, SeriesIO io, co
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = cplx<T>;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    Z* tw = buf + ((pl.M + 1) << twsh);
+    Z* tw = buf + (pl.M + 1) * ((1 << twsh) + 1);
     int tile, outer;
     if (!fft_item(im, tile, outer)) return;
     const int s0 = tile << twsh;
@@ -348,7 +342,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r(FftPlan pl, SeriesIO io, co
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = cplx<T>;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    Z* tw = buf + ((pl.M + 1) << twsh);
+    Z* tw = buf + (pl.M + 1) * ((1 << twsh) + 1);
     int tile, outer;
     if (!fft_item(im, tile, outer)) return;
     const int s0 = tile << twsh;
@@ -367,7 +361,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r(FftPlan pl, SeriesIO io, co
         const int n = e >> twsh, s = e & TWm;
         const int col = s0 + s;
         if (col >= io.S) continue;
-        const Z z = buf[e];
+        const Z z = buf[tix(n, s, twsh)];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int t = 2 * n + h;
@@ -414,7 +408,7 @@ __global__ __launch_bounds__(kFftThreads) void k_project(FftPlan pl, SeriesIO io
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = cplx<T>;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    Z* tw = buf + ((pl.M + 1) << twsh);
+    Z* tw = buf + (pl.M + 1) * ((1 << twsh) + 1);
     int tile, outer;
     if (!fft_item(im, tile, outer)) return;
     const int s0 = tile << twsh;
@@ -429,11 +423,11 @@ __global__ __launch_bounds__(kFftThreads) void k_project(FftPlan pl, SeriesIO io
     fft_tile<T, true>(buf, twsh, pl, tw);
     const T inv = T(1) / T(pl.M);
     for (int e = threadIdx.x; e < (pl.M << twsh); e += kFftThreads) {
-        const int n = e >> twsh;
-        Z z = buf[e];
+        const int n = e >> twsh, i = tix(n, e & TWm, twsh);
+        Z z = buf[i];
         z.x = (2 * n < nt) ? z.x * inv : T(0);
         z.y = (2 * n + 1 < nt) ? z.y * inv : T(0);
-        buf[e] = z;
+        buf[i] = z;
     }
     __syncthreads();
     fft_tile<T, false>(buf, twsh, pl, tw);
@@ -493,7 +487,7 @@ __global__ __launch_bounds__(kFftThreads) void k_load(FftPlan pl, LoadArgs la, c
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Z = double2;
     Z* buf = reinterpret_cast<Z*>(smem_raw);
-    Z* tw = buf + ((pl.M + 1) << twsh);
+    Z* tw = buf + (pl.M + 1) * ((1 << twsh) + 1);
     unsigned* lmax = reinterpret_cast<unsigned*>(tw + pl.L);
     int tile, rgroup;
     if (!fft_item(im, tile, rgroup)) return;
@@ -512,7 +506,7 @@ __global__ __launch_bounds__(kFftThreads) void k_load(FftPlan pl, LoadArgs la, c
         load_time<double, TIN>(buf, twsh, pl.M, src, la.t_stride, la.ncols, s0, la.Nt);
         if constexpr (PASS == 0 || !Fmt<P>::scaled) {
             for (int e = threadIdx.x; e < (pl.M << twsh); e += kFftThreads) {
-                const double2 z = buf[e];
+                const double2 z = buf[tix(e >> twsh, e & TWm, twsh)];
                 bad |= !isfinite(z.x) || !isfinite(z.y);
             }
         }
@@ -582,7 +576,7 @@ __global__ void k_zero_pad(uint8_t* __restrict__ fhat, long long rows, int pitch
 constexpr size_t kFftLdsTarget = 48 * 1024;
 
 static size_t fft_lds(int M, int twsh, size_t zbytes) {
-    return ((size_t)(M + 1) * ((size_t)1 << twsh) + (size_t)(2 * M)) * zbytes;
+    return ((size_t)(M + 1) * (((size_t)1 << twsh) + 1) + (size_t)(2 * M)) * zbytes;
 }
 
 int fft_tile_shift(int M, bool f64) {

@@ -1,0 +1,179 @@
+"""Full-size GPU parity in the launch configurations the benchmark times.
+
+The 600 x 16384 x 420 workload (BF16 spectrum, 16.5 GB) and the
+600 x 65536 x 420 one-GPU share (BF16, 66 GB).  Blocks are drawn on the GPU
+with the counter-based generator; the FP64 oracle regenerates on the CPU
+only the sensor rows (for F m and F F* e) or parameter columns (for F* d) it
+checks, and computes those outputs exactly.  Where the oracle would need
+the whole operator (the misfit value), properties that hold at any size are
+checked instead: central differences of the quadratic misfit, the adjoint
+identity, and the gradient's agreement with the autograd path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ensure_built()
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from paper_2501_14911_amd import P2O, P2OOperator, misfit  # noqa: E402
+
+TOL = 2e-3
+DEV = "cuda"
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def gpu_blocks(w, c0, n, lag_batch=35):
+    out = torch.empty((w.Nt, w.Nd, n), dtype=torch.float64, device=DEV)
+    cols = torch.arange(c0, c0 + n, device=DEV)
+    for k0 in range(0, w.Nt, lag_batch):
+        ks = list(range(k0, min(w.Nt, k0 + lag_batch)))
+        out[k0:k0 + len(ks)] = synth.operator_rows_cols(w, ks, cols=cols, backend="torch", device=DEV)
+    return out
+
+
+def rows_of_blocks(w, rows):
+    return synth.operator_rows_cols(w, range(w.Nt), rows=np.asarray(rows), backend="torch").numpy()
+
+
+def cols_of_blocks(w, cols):
+    return synth.operator_rows_cols(w, range(w.Nt), cols=np.asarray(cols), backend="torch").numpy()
+
+
+@pytest.fixture(scope="module")
+def paper_time():
+    w = synth.CONFIGS["paper_time"]
+    note(f"[fullsize] loading {w.name}")
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=64, device=DEV)
+    op.load(lambda c0, n: gpu_blocks(w, c0, n))
+    yield w, op
+    op.close()
+    del op
+    torch.cuda.empty_cache()
+
+
+def test_paper_time_single_rhs(paper_time):
+    w, op = paper_time
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(w.Nd, 6, replace=False))
+    cols = np.sort(rng.choice(w.Nm, 48, replace=False))
+    m = synth.param_series(w, 1)[0]
+    d = synth.data_series(w, 1)[0]
+    y = op.apply_F(torch.from_numpy(m).to(DEV, torch.float32)).double().cpu().numpy()
+    s = op.apply_Ft(torch.from_numpy(d).to(DEV, torch.float32)).double().cpu().numpy()
+    ey = oracle.rel_l2(y[:, rows], oracle.apply_F(rows_of_blocks(w, rows), m))
+    es = oracle.rel_l2(s[:, cols], oracle.apply_Ft(cols_of_blocks(w, cols), d))
+    note(f"  single: F rows {ey:.3e}, F* columns {es:.3e}")
+    assert ey <= TOL and es <= TOL
+
+
+def test_paper_time_hessian_columns_and_ragged(paper_time):
+    w, op = paper_time
+    idx = synth.hessian_column_indices(w, 64)
+    E = torch.from_numpy(synth.unit_data_vectors(w, idx)).to(DEV, torch.float32)
+    h = op.apply_FFt(E).double().cpu().numpy()
+    rows = np.sort(np.random.default_rng(12).choice(w.Nd, 4, replace=False))
+    worst = 0.0
+    for c in (0, 1, 17, 63):                         # includes t = 0 and t = Nt - 1
+        t0, sidx = divmod(int(idx[c]), w.Nd)
+        rs = np.unique(np.concatenate([rows, [sidx]]))
+        Frs = rows_of_blocks(w, rs)
+        e = np.zeros((w.Nt, len(rs)))
+        e[t0, np.searchsorted(rs, sidx)] = 1.0
+        href = oracle.apply_F(Frs, oracle.apply_Ft(Frs, e))
+        worst = max(worst, oracle.rel_l2(h[c][:, rs], href))
+    note(f"  64 F F* columns: worst sampled rel-L2 {worst:.3e}")
+    assert worst <= 2 * TOL                          # two quantised operators composed
+    # 32 ragged right-hand sides
+    n = synth.ragged_lengths(w, 32)
+    m = synth.param_series(w, 32, seed_offset=21)
+    y = op.apply_F(torch.from_numpy(m).to(DEV, torch.float32), nt_active=n).double().cpu().numpy()
+    Fr = rows_of_blocks(w, rows)
+    for b in range(0, 32, 7):
+        assert np.all(y[b, n[b]:] == 0.0)
+        yo = oracle.apply_F(Fr, m[b:b + 1], n[b:b + 1])[0]
+        assert oracle.rel_l2(y[b][:, rows], yo) <= TOL
+
+
+@pytest.fixture(scope="module")
+def largest():
+    w = synth.CONFIGS["largest"]
+    note(f"[fullsize] loading {w.name} (66 GB BF16 spectrum)")
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=16, device=DEV)
+    op.load(lambda c0, n: gpu_blocks(w, c0, n))
+    yield w, op
+    op.close()
+    del op
+    torch.cuda.empty_cache()
+
+
+def test_largest_single_and_16_rhs(largest):
+    w, op = largest
+    rng = np.random.default_rng(13)
+    rows = np.sort(rng.choice(w.Nd, 4, replace=False))
+    cols = np.sort(rng.choice(w.Nm, 32, replace=False))
+    m = synth.param_series(w, 16, backend="torch", smooth=True).numpy()
+    y = op.apply_F(torch.from_numpy(m).to(DEV, torch.float32)).double().cpu().numpy()      # 16 RHS, matrix cores
+    y1 = op.apply_F(torch.from_numpy(m[0]).to(DEV, torch.float32)).double().cpu().numpy()  # single RHS
+    Fr = rows_of_blocks(w, rows)
+    yo = oracle.apply_F(Fr, m[[0, 9]])
+    e16 = max(oracle.rel_l2(y[b][:, rows], yo[i]) for i, b in enumerate((0, 9)))
+    e1 = oracle.rel_l2(y1[:, rows], yo[0])
+    d = synth.data_series(w, 16)
+    s = op.apply_Ft(torch.from_numpy(d).to(DEV, torch.float32)).double().cpu().numpy()
+    so = oracle.apply_Ft(cols_of_blocks(w, cols), d[[3, 15]])
+    es = max(oracle.rel_l2(s[b][:, cols], so[i]) for i, b in enumerate((3, 15)))
+    note(f"  largest: F rows 16-RHS {e16:.3e}, single {e1:.3e}; F* columns {es:.3e}")
+    assert e16 <= TOL and e1 <= TOL and es <= TOL
+
+
+def test_largest_misfit_gradient_autograd(largest):
+    """d = F m_true + 0.01 eps; gradient via autograd at m = 0 and m_true:
+    central differences of the quadratic misfit, fused kernel == autograd,
+    and the adjoint identity."""
+    w, op = largest
+    m_true = synth.param_series(w, 1, backend="torch", device=DEV, smooth=True)[0].float()
+    with torch.no_grad():
+        d_obs = op.apply_F(m_true) + torch.from_numpy(synth.noise(w, 1)[0]).to(DEV, torch.float32)
+    sig2 = w.sigma ** 2
+    for m0 in (torch.zeros_like(m_true), m_true):
+        m = m0.clone().requires_grad_(True)
+        phi = misfit(m, op, d_obs, sig2)
+        phi.backward()
+        g = m.grad.double()
+        m2 = m0.clone().requires_grad_(True)
+        loss = 0.5 * ((P2O.apply(m2, op).double() - d_obs.double()) ** 2).sum() / sig2
+        loss.backward()
+        assert oracle.rel_l2(g.cpu().numpy(), m2.grad.double().cpu().numpy()) <= 1e-5
+        assert abs(float(phi.detach()) - float(loss.detach())) <= 1e-5 * float(loss.detach())
+        v = synth.param_series(w, 1, seed_offset=31, backend="torch", device=DEV)[0].float()
+        # exact for a quadratic at any step: take a large one so FP32 rounding
+        # of the misfit evaluations stays far below the difference
+        eps = float(m_true.norm()) / float(v.norm())
+        with torch.no_grad():
+            fp = float(misfit(m0 + eps * v, op, d_obs, sig2))
+            fm = float(misfit(m0 - eps * v, op, d_obs, sig2))
+        fd = (fp - fm) / (2 * eps)
+        gv = float((g * v.double()).sum())
+        note(f"  misfit {float(phi.detach()):.6e}: directional derivative {gv:.6e}, central difference {fd:.6e}")
+        assert abs(fd - gv) <= 1e-3 * abs(gv)
+    # at m_true the residual is the noise: misfit ~ chi-square / 2 with Nd*Nt dof
+    with torch.no_grad():
+        phi_true = float(misfit(m_true, op, d_obs, sig2))
+    dof = w.Nd * w.Nt
+    assert abs(phi_true - 0.5 * dof) <= 5 * np.sqrt(0.5 * dof)
+    # adjoint identity <F m, d> = <m, F* d> up to the BF16 spectrum rounding
+    with torch.no_grad():
+        lhs = float((op.apply_F(m_true).double() * d_obs.double()).sum())
+        rhs = float((m_true.double() * op.apply_Ft(d_obs).double()).sum())
+    assert abs(lhs - rhs) <= 2e-3 * abs(lhs)
