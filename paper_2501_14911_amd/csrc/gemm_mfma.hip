@@ -63,6 +63,14 @@ __device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) 
 
 __device__ __forceinline__ int xcd_item(int id, int Q) { return (id & 7) * Q + (id >> 3); }
 
+// Fragment slots in LDS.  A fragment for lane (K group g, column n) is a
+// 16-byte chunk; the chunk's bank quad is its slot mod 16.  Rotating the slot
+// by the K group (and K half) spreads the staging writes of one wavefront
+// over all 64 banks, while each 16-lane phase of the fragment reads still
+// touches 16 distinct quads.
+__device__ __forceinline__ int fwd_slot(int g, int n, int h) { return g * 16 + ((n + 4 * g + h) & 15); }
+__device__ __forceinline__ int adj_slot(int g, int n) { return g * 16 + ((n + (g & 1) + 8 * (g >> 1)) & 15); }
+
 // ---------------------------------------------------------------- forward
 template <int NB>
 __global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* __restrict__ fhat,
@@ -139,17 +147,19 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* __rest
             const int g = c >> 3, h = (c >> 2) & 1, cc = c & 3;
             const int nre = 2 * bl, nim = 2 * bl + 1;
             // real-part column: (x_r, -x_i); imaginary-part column: (x_i, x_r)
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][0][g * 16 + (nre & 15)])[cc] = rh | ((ih ^ 0x8000u) << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][1][g * 16 + (nre & 15)])[cc] = rl | ((il ^ 0x8000u) << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][0][g * 16 + (nim & 15)])[cc] = ih | (rh << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][1][g * 16 + (nim & 15)])[cc] = il | (rl << 16);
+            const int sre = fwd_slot(g, nre & 15, h), sim = fwd_slot(g, nim & 15, h);
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][0][sre])[cc] = rh | ((ih ^ 0x8000u) << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][1][sre])[cc] = rl | ((il ^ 0x8000u) << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][0][sim])[cc] = ih | (rh << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][1][sim])[cc] = il | (rl << 16);
         }
     };
     auto compute = [&](const Raw32 (&a)[MB], int buf) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const uint4 f0h = bs[buf][nb][0][0][lane], f0l = bs[buf][nb][0][1][lane];
-            const uint4 f1h = bs[buf][nb][1][0][lane], f1l = bs[buf][nb][1][1][lane];
+            const int s0 = fwd_slot(lg, lr, 0), s1 = fwd_slot(lg, lr, 1);
+            const uint4 f0h = bs[buf][nb][0][0][s0], f0l = bs[buf][nb][0][1][s0];
+            const uint4 f1h = bs[buf][nb][1][0][s1], f1l = bs[buf][nb][1][1][s1];
             // consecutive MFMAs use different accumulators (no dependent issue)
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].a, f0h, acc[mb][nb]);
@@ -283,10 +293,11 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __rest
             const int g = r >> 2, rho = r & 3;
             const int nre = 2 * bl, nim = 2 * bl + 1;
             // real-part column: (y_r, y_i); imaginary-part column: (y_i, -y_r)
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][0][g * 16 + (nre & 15)])[rho] = rh | (ih << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][1][g * 16 + (nre & 15)])[rho] = rl | (il << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][0][g * 16 + (nim & 15)])[rho] = ih | ((rh ^ 0x8000u) << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][1][g * 16 + (nim & 15)])[rho] = il | ((rl ^ 0x8000u) << 16);
+            const int sre = adj_slot(g, nre & 15), sim = adj_slot(g, nim & 15);
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][0][sre])[rho] = rh | (ih << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][1][sre])[rho] = rl | (il << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][0][sim])[rho] = ih | ((rh ^ 0x8000u) << 16);
+            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][1][sim])[rho] = il | ((rl ^ 0x8000u) << 16);
         }
     };
     auto compute = [&](int buf) {
@@ -298,7 +309,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __rest
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const uint4 fh = bs[buf][nb][0][lane], fl = bs[buf][nb][1][lane];
+            const int sl = adj_slot(lg, lr);
+            const uint4 fh = bs[buf][nb][0][sl], fl = bs[buf][nb][1][sl];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(afr[mb], fh, acc[mb][nb]);
 #pragma unroll
