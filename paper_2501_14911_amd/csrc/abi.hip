@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -162,10 +163,16 @@ void layout(p2o_plan* p) {
     const size_t R = (size_t)p->max_rhs;
     const size_t xparts = (size_t)(p->adj_nslab > 1 ? p->adj_nslab : 1);
     size_t yparts = (size_t)(p->fwd_chunks > 1 ? p->fwd_chunks : 1);
-    if (p->prec == kBF16 && (size_t)gemm_fwd_kchunks((int)p->pitch) > yparts) yparts = (size_t)gemm_fwd_kchunks((int)p->pitch);
+    size_t ylen = yparts * nfreq * R * (size_t)p->Nd;
+    if (p->prec == kBF16) {
+        // matrix-core path: forward partials per 4096-column chunk, and data
+        // spectra in quad storage with rows padded to a multiple of 8
+        ylen = std::max(ylen, (size_t)gemm_fwd_kchunks((int)p->pitch) * nfreq * R * (size_t)p->Nd);
+        ylen = std::max(ylen, nfreq * R * (size_t)gemm_data_pitch((int)p->Nd));
+    }
     p->off_X = 0;
     p->off_Y = align_up(p->off_X + xparts * nfreq * R * (size_t)p->pitch * p->cbytes);
-    p->off_D = align_up(p->off_Y + yparts * nfreq * R * (size_t)p->Nd * p->cbytes);
+    p->off_D = align_up(p->off_Y + ylen * p->cbytes);
     p->off_P = align_up(p->off_D + R * (size_t)p->Nt * (size_t)p->Nd * p->io_bytes);
     p->ws_total = align_up(p->off_P + R * (size_t)p->c2r_nd_blocks * sizeof(double));
 }
@@ -229,9 +236,12 @@ GemvArgs gemv_args(const p2o_plan* p, int64_t nrhs, bool fwd) {
 }
 
 // enqueue sequences ----------------------------------------------------------
-// Several right-hand sides with a BF16 spectrum go to the matrix cores.
+// Several right-hand sides with a BF16 spectrum go to the matrix cores.  Their
+// operands are written by the FFTs in quad storage, in place by the F F*
+// projection, whose tiles must then span whole groups of 4 series.
 bool mfma_on(const p2o_plan* p, int64_t nrhs) {
     if (p->prec != kBF16) return false;
+    if (fft_tile_shift(p->fft.M, false) < 2) return false;
     if (p->batched_mode == P2O_BATCHED_MFMA) return true;
     if (p->batched_mode == P2O_BATCHED_GEMV) return false;
     return nrhs >= 2;
@@ -276,11 +286,33 @@ p2o_status enqueue_adj_products(p2o_plan* p, const void* Y, void* X, int64_t nrh
     });
 }
 
+// parameter spectra for the products: quad storage on the matrix-core path
+SeriesIO io_param_rhs(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active, int nparts) {
+    SeriesIO io = io_param(p, nrhs, nt_active, nparts);
+    io.quad = mfma_on(p, nrhs) ? 1 : 0;
+    return io;
+}
+
+// data spectra for the adjoint products: on the matrix-core path in quad
+// storage, rows padded with zeros to gemm_data_pitch(Nd)
+SeriesIO io_data_rhs(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active) {
+    SeriesIO io = io_data(p, nrhs, nt_active, 1);
+    if (mfma_on(p, nrhs)) {
+        const int ld = gemm_data_pitch((int)p->Nd);
+        io.f_stride = nrhs * ld;
+        io.f_outer = ld;
+        io.f_part = p->nfreq * nrhs * ld;
+        io.S_pad = ld;
+        io.quad = 1;
+    }
+    return io;
+}
+
 p2o_status enqueue_forward_to_Y(p2o_plan* p, const void* m, int64_t nrhs, const int32_t* nt) {
     void* X = p->ws + p->off_X;
     void* Y = p->ws + p->off_Y;
     p2o_status s = staged(p, P2O_STAGE_R2C, "r2c (parameters)", [&] {
-        return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_param(p, nrhs, nt, 1), m, X, tw_of(p), p->stream);
+        return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_param_rhs(p, nrhs, nt, 1), m, X, tw_of(p), p->stream);
     });
     if (s) return s;
     return enqueue_fwd_products(p, X, Y, nrhs);
@@ -290,7 +322,7 @@ p2o_status enqueue_adjoint_to_X(p2o_plan* p, const void* d, int64_t nrhs, const 
     void* X = p->ws + p->off_X;
     void* Y = p->ws + p->off_Y;
     p2o_status s = staged(p, P2O_STAGE_R2C, "r2c (data)", [&] {
-        return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_data(p, nrhs, nt, 1), d, Y, tw_of(p), p->stream);
+        return launch_r2c(f64_plan(p), f64_plan(p), p->fft, io_data_rhs(p, nrhs, nt), d, Y, tw_of(p), p->stream);
     });
     if (s) return s;
     return enqueue_adj_products(p, Y, X, nrhs);
@@ -610,8 +642,8 @@ p2o_status p2o_apply_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, cons
         s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
         if (s) return s;
         s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
-            return launch_project(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, adj_parts(p, nrhs)), p->ws + p->off_X,
-                                  tw_of(p), p->stream);
+            return launch_project(f64_plan(p), p->fft, io_param_rhs(p, nrhs, nt_active, adj_parts(p, nrhs)),
+                                  p->ws + p->off_X, tw_of(p), p->stream);
         });
         if (s) return s;
         s = enqueue_fwd_products(p, p->ws + p->off_X, p->ws + p->off_Y, nrhs);

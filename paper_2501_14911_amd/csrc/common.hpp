@@ -111,6 +111,27 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
     return u >> 16;
 }
 
+// x = hi + lo with hi, lo BF16 (round to nearest even); the raw 16-bit codes.
+__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
+    hi = f32_to_bf16_rne(x);
+    lo = f32_to_bf16_rne(x - __uint_as_float(hi << 16));
+}
+
+// "Quad" storage of a complex FP32 series as BF16 hi/lo pairs, the operand
+// form of the matrix-core products: each group of 4 consecutive values takes
+// 32 bytes, first the 4 hi words then the 4 lo words, a word holding
+// (re, im) with re in the low half.  Same footprint as complex FP32; the
+// series must start at a multiple of 4 values.  Stores value c of the series
+// whose first word is q.
+__device__ __forceinline__ void store_quad(uint32_t* q, long long c, float re, float im) {
+    uint32_t rh, rl, ih, il;
+    split_bf16(re, rh, rl);
+    split_bf16(im, ih, il);
+    uint32_t* g = q + 8 * (c >> 2) + (c & 3);
+    g[0] = rh | (ih << 16);
+    g[4] = rl | (il << 16);
+}
+
 __device__ __forceinline__ uint32_t f32_to_f16_rne(float f) {
     _Float16 h = (_Float16)f;
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
@@ -136,6 +157,7 @@ struct SeriesIO {
     int nparts;              // partial sums to add when reading a spectrum
     int S;                   // live series per outer index
     int S_pad;               // series written in the frequency domain (zeros past S)
+    int quad;                // FP32 spectra written in quad BF16 hi/lo storage
     int Nt;                  // time steps
     int outer_count;
     const int* nt_active;    // per outer index, or nullptr

@@ -298,6 +298,28 @@ __device__ __forceinline__ void load_spec(cplx<T>* buf, int twsh, int M, const c
     }
 }
 
+// Half spectra of a transformed tile to row[k * f_stride + s0 + s], zeros for
+// series in [S, S_pad) (the tile holds zeros there), as complex values or,
+// with io.quad (FP32 only), in quad BF16 hi/lo storage.
+template <typename T>
+__device__ __forceinline__ void store_half_spectra(const cplx<T>* buf, int twsh, int M, const cplx<T>* tw,
+                                                   const SeriesIO& io, cplx<T>* row, int s0) {
+    using Z = cplx<T>;
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (io.quad) {
+            uint32_t* q = reinterpret_cast<uint32_t*>(row);
+            r2c_post<T>(buf, twsh, M, tw, [&](int k, int s, Z X) {
+                if (s0 + s < io.S_pad) store_quad(q + 2 * (long long)k * io.f_stride, s0 + s, X.x, X.y);
+            });
+            return;
+        }
+    }
+    Z* dst = row + s0;
+    r2c_post<T>(buf, twsh, M, tw, [&](int k, int s, Z X) {
+        if (s0 + s < io.S_pad) dst[(long long)k * io.f_stride + s] = X;
+    });
+}
+
 // ---------------------------------------------------------------- kernels
 // r2c: time series [outer][t][col] -> half spectra [outer][k][col] (cols >= S zero-filled up to S_pad)
 template <typename T, typename TIN>
@@ -316,10 +338,7 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c(FftPlan pl, SeriesIO io, co
     load_time<T, TIN>(buf, twsh, pl.M, in + (long long)outer * io.t_outer, io.t_stride, io.S, s0, nt);
     __syncthreads();
     fft_tile<T, false>(buf, twsh, pl, tw);
-    Z* dst = out + (long long)outer * io.f_outer + s0;
-    r2c_post<T>(buf, twsh, pl.M, tw, [&](int k, int s, Z X) {
-        if (s0 + s < io.S_pad) dst[(long long)k * io.f_stride + s] = X;
-    });
+    store_half_spectra<T>(buf, twsh, pl.M, tw, io, out + (long long)outer * io.f_outer, s0);
 }
 
 // c2r: half spectra (sum of nparts partials) -> time series, truncated to Nt
@@ -401,7 +420,8 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r(FftPlan pl, SeriesIO io, co
 // Truncate-and-repad between the adjoint and forward passes of F F^*:
 // half spectra (sum of partials) -> time series -> keep t < active length
 // -> half spectra again, written over partial 0 of the input (every
-// workgroup reads its whole tile before it writes).
+// workgroup reads its whole tile before it writes; in quad storage a tile
+// must span whole groups of 4 series).
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_project(FftPlan pl, SeriesIO io, cplx<T>* in_out,
                                                          const cplx<T>* __restrict__ twg, int twsh, ItemMap im) {
@@ -431,10 +451,7 @@ __global__ __launch_bounds__(kFftThreads) void k_project(FftPlan pl, SeriesIO io
     }
     __syncthreads();
     fft_tile<T, false>(buf, twsh, pl, tw);
-    Z* dst = base + s0;
-    r2c_post<T>(buf, twsh, pl.M, tw, [&](int k, int s, Z X) {
-        if (s0 + s < io.S_pad) dst[(long long)k * io.f_stride + s] = X;
-    });
+    store_half_spectra<T>(buf, twsh, pl.M, tw, io, base, s0);
 }
 
 // Fixed-order sum of the misfit partials: misfit[b] = 1/2 sum_x partials[b][x].

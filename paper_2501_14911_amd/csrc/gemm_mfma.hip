@@ -2,85 +2,127 @@
 // per launch): Y_w = Fhat_w X_w and X'_w = Fhat_w^H Y_w for a BF16 spectrum.
 //
 // With B right-hand sides the per-frequency matvecs of section 4 become one
-// complex GEMM per frequency.  Written over the reals with the spectrum in
-// its stored interleaved form (re, im, re, im, ... along the parameter
-// index), the forward product is a real GEMM of size Nd x 2Nm x 2B: each
-// complex right-hand side x contributes the two real columns
-// (x_r, -x_i, ...) and (x_i, x_r, ...), whose products with a row are the
-// real and imaginary parts of F x.  The adjoint contracts over sensors: with
-// K = (sensor, re/im) it is a real GEMM of size Nm x 2Nd x 2B whose two
-// columns per right-hand side are (y_r, y_i, ...) and (y_i, -y_r, ...).
+// complex GEMM per frequency, done with v_mfma_f32_32x32x16_bf16 (on gfx950
+// the 32x32 shape sustains about 1.5x the rate of the 16x16x32 one, and
+// does so with one wavefront per SIMD).  K runs over (index, re/im) pairs in
+// their stored interleaved order, so a complex product is two real ones
+// against forms of the spectrum fragment, each 32-bit word (re, im) being
+// rewritten by one or two VALU operations:
+//   forward  y_r = (a_r, -a_i) . (x_r, x_i)   y_i = (a_i, a_r) . (x_r, x_i)
+//   adjoint  x_r = (a_r,  a_i) . (y_r, y_i)   x_i = (-a_i, a_r) . (y_r, y_i)
+// (the adjoint takes conj(F)^T).  Right-hand sides arrive as quad BF16 hi/lo
+// storage (written by the FFT that produced them); hi and lo each go through
+// the matrix cores, giving about 16 significant bits of x with FP32
+// accumulation.  The per-(frequency, 4096-column block) power-of-two scale of
+// the stored spectrum multiplies finished outputs (exact).
 //
-// Operands.  The spectrum is BF16 and goes to v_mfma_f32_16x16x32_bf16
-// as is.  Right-hand sides are FP32 spectra; each value is split into a BF16
-// pair hi + lo (hi = RNE(x), lo = RNE(x - hi)), so two MFMAs per tile give
-// about 16 significant bits of the right-hand side while accumulating in
-// FP32.  The per-(frequency, 4096-column block) power-of-two scale of the
-// stored spectrum is folded into x (forward) or the finished columns
-// (adjoint); both are exact.
-//
-// Work.  Every spectrum byte is read once per launch.  Forward workgroups
-// own (frequency, 4096-column chunk, 320-row tile, right-hand-side group):
-// A fragments stream from HBM straight into registers (each lane loads 32
-// contiguous bytes of one row, covering two MFMA K steps), while the right-
-// hand sides of the chunk are staged through LDS, double buffered, already
-// in fragment order.  The chunk's partial products go to their own slot
-// (summed in fixed order by the inverse FFT).  Adjoint workgroups own
-// (frequency, 256-column tile): the spectrum tile of 16 sensors x 256
-// columns is loaded coalesced and transposed into LDS (rows padded to 20
-// words: conflict-free writes, 16-byte fragment reads).  Workgroup ids are
-// mapped so that consecutive ids on one XCD share the same frequency (and
-// forward column chunk): the right-hand-side spectra they all read stay in
-// that XCD's L2.
-//
-// Any permutation of K inside a lane's 8 values is harmless as long as A
-// and B use the same one; both sides below order a lane's values as
-// (re, im) pairs of consecutive complex entries.
+// Work.  A workgroup is 4 wavefronts, each owning 3 (or 5) blocks of 32
+// output rows (forward: sensors; adjoint: parameter columns) for 64 (or 32)
+// right-hand sides; the 4 share the right-hand sides of each K step through
+// LDS.  Spectrum fragments are loaded by each lane straight into registers
+// (no LDS), one pipeline step (4 K substeps of 8 complex entries) ahead of
+// the matrix cores; there is no cross-wave reuse of the spectrum to exploit,
+// and registers hold more bytes in flight than LDS could.  Forward lanes
+// load 16 bytes of a row per substep, so each row is read in 128-byte runs
+// per step; adjoint lanes gather 4 sensors of one column as 4-byte words
+// from 4 rows, each wavefront load covering 128 contiguous bytes of two rows.
+// Every spectrum byte is read once per launch.  Forward workgroups own
+// (frequency, 4096-column chunk, row tile, right-hand-side group) and write
+// the chunk's partial products to their own slot (summed in fixed order by
+// the inverse FFT); adjoint workgroups own (frequency, column tile,
+// right-hand-side group).  Workgroup ids are mapped so that consecutive ids
+// on one XCD share the frequency (and forward column chunk): the
+// right-hand-side spectra they all read stay in that XCD's L2.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace p2o {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kGemmThreads = 256;
-constexpr int kFwdMB = 5;          // 16-row blocks per wavefront (forward): 320 rows per workgroup
-constexpr int kAdjMB = 4;          // 16-column blocks per wavefront (adjoint): 256 columns per workgroup
-constexpr int kAdjAW = 20;         // LDS words per transposed column (16 sensors + 4 pad)
+constexpr int kU = 4;              // K substeps (8 complex entries, 16 real K) per pipeline step
 
-__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
-
-__device__ __forceinline__ f32x4 mfma(uint4 a, uint4 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+__device__ __forceinline__ f32x16 mfma32(uint4 a, uint4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                   c, 0, 0, 0);
 }
 
-// x = hi + lo with hi, lo BF16 (round to nearest even); returns the raw 16-bit codes.
-__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
-    hi = f32_to_bf16_rne(x);
-    lo = f32_to_bf16_rne(x - __uint_as_float(hi << 16));
+// forms of a fragment of (re, im) BF16 words
+__device__ __forceinline__ uint32_t w_swap(uint32_t w) { return __builtin_amdgcn_alignbit(w, w, 16); }
+__device__ __forceinline__ uint4 f_conj(uint4 a) {                       // (re, -im)
+    return make_uint4(a.x ^ 0x80000000u, a.y ^ 0x80000000u, a.z ^ 0x80000000u, a.w ^ 0x80000000u);
+}
+__device__ __forceinline__ uint4 f_swap(uint4 a) {                       // (im, re)
+    return make_uint4(w_swap(a.x), w_swap(a.y), w_swap(a.z), w_swap(a.w));
+}
+__device__ __forceinline__ uint4 f_jrot(uint4 a) {                       // (-im, re)
+    return make_uint4(w_swap(a.x) ^ 0x8000u, w_swap(a.y) ^ 0x8000u, w_swap(a.z) ^ 0x8000u, w_swap(a.w) ^ 0x8000u);
 }
 
 __device__ __forceinline__ int xcd_item(int id, int Q) { return (id & 7) * Q + (id >> 3); }
 
-// Fragment slots in LDS.  A fragment for lane (K group g, column n) is a
-// 16-byte chunk; the chunk's bank quad is its slot mod 16.  Rotating the slot
-// by the K group (and K half) spreads the staging writes of one wavefront
-// over all 64 banks, while each 16-lane phase of the fragment reads still
-// touches 16 distinct quads.
-__device__ __forceinline__ int fwd_slot(int g, int n, int h) { return g * 16 + ((n + 4 * g + h) & 15); }
-__device__ __forceinline__ int adj_slot(int g, int n) { return g * 16 + ((n + (g & 1) + 8 * (g >> 1)) & 15); }
+// Workgroup barrier that waits for this wavefront's LDS operations but not
+// for its loads in flight (__syncthreads would also drain the spectrum
+// prefetch).  The empty asm statements keep the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0); vmcnt, expcnt not waited on
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Right-hand sides of one pipeline step: 8 groups of 4 consecutive K entries
+// (columns or sensors) for 32 NB right-hand sides, loaded cooperatively and
+// stored in LDS as B fragments [substep][n block][hi/lo][lane] (16 bytes per
+// lane: lane n + 32 g holds the 4 entries of group 2 substep + g of
+// right-hand side n).  Groups at or past glim are zero; right-hand sides past
+// the last valid one repeat it (their outputs are never stored).
+template <int NB>
+struct RhsStage {
+    static constexpr int PAIRS = 32 * NB * 2 * kU;
+    static constexpr int PT = PAIRS / kGemmThreads;
+    static_assert(PT * kGemmThreads == PAIRS, "pairs per thread");
+    uint4 h[PT], l[PT];
+    uint32_t m[PT];           // all ones for groups below glim, else zero (applied when stored)
+
+    __device__ __forceinline__ void load(const uint8_t* rows, long long ld_bytes, int nb_valid, int g0, int glim,
+                                         int tid) {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int p = tid + i * kGemmThreads;
+            const int g = p & (2 * kU - 1), bl = min(p >> 3, nb_valid - 1);
+            const int gi = g0 + g;
+            const bool ok = gi < glim;
+            const uint4* src = reinterpret_cast<const uint4*>(rows + bl * ld_bytes + (long long)(ok ? gi : 0) * 32);
+            h[i] = src[0];
+            l[i] = src[1];
+            m[i] = ok ? 0xffffffffu : 0u;
+        }
+    }
+    __device__ __forceinline__ void store(uint4 (*bf)[NB][2][64], int tid) const {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int p = tid + i * kGemmThreads;
+            const int g = p & (2 * kU - 1), bl = p >> 3;
+            const int lane = (bl & 31) + 32 * (g & 1);
+            const uint32_t k = m[i];
+            bf[g >> 1][bl >> 5][0][lane] = make_uint4(h[i].x & k, h[i].y & k, h[i].z & k, h[i].w & k);
+            bf[g >> 1][bl >> 5][1][lane] = make_uint4(l[i].x & k, l[i].y & k, l[i].z & k, l[i].w & k);
+        }
+    }
+};
 
 // ---------------------------------------------------------------- forward
-template <int NB>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* __restrict__ fhat,
+// Yp[kc][w][b][row] = scale * sum over the chunk's columns j of F[w][row][j] x_b[w][j]
+template <int MB, int NB>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* fhat,
                                                            const float* __restrict__ scales,
-                                                           const float2* __restrict__ X,
+                                                           const uint8_t* Xq,
                                                            float2* __restrict__ Yp, GemmArgs ga) {
-    constexpr int MB = kFwdMB;
-    constexpr int RB = 8 * NB;                 // right-hand sides per group (16 real columns per block)
-    constexpr int ROWS = 4 * MB * 16;
-    __shared__ uint4 bs[2][NB][2][2][64];      // [buffer][n block][K half][hi/lo][lane]
+    __shared__ __align__(16) uint4 bfr[2][kU][NB][2][64];
 
     const int q = xcd_item(blockIdx.x, ga.Q);
     if (q >= ga.items) return;
@@ -90,138 +132,130 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* __rest
     const int kc = t % ga.n_kc; t /= ga.n_kc;
     const int w = t;
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lr = lane & 15, lg = lane >> 4;
-    const int b0 = bg * RB;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int r = lane & 31, kg = lane >> 5;
+    const int b0 = bg * 32 * NB;
+    const int nb_valid = min(32 * NB, ga.nrhs - b0);
     const int jbeg = kc * ga.kchunk;
     const int jend = min(ga.pitch, jbeg + ga.kchunk);
-    const int nsteps = (jend - jbeg + 31) >> 5;
-    const float sc = scales[(long long)w * ga.nblk + jbeg / kScaleBlock];
+    const int nst = (jend - jbeg + 8 * kU - 1) / (8 * kU);
+    const int row0 = (mt * 4 + wave) * 32 * MB;
 
-    const int rowbase = mt * ROWS + wave * MB * 16;
+    // lane (r, kg) of m block mb reads row row0 + 32 mb + r, columns 4 kg ..
+    // 4 kg + 3 of each substep.  Rows past Nd repeat the last one (their
+    // outputs are not stored); the wavefronts of a workgroup move in step, so
+    // computing them costs no time.
     const uint8_t* arow[MB];
-    bool rok[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-        const int row = rowbase + mb * 16 + lr;
-        rok[mb] = row < ga.Nd;
-        arow[mb] = fhat + (((long long)w * ga.Nd + (rok[mb] ? row : 0)) * ga.pitch + jbeg + 8 * lg) * 4;
+        const int row = min(row0 + 32 * mb + r, ga.Nd - 1);
+        arow[mb] = fhat + (((long long)w * ga.Nd + row) * ga.pitch + 4 * kg) * 4;
     }
-    auto load_a = [&](Raw32 (&a)[MB], int s) {
-        const int j = jbeg + 32 * s + 8 * lg;
+    auto load_a = [&](uint4 (&a)[MB][kU], int st) {
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            if (rok[mb] && j < jend) a[mb] = load32(arow[mb] + (long long)s * 128);
-            else a[mb] = Raw32{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+        for (int u = 0; u < kU; ++u) {
+            int j = jbeg + st * 8 * kU + 8 * u;
+            if (j >= jend) j = jbeg;                 // past the chunk: B is zero there
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) a[mb][u] = *reinterpret_cast<const uint4*>(arow[mb] + (long long)j * 4);
         }
     };
+    const uint8_t* xrows = Xq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
+    const long long ldb_bytes = (long long)ga.ldb * 8;
+    auto load_b = [&](RhsStage<NB>& rs, int st) {
+        rs.load(xrows, ldb_bytes, nb_valid, (jbeg + st * 8 * kU) / 4, jend / 4, tid);
+    };
 
-    f32x4 acc[MB][NB];
+    f32x16 accr[MB][NB], acci[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < NB; ++nb) accr[mb][nb] = acci[mb][nb] = f32x16{};
 
-    // right-hand-side values a thread stages per step (32 columns x RB)
-    constexpr int XPT = (32 * RB + kGemmThreads - 1) / kGemmThreads;
-    const float2* Xw = X + (long long)w * ga.nrhs * ga.pitch;
-    auto load_x = [&](float2 (&xv)[XPT], int s) {
+    auto compute = [&](const uint4 (&a)[MB][kU], int buf) {
 #pragma unroll
-        for (int u = 0; u < XPT; ++u) {
-            const int e = tid + u * kGemmThreads;
-            const int c = e & 31, bl = e >> 5;
-            const int b = b0 + bl, j = jbeg + 32 * s + c;
-            xv[u] = (e < 32 * RB && b < ga.nrhs && j < jend) ? Xw[(long long)b * ga.pitch + j] : make_float2(0.f, 0.f);
-        }
-    };
-    // BF16 hi/lo fragments in [n block][K half][hi/lo][lane] order
-    auto stage_x = [&](const float2 (&xv)[XPT], int buf) {
+        for (int u = 0; u < kU; ++u) {
+            __builtin_amdgcn_sched_barrier(0);
+            uint4 bh[NB], bl[NB];
 #pragma unroll
-        for (int u = 0; u < XPT; ++u) {
-            const int e = tid + u * kGemmThreads;
-            if (e >= 32 * RB) break;
-            const int c = e & 31, bl = e >> 5;
-            uint32_t rh, rl, ih, il;
-            split_bf16(xv[u].x * sc, rh, rl);
-            split_bf16(xv[u].y * sc, ih, il);
-            const int g = c >> 3, h = (c >> 2) & 1, cc = c & 3;
-            const int nre = 2 * bl, nim = 2 * bl + 1;
-            // real-part column: (x_r, -x_i); imaginary-part column: (x_i, x_r)
-            const int sre = fwd_slot(g, nre & 15, h), sim = fwd_slot(g, nim & 15, h);
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][0][sre])[cc] = rh | ((ih ^ 0x8000u) << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][h][1][sre])[cc] = rl | ((il ^ 0x8000u) << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][0][sim])[cc] = ih | (rh << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][h][1][sim])[cc] = il | (rl << 16);
-        }
-    };
-    auto compute = [&](const Raw32 (&a)[MB], int buf) {
+            for (int nb = 0; nb < NB; ++nb) {
+                bh[nb] = bfr[buf][u][nb][0][lane];
+                bl[nb] = bfr[buf][u][nb][1][lane];
+            }
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int s0 = fwd_slot(lg, lr, 0), s1 = fwd_slot(lg, lr, 1);
-            const uint4 f0h = bs[buf][nb][0][0][s0], f0l = bs[buf][nb][0][1][s0];
-            const uint4 f1h = bs[buf][nb][1][0][s1], f1l = bs[buf][nb][1][1][s1];
-            // consecutive MFMAs use different accumulators (no dependent issue)
+            for (int mb = 0; mb < MB; ++mb) {
+                const uint4 a1 = f_conj(a[mb][u]), a2 = f_swap(a[mb][u]);
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].a, f0h, acc[mb][nb]);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].a, f0l, acc[mb][nb]);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].b, f1h, acc[mb][nb]);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(a[mb].b, f1l, acc[mb][nb]);
+                for (int nb = 0; nb < NB; ++nb) {
+                    accr[mb][nb] = mfma32(a1, bh[nb], accr[mb][nb]);
+                    acci[mb][nb] = mfma32(a2, bh[nb], acci[mb][nb]);
+                    accr[mb][nb] = mfma32(a1, bl[nb], accr[mb][nb]);
+                    acci[mb][nb] = mfma32(a2, bl[nb], acci[mb][nb]);
+                }
+            }
         }
     };
 
-    // two register sets: loads for step s + 2 are in flight while step s computes
-    Raw32 a0[MB], a1[MB];
-    float2 x0[XPT], x1[XPT];
+// Step st of the pipeline (both directions): stage B(st+1), loaded one step
+    // earlier, into the LDS buffer step st-1 read; load B(st+2); prefetch
+    // A(st+2) into the buffer step st-1 used; compute step st; barrier.
+    // Loads retire in order and B(st+1) was issued before A(st+1), so waiting
+    // for it leaves A(st+1) and A(st+2) in flight: every A prefetch has two
+    // compute phases to arrive.  Prefetches past the last step repeat it (A)
+    // or read zeros (B) and are never used; the step has no branches.
+    uint4 a0[MB][kU], a1[MB][kU], a2[MB][kU];
+    RhsStage<NB> rs;
+    auto step = [&](const uint4 (&cur)[MB][kU], uint4 (&pre)[MB][kU], int st) {
+        rs.store(bfr[(st + 1) & 1], tid);
+        load_b(rs, st + 2);
+        load_a(pre, min(st + 2, nst - 1));
+        compute(cur, st & 1);
+        lds_barrier();
+    };
+    load_b(rs, 0);
     load_a(a0, 0);
-    load_x(x0, 0);
-    if (nsteps > 1) { load_a(a1, 1); load_x(x1, 1); }
-    for (int s = 0; s < nsteps; s += 2) {
-        stage_x(x0, 0);
-        if (s + 2 < nsteps) load_x(x0, s + 2);
-        __syncthreads();
-        compute(a0, 0);
-        if (s + 2 < nsteps) load_a(a0, s + 2);
-        if (s + 1 < nsteps) {
-            stage_x(x1, 1);
-            if (s + 3 < nsteps) load_x(x1, s + 3);
-            __syncthreads();
-            compute(a1, 1);
-            if (s + 3 < nsteps) load_a(a1, s + 3);
-        }
+    rs.store(bfr[0], tid);
+    load_b(rs, 1);
+    load_a(a1, min(1, nst - 1));
+    lds_barrier();
+    int st = 0;
+    for (; st + 3 <= nst; st += 3) {
+        step(a0, a2, st);
+        step(a1, a0, st + 1);
+        step(a2, a1, st + 2);
     }
+    if (st < nst) step(a0, a2, st);
+    if (st + 1 < nst) step(a1, a0, st + 1);
 
-    // partial sums of this column chunk: Yp[kc][w][b][row], row-block lanes hold rows 4 lg + r
-    float* out = reinterpret_cast<float*>(Yp + (long long)kc * ga.part_stride + (long long)w * ga.nrhs * ga.Nd);
+    // output tile (32 rows x 32 right-hand sides): lane (n, h) holds rows
+    // 8 (v / 4) + 4 h + v % 4 of column n in element v
+    const float sc = scales[(long long)w * ga.nblk + jbeg / kScaleBlock];
+    float2* out = Yp + (long long)kc * ga.part_stride + (long long)w * ga.nrhs * ga.Nd;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        const int ncol = nb * 16 + lr;
-        const int b = b0 + (ncol >> 1), comp = ncol & 1;
+        const int b = b0 + 32 * nb + r;
         if (b >= ga.nrhs) continue;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rowbase + mb * 16 + 4 * lg + r;
-                if (row < ga.Nd) out[2 * ((long long)b * ga.Nd + row) + comp] = acc[mb][nb][r];
+            for (int v = 0; v < 16; ++v) {
+                const int row = row0 + 32 * mb + 8 * (v >> 2) + 4 * kg + (v & 3);
+                if (row < ga.Nd)
+                    out[(long long)b * ga.Nd + row] = make_float2(accr[mb][nb][v] * sc, acci[mb][nb][v] * sc);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------- adjoint
-template <int NB>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __restrict__ fhat,
+// Xp[w][b][j] = scale_j * sum over sensors i of conj(F[w][i][j]) y_b[w][i]
+template <int MB, int NB>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* fhat,
                                                            const float* __restrict__ scales,
-                                                           const float2* __restrict__ Y,
+                                                           const uint8_t* Yq,
                                                            float2* __restrict__ Xp, GemmArgs ga) {
-    constexpr int MB = kAdjMB;
-    constexpr int RB = 8 * NB;
-    constexpr int COLS = 4 * MB * 16;
-    __shared__ uint32_t as[2][COLS * kAdjAW];  // [buffer][column][sensor + pad]
-    __shared__ uint4 bs[2][NB][2][64];         // [buffer][n block][hi/lo][lane]
+    __shared__ __align__(16) uint4 bfr[2][kU][NB][2][64];
 
     const int q = xcd_item(blockIdx.x, ga.Q);
     if (q >= ga.items) return;
@@ -230,177 +264,166 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* __rest
     const int bg = t % ga.n_bg; t /= ga.n_bg;
     const int w = t;
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lr = lane & 15, lg = lane >> 4;
-    const int b0 = bg * RB;
-    const int j0 = jt * COLS;
-    const int nsteps = (ga.Nd + 15) >> 4;
-    const uint8_t* Fw = fhat + (long long)w * ga.Nd * ga.pitch * 4;
-    const float2* Yw = Y + (long long)w * ga.nrhs * ga.Nd;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int c = lane & 31, kg = lane >> 5;
+    const int b0 = bg * 32 * NB;
+    const int nb_valid = min(32 * NB, ga.nrhs - b0);
+    const int col0 = (jt * 4 + wave) * 32 * MB;
+    const int nst = (ga.ldb + 8 * kU - 1) / (8 * kU);
 
-    f32x4 acc[MB][NB];
+    // lane (c, kg) of m block mb reads column col0 + 32 mb + c, sensors
+    // 4 kg .. 4 kg + 3 of each substep (rows past Nd repeat the last one:
+    // their B entries are zero; columns past the pitch repeat the last one
+    // and are not stored)
+    const uint32_t* Fw = reinterpret_cast<const uint32_t*>(fhat) + (long long)w * ga.Nd * ga.pitch;
+    int jcol[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) jcol[mb] = min(col0 + 32 * mb + c, ga.pitch - 1);
+    auto load_a = [&](uint4 (&a)[MB][kU], int st) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i0 = st * 8 * kU + 8 * u + 4 * kg;
+            const uint32_t* r0 = Fw + (long long)min(i0, ga.Nd - 1) * ga.pitch;
+            const uint32_t* r1 = Fw + (long long)min(i0 + 1, ga.Nd - 1) * ga.pitch;
+            const uint32_t* r2 = Fw + (long long)min(i0 + 2, ga.Nd - 1) * ga.pitch;
+            const uint32_t* r3 = Fw + (long long)min(i0 + 3, ga.Nd - 1) * ga.pitch;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) a[mb][u] = make_uint4(r0[jcol[mb]], r1[jcol[mb]], r2[jcol[mb]], r3[jcol[mb]]);
+        }
+    };
+    const uint8_t* yrows = Yq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
+    const long long ldb_bytes = (long long)ga.ldb * 8;
+    auto load_b = [&](RhsStage<NB>& rs, int st) {
+        rs.load(yrows, ldb_bytes, nb_valid, st * 2 * kU, ga.ldb / 4, tid);
+    };
+
+    f32x16 accr[MB][NB], acci[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < NB; ++nb) accr[mb][nb] = acci[mb][nb] = f32x16{};
 
-    // per-thread share of one step: spectrum tile (16 x COLS/4 chunks of 16 B)
-    // and right-hand sides (16 x RB values)
-    constexpr int APT = (16 * (COLS / 4) + kGemmThreads - 1) / kGemmThreads;
-    constexpr int BPT = (16 * RB + kGemmThreads - 1) / kGemmThreads;
-    auto load_ab = [&](uint4 (&av)[APT], float2 (&bv)[BPT], int s) {
-        const int i0 = 16 * s;
+    auto compute = [&](const uint4 (&a)[MB][kU], int buf) {
 #pragma unroll
-        for (int u = 0; u < APT; ++u) {
-            const int e = tid + u * kGemmThreads;
-            const int r = e & 15, ch = e >> 4;
-            const int i = i0 + r, j = j0 + 4 * ch;
-            av[u] = make_uint4(0, 0, 0, 0);
-            if (e < 16 * (COLS / 4) && i < ga.Nd && j < ga.pitch) {
-                const u32x4 raw = __builtin_nontemporal_load(
-                    reinterpret_cast<const u32x4*>(Fw + ((long long)i * ga.pitch + j) * 4));
-                av[u] = make_uint4(raw.x, raw.y, raw.z, raw.w);
+        for (int u = 0; u < kU; ++u) {
+            __builtin_amdgcn_sched_barrier(0);
+            uint4 bh[NB], bl[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                bh[nb] = bfr[buf][u][nb][0][lane];
+                bl[nb] = bfr[buf][u][nb][1][lane];
+            }
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const uint4 a1 = a[mb][u], a2 = f_jrot(a[mb][u]);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    accr[mb][nb] = mfma32(a1, bh[nb], accr[mb][nb]);
+                    acci[mb][nb] = mfma32(a2, bh[nb], acci[mb][nb]);
+                    accr[mb][nb] = mfma32(a1, bl[nb], accr[mb][nb]);
+                    acci[mb][nb] = mfma32(a2, bl[nb], acci[mb][nb]);
+                }
             }
         }
-#pragma unroll
-        for (int u = 0; u < BPT; ++u) {
-            const int e = tid + u * kGemmThreads;
-            const int r = e & 15, bl = e >> 4;
-            const int b = b0 + bl, i = i0 + r;
-            bv[u] = (e < 16 * RB && b < ga.nrhs && i < ga.Nd) ? Yw[(long long)b * ga.Nd + i] : make_float2(0.f, 0.f);
-        }
     };
-    auto stage_ab = [&](const uint4 (&av)[APT], const float2 (&bv)[BPT], int buf) {
-#pragma unroll
-        for (int u = 0; u < APT; ++u) {
-            const int e = tid + u * kGemmThreads;
-            if (e >= 16 * (COLS / 4)) break;
-            const int r = e & 15, ch = e >> 4;
-            uint32_t* dst = &as[buf][(4 * ch) * kAdjAW + r];     // transposed to [column][sensor]
-            dst[0] = av[u].x;
-            dst[kAdjAW] = av[u].y;
-            dst[2 * kAdjAW] = av[u].z;
-            dst[3 * kAdjAW] = av[u].w;
-        }
-#pragma unroll
-        for (int u = 0; u < BPT; ++u) {
-            const int e = tid + u * kGemmThreads;
-            if (e >= 16 * RB) break;
-            const int r = e & 15, bl = e >> 4;
-            uint32_t rh, rl, ih, il;
-            split_bf16(bv[u].x, rh, rl);
-            split_bf16(bv[u].y, ih, il);
-            const int g = r >> 2, rho = r & 3;
-            const int nre = 2 * bl, nim = 2 * bl + 1;
-            // real-part column: (y_r, y_i); imaginary-part column: (y_i, -y_r)
-            const int sre = adj_slot(g, nre & 15), sim = adj_slot(g, nim & 15);
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][0][sre])[rho] = rh | (ih << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nre >> 4][1][sre])[rho] = rl | (il << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][0][sim])[rho] = ih | ((rh ^ 0x8000u) << 16);
-            reinterpret_cast<uint32_t*>(&bs[buf][nim >> 4][1][sim])[rho] = il | ((rl ^ 0x8000u) << 16);
-        }
+
+// Step st of the pipeline (both directions): stage B(st+1), loaded one step
+    // earlier, into the LDS buffer step st-1 read; load B(st+2); prefetch
+    // A(st+2) into the buffer step st-1 used; compute step st; barrier.
+    // Loads retire in order and B(st+1) was issued before A(st+1), so waiting
+    // for it leaves A(st+1) and A(st+2) in flight: every A prefetch has two
+    // compute phases to arrive.  Prefetches past the last step repeat it (A)
+    // or read zeros (B) and are never used; the step has no branches.
+    uint4 a0[MB][kU], a1[MB][kU], a2[MB][kU];
+    RhsStage<NB> rs;
+    auto step = [&](const uint4 (&cur)[MB][kU], uint4 (&pre)[MB][kU], int st) {
+        rs.store(bfr[(st + 1) & 1], tid);
+        load_b(rs, st + 2);
+        load_a(pre, min(st + 2, nst - 1));
+        compute(cur, st & 1);
+        lds_barrier();
     };
-    auto compute = [&](int buf) {
-        uint4 afr[MB];
+    load_b(rs, 0);
+    load_a(a0, 0);
+    rs.store(bfr[0], tid);
+    load_b(rs, 1);
+    load_a(a1, min(1, nst - 1));
+    lds_barrier();
+    int st = 0;
+    for (; st + 3 <= nst; st += 3) {
+        step(a0, a2, st);
+        step(a1, a0, st + 1);
+        step(a2, a1, st + 2);
+    }
+    if (st < nst) step(a0, a2, st);
+    if (st + 1 < nst) step(a1, a0, st + 1);
+
+    // output tile (32 columns x 32 right-hand sides); an m block lies in one
+    // 4096-column scale block
+    float2* out = Xp + (long long)w * ga.nrhs * ga.pitch;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int col = wave * MB * 16 + mb * 16 + lr;
-            afr[mb] = *reinterpret_cast<const uint4*>(&as[buf][col * kAdjAW + 4 * lg]);
-        }
+    for (int mb = 0; mb < MB; ++mb) {
+        const int jb = col0 + 32 * mb;
+        if (jb >= ga.pitch) continue;
+        const float sc = scales[(long long)w * ga.nblk + jb / kScaleBlock];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const int sl = adj_slot(lg, lr);
-            const uint4 fh = bs[buf][nb][0][sl], fl = bs[buf][nb][1][sl];
+            const int b = b0 + 32 * nb + c;
+            if (b >= ga.nrhs) continue;
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(afr[mb], fh, acc[mb][nb]);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma(afr[mb], fl, acc[mb][nb]);
-        }
-    };
-
-    // two register sets: loads for step s + 2 are in flight while step s computes
-    uint4 av0[APT], av1[APT];
-    float2 bv0[BPT], bv1[BPT];
-    load_ab(av0, bv0, 0);
-    if (nsteps > 1) load_ab(av1, bv1, 1);
-    for (int s = 0; s < nsteps; s += 2) {
-        stage_ab(av0, bv0, 0);
-        if (s + 2 < nsteps) load_ab(av0, bv0, s + 2);
-        __syncthreads();
-        compute(0);
-        if (s + 1 < nsteps) {
-            stage_ab(av1, bv1, 1);
-            if (s + 3 < nsteps) load_ab(av1, bv1, s + 3);
-            __syncthreads();
-            compute(1);
-        }
-    }
-
-    const float sc = scales[(long long)w * ga.nblk + j0 / kScaleBlock];
-    float* out = reinterpret_cast<float*>(Xp + (long long)w * ga.nrhs * ga.pitch);
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int ncol = nb * 16 + lr;
-        const int b = b0 + (ncol >> 1), comp = ncol & 1;
-        if (b >= ga.nrhs) continue;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = j0 + wave * MB * 16 + mb * 16 + 4 * lg + r;
-                if (j < ga.pitch) out[2 * ((long long)b * ga.pitch + j) + comp] = acc[mb][nb][r] * sc;
+            for (int v = 0; v < 16; ++v) {
+                const int j = jb + 8 * (v >> 2) + 4 * kg + (v & 3);
+                if (j < ga.pitch)
+                    out[(long long)b * ga.pitch + j] = make_float2(accr[mb][nb][v] * sc, acci[mb][nb][v] * sc);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------- host launchers
-static int gemm_nb(int nrhs) { return nrhs > 32 ? 8 : nrhs > 16 ? 4 : nrhs > 8 ? 2 : 1; }
-
 int gemm_fwd_kchunks(int pitch) { return (pitch + kScaleBlock - 1) / kScaleBlock; }
 
-hipError_t launch_gemm_fwd(const GemmArgs& in, const void* fhat, const float* scales, const void* X, void* Yp,
+int gemm_data_pitch(int Nd) { return (Nd + 7) / 8 * 8; }
+
+hipError_t launch_gemm_fwd(const GemmArgs& in, const void* fhat, const float* scales, const void* Xq, void* Yp,
                            hipStream_t st) {
     GemmArgs ga = in;
-    const int NB = gemm_nb(ga.nrhs);
+    const bool wide = ga.nrhs > 32;
+    const int MB = wide ? 3 : 5, NB = wide ? 2 : 1;
+    ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.pitch);
-    ga.n_mt = (ga.Nd + 4 * kFwdMB * 16 - 1) / (4 * kFwdMB * 16);
-    ga.n_bg = (ga.nrhs + 8 * NB - 1) / (8 * NB);
+    ga.n_mt = (ga.Nd + 4 * 32 * MB - 1) / (4 * 32 * MB);
+    ga.n_bg = (ga.nrhs + 32 * NB - 1) / (32 * NB);
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
     dim3 grid(8 * ga.Q);
     const uint8_t* F = (const uint8_t*)fhat;
-    const float2* x = (const float2*)X;
+    const uint8_t* x = (const uint8_t*)Xq;
     float2* y = (float2*)Yp;
-    switch (NB) {
-        case 8: hipLaunchKernelGGL((k_gemm_fwd<8>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
-        case 4: hipLaunchKernelGGL((k_gemm_fwd<4>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
-        case 2: hipLaunchKernelGGL((k_gemm_fwd<2>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
-        default: hipLaunchKernelGGL((k_gemm_fwd<1>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga); break;
-    }
+    if (wide) hipLaunchKernelGGL((k_gemm_fwd<3, 2>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga);
+    else hipLaunchKernelGGL((k_gemm_fwd<5, 1>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga);
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_adj(const GemmArgs& in, const void* fhat, const float* scales, const void* Y, void* Xp,
+hipError_t launch_gemm_adj(const GemmArgs& in, const void* fhat, const float* scales, const void* Yq, void* Xp,
                            hipStream_t st) {
     GemmArgs ga = in;
-    const int NB = gemm_nb(ga.nrhs);
-    ga.n_mt = (ga.pitch + 4 * kAdjMB * 16 - 1) / (4 * kAdjMB * 16);
+    const bool wide = ga.nrhs > 32;
+    const int MB = wide ? 3 : 5, NB = wide ? 2 : 1;
+    ga.ldb = gemm_data_pitch(ga.Nd);
+    ga.n_mt = (ga.pitch + 4 * 32 * MB - 1) / (4 * 32 * MB);
     ga.n_kc = 1;
-    ga.n_bg = (ga.nrhs + 8 * NB - 1) / (8 * NB);
+    ga.n_bg = (ga.nrhs + 32 * NB - 1) / (32 * NB);
     ga.items = ga.nfreq * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
     dim3 grid(8 * ga.Q);
     const uint8_t* F = (const uint8_t*)fhat;
-    const float2* y = (const float2*)Y;
+    const uint8_t* y = (const uint8_t*)Yq;
     float2* x = (float2*)Xp;
-    switch (NB) {
-        case 8: hipLaunchKernelGGL((k_gemm_adj<8>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
-        case 4: hipLaunchKernelGGL((k_gemm_adj<4>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
-        case 2: hipLaunchKernelGGL((k_gemm_adj<2>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
-        default: hipLaunchKernelGGL((k_gemm_adj<1>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga); break;
-    }
+    if (wide) hipLaunchKernelGGL((k_gemm_adj<3, 2>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga);
+    else hipLaunchKernelGGL((k_gemm_adj<5, 1>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga);
     return hipGetLastError();
 }
 

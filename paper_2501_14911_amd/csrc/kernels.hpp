@@ -25,6 +25,7 @@ struct GemmArgs {
     int nblk;
     long long part_stride;  // complex elements between forward partial outputs
     // filled in by the launcher
+    int ldb;                // complex values per right-hand-side row of the quad B operand
     int kchunk;             // complex columns per forward K chunk
     int n_kc, n_mt, n_bg;   // K chunks, row (or column) tiles, right-hand-side groups
     int items, Q;           // work items and items per XCD
@@ -73,6 +74,7 @@ hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int 
 
 // gemm_mfma.hip
 int gemm_fwd_kchunks(int pitch);
+int gemm_data_pitch(int Nd);   // row length of data-side quad spectra read by the adjoint (Nd rounded up to 8)
 hipError_t launch_gemm_fwd(const GemmArgs& ga, const void* fhat, const float* scales, const void* X, void* Yp,
                            hipStream_t st);
 hipError_t launch_gemm_adj(const GemmArgs& ga, const void* fhat, const float* scales, const void* Y, void* Xp,
