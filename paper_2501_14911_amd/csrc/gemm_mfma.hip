@@ -16,16 +16,17 @@
 // accumulation.  The per-(frequency, 4096-column block) power-of-two scale of
 // the stored spectrum multiplies finished outputs (exact).
 //
-// Work.  A workgroup is 4 wavefronts, each owning 3 (or 5) blocks of 32
-// output rows (forward: sensors; adjoint: parameter columns) for 64 (or 32)
-// right-hand sides; the 4 share the right-hand sides of each K step through
-// LDS.  Spectrum fragments are loaded by each lane straight into registers
-// (no LDS), one pipeline step (4 K substeps of 8 complex entries) ahead of
-// the matrix cores; there is no cross-wave reuse of the spectrum to exploit,
-// and registers hold more bytes in flight than LDS could.  Forward lanes
-// load 16 bytes of a row per substep, so each row is read in 128-byte runs
-// per step; adjoint lanes gather 4 sensors of one column as 4-byte words
-// from 4 rows, each wavefront load covering 128 contiguous bytes of two rows.
+// Work.  A workgroup is 4 wavefronts: RG row groups x (4 / RG) halves of the
+// right-hand sides, each wavefront computing 5 blocks of 32 output rows
+// (forward: sensors; adjoint: parameter columns) for 32 right-hand sides.
+// Each K step (KU substeps of 8 complex entries) the workgroup stages its
+// spectrum tile and right-hand-side tile in LDS, loaded cooperatively with
+// whole 128-byte lines per 8 lanes: forward rows in runs of 32 (or 16)
+// columns, adjoint sensor rows of 320 (or 640) contiguous columns.  Loads
+// run two steps ahead through registers into a double buffer, and one
+// barrier per step separates staging from the matrix-core work.  Fragments
+// come from padded LDS rows without bank conflicts: forward lanes read 16
+// bytes of a row, adjoint lanes gather 4 sensors of a column as 4-byte words.
 // Every spectrum byte is read once per launch.  Forward workgroups own
 // (frequency, 4096-column chunk, row tile, right-hand-side group) and write
 // the chunk's partial products to their own slot (summed in fixed order by
@@ -40,9 +41,10 @@ namespace p2o {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));   // native vector: staged copies stay in registers
 
 constexpr int kGemmThreads = 256;
-constexpr int kU = 4;              // K substeps (8 complex entries, 16 real K) per pipeline step
+constexpr int kGemmMB = 5;                 // 32-row blocks per wavefront
 
 __device__ __forceinline__ f32x16 mfma32(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
@@ -64,9 +66,8 @@ __device__ __forceinline__ uint4 f_jrot(uint4 a) {                       // (-im
 __device__ __forceinline__ int xcd_item(int id, int Q) { return (id & 7) * Q + (id >> 3); }
 
 // Workgroup barrier that waits for this wavefront's LDS operations but not
-// for its loads in flight (__syncthreads would also drain the spectrum
-// prefetch).  The empty asm statements keep the compiler from moving memory
-// accesses across it.
+// for its loads in flight (__syncthreads would also drain the prefetch).  The
+// empty asm statements keep the compiler from moving memory accesses across.
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0); vmcnt, expcnt not waited on
@@ -74,55 +75,49 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("" ::: "memory");
 }
 
-// Right-hand sides of one pipeline step: 8 groups of 4 consecutive K entries
-// (columns or sensors) for 32 NB right-hand sides, loaded cooperatively and
-// stored in LDS as B fragments [substep][n block][hi/lo][lane] (16 bytes per
-// lane: lane n + 32 g holds the 4 entries of group 2 substep + g of
-// right-hand side n).  Groups at or past glim are zero; right-hand sides past
-// the last valid one repeat it (their outputs are never stored).
-template <int NB>
-struct RhsStage {
-    static constexpr int PAIRS = 32 * NB * 2 * kU;
-    static constexpr int PT = PAIRS / kGemmThreads;
-    static_assert(PT * kGemmThreads == PAIRS, "pairs per thread");
-    uint4 h[PT], l[PT];
-    uint32_t m[PT];           // all ones for groups below glim, else zero (applied when stored)
-
-    __device__ __forceinline__ void load(const uint8_t* rows, long long ld_bytes, int nb_valid, int g0, int glim,
-                                         int tid) {
-#pragma unroll
-        for (int i = 0; i < PT; ++i) {
-            const int p = tid + i * kGemmThreads;
-            const int g = p & (2 * kU - 1), bl = min(p >> 3, nb_valid - 1);
-            const int gi = g0 + g;
-            const bool ok = gi < glim;
-            const uint4* src = reinterpret_cast<const uint4*>(rows + bl * ld_bytes + (long long)(ok ? gi : 0) * 32);
-            h[i] = src[0];
-            l[i] = src[1];
-            m[i] = ok ? 0xffffffffu : 0u;
-        }
-    }
-    __device__ __forceinline__ void store(uint4 (*bf)[NB][2][64], int tid) const {
-#pragma unroll
-        for (int i = 0; i < PT; ++i) {
-            const int p = tid + i * kGemmThreads;
-            const int g = p & (2 * kU - 1), bl = p >> 3;
-            const int lane = (bl & 31) + 32 * (g & 1);
-            const uint32_t k = m[i];
-            bf[g >> 1][bl >> 5][0][lane] = make_uint4(h[i].x & k, h[i].y & k, h[i].z & k, h[i].w & k);
-            bf[g >> 1][bl >> 5][1][lane] = make_uint4(l[i].x & k, l[i].y & k, l[i].z & k, l[i].w & k);
-        }
-    }
+// Tile geometry.  FWD: the A tile is MROWS rows x KC columns, row stride
+// A_RS bytes (16 bytes of padding: the 16-byte fragment reads of 16
+// consecutive rows hit distinct banks).  ADJ: KC sensor rows x MROWS columns,
+// row stride A_RS with 4 A_RS / 4 = 32 (mod 64) banks, so the two sensor
+// quartets a fragment read covers fall in different bank halves.
+template <bool FWD, int RG, int KU>
+struct Tile {
+    static constexpr int NH = 4 / RG;                  // right-hand-side halves of 32
+    static constexpr int MROWS = RG * 32 * kGemmMB;    // output rows per workgroup
+    static constexpr int KC = 8 * KU;                  // complex K entries per step
+    static constexpr int RHS = 32 * NH;
+    static constexpr int A_RS = FWD ? KC * 4 + 16 : MROWS * 4 + 32;
+    static constexpr int A_BYTES = FWD ? MROWS * A_RS : KC * A_RS;
+    static constexpr int A_CPR = FWD ? KC / 4 : MROWS / 4;   // 16-byte chunks per stored row
+    static constexpr int A_PT = MROWS * KC / 4 / kGemmThreads;
+    static constexpr int B_PT = RHS * KC / 2 / kGemmThreads;  // 16-byte hi or lo chunks
+    static_assert(A_PT * kGemmThreads * 4 == MROWS * KC, "A chunks per thread");
+    static_assert(B_PT * kGemmThreads * 2 == RHS * KC, "B chunks per thread");
 };
 
-// ---------------------------------------------------------------- forward
-// Yp[kc][w][b][row] = scale * sum over the chunk's columns j of F[w][row][j] x_b[w][j]
-template <int MB, int NB>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* fhat,
-                                                           const float* __restrict__ scales,
-                                                           const uint8_t* Xq,
-                                                           float2* __restrict__ Yp, GemmArgs ga) {
-    __shared__ __align__(16) uint4 bfr[2][kU][NB][2][64];
+// LDS slot of lane L's B fragment in plane (substep u, hi/lo hl): the low 4
+// bits are rotated by 4 u + 2 hl + L / 32, so that the 16 chunks one
+// right-hand side contributes per step (8 groups x hi/lo) land in 16
+// different bank groups when stored, while the 64 lanes of a fragment read
+// still cover one contiguous kilobyte.
+__device__ __forceinline__ int b_slot(int L, int u, int hl) { return (L & 48) | ((L + 4 * u + 2 * hl + (L >> 5)) & 15); }
+
+// Registers of one staged step (A and B chunks, B validity masks).
+template <int AP, int BP>
+struct Staged {
+    v4u a[AP];
+    v4u b[BP];
+    uint32_t m[BP];
+};
+
+template <bool FWD, int RG, int KU>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm(const uint8_t* fhat, const float* __restrict__ scales,
+                                                       const uint8_t* Bq, float2* __restrict__ out_base,
+                                                       GemmArgs ga) {
+    using T = Tile<FWD, RG, KU>;
+    constexpr int MB = kGemmMB;
+    __shared__ __align__(16) uint8_t as[2][T::A_BYTES];
+    __shared__ __align__(16) v4u bfr[2][KU][T::NH][2][64];
 
     const int q = xcd_item(blockIdx.x, ga.Q);
     if (q >= ga.items) return;
@@ -134,248 +129,159 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm_fwd(const uint8_t* fhat,
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rg = wave % RG, nh = wave / RG;
     const int r = lane & 31, kg = lane >> 5;
-    const int b0 = bg * 32 * NB;
-    const int nb_valid = min(32 * NB, ga.nrhs - b0);
-    const int jbeg = kc * ga.kchunk;
-    const int jend = min(ga.pitch, jbeg + ga.kchunk);
-    const int nst = (jend - jbeg + 8 * kU - 1) / (8 * kU);
-    const int row0 = (mt * 4 + wave) * 32 * MB;
+    const int b0 = bg * T::RHS;
+    const int nb_valid = min(T::RHS, ga.nrhs - b0);
+    const int m0 = mt * T::MROWS;                      // first output row (sensor or column) of the tile
+    // K range: forward columns [kbeg, kend) of the chunk, adjoint sensors [0, ldb)
+    const int kbeg = FWD ? kc * ga.kchunk : 0;
+    const int kend = FWD ? min(ga.pitch, kbeg + ga.kchunk) : ga.ldb;
+    const int nst = (kend - kbeg + T::KC - 1) / T::KC;
+    const uint32_t* Fw = reinterpret_cast<const uint32_t*>(fhat) + (long long)w * ga.Nd * ga.pitch;
+    const uint8_t* brows = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
+    const long long ldb_bytes = (long long)ga.ldb * 8;
 
-    // lane (r, kg) of m block mb reads row row0 + 32 mb + r, columns 4 kg ..
-    // 4 kg + 3 of each substep.  Rows past Nd repeat the last one (their
-    // outputs are not stored); the wavefronts of a workgroup move in step, so
-    // computing them costs no time.
-    const uint8_t* arow[MB];
+    using S = Staged<T::A_PT, T::B_PT>;
+    // Loads of step st.  A: chunk c covers 4 consecutive entries of a stored
+    // row (forward: sensor row m0 + c / A_CPR, columns from 4 (c % A_CPR);
+    // adjoint: sensor row c / A_CPR, columns m0 + 4 (c % A_CPR)); rows past
+    // Nd and columns past the chunk or the pitch read a valid address (their
+    // B entries are zero or their outputs are not stored).  B: chunk c is the
+    // hi (even c) or lo half of the 4-entry group g of right-hand side bl.
+    auto load = [&](S& sg, int st) {
+        const int sa = min(st, nst - 1);
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const int row = min(row0 + 32 * mb + r, ga.Nd - 1);
-        arow[mb] = fhat + (((long long)w * ga.Nd + row) * ga.pitch + 4 * kg) * 4;
-    }
-    auto load_a = [&](uint4 (&a)[MB][kU], int st) {
+        for (int i = 0; i < T::A_PT; ++i) {
+            const int c = tid + i * kGemmThreads;
+            const int row = c / T::A_CPR, cc = c % T::A_CPR;
+            long long off;
+            if constexpr (FWD) {
+                const int sr = min(m0 + row, ga.Nd - 1);
+                int j = kbeg + sa * T::KC + 4 * cc;
+                if (j >= kend) j = kbeg;
+                off = (long long)sr * ga.pitch + j;
+            } else {
+                const int sr = min(sa * T::KC + row, ga.Nd - 1);
+                const int j = min(m0 + 4 * cc, ga.pitch - 4);
+                off = (long long)sr * ga.pitch + j;
+            }
+            sg.a[i] = *reinterpret_cast<const v4u*>(Fw + off);
+        }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            int j = jbeg + st * 8 * kU + 8 * u;
-            if (j >= jend) j = jbeg;                 // past the chunk: B is zero there
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) a[mb][u] = *reinterpret_cast<const uint4*>(arow[mb] + (long long)j * 4);
+        for (int i = 0; i < T::B_PT; ++i) {
+            const int c = tid + i * kGemmThreads;
+            const int p = c >> 1, hl = c & 1;
+            const int g = p % (T::KC / 4), bl = min(p / (T::KC / 4), nb_valid - 1);
+            const int gi = (kbeg + st * T::KC) / 4 + g;
+            const bool ok = gi < kend / 4;
+            sg.b[i] = *reinterpret_cast<const v4u*>(brows + bl * ldb_bytes + (long long)(ok ? gi : 0) * 32 + hl * 16);
+            sg.m[i] = ok ? 0xffffffffu : 0u;
         }
     };
-    const uint8_t* xrows = Xq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
-    const long long ldb_bytes = (long long)ga.ldb * 8;
-    auto load_b = [&](RhsStage<NB>& rs, int st) {
-        rs.load(xrows, ldb_bytes, nb_valid, (jbeg + st * 8 * kU) / 4, jend / 4, tid);
+    auto store = [&](const S& sg, int buf) {
+#pragma unroll
+        for (int i = 0; i < T::A_PT; ++i) {
+            const int c = tid + i * kGemmThreads;
+            const int row = c / T::A_CPR, cc = c % T::A_CPR;
+            *reinterpret_cast<v4u*>(&as[buf][row * T::A_RS + cc * 16]) = sg.a[i];
+        }
+#pragma unroll
+        for (int i = 0; i < T::B_PT; ++i) {
+            const int c = tid + i * kGemmThreads;
+            const int p = c >> 1, hl = c & 1;
+            const int g = p % (T::KC / 4), bl = p / (T::KC / 4);
+            bfr[buf][g >> 1][bl >> 5][hl][b_slot((bl & 31) + 32 * (g & 1), g >> 1, hl)] = sg.b[i] & sg.m[i];
+        }
     };
 
-    f32x16 accr[MB][NB], acci[MB][NB];
+    f32x16 accr[MB], acci[MB];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) accr[mb][nb] = acci[mb][nb] = f32x16{};
+    for (int mb = 0; mb < MB; ++mb) accr[mb] = acci[mb] = f32x16{};
 
-    auto compute = [&](const uint4 (&a)[MB][kU], int buf) {
+    // A fragment of block mb, substep u: forward lane (r, kg) holds row r,
+    // entries 4 kg .. 4 kg + 3 of the substep; adjoint lane (r, kg) holds
+    // sensors 4 kg .. 4 kg + 3 of the substep for column r.
+    auto frag = [&](int buf, int mb, int u) -> uint4 {
+        const int mrow = (rg * MB + mb) * 32 + r;
+        if constexpr (FWD) {
+            const v4u v = *reinterpret_cast<const v4u*>(&as[buf][mrow * T::A_RS + (2 * u + kg) * 16]);
+            return make_uint4(v.x, v.y, v.z, v.w);
+        } else {
+            const uint8_t* p = &as[buf][(8 * u + 4 * kg) * T::A_RS + mrow * 4];
+            return make_uint4(*reinterpret_cast<const uint32_t*>(p),
+                              *reinterpret_cast<const uint32_t*>(p + T::A_RS),
+                              *reinterpret_cast<const uint32_t*>(p + 2 * T::A_RS),
+                              *reinterpret_cast<const uint32_t*>(p + 3 * T::A_RS));
+        }
+    };
+    auto compute = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            __builtin_amdgcn_sched_barrier(0);
-            uint4 bh[NB], bl[NB];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                bh[nb] = bfr[buf][u][nb][0][lane];
-                bl[nb] = bfr[buf][u][nb][1][lane];
-            }
+        for (int u = 0; u < KU; ++u) {
+            const v4u vh = bfr[buf][u][nh][0][b_slot(lane, u, 0)], vl = bfr[buf][u][nh][1][b_slot(lane, u, 1)];
+            const uint4 bh = make_uint4(vh.x, vh.y, vh.z, vh.w), bl = make_uint4(vl.x, vl.y, vl.z, vl.w);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
-                const uint4 a1 = f_conj(a[mb][u]), a2 = f_swap(a[mb][u]);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    accr[mb][nb] = mfma32(a1, bh[nb], accr[mb][nb]);
-                    acci[mb][nb] = mfma32(a2, bh[nb], acci[mb][nb]);
-                    accr[mb][nb] = mfma32(a1, bl[nb], accr[mb][nb]);
-                    acci[mb][nb] = mfma32(a2, bl[nb], acci[mb][nb]);
-                }
+                const uint4 a = frag(buf, mb, u);
+                const uint4 a1 = FWD ? f_conj(a) : a;
+                const uint4 a2 = FWD ? f_swap(a) : f_jrot(a);
+                accr[mb] = mfma32(a1, bh, accr[mb]);
+                acci[mb] = mfma32(a2, bh, acci[mb]);
+                accr[mb] = mfma32(a1, bl, accr[mb]);
+                acci[mb] = mfma32(a2, bl, acci[mb]);
             }
         }
     };
 
-// Step st of the pipeline (both directions): stage B(st+1), loaded one step
-    // earlier, into the LDS buffer step st-1 read; load B(st+2); prefetch
-    // A(st+2) into the buffer step st-1 used; compute step st; barrier.
-    // Loads retire in order and B(st+1) was issued before A(st+1), so waiting
-    // for it leaves A(st+1) and A(st+2) in flight: every A prefetch has two
-    // compute phases to arrive.  Prefetches past the last step repeat it (A)
-    // or read zeros (B) and are never used; the step has no branches.
-    uint4 a0[MB][kU], a1[MB][kU], a2[MB][kU];
-    RhsStage<NB> rs;
-    auto step = [&](const uint4 (&cur)[MB][kU], uint4 (&pre)[MB][kU], int st) {
-        rs.store(bfr[(st + 1) & 1], tid);
-        load_b(rs, st + 2);
-        load_a(pre, min(st + 2, nst - 1));
-        compute(cur, st & 1);
+    // Step st: store step st+1 (loaded two steps earlier) into the LDS
+    // buffer step st-1 read; load step st+3 into the freed registers; compute
+    // step st; barrier.  Loads retire in order and step st+1 was issued
+    // before step st+2, so waiting for it leaves two steps in flight.  Loads
+    // past the last step repeat it (A) or read zeros (B) and are never used.
+    auto step = [&](S& sn, int buf, int st) {
+        store(sn, buf ^ 1);
+        load(sn, st + 3);
+        compute(buf);
         lds_barrier();
     };
-    load_b(rs, 0);
-    load_a(a0, 0);
-    rs.store(bfr[0], tid);
-    load_b(rs, 1);
-    load_a(a1, min(1, nst - 1));
+    S s0, s1;
+    load(s0, 0);
+    load(s1, 1);
+    store(s0, 0);
+    load(s0, 2);
     lds_barrier();
     int st = 0;
-    for (; st + 3 <= nst; st += 3) {
-        step(a0, a2, st);
-        step(a1, a0, st + 1);
-        step(a2, a1, st + 2);
+    for (; st + 2 <= nst; st += 2) {
+        step(s1, 0, st);
+        step(s0, 1, st + 1);
     }
-    if (st < nst) step(a0, a2, st);
-    if (st + 1 < nst) step(a1, a0, st + 1);
+    if (st < nst) step(s1, 0, st);
 
     // output tile (32 rows x 32 right-hand sides): lane (n, h) holds rows
     // 8 (v / 4) + 4 h + v % 4 of column n in element v
-    const float sc = scales[(long long)w * ga.nblk + jbeg / kScaleBlock];
-    float2* out = Yp + (long long)kc * ga.part_stride + (long long)w * ga.nrhs * ga.Nd;
+    const int b = b0 + 32 * nh + r;
+    if (b >= ga.nrhs) return;
+    if constexpr (FWD) {
+        const float sc = scales[(long long)w * ga.nblk + kbeg / kScaleBlock];
+        float2* out = out_base + (long long)kc * ga.part_stride + ((long long)w * ga.nrhs + b) * ga.Nd;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int b = b0 + 32 * nb + r;
-        if (b >= ga.nrhs) continue;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int row = row0 + 32 * mb + 8 * (v >> 2) + 4 * kg + (v & 3);
-                if (row < ga.Nd)
-                    out[(long long)b * ga.Nd + row] = make_float2(accr[mb][nb][v] * sc, acci[mb][nb][v] * sc);
+                const int row = m0 + (rg * MB + mb) * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
+                if (row < ga.Nd) out[row] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
             }
-        }
-    }
-}
-
-// ---------------------------------------------------------------- adjoint
-// Xp[w][b][j] = scale_j * sum over sensors i of conj(F[w][i][j]) y_b[w][i]
-template <int MB, int NB>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm_adj(const uint8_t* fhat,
-                                                           const float* __restrict__ scales,
-                                                           const uint8_t* Yq,
-                                                           float2* __restrict__ Xp, GemmArgs ga) {
-    __shared__ __align__(16) uint4 bfr[2][kU][NB][2][64];
-
-    const int q = xcd_item(blockIdx.x, ga.Q);
-    if (q >= ga.items) return;
-    int t = q;
-    const int jt = t % ga.n_mt; t /= ga.n_mt;
-    const int bg = t % ga.n_bg; t /= ga.n_bg;
-    const int w = t;
-
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int c = lane & 31, kg = lane >> 5;
-    const int b0 = bg * 32 * NB;
-    const int nb_valid = min(32 * NB, ga.nrhs - b0);
-    const int col0 = (jt * 4 + wave) * 32 * MB;
-    const int nst = (ga.ldb + 8 * kU - 1) / (8 * kU);
-
-    // lane (c, kg) of m block mb reads column col0 + 32 mb + c, sensors
-    // 4 kg .. 4 kg + 3 of each substep (rows past Nd repeat the last one:
-    // their B entries are zero; columns past the pitch repeat the last one
-    // and are not stored)
-    const uint32_t* Fw = reinterpret_cast<const uint32_t*>(fhat) + (long long)w * ga.Nd * ga.pitch;
-    int jcol[MB];
+    } else {
+        float2* out = out_base + ((long long)w * ga.nrhs + b) * ga.pitch;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) jcol[mb] = min(col0 + 32 * mb + c, ga.pitch - 1);
-    auto load_a = [&](uint4 (&a)[MB][kU], int st) {
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i0 = st * 8 * kU + 8 * u + 4 * kg;
-            const uint32_t* r0 = Fw + (long long)min(i0, ga.Nd - 1) * ga.pitch;
-            const uint32_t* r1 = Fw + (long long)min(i0 + 1, ga.Nd - 1) * ga.pitch;
-            const uint32_t* r2 = Fw + (long long)min(i0 + 2, ga.Nd - 1) * ga.pitch;
-            const uint32_t* r3 = Fw + (long long)min(i0 + 3, ga.Nd - 1) * ga.pitch;
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) a[mb][u] = make_uint4(r0[jcol[mb]], r1[jcol[mb]], r2[jcol[mb]], r3[jcol[mb]]);
-        }
-    };
-    const uint8_t* yrows = Yq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
-    const long long ldb_bytes = (long long)ga.ldb * 8;
-    auto load_b = [&](RhsStage<NB>& rs, int st) {
-        rs.load(yrows, ldb_bytes, nb_valid, st * 2 * kU, ga.ldb / 4, tid);
-    };
-
-    f32x16 accr[MB][NB], acci[MB][NB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) accr[mb][nb] = acci[mb][nb] = f32x16{};
-
-    auto compute = [&](const uint4 (&a)[MB][kU], int buf) {
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            __builtin_amdgcn_sched_barrier(0);
-            uint4 bh[NB], bl[NB];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                bh[nb] = bfr[buf][u][nb][0][lane];
-                bl[nb] = bfr[buf][u][nb][1][lane];
-            }
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const uint4 a1 = a[mb][u], a2 = f_jrot(a[mb][u]);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    accr[mb][nb] = mfma32(a1, bh[nb], accr[mb][nb]);
-                    acci[mb][nb] = mfma32(a2, bh[nb], acci[mb][nb]);
-                    accr[mb][nb] = mfma32(a1, bl[nb], accr[mb][nb]);
-                    acci[mb][nb] = mfma32(a2, bl[nb], acci[mb][nb]);
-                }
-            }
-        }
-    };
-
-// Step st of the pipeline (both directions): stage B(st+1), loaded one step
-    // earlier, into the LDS buffer step st-1 read; load B(st+2); prefetch
-    // A(st+2) into the buffer step st-1 used; compute step st; barrier.
-    // Loads retire in order and B(st+1) was issued before A(st+1), so waiting
-    // for it leaves A(st+1) and A(st+2) in flight: every A prefetch has two
-    // compute phases to arrive.  Prefetches past the last step repeat it (A)
-    // or read zeros (B) and are never used; the step has no branches.
-    uint4 a0[MB][kU], a1[MB][kU], a2[MB][kU];
-    RhsStage<NB> rs;
-    auto step = [&](const uint4 (&cur)[MB][kU], uint4 (&pre)[MB][kU], int st) {
-        rs.store(bfr[(st + 1) & 1], tid);
-        load_b(rs, st + 2);
-        load_a(pre, min(st + 2, nst - 1));
-        compute(cur, st & 1);
-        lds_barrier();
-    };
-    load_b(rs, 0);
-    load_a(a0, 0);
-    rs.store(bfr[0], tid);
-    load_b(rs, 1);
-    load_a(a1, min(1, nst - 1));
-    lds_barrier();
-    int st = 0;
-    for (; st + 3 <= nst; st += 3) {
-        step(a0, a2, st);
-        step(a1, a0, st + 1);
-        step(a2, a1, st + 2);
-    }
-    if (st < nst) step(a0, a2, st);
-    if (st + 1 < nst) step(a1, a0, st + 1);
-
-    // output tile (32 columns x 32 right-hand sides); an m block lies in one
-    // 4096-column scale block
-    float2* out = Xp + (long long)w * ga.nrhs * ga.pitch;
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const int jb = col0 + 32 * mb;
-        if (jb >= ga.pitch) continue;
-        const float sc = scales[(long long)w * ga.nblk + jb / kScaleBlock];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int b = b0 + 32 * nb + c;
-            if (b >= ga.nrhs) continue;
+        for (int mb = 0; mb < MB; ++mb) {
+            const int jb = m0 + (rg * MB + mb) * 32;        // an m block lies in one 4096-column scale block
+            if (jb >= ga.pitch) continue;
+            const float sc = scales[(long long)w * ga.nblk + jb / kScaleBlock];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int j = jb + 8 * (v >> 2) + 4 * kg + (v & 3);
-                if (j < ga.pitch)
-                    out[(long long)b * ga.pitch + j] = make_float2(accr[mb][nb][v] * sc, acci[mb][nb][v] * sc);
+                if (j < ga.pitch) out[j] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
             }
         }
     }
@@ -386,45 +292,39 @@ int gemm_fwd_kchunks(int pitch) { return (pitch + kScaleBlock - 1) / kScaleBlock
 
 int gemm_data_pitch(int Nd) { return (Nd + 7) / 8 * 8; }
 
+template <bool FWD, int RG, int KU>
+static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
+                              hipStream_t st) {
+    using T = Tile<FWD, RG, KU>;
+    ga.n_mt = ((FWD ? ga.Nd : ga.pitch) + T::MROWS - 1) / T::MROWS;
+    ga.n_bg = (ga.nrhs + T::RHS - 1) / T::RHS;
+    ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
+    ga.Q = (ga.items + 7) / 8;
+    hipLaunchKernelGGL((k_gemm<FWD, RG, KU>), dim3(8 * ga.Q), dim3(kGemmThreads), 0, st, (const uint8_t*)fhat,
+                       scales, (const uint8_t*)Bq, (float2*)out, ga);
+    return hipGetLastError();
+}
+
+// 33 or more right-hand sides: 2 row groups x 2 halves of 64, 4 substeps per
+// step; up to 32: 4 row groups x 32, 2 substeps per step.
 hipError_t launch_gemm_fwd(const GemmArgs& in, const void* fhat, const float* scales, const void* Xq, void* Yp,
                            hipStream_t st) {
     GemmArgs ga = in;
-    const bool wide = ga.nrhs > 32;
-    const int MB = wide ? 3 : 5, NB = wide ? 2 : 1;
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.pitch);
-    ga.n_mt = (ga.Nd + 4 * 32 * MB - 1) / (4 * 32 * MB);
-    ga.n_bg = (ga.nrhs + 32 * NB - 1) / (32 * NB);
-    ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
-    ga.Q = (ga.items + 7) / 8;
-    dim3 grid(8 * ga.Q);
-    const uint8_t* F = (const uint8_t*)fhat;
-    const uint8_t* x = (const uint8_t*)Xq;
-    float2* y = (float2*)Yp;
-    if (wide) hipLaunchKernelGGL((k_gemm_fwd<3, 2>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga);
-    else hipLaunchKernelGGL((k_gemm_fwd<5, 1>), grid, dim3(kGemmThreads), 0, st, F, scales, x, y, ga);
-    return hipGetLastError();
+    return ga.nrhs > 32 ? launch_tile<true, 2, 4>(ga, fhat, scales, Xq, Yp, st)
+                        : launch_tile<true, 4, 2>(ga, fhat, scales, Xq, Yp, st);
 }
 
 hipError_t launch_gemm_adj(const GemmArgs& in, const void* fhat, const float* scales, const void* Yq, void* Xp,
                            hipStream_t st) {
     GemmArgs ga = in;
-    const bool wide = ga.nrhs > 32;
-    const int MB = wide ? 3 : 5, NB = wide ? 2 : 1;
     ga.ldb = gemm_data_pitch(ga.Nd);
-    ga.n_mt = (ga.pitch + 4 * 32 * MB - 1) / (4 * 32 * MB);
+    ga.kchunk = 0;
     ga.n_kc = 1;
-    ga.n_bg = (ga.nrhs + 32 * NB - 1) / (32 * NB);
-    ga.items = ga.nfreq * ga.n_bg * ga.n_mt;
-    ga.Q = (ga.items + 7) / 8;
-    dim3 grid(8 * ga.Q);
-    const uint8_t* F = (const uint8_t*)fhat;
-    const uint8_t* y = (const uint8_t*)Yq;
-    float2* x = (float2*)Xp;
-    if (wide) hipLaunchKernelGGL((k_gemm_adj<3, 2>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga);
-    else hipLaunchKernelGGL((k_gemm_adj<5, 1>), grid, dim3(kGemmThreads), 0, st, F, scales, y, x, ga);
-    return hipGetLastError();
+    return ga.nrhs > 32 ? launch_tile<false, 2, 4>(ga, fhat, scales, Yq, Xp, st)
+                        : launch_tile<false, 4, 2>(ga, fhat, scales, Yq, Xp, st);
 }
 
 }  // namespace p2o
