@@ -37,8 +37,23 @@ template <> struct FftCap<double> { static constexpr int cap = 1792; };
 __device__ __forceinline__ int tix(int n, int s, int twsh) { return n * ((1 << twsh) + 1) + s; }
 
 // ---------------------------------------------------------------- butterflies
+// cos(2 pi m / R) and sin(2 pi m / R), m = 1 .. (R - 1) / 2, for the odd
+// prime radices (to 21 significant digits).
+template <typename T, int R>
+__device__ __forceinline__ constexpr T prime_cos(int m) {
+    if constexpr (R == 3) return T(-0.5);
+    if constexpr (R == 5) return m == 1 ? T(0.309016994374947424102) : T(-0.809016994374947424102);
+    return m == 1 ? T(0.623489801858733530525) : m == 2 ? T(-0.222520933956314404289) : T(-0.900968867902419126236);
+}
+template <typename T, int R>
+__device__ __forceinline__ constexpr T prime_sin(int m) {
+    if constexpr (R == 3) return T(0.866025403784438646764);
+    if constexpr (R == 5) return m == 1 ? T(0.951056516295153572116) : T(0.587785252292473129169);
+    return m == 1 ? T(0.781831482468029808708) : m == 2 ? T(0.974927912181823607018) : T(0.433883739117558120476);
+}
+
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void dft_small(cplx<T>* a, const cplx<T>* w) {
+__device__ __forceinline__ void dft_small(cplx<T>* a) {
     using Z = cplx<T>;
     if constexpr (R == 2) {
         Z t = a[0];
@@ -59,8 +74,8 @@ __device__ __forceinline__ void dft_small(cplx<T>* a, const cplx<T>* w) {
     } else if constexpr (R == 8) {
         Z e[4] = {a[0], a[2], a[4], a[6]};
         Z o[4] = {a[1], a[3], a[5], a[7]};
-        dft_small<T, 4, INV>(e, w);
-        dft_small<T, 4, INV>(o, w);
+        dft_small<T, 4, INV>(e);
+        dft_small<T, 4, INV>(o);
         const T c = T(0.70710678118654752440084436210485);   // sqrt(2)/2
         Z o1, o2, o3;
         if constexpr (!INV) {   // e^{-i pi p / 4} o_p
@@ -77,17 +92,42 @@ __device__ __forceinline__ void dft_small(cplx<T>* a, const cplx<T>* w) {
         a[2] = cadd(e[2], o2);   a[6] = csub(e[2], o2);
         a[3] = cadd(e[3], o3);   a[7] = csub(e[3], o3);
     } else {
-        // odd prime radix: direct DFT with the R-th roots w[m] = e^{-+2 pi i m / R}
-        Z out[R];
+        // odd prime radix.  With s_q = a_q + a_{R-q}, d_q = a_q - a_{R-q} and
+        // theta = 2 pi p q / R, output p of the forward DFT is
+        //   a_0 + sum_q s_q cos(theta) - i sum_q d_q sin(theta)
+        // and output R - p the same with + i (q, p = 1 .. (R - 1) / 2): real
+        // coefficients instead of complex roots, a third of the multiplies.
+        constexpr int H = (R - 1) / 2;
+        Z sm[H + 1], df[H + 1];
+        Z a0 = a[0], out0 = a[0];
 #pragma unroll
-        for (int p = 0; p < R; ++p) {
-            Z acc = a[0];
-#pragma unroll
-            for (int q = 1; q < R; ++q) acc = cadd(acc, cmul(a[q], w[(p * q) % R]));
-            out[p] = acc;
+        for (int q = 1; q <= H; ++q) {
+            sm[q] = cadd(a[q], a[R - q]);
+            df[q] = csub(a[q], a[R - q]);
+            out0 = cadd(out0, sm[q]);
         }
 #pragma unroll
-        for (int p = 0; p < R; ++p) a[p] = out[p];
+        for (int p = 1; p <= H; ++p) {
+            T ar = a0.x, ai = a0.y, br = T(0), bi = T(0);
+#pragma unroll
+            for (int q = 1; q <= H; ++q) {
+                const int m = (p * q) % R;
+                const T c = prime_cos<T, R>(m <= H ? m : R - m);
+                const T sn = m <= H ? prime_sin<T, R>(m) : -prime_sin<T, R>(R - m);
+                ar += c * sm[q].x;
+                ai += c * sm[q].y;
+                br += sn * df[q].x;
+                bi += sn * df[q].y;
+            }
+            if constexpr (!INV) {
+                a[p] = cmk<T>(ar + bi, ai - br);
+                a[R - p] = cmk<T>(ar - bi, ai + br);
+            } else {
+                a[p] = cmk<T>(ar - bi, ai + br);
+                a[R - p] = cmk<T>(ar + bi, ai - br);
+            }
+        }
+        a[0] = out0;
     }
 }
 
@@ -105,14 +145,6 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
     const int tstep = L / (Ns * R);
     // j / Ns by multiply-high: exact for j, Ns < 2^16
     const uint32_t mNs = Ns > 1 ? 0xFFFFFFFFu / (uint32_t)Ns + 1u : 0u;
-    Z w[R];
-    if constexpr (R == 3 || R == 5 || R == 7) {
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            Z t = tw[m * (L / R)];
-            w[m] = INV ? cconj(t) : t;
-        }
-    }
     Z v[MAXBF][R];
 #pragma unroll
     for (int u = 0; u < MAXBF; ++u) {
@@ -131,7 +163,7 @@ __device__ __forceinline__ void fft_pass(cplx<T>* buf, int twsh, int M, int Ns,
                 }
                 v[u][q] = a;
             }
-            dft_small<T, R, INV>(v[u], w);
+            dft_small<T, R, INV>(v[u]);
         }
     }
     __syncthreads();
