@@ -92,6 +92,16 @@ def main():
     log(f"[bench] BF16 spectrum loaded ({op.fhat_bytes / 1e9:.2f} GB) in {time.perf_counter() - t0:.1f} s "
         f"(load kernels {load_ms:.1f} ms)")
 
+    # matrix-core tile variants for the two batched widths (autotuner, before timing)
+    from paper_2501_14911_amd import gemm_tiles
+    tiles = gemm_tiles()
+    tuned = {}
+    for nr in (N_HESS, N_RAGGED):
+        r = op.autotune(nr, reps=2)
+        tuned[nr] = {d: {"tile": r[d][0], "shape": tiles[r[d][0]], "ms": r[d][1]} for d in ("fwd", "adj")}
+        log(f"[bench] autotune nrhs={nr}: fwd tile {r['fwd'][0]} {tiles[r['fwd'][0]]} {r['fwd'][1]:.3f} ms, "
+            f"adj tile {r['adj'][0]} {tiles[r['adj'][0]]} {r['adj'][1]:.3f} ms")
+
     # inputs
     m = synth.param_series(w, 1, backend="torch", device=dev, smooth=(w.name == "largest"))[0].float()
     d_obs = synth.data_series(w, 1, backend="torch", device=dev)[0].float()
@@ -182,8 +192,14 @@ def main():
              "gemm_fwd_32": st32["gemm_fwd"][0], "gemm_adj_32": st32["gemm_adj"][0]}
     dom = max(share, key=share.get)
     dk = kern[dom]
+    dom_tile = None
+    if dom.startswith("gemm_"):
+        dom_tile = tuned[int(dom.rsplit("_", 1)[1])][dom.split("_")[1]]["tile"]
+    traffic = measured_traffic(dom, dom_tile, w)
     roof = {"bound": "hbm", "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dk["GBs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+            "frac": dk["GBs"] / HBM_PEAK_GBS,
+            "traffic": traffic["bytes"] if traffic else None, "traffic_unit": "bytes/launch",
+            "traffic_detail": traffic, "kernel": dom, "tile": dom_tile,
             "algorithmic_bytes_per_launch": dk["bytes"], "avg_launch_us": dk["us"]}
 
     result = {
@@ -212,6 +228,7 @@ def main():
         "kernels_us_by_nrhs": {str(n): {k: avg_us(k, st) for k in st if st[k][1]}
                                for n, st in ((1, st1), (N_HESS, st64), (N_RAGGED, st32))},
         "load_ms": load_ms,
+        "autotune": {str(k): v for k, v in tuned.items()},
     }
 
     from paper_2501_14911_amd import bandwidth_probe
@@ -229,6 +246,33 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_cols, np)
     print(json.dumps(result), flush=True)
+
+
+# HBM traffic per launch of the timed kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of this benchmark (copy-kernel calibration: fetched KiB x 2,
+# written KiB x 1; see profiles/).  Valid only for the kernel source it was
+# measured on: keyed by the SHA-1 of that file and the tile variant.
+TRAFFIC = {
+    # (kernel, tile): (source file, sha1, fetch bytes, write bytes, workload)
+}
+
+
+def measured_traffic(kernel, tile, w):
+    import hashlib
+    ent = TRAFFIC.get((kernel, tile))
+    if not ent:
+        return None
+    src, sha, fetch, write, workload = ent
+    if workload != w.name:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), src)
+    try:
+        cur = hashlib.sha1(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if cur != sha:
+        return None
+    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "source": src, "sha1": sha}
 
 
 def accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np):

@@ -172,7 +172,9 @@ typedef enum {
 
 /* Plan options (p2o_set_option). */
 typedef enum {
-    P2O_OPT_BATCHED = 0      /* value: p2o_batched_mode                      */
+    P2O_OPT_BATCHED = 0,     /* value: p2o_batched_mode                      */
+    P2O_OPT_GEMM_TILE = 1    /* value: matrix-core tile variant in [0, p2o_gemm_tile_info's count), or -1
+                                (default) for the autotuned or built-in choice; both directions */
 } p2o_option;
 
 /* How calls with several right-hand sides do the per-frequency products.
@@ -189,6 +191,28 @@ typedef enum {
 
 /* Set a plan option; takes effect for later calls. */
 p2o_status p2o_set_option(p2o_plan* plan, int32_t option, int64_t value);
+
+/* Matrix-core tile variants of the batched products (section 4's per-frequency
+ * products as complex GEMMs, one per frequency).  Variant `tile` assigns
+ * 32 * row_groups * 5 output rows (sensors, or parameter columns for the
+ * adjoint) and rhs_per_group right-hand sides to a workgroup and stages K in
+ * steps of 8 * substeps entries.  Returns P2O_ERR_ARG for an unknown variant;
+ * variants are numbered from 0 without gaps, so the first index that fails
+ * is the count.  Any output pointer may be NULL. */
+p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* rhs_per_group);
+
+/* Autotuner: times every tile variant of the forward and the adjoint
+ * matrix-core products with `nrhs` right-hand sides on this plan's loaded
+ * spectrum (one warm-up and `reps` timed launches each, HIP events on the
+ * plan's stream), keeps the fastest for later calls with exactly `nrhs`
+ * right-hand sides, and returns the choices and their mean launch times in
+ * milliseconds (any output pointer may be NULL).  Uses the workspace as
+ * operands (its contents are overwritten) and synchronises the stream.
+ * Needs a loaded BF16 plan whose calls with nrhs right-hand sides use the
+ * matrix cores (P2O_ERR_DTYPE otherwise), 1 <= nrhs <= max_rhs and
+ * 1 <= reps <= 100. */
+p2o_status p2o_autotune(p2o_plan* plan, int64_t nrhs, int32_t reps, int32_t* fwd_tile, int32_t* adj_tile,
+                        double* fwd_ms, double* adj_ms);
 
 /* Per-stage timing with HIP events recorded on the plan's stream around
  * every launch (enable = 1) or not (enable = 0).  Either call resets the

@@ -6,7 +6,7 @@ HIP kernels behind a C ABI (include/p2o.h, libp2o.so).  Importing the
 package loads the library and fails if it has not been built.
 """
 from ._lib import P2OError, LIB_PATH, PRECISIONS, lib, status_name, last_error
-from .ops import P2OOperator, P2O, P2OT, misfit, SCALE_BLOCK, bandwidth_probe
+from .ops import P2OOperator, P2O, P2OT, misfit, SCALE_BLOCK, bandwidth_probe, gemm_tiles
 
-__all__ = ["bandwidth_probe", "P2OOperator", "P2O", "P2OT", "misfit", "P2OError", "PRECISIONS", "SCALE_BLOCK",
+__all__ = ["bandwidth_probe", "gemm_tiles", "P2OOperator", "P2O", "P2OT", "misfit", "P2OError", "PRECISIONS", "SCALE_BLOCK",
            "lib", "LIB_PATH", "status_name", "last_error"]

@@ -73,6 +73,8 @@ struct p2o_plan {
     int adj_rows = 1, adj_nslab = 1;
     int c2r_nd_blocks = 1;
     int batched_mode = P2O_BATCHED_AUTO;
+    int gemm_tile = -1;                     // forced matrix-core tile variant, -1: tuned or built-in
+    std::map<int64_t, int> tuned_fwd, tuned_adj;   // autotuned variant per right-hand-side count
     // bound memory
     char* fhat = nullptr;
     char* ws = nullptr;
@@ -264,11 +266,19 @@ GemmArgs gemm_args(const p2o_plan* p, int64_t nrhs) {
     return ga;
 }
 
+// matrix-core tile variant for a call with nrhs right-hand sides
+int gemm_tile_for(const p2o_plan* p, const std::map<int64_t, int>& tuned, int64_t nrhs) {
+    if (p->gemm_tile >= 0) return p->gemm_tile;
+    auto it = tuned.find(nrhs);
+    return it == tuned.end() ? -1 : it->second;
+}
+
 // X (parameter spectra) -> Y partial products
 p2o_status enqueue_fwd_products(p2o_plan* p, const void* X, void* Y, int64_t nrhs) {
     if (mfma_on(p, nrhs))
         return staged(p, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores)", [&] {
-            return launch_gemm_fwd(gemm_args(p, nrhs), p->fhat, scales_of(p), X, Y, p->stream);
+            return launch_gemm_fwd(gemm_args(p, nrhs), gemm_tile_for(p, p->tuned_fwd, nrhs), p->fhat, scales_of(p), X,
+                                   Y, p->stream);
         });
     return staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
         return launch_gemv_fwd(p->prec, gemv_args(p, nrhs, true), p->fhat, scales_of(p), X, Y, p->stream);
@@ -279,7 +289,8 @@ p2o_status enqueue_fwd_products(p2o_plan* p, const void* X, void* Y, int64_t nrh
 p2o_status enqueue_adj_products(p2o_plan* p, const void* Y, void* X, int64_t nrhs) {
     if (mfma_on(p, nrhs))
         return staged(p, P2O_STAGE_GEMM_ADJ, "adjoint per-frequency products (matrix cores)", [&] {
-            return launch_gemm_adj(gemm_args(p, nrhs), p->fhat, scales_of(p), Y, X, p->stream);
+            return launch_gemm_adj(gemm_args(p, nrhs), gemm_tile_for(p, p->tuned_adj, nrhs), p->fhat, scales_of(p), Y,
+                                   X, p->stream);
         });
     return staged(p, P2O_STAGE_GEMV_ADJ, "adjoint per-frequency products", [&] {
         return launch_gemv_adj(p->prec, gemv_args(p, nrhs, false), p->fhat, scales_of(p), Y, X, p->stream);
@@ -421,7 +432,77 @@ p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
         p->batched_mode = (int)value;
         return P2O_OK;
     }
+    if (option == P2O_OPT_GEMM_TILE) {
+        if (value < -1 || value >= gemm_tile_count())
+            return fail(P2O_ERR_ARG, "tile variant %lld not in [-1, %d)", (long long)value, gemm_tile_count());
+        p->gemm_tile = (int)value;
+        return P2O_OK;
+    }
     return fail(P2O_ERR_ARG, "unknown option %d", (int)option);
+}
+
+p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* rhs_per_group) {
+    int rg = 0, ku = 0;
+    if (gemm_tile_shape(tile, &rg, &ku)) return fail(P2O_ERR_ARG, "tile variant %d not in [0, %d)", (int)tile, gemm_tile_count());
+    if (row_groups) *row_groups = rg;
+    if (substeps) *substeps = ku;
+    if (rhs_per_group) *rhs_per_group = 32 * (4 / rg);
+    return P2O_OK;
+}
+
+p2o_status p2o_autotune(p2o_plan* p, int64_t nrhs, int32_t reps, int32_t* fwd_tile, int32_t* adj_tile,
+                        double* fwd_ms, double* adj_ms) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (p->state != kReady) return fail(P2O_ERR_STATE, "spectrum not loaded (call p2o_load_blocks and p2o_load_finalize)");
+        if (nrhs < 1 || nrhs > p->max_rhs) return fail(P2O_ERR_ARG, "nrhs=%lld not in [1, %lld]", (long long)nrhs, (long long)p->max_rhs);
+        if (reps < 1 || reps > 100) return fail(P2O_ERR_ARG, "reps=%d not in [1, 100]", (int)reps);
+        if (!mfma_on(p, nrhs)) return fail(P2O_ERR_DTYPE, "calls with nrhs=%lld do not use the matrix cores on this plan", (long long)nrhs);
+        if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+        // Operands: the workspace's spectra regions, cleared (their values do not
+        // change the timing; clearing keeps them finite).
+        void* X = p->ws + p->off_X;
+        void* Y = p->ws + p->off_Y;
+        p2o_status s = check_hip(hipMemsetAsync(p->ws, 0, p->off_D, p->stream), "autotune operand clear");
+        if (s) return s;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            return fail(P2O_ERR_HIP, "event creation failed");
+        }
+        const GemmArgs ga = gemm_args(p, nrhs);
+        double best[2] = {1e300, 1e300};
+        int pick[2] = {-1, -1};
+        for (int dir = 0; dir < 2 && !s; ++dir) {
+            for (int t = 0; t < gemm_tile_count() && !s; ++t) {
+                auto run = [&]() {
+                    return dir == 0 ? launch_gemm_fwd(ga, t, p->fhat, scales_of(p), X, Y, p->stream)
+                                    : launch_gemm_adj(ga, t, p->fhat, scales_of(p), Y, X, p->stream);
+                };
+                s = check_hip(run(), "autotune warm-up launch");
+                if (s) break;
+                s = check_hip(hipEventRecord(a, p->stream), "event record");
+                for (int r = 0; r < reps && !s; ++r) s = check_hip(run(), "autotune launch");
+                if (!s) s = check_hip(hipEventRecord(b, p->stream), "event record");
+                if (!s) s = check_hip(hipEventSynchronize(b), "autotune synchronisation");
+                float ms = 0.f;
+                if (!s) s = check_hip(hipEventElapsedTime(&ms, a, b), "event timing");
+                if (!s && ms / reps < best[dir]) { best[dir] = ms / reps; pick[dir] = t; }
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (s) return s;
+        p->tuned_fwd[nrhs] = pick[0];
+        p->tuned_adj[nrhs] = pick[1];
+        if (fwd_tile) *fwd_tile = pick[0];
+        if (adj_tile) *adj_tile = pick[1];
+        if (fwd_ms) *fwd_ms = best[0];
+        if (adj_ms) *adj_ms = best[1];
+        return P2O_OK;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_autotune");
+    }
 }
 
 p2o_status p2o_profile_enable(p2o_plan* p, int32_t enable) {

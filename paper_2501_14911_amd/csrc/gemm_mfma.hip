@@ -305,26 +305,53 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
     return hipGetLastError();
 }
 
-// 33 or more right-hand sides: 2 row groups x 2 halves of 64, 4 substeps per
-// step; up to 32: 4 row groups x 32, 2 substeps per step.
-hipError_t launch_gemm_fwd(const GemmArgs& in, const void* fhat, const float* scales, const void* Xq, void* Yp,
-                           hipStream_t st) {
+// Tile variants (row groups RG, substeps per step KU): 32 (4 / RG) x 2
+// right-hand sides and 160 RG output rows per workgroup, K steps of 8 KU
+// entries.  The built-in choice takes 64-wide groups for 33 or more
+// right-hand sides; a plan's autotuner may pick another.
+struct TileShape {
+    int rg, ku;
+};
+static const TileShape kTiles[] = {{2, 4}, {2, 2}, {4, 2}};
+constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
+
+int gemm_tile_count() { return kTileCount; }
+
+int gemm_tile_shape(int tile, int* rg, int* ku) {
+    if (tile < 0 || tile >= kTileCount) return -1;
+    *rg = kTiles[tile].rg;
+    *ku = kTiles[tile].ku;
+    return 0;
+}
+
+int gemm_default_tile(int nrhs) { return nrhs > 32 ? 0 : 2; }
+
+hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Xq,
+                           void* Yp, hipStream_t st) {
     GemmArgs ga = in;
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.pitch);
-    return ga.nrhs > 32 ? launch_tile<true, 2, 4>(ga, fhat, scales, Xq, Yp, st)
-                        : launch_tile<true, 4, 2>(ga, fhat, scales, Xq, Yp, st);
+    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs);
+    switch (tile) {
+        case 0: return launch_tile<true, 2, 4>(ga, fhat, scales, Xq, Yp, st);
+        case 1: return launch_tile<true, 2, 2>(ga, fhat, scales, Xq, Yp, st);
+        default: return launch_tile<true, 4, 2>(ga, fhat, scales, Xq, Yp, st);
+    }
 }
 
-hipError_t launch_gemm_adj(const GemmArgs& in, const void* fhat, const float* scales, const void* Yq, void* Xp,
-                           hipStream_t st) {
+hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Yq,
+                           void* Xp, hipStream_t st) {
     GemmArgs ga = in;
     ga.ldb = gemm_data_pitch(ga.Nd);
     ga.kchunk = 0;
     ga.n_kc = 1;
-    return ga.nrhs > 32 ? launch_tile<false, 2, 4>(ga, fhat, scales, Yq, Xp, st)
-                        : launch_tile<false, 4, 2>(ga, fhat, scales, Yq, Xp, st);
+    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs);
+    switch (tile) {
+        case 0: return launch_tile<false, 2, 4>(ga, fhat, scales, Yq, Xp, st);
+        case 1: return launch_tile<false, 2, 2>(ga, fhat, scales, Yq, Xp, st);
+        default: return launch_tile<false, 4, 2>(ga, fhat, scales, Yq, Xp, st);
+    }
 }
 
 }  // namespace p2o

@@ -94,6 +94,21 @@ class P2OOperator:
         cores, BF16 spectra only)."""
         check(lib.p2o_set_option(self._plan, 0, BATCHED[mode]))
 
+    def set_gemm_tile(self, tile: int = -1):
+        """Force matrix-core tile variant ``tile`` (see ``gemm_tiles()``) for
+        both directions, or -1 for the autotuned or built-in choice."""
+        check(lib.p2o_set_option(self._plan, 1, int(tile)))
+
+    def autotune(self, nrhs: int, reps: int = 3) -> dict:
+        """Time every matrix-core tile variant for calls with ``nrhs``
+        right-hand sides and keep the fastest (per direction) for later calls
+        with exactly that many.  Overwrites the workspace; synchronises."""
+        ft, at = ctypes.c_int32(), ctypes.c_int32()
+        fm, am = ctypes.c_double(), ctypes.c_double()
+        check(lib.p2o_autotune(self._plan, int(nrhs), int(reps), ctypes.byref(ft), ctypes.byref(at),
+                               ctypes.byref(fm), ctypes.byref(am)))
+        return {"fwd": (ft.value, fm.value), "adj": (at.value, am.value)}
+
     # ------------------------------------------------------------------ timing
     def profile(self, enable: bool = True):
         """Start (or stop) per-stage HIP-event timing; resets the totals."""
@@ -259,6 +274,16 @@ def misfit(m: torch.Tensor, op: P2OOperator, d_obs: torch.Tensor, noise_var, nt_
     """Phi(m) = 1/2 ||F m - d_obs||^2_{Gamma_noise^-1} (float64, per right-hand
     side) with the fused gradient kernel as its backward."""
     return _Misfit.apply(m, op, d_obs, noise_var, nt_active)
+
+
+def gemm_tiles() -> list:
+    """Matrix-core tile variants: [(row_groups, substeps, rhs_per_group), ...]."""
+    out = []
+    while True:
+        rg, ku, nr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        if lib.p2o_gemm_tile_info(len(out), ctypes.byref(rg), ctypes.byref(ku), ctypes.byref(nr)) != 0:
+            return out
+        out.append((rg.value, ku.value, nr.value))
 
 
 def bandwidth_probe(nbytes: int = 8 << 30, reps: int = 10, device="cuda", blocks: int = 8192) -> dict:

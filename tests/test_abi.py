@@ -140,3 +140,18 @@ def test_scaled_loads_need_whole_blocks():
 def test_python_operator_requires_a_gpu_device():
     with pytest.raises(ValueError):
         p2o.P2OOperator(4, 64, 16, "fp64", device="cpu")
+
+
+def test_gemm_tile_table_and_autotune_checks():
+    tiles = p2o.gemm_tiles()
+    assert tiles == [(2, 4, 64), (2, 2, 64), (4, 2, 32)]
+    assert lib.p2o_gemm_tile_info(len(tiles), None, None, None) == ARG
+    assert lib.p2o_gemm_tile_info(-1, None, None, None) == ARG
+    st, plan = create(Nd=4, Nm=64, Nt=16, prec=2, max_rhs=4)
+    assert lib.p2o_set_option(plan, 1, len(tiles)) == ARG
+    assert lib.p2o_set_option(plan, 1, -2) == ARG
+    assert lib.p2o_set_option(plan, 1, 0) == OK
+    assert lib.p2o_set_option(plan, 1, -1) == OK
+    assert lib.p2o_autotune(plan, 2, 3, None, None, None, None) == STATE      # not loaded
+    assert lib.p2o_autotune(None, 2, 3, None, None, None, None) == ARG
+    lib.p2o_destroy(plan)

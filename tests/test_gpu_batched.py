@@ -116,6 +116,45 @@ def test_batched_misfit_gradient():
         assert oracle.rel_l2(g[b], g_o[b]) <= TOL_BF16
 
 
+@pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
+def test_every_tile_variant(w):
+    """Each matrix-core tile variant the autotuner can pick, forced, against
+    the oracle (a full 64-wide group and a ragged one)."""
+    from paper_2501_14911_amd import gemm_tiles
+    nrhs = 70
+    op, F = build(w, nrhs)
+    m = synth.param_series(w, nrhs)
+    d = synth.data_series(w, nrhs)
+    yo, so = oracle.apply_F(F, m), oracle.apply_Ft(F, d)
+    for t in range(len(gemm_tiles())):
+        op.set_gemm_tile(t)
+        y = host(op.apply_F(dev(m)))
+        s = host(op.apply_Ft(dev(d)))
+        worst = max(max(oracle.rel_l2(y[b], yo[b]), oracle.rel_l2(s[b], so[b])) for b in range(nrhs))
+        note(f"[batched] {w.name} tile {t}: worst rel-L2 {worst:.3e}")
+        assert worst <= TOL_BF16
+
+
+def test_autotune_then_apply():
+    w = SHAPES[0]
+    nrhs = 40
+    op, F = build(w, nrhs)
+    res = op.autotune(nrhs, reps=2)
+    note(f"[batched] autotune {res}")
+    from paper_2501_14911_amd import gemm_tiles
+    for key in ("fwd", "adj"):
+        assert 0 <= res[key][0] < len(gemm_tiles()) and res[key][1] > 0
+    m = synth.param_series(w, nrhs)
+    d = synth.data_series(w, nrhs)
+    y = host(op.apply_F(dev(m)))
+    s = host(op.apply_Ft(dev(d)))
+    yo, so = oracle.apply_F(F, m), oracle.apply_Ft(F, d)
+    assert max(oracle.rel_l2(y[b], yo[b]) for b in range(nrhs)) <= TOL_BF16
+    assert max(oracle.rel_l2(s[b], so[b]) for b in range(nrhs)) <= TOL_BF16
+    with pytest.raises(Exception):
+        op.autotune(nrhs + 1)                    # beyond max_rhs
+
+
 def test_mfma_option_needs_bf16():
     w = synth.CONFIGS["tiny"]
     op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp32", max_rhs=2, device=DEV)
