@@ -252,8 +252,16 @@ def main():
 # WRITE_SIZE runs of this benchmark (copy-kernel calibration: fetched KiB x 2,
 # written KiB x 1; see profiles/).  Valid only for the kernel source it was
 # measured on: keyed by the SHA-1 of that file and the tile variant.
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "c6a47c11420ef01d87749be6446e79dd8524d0ab")
+_GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "fd80bdf513763482c5e0e531d01284b78a223d99")
 TRAFFIC = {
     # (kernel, tile): (source file, sha1, fetch bytes, write bytes, workload)
+    ("gemm_fwd_64", 0): (*_GEMM, 21500095473, 523757480, "paper_time"),
+    ("gemm_adj_64", 1): (*_GEMM, 17084969105, 3531955480, "paper_time"),
+    ("gemm_fwd_32", 2): (*_GEMM, 24577390028, 267290431, "paper_time"),
+    ("gemm_adj_32", 2): (*_GEMM, 16696744945, 1766560097, "paper_time"),
+    ("gemv_fwd", None): (*_GEMV, 17222871392, 16166400, "paper_time"),
+    ("gemv_adj", None): (*_GEMV, 17021801913, 55183274, "paper_time"),
 }
 
 
