@@ -191,7 +191,12 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const uint8_t* fhat, cons
             const int c = tid + i * kGemmThreads;
             const int p = c >> 1, hl = c & 1;
             const int g = p % (T::KC / 4), bl = p / (T::KC / 4);
-            bfr[buf][g >> 1][bl >> 5][hl][b_slot((bl & 31) + 32 * (g & 1), g >> 1, hl)] = sg.b[i] & sg.m[i];
+            // The empty asm pins the first use of the loaded chunk here: left
+            // free, the compiler hoists the masking into the previous step,
+            // whose wait for this load then drains the other step in flight.
+            v4u v = sg.b[i];
+            asm volatile("" : "+v"(v));
+            bfr[buf][g >> 1][bl >> 5][hl][b_slot((bl & 31) + 32 * (g & 1), g >> 1, hl)] = v & sg.m[i];
         }
     };
 
