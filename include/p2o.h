@@ -173,8 +173,12 @@ typedef enum {
 /* Plan options (p2o_set_option). */
 typedef enum {
     P2O_OPT_BATCHED = 0,     /* value: p2o_batched_mode                      */
-    P2O_OPT_GEMM_TILE = 1    /* value: matrix-core tile variant in [0, p2o_gemm_tile_info's count), or -1
+    P2O_OPT_GEMM_TILE = 1,   /* value: matrix-core tile variant in [0, p2o_gemm_tile_info's count), or -1
                                 (default) for the autotuned or built-in choice; both directions */
+    P2O_OPT_FFT_FIXED = 2    /* value: 1 (default) runs the time-axis FFTs (section 4's circulant
+                                embedding) with kernels compiled for the plan's transform length when
+                                the library has them (lengths L = 32, 256, 840), 0 always with the
+                                runtime-length kernels; both compute the same transforms */
 } p2o_option;
 
 /* How calls with several right-hand sides do the per-frequency products.

@@ -380,6 +380,7 @@ p2o_status p2o_create(p2o_plan** out, int64_t Nd, int64_t Nm, int64_t Nt, int32_
         for (int r : {8, 4, 2, 3, 5, 7})
             while (m % r == 0 && np < kMaxPasses) { fp.radix[np++] = r; m /= r; }
         fp.npass = np;
+        fp.fixed = 1;
         if (m != 1 || fft_tile_shift((int)M, true) < 0 || fft_tile_shift((int)M, false) < 0 || load_tile_shift((int)M) < 0)
             return fail(P2O_ERR_ARG, "Nt=%lld too long (transform length %lld exceeds the LDS tile)", (long long)Nt,
                         (long long)(2 * M));
@@ -436,6 +437,11 @@ p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
         if (value < -1 || value >= gemm_tile_count())
             return fail(P2O_ERR_ARG, "tile variant %lld not in [-1, %d)", (long long)value, gemm_tile_count());
         p->gemm_tile = (int)value;
+        return P2O_OK;
+    }
+    if (option == P2O_OPT_FFT_FIXED) {
+        if (value != 0 && value != 1) return fail(P2O_ERR_ARG, "fixed-length FFT switch %lld is not 0 or 1", (long long)value);
+        p->fft.fixed = (int)value;
         return P2O_OK;
     }
     return fail(P2O_ERR_ARG, "unknown option %d", (int)option);

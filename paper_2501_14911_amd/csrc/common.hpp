@@ -111,6 +111,14 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
     return u >> 16;
 }
 
+// Two values rounded to BF16 (nearest even) in one word, a in the low half
+// (one v_cvt_pk_bf16_f32 on gfx950).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16_rne(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
+}
+
 // x = hi + lo with hi, lo BF16 (round to nearest even); the raw 16-bit codes.
 __device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
     hi = f32_to_bf16_rne(x);
@@ -124,12 +132,11 @@ __device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) 
 // series must start at a multiple of 4 values.  Stores value c of the series
 // whose first word is q.
 __device__ __forceinline__ void store_quad(uint32_t* q, long long c, float re, float im) {
-    uint32_t rh, rl, ih, il;
-    split_bf16(re, rh, rl);
-    split_bf16(im, ih, il);
+    const uint32_t hi = pack_bf16_rne(re, im);
+    const uint32_t lo = pack_bf16_rne(re - __uint_as_float(hi << 16), im - __uint_as_float(hi & 0xffff0000u));
     uint32_t* g = q + 8 * (c >> 2) + (c & 3);
-    g[0] = rh | (ih << 16);
-    g[4] = rl | (il << 16);
+    g[0] = hi;
+    g[4] = lo;
 }
 
 __device__ __forceinline__ uint32_t f32_to_f16_rne(float f) {
@@ -143,6 +150,7 @@ struct FftPlan {
     int L;          // circulant length
     int npass;
     int radix[kMaxPasses];
+    int fixed;      // nonzero: use the kernels compiled for this M when there are any
 };
 
 // Addressing of a batch of real time series and their half spectra.

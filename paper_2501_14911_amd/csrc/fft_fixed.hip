@@ -1,0 +1,643 @@
+// Batched real FFTs along time, compiled for fixed transform lengths.
+//
+// These compute what the runtime-length kernels in fft.hip compute (the
+// circulant embedding of section 4: a tile of TW adjacent series x all bins
+// in LDS as [bin][series], each real series of length L = 2M transformed as
+// one complex series of length M, Stockham passes in place, zero padding and
+// truncation fused into the loads and stores), with M, the tile width and
+// the radix sequence known to the compiler.  That removes most of the
+// integer work of the runtime-length passes:
+//  - every LDS address of a pass is a per-thread base plus an instruction
+//    immediate, and butterfly indices are divisions by constants;
+//  - each pass reads its twiddles w[k][q] = e^{-2 pi i q k / (Ns R)} from a
+//    table laid out in the order a butterfly uses them;
+//  - the forward transform's first pass takes its inputs straight from the
+//    time series, and the inverse transform's last pass writes its outputs
+//    straight to them;
+//  - in the truncate-and-repad kernel the inverse transform runs its radices
+//    in reverse order, so that its last pass and the forward transform's
+//    first pass cover the same index sets: both passes and the truncation
+//    between them run on registers;
+//  - the real-transform pre and post steps take bins k and M - k together
+//    (they share their inputs, and W^(M-k) = -conj(W^k));
+//  - workgroups are persistent (a grid of resident workgroups loops over the
+//    tiles), so the twiddle tables are staged once per workgroup.
+// Transform lengths without a compiled kernel use the runtime-length ones.
+#include <algorithm>
+#include <utility>
+
+#include "common.hpp"
+#include "fft_common.hpp"
+#include "kernels.hpp"
+
+namespace p2o {
+namespace {
+
+constexpr int kFxThreads = 256;
+
+// M factored greedily over 8, 4, 2, 3, 5, 7 (as the plan does), in that order
+// or reversed.  ns: product of the radices of the earlier passes; toff: first
+// entry of the pass's twiddles in its table (the table has M - 1 entries).
+struct RadixSeq {
+    int n;
+    int r[kMaxPasses];
+    int ns[kMaxPasses];
+    int toff[kMaxPasses];
+};
+
+constexpr RadixSeq radix_seq(int M, bool reversed) {
+    RadixSeq f{};
+    const int order[6] = {8, 4, 2, 3, 5, 7};
+    int fac[kMaxPasses] = {};
+    int n = 0, m = M;
+    for (int i = 0; i < 6; ++i)
+        while (m % order[i] == 0 && n < kMaxPasses) {
+            fac[n++] = order[i];
+            m /= order[i];
+        }
+    int ns = 1, off = 0;
+    for (int p = 0; p < n; ++p) {
+        const int r = reversed ? fac[n - 1 - p] : fac[p];
+        f.r[p] = r;
+        f.ns[p] = ns;
+        f.toff[p] = off;
+        off += ns * (r - 1);
+        ns *= r;
+    }
+    f.n = n;
+    return f;
+}
+
+template <int M, int SH>
+struct Geo {
+    static constexpr int TW = 1 << SH;             // series per tile
+    static constexpr int RS = TW + 1;              // LDS row stride in complex entries (odd: spreads banks)
+    static constexpr int JS = kFxThreads >> SH;    // bins (or butterflies) per sweep of the workgroup
+    static constexpr RadixSeq FWD = radix_seq(M, false);
+    static constexpr RadixSeq REV = radix_seq(M, true);
+    static constexpr int NP = FWD.n;
+    static constexpr int NPAIR = M / 2 + 1;        // bin pairs (k, M - k), k = 0 .. M / 2
+    static constexpr int TILE = (M + 1) * RS;      // complex entries of the tile (bins 0 .. M)
+    static_assert(M % 2 == 0 && NP >= 2, "fixed-length kernels take even M with at least two passes");
+};
+
+// Pass P of a radix order: butterfly j < MR = M / R reads entries j + q MR,
+// multiplies entry q by w[k][q] (k = j mod Ns), transforms, and writes
+// entry p to (j - k) R + k + p Ns.  A thread takes butterflies
+// j = j0 + u JS, u < NU (the last sweep may be partial).
+template <int M, int SH, bool REV, int P>
+struct Pass {
+    using G = Geo<M, SH>;
+    static constexpr RadixSeq S = REV ? G::REV : G::FWD;
+    static constexpr int R = S.r[P], NS = S.ns[P], TOFF = S.toff[P];
+    static constexpr int MR = M / R;
+    static constexpr int NU = (MR + G::JS - 1) / G::JS;
+    __device__ static bool live(int u, int j) { return MR % G::JS == 0 || u < NU - 1 || j < MR; }
+    __device__ static int kof(int j0, int j) {
+        if constexpr (NS == 1) return 0;
+        else if constexpr (G::JS % NS == 0) return (int)((unsigned)j0 % NS);
+        else return (int)((unsigned)j % NS);
+    }
+};
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void apply_tw(cplx<T>* v, const cplx<T>* t) {
+#pragma unroll
+    for (int q = 1; q < R; ++q) v[q] = cmul(v[q], INV ? cconj(t[q - 1]) : t[q - 1]);
+}
+
+// ---------------------------------------------------------------- twiddle staging
+// twg: e^{-2 pi i n / L}, n < L = 2M.  Pair table: W^k, k <= M / 2.  Pass
+// table of a radix order: pass P's entry k (R - 1) + q - 1 is
+// e^{-2 pi i q k / (Ns R)} = twg[q k L / (Ns R)].
+template <typename T, int M, int SH>
+__device__ __forceinline__ void stage_pair_tw(cplx<T>* twq, const cplx<T>* __restrict__ twg) {
+    for (int k = threadIdx.x; k < Geo<M, SH>::NPAIR; k += kFxThreads) twq[k] = twg[k];
+}
+
+template <typename T, int M, int SH, bool REV>
+__device__ __forceinline__ void stage_pass_tw(cplx<T>* tab, const cplx<T>* __restrict__ twg) {
+    static_for<0, Geo<M, SH>::NP>([&](auto pc) {
+        using Ps = Pass<M, SH, REV, decltype(pc)::value>;
+        constexpr int R = Ps::R, NS = Ps::NS, STEP = 2 * M / (NS * R);
+        for (int e = threadIdx.x; e < NS * (R - 1); e += kFxThreads) {
+            const int k = e / (R - 1), q = e - k * (R - 1) + 1;
+            tab[Ps::TOFF + e] = twg[q * k * STEP];
+        }
+    });
+}
+
+// ---------------------------------------------------------------- passes
+// Pass P on the LDS tile (read, barrier, write, barrier).
+template <typename T, int M, int SH, bool REV, bool INV, int P>
+__device__ __forceinline__ void lds_pass(cplx<T>* buf, const cplx<T>* tab, int s, int j0) {
+    using Z = cplx<T>;
+    using G = Geo<M, SH>;
+    using Ps = Pass<M, SH, REV, P>;
+    constexpr int R = Ps::R, NS = Ps::NS, MR = Ps::MR, NU = Ps::NU, RS = G::RS, JS = G::JS;
+    Z v[NU][R];
+    const Z* rb = buf + j0 * RS + s;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int j = j0 + u * JS;
+        if (Ps::live(u, j)) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[u][q] = rb[(u * JS + q * MR) * RS];
+            if constexpr (NS > 1) apply_tw<T, R, INV>(v[u], tab + Ps::TOFF + Ps::kof(j0, j) * (R - 1));
+            dft_small<T, R, INV>(v[u]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int j = j0 + u * JS;
+        if (Ps::live(u, j)) {
+            const int k = Ps::kof(j0, j);
+            Z* wb = buf + (j * R - k * (R - 1)) * RS + s;
+#pragma unroll
+            for (int p = 0; p < R; ++p) wb[p * NS * RS] = v[u][p];
+        }
+    }
+    __syncthreads();
+}
+
+// First forward pass fed by the time series: z[n] = x[2n] + i x[2n+1],
+// x[t] = 0 for t >= nt or for a series past S (ok false).
+template <typename T, typename TIN, int M, int SH>
+__device__ __forceinline__ void first_pass_from_time(cplx<T>* buf, const TIN* __restrict__ src, long long t_stride,
+                                                     bool ok, int nt, int s, int j0) {
+    using Z = cplx<T>;
+    using G = Geo<M, SH>;
+    using Ps = Pass<M, SH, false, 0>;
+    constexpr int R = Ps::R, MR = Ps::MR, NU = Ps::NU, RS = G::RS, JS = G::JS;
+    Z v[NU][R];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int j = j0 + u * JS;
+        if (Ps::live(u, j)) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int t0 = 2 * (j + q * MR);
+                T x0 = T(0), x1 = T(0);
+                if (ok && t0 < nt) x0 = (T)src[(long long)t0 * t_stride];
+                if (ok && t0 + 1 < nt) x1 = (T)src[(long long)(t0 + 1) * t_stride];
+                v[u][q] = cmk<T>(x0, x1);
+            }
+            dft_small<T, R, false>(v[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int j = j0 + u * JS;
+        if (Ps::live(u, j)) {
+            Z* wb = buf + j * R * RS + s;
+#pragma unroll
+            for (int p = 0; p < R; ++p) wb[p * RS] = v[u][p];
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- real <-> half spectrum, by bin pairs
+// Inverse pre-step: Z[k] = E + i O with E = (X[k] + conj X[M-k]) / 2,
+// O = conj(W^k) (X[k] - conj X[M-k]) / 2.
+template <typename T>
+__device__ __forceinline__ cplx<T> pre_one(cplx<T> xa, cplx<T> xb, cplx<T> w) {
+    const cplx<T> cb = cconj(xb);
+    const cplx<T> e = cadd(xa, cb);
+    const cplx<T> o = cmul(cconj(w), csub(xa, cb));
+    return cmk<T>(T(0.5) * (e.x - o.y), T(0.5) * (e.y + o.x));
+}
+
+// Forward post-step: X[k] = (Z[k] + conj Z[M-k]) / 2 - (i/2) W^k (Z[k] - conj Z[M-k]).
+template <typename T>
+__device__ __forceinline__ cplx<T> post_one(cplx<T> a, cplx<T> b, cplx<T> w) {
+    const cplx<T> cb = cconj(b);
+    const cplx<T> sum = cadd(a, cb);
+    const cplx<T> t = cmul(w, csub(a, cb));
+    return cmk<T>(T(0.5) * (sum.x + t.y), T(0.5) * (sum.y - t.x));
+}
+
+// Half spectra X[0..M] (sum of nparts partials; zero for a series past S)
+// into Z[0..M-1] on the tile.  Bins 0 and M are taken as real.
+template <typename T, int M, int SH>
+__device__ __forceinline__ void load_pre(cplx<T>* buf, const cplx<T>* twq, const cplx<T>* __restrict__ src,
+                                         const SeriesIO& io, bool ok, int s, int j0) {
+    using Z = cplx<T>;
+    using G = Geo<M, SH>;
+    constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
+    Z xa[NU], xb[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) xa[u] = xb[u] = cmk<T>(T(0), T(0));
+    if (ok) {
+        for (int part = 0; part < io.nparts; ++part) {
+            const Z* sp = src + (long long)part * io.f_part;
+            Z va[NU], vb[NU];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = j0 + u * JS;
+                if (u < NU - 1 || k < G::NPAIR) {
+                    va[u] = sp[(long long)k * io.f_stride];
+                    vb[u] = sp[(long long)(M - k) * io.f_stride];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = j0 + u * JS;
+                if (u < NU - 1 || k < G::NPAIR) {
+                    xa[u] = cadd(xa[u], va[u]);
+                    xb[u] = cadd(xb[u], vb[u]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int k = j0 + u * JS;
+        if (u < NU - 1 || k < G::NPAIR) {
+            Z a = xa[u], b = xb[u];
+            if (u == 0 && k == 0) { a.y = T(0); b.y = T(0); }
+            const Z w = twq[k];
+            buf[k * RS + s] = pre_one<T>(a, b, w);
+            if ((u > 0 || k > 0) && 2 * k != M) buf[(M - k) * RS + s] = pre_one<T>(b, a, cmk<T>(-w.x, w.y));
+        }
+    }
+    __syncthreads();
+}
+
+// Half spectra X[0..M] from Z[0..M-1] on the tile, to row[k f_stride + s0 + s]
+// (complex, or quad BF16 hi/lo for FP32 with io.quad) for series below S_pad.
+template <typename T, int M, int SH>
+__device__ __forceinline__ void post_store(const cplx<T>* buf, const cplx<T>* twq, const SeriesIO& io,
+                                           cplx<T>* row, int s0, int s, int j0) {
+    using Z = cplx<T>;
+    using G = Geo<M, SH>;
+    constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
+    const bool ok = s0 + s < io.S_pad;
+    auto put = [&](int k, Z X) {
+        if constexpr (sizeof(T) == sizeof(float)) {
+            if (io.quad) {
+                store_quad(reinterpret_cast<uint32_t*>(row) + 2 * (long long)k * io.f_stride, s0 + s, X.x, X.y);
+                return;
+            }
+        }
+        row[(long long)k * io.f_stride + s0 + s] = X;
+    };
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int k = j0 + u * JS;
+        if (u < NU - 1 || k < G::NPAIR) {
+            const int km = (u == 0 && k == 0) ? 0 : M - k;     // Z is M-periodic
+            const Z a = buf[k * RS + s], b = buf[km * RS + s];
+            const Z w = twq[k];
+            const Z xk = post_one<T>(a, b, w);
+            const Z xm = post_one<T>(b, a, cmk<T>(-w.x, w.y));
+            if (ok) {
+                put(k, xk);
+                if (2 * k != M) put(M - k, xm);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+// Persistent item loop: workgroup b runs on XCD b % 8 and takes the items
+// x Q + i, i = b / 8, b / 8 + G / 8, ... of that XCD's share [x Q, (x + 1) Q)
+// (G = grid size, a multiple of 8): at any time the workgroups of one XCD
+// work on adjacent tiles.
+template <typename T, typename TIN, int M, int SH>
+__global__ __launch_bounds__(kFxThreads) void k_r2c_fx(SeriesIO io, const TIN* __restrict__ in,
+                                                       cplx<T>* __restrict__ out, const cplx<T>* __restrict__ twg,
+                                                       ItemMap im) {
+    using Z = cplx<T>;
+    using G = Geo<M, SH>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    Z* twq = buf + G::TILE;
+    Z* twf = twq + G::NPAIR;
+    stage_pair_tw<T, M, SH>(twq, twg);
+    stage_pass_tw<T, M, SH, false>(twf, twg);
+    __syncthreads();
+    const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
+    const int xq = (int)(blockIdx.x & 7) * im.Q, nper = (int)(gridDim.x >> 3);
+    for (int i = (int)(blockIdx.x >> 3); i < im.Q && xq + i < im.items; i += nper) {
+        const int outer = (xq + i) / im.ntiles, tile = xq + i - outer * im.ntiles;
+        // Fresh copies of the lane indices each tile: otherwise every address
+        // derived from them is hoisted out of the loop and held in registers.
+        int s = s_, j0 = j0_;
+        asm volatile("" : "+v"(s), "+v"(j0));
+        const int s0 = tile << SH;
+        const int nt = active_len(io, outer);
+        first_pass_from_time<T, TIN, M, SH>(buf, in + (long long)outer * io.t_outer + s0 + s, io.t_stride,
+                                            s0 + s < io.S, nt, s, j0);
+        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
+        post_store<T, M, SH>(buf, twq, io, out + (long long)outer * io.f_outer, s0, s, j0);
+        __syncthreads();
+    }
+}
+
+template <typename T, typename TOUT, int M, int SH, int EPI>
+__global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T>* __restrict__ in,
+                                                       TOUT* __restrict__ out, const cplx<T>* __restrict__ twg,
+                                                       MisfitArgs ma, ItemMap im) {
+    using Z = cplx<T>;
+    using G = Geo<M, SH>;
+    using Pl = Pass<M, SH, true, G::NP - 1>;
+    constexpr int R = Pl::R, NS = Pl::NS, MR = Pl::MR, NU = Pl::NU, RS = G::RS, JS = G::JS;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    Z* twq = buf + G::TILE;
+    Z* twr = twq + G::NPAIR;
+    stage_pair_tw<T, M, SH>(twq, twg);
+    stage_pass_tw<T, M, SH, true>(twr, twg);
+    __syncthreads();
+    const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
+    const T inv = T(1) / T(M);
+    const int xq = (int)(blockIdx.x & 7) * im.Q, nper = (int)(gridDim.x >> 3);
+    for (int i = (int)(blockIdx.x >> 3); i < im.Q && xq + i < im.items; i += nper) {
+        const int outer = (xq + i) / im.ntiles, tile = xq + i - outer * im.ntiles;
+        // Fresh copies of the lane indices each tile: otherwise every address
+        // derived from them is hoisted out of the loop and held in registers.
+        int s = s_, j0 = j0_;
+        asm volatile("" : "+v"(s), "+v"(j0));
+        const int s0 = tile << SH;
+        const int col = s0 + s;
+        const bool ok = col < io.S;
+        const int nt = active_len(io, outer);
+        load_pre<T, M, SH>(buf, twq, in + (long long)outer * io.f_outer + col, io, ok, s, j0);
+        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
+        // last inverse pass: butterfly j (< MR = NS) writes z[j + p NS] straight to the time series
+        Z v[NU][R];
+        const Z* rb = buf + j0 * RS + s;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int j = j0 + u * JS;
+            if (Pl::live(u, j)) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) v[u][q] = rb[(u * JS + q * MR) * RS];
+                apply_tw<T, R, true>(v[u], twr + Pl::TOFF + j * (R - 1));
+                dft_small<T, R, true>(v[u]);
+            }
+        }
+        TOUT* dst = out + (long long)outer * io.t_outer + col;
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int j = j0 + u * JS;
+            if (ok && Pl::live(u, j)) {
+#pragma unroll
+                for (int p = 0; p < R; ++p) {
+                    const int n = j + p * NS;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int t = 2 * n + h;
+                        if (t < io.Nt) {
+                            const T y = (h == 0 ? v[u][p].x : v[u][p].y) * inv;
+                            const long long off = (long long)t * io.t_stride;
+                            if constexpr (EPI == EPI_PLAIN) {
+                                dst[off] = (t < nt) ? (TOUT)y : TOUT(0);
+                            } else {
+                                const TOUT* dob = reinterpret_cast<const TOUT*>(ma.d_obs) + (long long)outer * io.t_outer + col;
+                                double wv = 0.0;
+                                if (t < nt) {
+                                    const double var = ma.var_mode == 0 ? ma.var[0]
+                                                     : ma.var_mode == 1 ? ma.var[col]
+                                                                        : ma.var[(long long)t * io.S + col];
+                                    const double r = (double)y - (double)dob[off];
+                                    wv = r / var;
+                                    acc += r * wv;
+                                }
+                                dst[off] = (TOUT)wv;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();                       // tile reads done: the LDS is free
+        if constexpr (EPI == EPI_MISFIT) {
+            static_assert(G::TILE * sizeof(Z) >= kFxThreads * sizeof(double), "reduction fits in the tile");
+            double* red = reinterpret_cast<double*>(smem_raw);
+            red[threadIdx.x] = acc;
+            __syncthreads();
+            for (int w = kFxThreads / 2; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) ma.partials[(long long)outer * im.ntiles + tile] = red[0];
+            __syncthreads();
+        }
+    }
+}
+
+// Truncate-and-repad (see k_project in fft.hip), written over partial 0.
+template <typename T, int M, int SH>
+__global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>* in_out,
+                                                           const cplx<T>* __restrict__ twg, ItemMap im) {
+    using Z = cplx<T>;
+    using G = Geo<M, SH>;
+    using Pl = Pass<M, SH, true, G::NP - 1>;    // last inverse pass
+    using Pf = Pass<M, SH, false, 0>;           // first forward pass: same radix, same index sets
+    static_assert(Pl::R == Pf::R && Pl::NS == Pf::MR, "reversed order ends with the forward order's first radix");
+    constexpr int R = Pl::R, MR = Pl::MR, NU = Pl::NU, RS = G::RS, JS = G::JS;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    Z* twq = buf + G::TILE;
+    Z* twf = twq + G::NPAIR;
+    Z* twr = twf + (M - 1);
+    stage_pair_tw<T, M, SH>(twq, twg);
+    stage_pass_tw<T, M, SH, false>(twf, twg);
+    stage_pass_tw<T, M, SH, true>(twr, twg);
+    __syncthreads();
+    const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
+    const T inv = T(1) / T(M);
+    const int xq = (int)(blockIdx.x & 7) * im.Q, nper = (int)(gridDim.x >> 3);
+    for (int i = (int)(blockIdx.x >> 3); i < im.Q && xq + i < im.items; i += nper) {
+        const int outer = (xq + i) / im.ntiles, tile = xq + i - outer * im.ntiles;
+        // Fresh copies of the lane indices each tile: otherwise every address
+        // derived from them is hoisted out of the loop and held in registers.
+        int s = s_, j0 = j0_;
+        asm volatile("" : "+v"(s), "+v"(j0));
+        const int s0 = tile << SH;
+        const int nt = active_len(io, outer);
+        Z* base = in_out + (long long)outer * io.f_outer;
+        load_pre<T, M, SH>(buf, twq, base + s0 + s, io, s0 + s < io.S, s, j0);
+        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
+        // last inverse pass -> z[j + p MR]; keep t < nt (t = 2n, 2n + 1) and
+        // scale by 1 / M; first forward pass on the same entries
+        Z v[NU][R];
+        const Z* rb = buf + j0 * RS + s;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int j = j0 + u * JS;
+            if (Pl::live(u, j)) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) v[u][q] = rb[(u * JS + q * MR) * RS];
+                apply_tw<T, R, true>(v[u], twr + Pl::TOFF + j * (R - 1));
+                dft_small<T, R, true>(v[u]);
+#pragma unroll
+                for (int p = 0; p < R; ++p) {
+                    const int n = j + p * MR;
+                    v[u][p].x = (2 * n < nt) ? v[u][p].x * inv : T(0);
+                    v[u][p].y = (2 * n + 1 < nt) ? v[u][p].y * inv : T(0);
+                }
+                dft_small<T, R, false>(v[u]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int j = j0 + u * JS;
+            if (Pl::live(u, j)) {
+                Z* wb = buf + j * R * RS + s;
+#pragma unroll
+                for (int p = 0; p < R; ++p) wb[p * RS] = v[u][p];
+            }
+        }
+        __syncthreads();
+        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
+        post_store<T, M, SH>(buf, twq, io, base, s0, s, j0);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- host side
+template <int M, int SH>
+constexpr size_t fx_lds(size_t zbytes, int ntables) {
+    return ((size_t)Geo<M, SH>::TILE + Geo<M, SH>::NPAIR + (size_t)ntables * (M - 1)) * zbytes;
+}
+
+// Grid of resident workgroups for kernel K (occupancy per CU cached per
+// kernel; the CU count is queried each time), at most 8 Q.
+template <auto K>
+dim3 fx_grid(size_t lds, const ItemMap& im) {
+    static int occ = 0;
+    if (occ == 0) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, K, kFxThreads, lds) != hipSuccess || o < 1) o = 1;
+        occ = o;
+    }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    const int per_xcd = (occ * ncu + 7) / 8;
+    return dim3(8 * (unsigned)std::max(1, std::min(im.Q, per_xcd)));
+}
+
+ItemMap fx_items(int S, int sh, int outer) {
+    ItemMap im;
+    im.ntiles = (S + (1 << sh) - 1) >> sh;
+    im.items = im.ntiles * outer;
+    im.Q = (im.items + 7) / 8;
+    return im;
+}
+
+template <typename T, int M, int SH>
+hipError_t fx_r2c(bool in_f64, const SeriesIO& io, const void* in, void* out, const void* tw, hipStream_t st) {
+    const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
+    if (im.items == 0) return hipSuccess;
+    const size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 1);
+    if (in_f64) {
+        constexpr auto k = k_r2c_fx<T, double, M, SH>;
+        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const double*)in, (cplx<T>*)out,
+                           (const cplx<T>*)tw, im);
+    } else {
+        constexpr auto k = k_r2c_fx<T, float, M, SH>;
+        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const float*)in, (cplx<T>*)out,
+                           (const cplx<T>*)tw, im);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int M, int SH>
+hipError_t fx_c2r(const SeriesIO& io, const void* in, void* out, const void* tw, const MisfitArgs& ma,
+                  hipStream_t st) {
+    const ItemMap im = fx_items(io.S, SH, io.outer_count);
+    if (im.items == 0) return hipSuccess;
+    size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 1);
+    if (lds < kFxThreads * sizeof(double)) lds = kFxThreads * sizeof(double);
+    if (ma.d_obs) {
+        constexpr auto k = k_c2r_fx<T, T, M, SH, EPI_MISFIT>;
+        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const cplx<T>*)in, (T*)out,
+                           (const cplx<T>*)tw, ma, im);
+    } else {
+        constexpr auto k = k_c2r_fx<T, T, M, SH, EPI_PLAIN>;
+        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const cplx<T>*)in, (T*)out,
+                           (const cplx<T>*)tw, ma, im);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int M, int SH>
+hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStream_t st) {
+    const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
+    if (im.items == 0) return hipSuccess;
+    const size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 2);
+    constexpr auto k = k_project_fx<T, M, SH>;
+    hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (cplx<T>*)in_out, (const cplx<T>*)tw, im);
+    return hipGetLastError();
+}
+
+// Compiled (M, tile shift) pairs: the transform lengths of the common
+// workloads (Nt = 16, 128, 420), with the tile widths fft_tile_shift picks.
+#define P2O_FX_CASES(X) \
+    X(float, 16, 5)     \
+    X(float, 128, 4)    \
+    X(float, 420, 3)    \
+    X(double, 16, 5)    \
+    X(double, 128, 3)   \
+    X(double, 420, 2)
+
+}  // namespace
+
+bool launch_fixed_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
+                      const void* tw, int sh, hipStream_t st, hipError_t* err) {
+    if (!pl.fixed) return false;
+#define X(T, M_, SH_)                                                                  \
+    if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
+        *err = fx_r2c<T, M_, SH_>(in_f64, io, in, out, tw, st);                        \
+        return true;                                                                   \
+    }
+    P2O_FX_CASES(X)
+#undef X
+    return false;
+}
+
+bool launch_fixed_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
+                      int sh, const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st,
+                      hipError_t* err) {
+    if (!pl.fixed) return false;
+    const MisfitArgs ma{d_obs, var, var_mode, partials};
+#define X(T, M_, SH_)                                                                  \
+    if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
+        *err = fx_c2r<T, M_, SH_>(io, in, out, tw, ma, st);                            \
+        return true;                                                                   \
+    }
+    P2O_FX_CASES(X)
+#undef X
+    return false;
+}
+
+bool launch_fixed_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,
+                          hipStream_t st, hipError_t* err) {
+    if (!pl.fixed) return false;
+#define X(T, M_, SH_)                                                                  \
+    if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
+        *err = fx_project<T, M_, SH_>(io, in_out, tw, st);                             \
+        return true;                                                                   \
+    }
+    P2O_FX_CASES(X)
+#undef X
+    return false;
+}
+
+}  // namespace p2o

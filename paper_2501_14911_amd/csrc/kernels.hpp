@@ -61,6 +61,17 @@ hipError_t launch_load(int prec, bool in_f64, const FftPlan& pl, const LoadArgs&
 hipError_t launch_zero_pad(void* fhat, long long rows, int pitch, int Nm, int bytes, hipStream_t st);
 int load_tile_shift(int M);
 
+// fft_fixed.hip: kernels compiled for fixed transform lengths.  Each returns
+// false when there is none for (M, tile shift, precision) or the plan turned
+// them off (pl.fixed == 0); otherwise it launches and sets *err.
+bool launch_fixed_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
+                      const void* tw, int sh, hipStream_t st, hipError_t* err);
+bool launch_fixed_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
+                      int sh, const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st,
+                      hipError_t* err);
+bool launch_fixed_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,
+                          hipStream_t st, hipError_t* err);
+
 // gemv.hip
 int gemv_cols_per_lane(int prec);
 int gemv_fwd_chunks(int prec, int pitch);

@@ -99,6 +99,11 @@ class P2OOperator:
         both directions, or -1 for the autotuned or built-in choice."""
         check(lib.p2o_set_option(self._plan, 1, int(tile)))
 
+    def set_fixed_fft(self, on: bool = True):
+        """Use the FFT kernels compiled for this plan's transform length when
+        the library has them (default), or always the runtime-length ones."""
+        check(lib.p2o_set_option(self._plan, 2, 1 if on else 0))
+
     def autotune(self, nrhs: int, reps: int = 3) -> dict:
         """Time every matrix-core tile variant for calls with ``nrhs``
         right-hand sides and keep the fastest (per direction) for later calls
