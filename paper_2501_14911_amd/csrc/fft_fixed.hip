@@ -100,6 +100,20 @@ struct Pass {
     }
 };
 
+// Active length of a right-hand side, read without a branch (from this
+// constant when the call has no per-right-hand-side lengths) so that the
+// load can be issued early and waited for only where the length is used.
+__device__ const int kNoLimit = 0x7fffffff;
+
+__device__ __forceinline__ int active_raw(const SeriesIO& io, int outer) {
+    typedef const __attribute__((address_space(1))) int gint;   // global memory: a plain vector load
+    gint* p = io.nt_active ? (gint*)(io.nt_active + outer) : (gint*)&kNoLimit;
+    return *p;
+}
+__device__ __forceinline__ int active_clamp(const SeriesIO& io, int raw) {
+    return raw < 0 ? 0 : (raw < io.Nt ? raw : io.Nt);
+}
+
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
     if constexpr (B < E) {
@@ -112,6 +126,20 @@ template <typename T, int R, bool INV>
 __device__ __forceinline__ void apply_tw(cplx<T>* v, const cplx<T>* t) {
 #pragma unroll
     for (int q = 1; q < R; ++q) v[q] = cmul(v[q], INV ? cconj(t[q - 1]) : t[q - 1]);
+}
+
+// Element at byte offset `off` from a workgroup-uniform base.  Bases advance
+// by whole sweeps of bins or time steps (uniform arithmetic); the per-lane
+// part is a 32-bit offset of fewer than JS bins or 2 JS time steps (the
+// launchers check that it fits), so each access costs at most one address
+// add instead of a 64-bit multiply-add.
+template <typename E>
+__device__ __forceinline__ E ld(const E* base, uint32_t off) {
+    return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename E>
+__device__ __forceinline__ void st(E* base, uint32_t off, E v) {
+    *reinterpret_cast<E*>(reinterpret_cast<char*>(base) + off) = v;
 }
 
 // ---------------------------------------------------------------- twiddle staging
@@ -169,11 +197,15 @@ __device__ __forceinline__ void lds_pass(cplx<T>* buf, const cplx<T>* tab, int s
     __syncthreads();
 }
 
-// First forward pass fed by the time series: z[n] = x[2n] + i x[2n+1],
-// x[t] = 0 for t >= nt or for a series past S (ok false).
+// First forward pass fed by the time series (src: series s0 at t = 0; lane
+// s reads series s0 + s): z[n] = x[2n] + i x[2n+1], x[t] = 0 for t >= nt or
+// for a series past S (ok false).
 template <typename T, typename TIN, int M, int SH>
 __device__ __forceinline__ void first_pass_from_time(cplx<T>* buf, const TIN* __restrict__ src, long long t_stride,
                                                      bool ok, int nt, int s, int j0) {
+    const uint32_t ts = (uint32_t)t_stride * (uint32_t)sizeof(TIN);
+    uint32_t o0 = 2u * (uint32_t)j0 * ts + (uint32_t)s * (uint32_t)sizeof(TIN);   // t = 2 j0 from the sweep base
+    asm volatile("" : "+v"(o0));
     using Z = cplx<T>;
     using G = Geo<M, SH>;
     using Ps = Pass<M, SH, false, 0>;
@@ -187,8 +219,9 @@ __device__ __forceinline__ void first_pass_from_time(cplx<T>* buf, const TIN* __
             for (int q = 0; q < R; ++q) {
                 const int t0 = 2 * (j + q * MR);
                 T x0 = T(0), x1 = T(0);
-                if (ok && t0 < nt) x0 = (T)src[(long long)t0 * t_stride];
-                if (ok && t0 + 1 < nt) x1 = (T)src[(long long)(t0 + 1) * t_stride];
+                const TIN* sb = src + (long long)(2 * (u * JS + q * MR)) * t_stride;   // t = 2 (u JS + q MR)
+                if (ok && t0 < nt) x0 = (T)ld(sb, o0);
+                if (ok && t0 + 1 < nt) x1 = (T)ld(sb, o0 + ts);
                 v[u][q] = cmk<T>(x0, x1);
             }
             dft_small<T, R, false>(v[u]);
@@ -227,37 +260,49 @@ __device__ __forceinline__ cplx<T> post_one(cplx<T> a, cplx<T> b, cplx<T> w) {
 }
 
 // Half spectra X[0..M] (sum of nparts partials; zero for a series past S)
-// into Z[0..M-1] on the tile.  Bins 0 and M are taken as real.
+// into Z[0..M-1] on the tile.  Bins 0 and M are taken as real.  src: series
+// s0 of bin 0 of partial 0; lane s reads series s0 + s.
 template <typename T, int M, int SH>
 __device__ __forceinline__ void load_pre(cplx<T>* buf, const cplx<T>* twq, const cplx<T>* __restrict__ src,
                                          const SeriesIO& io, bool ok, int s, int j0) {
     using Z = cplx<T>;
     using G = Geo<M, SH>;
     constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
+    // bin k = j0 + u JS: base row u JS, lane offset j0 rows; bin M - k: base
+    // row M - (JS - 1) - u JS, lane offset JS - 1 - j0 rows
+    static_assert(M - (JS - 1) - (NU - 1) * JS >= 0, "partner rows start inside the spectrum");
+    const uint32_t fs = (uint32_t)io.f_stride * (uint32_t)sizeof(Z), so = (uint32_t)s * (uint32_t)sizeof(Z);
+    const uint32_t oa = (uint32_t)j0 * fs + so, ob = (uint32_t)(JS - 1 - j0) * fs + so;
     Z xa[NU], xb[NU];
+    auto gather = [&](const Z* sp, Z (&va)[NU], Z (&vb)[NU]) {
+        // opaque copies: keeps each offset computation next to its load, where
+        // it is matched as a 32-bit offset from a scalar base
+        uint32_t a0 = oa, b0 = ob;
+        asm volatile("" : "+v"(a0), "+v"(b0));
 #pragma unroll
-    for (int u = 0; u < NU; ++u) xa[u] = xb[u] = cmk<T>(T(0), T(0));
-    if (ok) {
-        for (int part = 0; part < io.nparts; ++part) {
-            const Z* sp = src + (long long)part * io.f_part;
-            Z va[NU], vb[NU];
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                const int k = j0 + u * JS;
-                if (u < NU - 1 || k < G::NPAIR) {
-                    va[u] = sp[(long long)k * io.f_stride];
-                    vb[u] = sp[(long long)(M - k) * io.f_stride];
-                }
+        for (int u = 0; u < NU; ++u) {
+            if (u < NU - 1 || j0 + u * JS < G::NPAIR) {
+                va[u] = ld(sp + (long long)(u * JS) * io.f_stride, a0);
+                vb[u] = ld(sp + (long long)(M - (JS - 1) - u * JS) * io.f_stride, b0);
             }
+        }
+    };
+    if (ok) {
+        gather(src, xa, xb);
+        for (int part = 1; part < io.nparts; ++part) {
+            Z va[NU], vb[NU];
+            gather(src + (long long)part * io.f_part, va, vb);
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                const int k = j0 + u * JS;
-                if (u < NU - 1 || k < G::NPAIR) {
+                if (u < NU - 1 || j0 + u * JS < G::NPAIR) {
                     xa[u] = cadd(xa[u], va[u]);
                     xb[u] = cadd(xb[u], vb[u]);
                 }
             }
         }
+    } else {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) xa[u] = xb[u] = cmk<T>(T(0), T(0));
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -282,14 +327,29 @@ __device__ __forceinline__ void post_store(const cplx<T>* buf, const cplx<T>* tw
     using G = Geo<M, SH>;
     constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
     const bool ok = s0 + s < io.S_pad;
-    auto put = [&](int k, Z X) {
+    // quad storage: series c of a bin is word 8 (c / 4) + c % 4 (hi) and 4 words
+    // further (lo) from the bin's first word; tiles start at multiples of 4
+    bool quad = false;
+    if constexpr (sizeof(T) == sizeof(float)) quad = io.quad != 0;
+    static_assert(M - (JS - 1) - (NU - 1) * JS >= 0, "partner rows start inside the spectrum");
+    Z* const rb = row + s0;
+    const uint32_t fs = (uint32_t)io.f_stride * (uint32_t)sizeof(Z);
+    const uint32_t lo_ = quad ? (uint32_t)(8 * (s >> 2) + (s & 3)) * 4u : (uint32_t)s * (uint32_t)sizeof(Z);
+    // bins k = j0 + u JS and M - k from base rows u JS and M - (JS - 1) - u JS
+    uint32_t oa = (uint32_t)j0 * fs + lo_, ob = (uint32_t)(JS - 1 - j0) * fs + lo_;
+    asm volatile("" : "+v"(oa), "+v"(ob));
+    auto put = [&](Z* rbase, uint32_t off, Z X) {
         if constexpr (sizeof(T) == sizeof(float)) {
-            if (io.quad) {
-                store_quad(reinterpret_cast<uint32_t*>(row) + 2 * (long long)k * io.f_stride, s0 + s, X.x, X.y);
+            if (quad) {
+                const uint32_t hi = pack_bf16_rne(X.x, X.y);
+                const uint32_t lo = pack_bf16_rne(X.x - __uint_as_float(hi << 16), X.y - __uint_as_float(hi & 0xffff0000u));
+                uint32_t* qb = reinterpret_cast<uint32_t*>(rbase);
+                st(qb, off, hi);
+                st(qb, off + 16u, lo);
                 return;
             }
         }
-        row[(long long)k * io.f_stride + s0 + s] = X;
+        st(rbase, off, X);
     };
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -301,8 +361,8 @@ __device__ __forceinline__ void post_store(const cplx<T>* buf, const cplx<T>* tw
             const Z xk = post_one<T>(a, b, w);
             const Z xm = post_one<T>(b, a, cmk<T>(-w.x, w.y));
             if (ok) {
-                put(k, xk);
-                if (2 * k != M) put(M - k, xm);
+                put(rb + (long long)(u * JS) * io.f_stride, oa, xk);
+                if (2 * k != M) put(rb + (long long)(M - (JS - 1) - u * JS) * io.f_stride, ob, xm);
             }
         }
     }
@@ -335,8 +395,8 @@ __global__ __launch_bounds__(kFxThreads) void k_r2c_fx(SeriesIO io, const TIN* _
         int s = s_, j0 = j0_;
         asm volatile("" : "+v"(s), "+v"(j0));
         const int s0 = tile << SH;
-        const int nt = active_len(io, outer);
-        first_pass_from_time<T, TIN, M, SH>(buf, in + (long long)outer * io.t_outer + s0 + s, io.t_stride,
+        const int nt = active_clamp(io, active_raw(io, outer));
+        first_pass_from_time<T, TIN, M, SH>(buf, in + (long long)outer * io.t_outer + s0, io.t_stride,
                                             s0 + s < io.S, nt, s, j0);
         static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
         post_store<T, M, SH>(buf, twq, io, out + (long long)outer * io.f_outer, s0, s, j0);
@@ -371,8 +431,9 @@ __global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T
         const int s0 = tile << SH;
         const int col = s0 + s;
         const bool ok = col < io.S;
-        const int nt = active_len(io, outer);
-        load_pre<T, M, SH>(buf, twq, in + (long long)outer * io.f_outer + col, io, ok, s, j0);
+        const int nt_raw = active_raw(io, outer);      // used after the transform
+        load_pre<T, M, SH>(buf, twq, in + (long long)outer * io.f_outer + s0, io, ok, s, j0);
+        const int nt = active_clamp(io, nt_raw);
         static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
         // last inverse pass: butterfly j (< MR = NS) writes z[j + p NS] straight to the time series
         Z v[NU][R];
@@ -387,7 +448,10 @@ __global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T
                 dft_small<T, R, true>(v[u]);
             }
         }
-        TOUT* dst = out + (long long)outer * io.t_outer + col;
+        TOUT* dst = out + (long long)outer * io.t_outer + s0;
+        const uint32_t ts = (uint32_t)io.t_stride * (uint32_t)sizeof(TOUT);
+        uint32_t o0 = 2u * (uint32_t)j0 * ts + (uint32_t)s * (uint32_t)sizeof(TOUT);   // t = 2 j0
+        asm volatile("" : "+v"(o0));
         double acc = 0.0;
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
@@ -401,21 +465,22 @@ __global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T
                         const int t = 2 * n + h;
                         if (t < io.Nt) {
                             const T y = (h == 0 ? v[u][p].x : v[u][p].y) * inv;
-                            const long long off = (long long)t * io.t_stride;
+                            const long long trow = 2 * (u * JS + p * NS) + h;   // t - 2 j0
+                            const uint32_t off = o0;
                             if constexpr (EPI == EPI_PLAIN) {
-                                dst[off] = (t < nt) ? (TOUT)y : TOUT(0);
+                                st(dst + trow * io.t_stride, off, (t < nt) ? (TOUT)y : TOUT(0));
                             } else {
-                                const TOUT* dob = reinterpret_cast<const TOUT*>(ma.d_obs) + (long long)outer * io.t_outer + col;
+                                const TOUT* dob = reinterpret_cast<const TOUT*>(ma.d_obs) + (long long)outer * io.t_outer + s0;
                                 double wv = 0.0;
                                 if (t < nt) {
                                     const double var = ma.var_mode == 0 ? ma.var[0]
                                                      : ma.var_mode == 1 ? ma.var[col]
                                                                         : ma.var[(long long)t * io.S + col];
-                                    const double r = (double)y - (double)dob[off];
+                                    const double r = (double)y - (double)ld(dob + trow * io.t_stride, off);
                                     wv = r / var;
                                     acc += r * wv;
                                 }
-                                dst[off] = (TOUT)wv;
+                                st(dst + trow * io.t_stride, off, (TOUT)wv);
                             }
                         }
                     }
@@ -467,9 +532,10 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>*
         int s = s_, j0 = j0_;
         asm volatile("" : "+v"(s), "+v"(j0));
         const int s0 = tile << SH;
-        const int nt = active_len(io, outer);
+        const int nt_raw = active_raw(io, outer);      // used between the transforms
         Z* base = in_out + (long long)outer * io.f_outer;
-        load_pre<T, M, SH>(buf, twq, base + s0 + s, io, s0 + s < io.S, s, j0);
+        load_pre<T, M, SH>(buf, twq, base + s0, io, s0 + s < io.S, s, j0);
+        const int nt = active_clamp(io, nt_raw);
         static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
         // last inverse pass -> z[j + p MR]; keep t < nt (t = 2n, 2n + 1) and
         // scale by 1 / M; first forward pass on the same entries
@@ -597,11 +663,20 @@ hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStrea
     X(double, 128, 3)   \
     X(double, 420, 2)
 
+// Lane offsets of `rows` rows of `stride` elements (plus a tile) fit the
+// 32-bit offsets the kernels use (rows: one sweep, 256 >> shift bins or
+// twice that many time steps).
+bool fits32(long long rows, long long stride, size_t esz) {
+    return (rows * stride + 64) * (long long)esz < (1LL << 31);
+}
+
 }  // namespace
 
 bool launch_fixed_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
                       const void* tw, int sh, hipStream_t st, hipError_t* err) {
-    if (!pl.fixed) return false;
+    const size_t z = f64 ? 16 : 8;
+    const int js = kFxThreads >> sh;
+    if (!pl.fixed || !fits32(2 * js, io.t_stride, in_f64 ? 8 : 4) || !fits32(js, io.f_stride, z)) return false;
 #define X(T, M_, SH_)                                                                  \
     if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
         *err = fx_r2c<T, M_, SH_>(in_f64, io, in, out, tw, st);                        \
@@ -615,7 +690,9 @@ bool launch_fixed_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& 
 bool launch_fixed_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
                       int sh, const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st,
                       hipError_t* err) {
-    if (!pl.fixed) return false;
+    const size_t z = f64 ? 16 : 8;
+    const int js = kFxThreads >> sh;
+    if (!pl.fixed || !fits32(2 * js, io.t_stride, z / 2) || !fits32(js, io.f_stride, z)) return false;
     const MisfitArgs ma{d_obs, var, var_mode, partials};
 #define X(T, M_, SH_)                                                                  \
     if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
@@ -629,7 +706,7 @@ bool launch_fixed_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const voi
 
 bool launch_fixed_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,
                           hipStream_t st, hipError_t* err) {
-    if (!pl.fixed) return false;
+    if (!pl.fixed || !fits32(kFxThreads >> sh, io.f_stride, f64 ? 16 : 8)) return false;
 #define X(T, M_, SH_)                                                                  \
     if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
         *err = fx_project<T, M_, SH_>(io, in_out, tw, st);                             \
