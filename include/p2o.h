@@ -198,12 +198,13 @@ p2o_status p2o_set_option(p2o_plan* plan, int32_t option, int64_t value);
 
 /* Matrix-core tile variants of the batched products (section 4's per-frequency
  * products as complex GEMMs, one per frequency).  Variant `tile` assigns
- * 32 * row_groups * 5 output rows (sensors, or parameter columns for the
+ * 32 * row_groups * blocks output rows (sensors, or parameter columns for the
  * adjoint) and rhs_per_group right-hand sides to a workgroup and stages K in
  * steps of 8 * substeps entries.  Returns P2O_ERR_ARG for an unknown variant;
  * variants are numbered from 0 without gaps, so the first index that fails
  * is the count.  Any output pointer may be NULL. */
-p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* rhs_per_group);
+p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* blocks,
+                              int32_t* rhs_per_group);
 
 /* Autotuner: times every tile variant of the forward and the adjoint
  * matrix-core products with `nrhs` right-hand sides on this plan's loaded

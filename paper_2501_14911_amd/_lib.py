@@ -62,7 +62,7 @@ def _load():
         "p2o_profile_read_nrhs": [pv, c_int32, c_int64, POINTER(c_double), POINTER(c_int64)],
         "p2o_bandwidth_probe": [c_int32, pv, pv, c_size_t, c_int32, pv],
         "p2o_profile_read": [pv, c_int32, POINTER(c_double), POINTER(c_int64)],
-        "p2o_gemm_tile_info": [c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)],
+        "p2o_gemm_tile_info": [c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)],
         "p2o_autotune": [pv, c_int64, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_double),
                          POINTER(c_double)],
     }

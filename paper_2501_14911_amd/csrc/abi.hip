@@ -447,11 +447,14 @@ p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
     return fail(P2O_ERR_ARG, "unknown option %d", (int)option);
 }
 
-p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* rhs_per_group) {
-    int rg = 0, ku = 0;
-    if (gemm_tile_shape(tile, &rg, &ku)) return fail(P2O_ERR_ARG, "tile variant %d not in [0, %d)", (int)tile, gemm_tile_count());
+p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* blocks,
+                              int32_t* rhs_per_group) {
+    int rg = 0, ku = 0, mb = 0;
+    if (gemm_tile_shape(tile, &rg, &ku, &mb))
+        return fail(P2O_ERR_ARG, "tile variant %d not in [0, %d)", (int)tile, gemm_tile_count());
     if (row_groups) *row_groups = rg;
     if (substeps) *substeps = ku;
+    if (blocks) *blocks = mb;
     if (rhs_per_group) *rhs_per_group = 32 * (4 / rg);
     return P2O_OK;
 }

@@ -17,12 +17,12 @@
 // the stored spectrum multiplies finished outputs (exact).
 //
 // Work.  A workgroup is 4 wavefronts: RG row groups x (4 / RG) halves of the
-// right-hand sides, each wavefront computing 5 blocks of 32 output rows
-// (forward: sensors; adjoint: parameter columns) for 32 right-hand sides.
+// right-hand sides, each wavefront computing MB (4 or 5) blocks of 32 output
+// rows (forward: sensors; adjoint: parameter columns) for 32 right-hand sides.
 // Each K step (KU substeps of 8 complex entries) the workgroup stages its
 // spectrum tile and right-hand-side tile in LDS, loaded cooperatively with
 // whole 128-byte lines per 8 lanes: forward rows in runs of 32 (or 16)
-// columns, adjoint sensor rows of 320 (or 640) contiguous columns.  Loads
+// columns, adjoint sensor rows of 256 to 640 contiguous columns.  Loads
 // run two steps ahead through registers into a double buffer, and one
 // barrier per step separates staging from the matrix-core work.  Fragments
 // come from padded LDS rows without bank conflicts: forward lanes read 16
@@ -44,7 +44,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));   // native vector: staged copies stay in registers
 
 constexpr int kGemmThreads = 256;
-constexpr int kGemmMB = 5;                 // 32-row blocks per wavefront
 
 __device__ __forceinline__ f32x16 mfma32(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
@@ -80,10 +79,11 @@ __device__ __forceinline__ void lds_barrier() {
 // consecutive rows hit distinct banks).  ADJ: KC sensor rows x MROWS columns,
 // row stride A_RS with 4 A_RS / 4 = 32 (mod 64) banks, so the two sensor
 // quartets a fragment read covers fall in different bank halves.
-template <bool FWD, int RG, int KU>
+template <bool FWD, int RG, int KU, int MB_>
 struct Tile {
+    static constexpr int MB = MB_;                     // 32-row blocks per wavefront
     static constexpr int NH = 4 / RG;                  // right-hand-side halves of 32
-    static constexpr int MROWS = RG * 32 * kGemmMB;    // output rows per workgroup
+    static constexpr int MROWS = RG * 32 * MB;         // output rows per workgroup
     static constexpr int KC = 8 * KU;                  // complex K entries per step
     static constexpr int RHS = 32 * NH;
     static constexpr int A_RS = FWD ? KC * 4 + 16 : MROWS * 4 + 32;
@@ -110,12 +110,17 @@ struct Staged {
     uint32_t m[BP];
 };
 
-template <bool FWD, int RG, int KU>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm(const uint8_t* fhat, const float* __restrict__ scales,
-                                                       const uint8_t* Bq, float2* __restrict__ out_base,
-                                                       GemmArgs ga) {
-    using T = Tile<FWD, RG, KU>;
-    constexpr int MB = kGemmMB;
+// WPE: wavefronts per SIMD the register allocation must allow (2: the
+// accumulators share the 256 registers of a wavefront with everything else).
+// PF: steps staged in registers ahead of the LDS double buffer (2, or 1 to
+// fit two wavefronts per SIMD; the other workgroup on the CU then covers the
+// shorter lead).
+template <bool FWD, int RG, int KU, int MB_, int WPE, int PF>
+__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq, float2* __restrict__ out_base,
+            GemmArgs ga) {
+    using T = Tile<FWD, RG, KU, MB_>;
+    constexpr int MB = MB_;
     __shared__ __align__(16) uint8_t as[2][T::A_BYTES];
     __shared__ __align__(16) v4u bfr[2][KU][T::NH][2][64];
 
@@ -238,29 +243,44 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const uint8_t* fhat, cons
         }
     };
 
-    // Step st: store step st+1 (loaded two steps earlier) into the LDS
-    // buffer step st-1 read; load step st+3 into the freed registers; compute
+    // Step st: store step st+1 (loaded PF steps earlier) into the LDS buffer
+    // step st-1 read; load step st+1+PF into the freed registers; compute
     // step st; barrier.  Loads retire in order and step st+1 was issued
-    // before step st+2, so waiting for it leaves two steps in flight.  Loads
-    // past the last step repeat it (A) or read zeros (B) and are never used.
+    // before the later ones, so waiting for it leaves PF-1 steps in flight.
+    // Loads past the last step repeat it (A) or read zeros (B) and are never
+    // used.
     auto step = [&](S& sn, int buf, int st) {
         store(sn, buf ^ 1);
-        load(sn, st + 3);
+        load(sn, st + 1 + PF);
         compute(buf);
         lds_barrier();
     };
-    S s0, s1;
-    load(s0, 0);
-    load(s1, 1);
-    store(s0, 0);
-    load(s0, 2);
-    lds_barrier();
-    int st = 0;
-    for (; st + 2 <= nst; st += 2) {
-        step(s1, 0, st);
-        step(s0, 1, st + 1);
+    if constexpr (PF == 2) {
+        S s0, s1;
+        load(s0, 0);
+        load(s1, 1);
+        store(s0, 0);
+        load(s0, 2);
+        lds_barrier();
+        int st = 0;
+        for (; st + 2 <= nst; st += 2) {
+            step(s1, 0, st);
+            step(s0, 1, st + 1);
+        }
+        if (st < nst) step(s1, 0, st);
+    } else {
+        S s0;
+        load(s0, 0);
+        store(s0, 0);
+        load(s0, 1);
+        lds_barrier();
+        int st = 0;
+        for (; st + 2 <= nst; st += 2) {
+            step(s0, 0, st);
+            step(s0, 1, st + 1);
+        }
+        if (st < nst) step(s0, 0, st);
     }
-    if (st < nst) step(s1, 0, st);
 
     // output tile (32 rows x 32 right-hand sides): lane (n, h) holds rows
     // 8 (v / 4) + 4 h + v % 4 of column n in element v
@@ -297,35 +317,42 @@ int gemm_fwd_kchunks(int pitch) { return (pitch + kScaleBlock - 1) / kScaleBlock
 
 int gemm_data_pitch(int Nd) { return (Nd + 7) / 8 * 8; }
 
-template <bool FWD, int RG, int KU>
+template <bool FWD, int RG, int KU, int MB, int WPE, int PF>
 static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
                               hipStream_t st) {
-    using T = Tile<FWD, RG, KU>;
+    using T = Tile<FWD, RG, KU, MB>;
     ga.n_mt = ((FWD ? ga.Nd : ga.pitch) + T::MROWS - 1) / T::MROWS;
     ga.n_bg = (ga.nrhs + T::RHS - 1) / T::RHS;
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
-    hipLaunchKernelGGL((k_gemm<FWD, RG, KU>), dim3(8 * ga.Q), dim3(kGemmThreads), 0, st, (const uint8_t*)fhat,
+    hipLaunchKernelGGL((k_gemm<FWD, RG, KU, MB, WPE, PF>), dim3(8 * ga.Q), dim3(kGemmThreads), 0, st, (const uint8_t*)fhat,
                        scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
 }
 
-// Tile variants (row groups RG, substeps per step KU): 32 (4 / RG) x 2
-// right-hand sides and 160 RG output rows per workgroup, K steps of 8 KU
-// entries.  The built-in choice takes 64-wide groups for 33 or more
-// right-hand sides; a plan's autotuner may pick another.
+// Tile variants (row groups RG, substeps per step KU, 32-row blocks per
+// wavefront MB, wavefronts per SIMD WPE): 32 (4 / RG) right-hand sides and
+// 32 MB RG output rows per workgroup, K steps of 8 KU entries.  MB = 5 fits
+// 600-sensor forward tiles (two of 320 or one of 640 rows); MB = 4 keeps the
+// accumulators at 128 registers so that two workgroups share a CU, which
+// lets one workgroup's loads run under another's prologue and epilogue (the
+// adjoint's 256-column tiles also divide 4096-column blocks evenly).  The
+// built-in choice takes 64-wide groups for 33 or more right-hand sides; a
+// plan's autotuner may pick another.
 struct TileShape {
-    int rg, ku;
+    int rg, ku, mb, wpe, pf;
 };
-static const TileShape kTiles[] = {{2, 4}, {2, 2}, {4, 2}};
+static const TileShape kTiles[] = {{2, 4, 5, 1, 2}, {2, 2, 5, 1, 2}, {4, 2, 5, 1, 2}, {2, 2, 4, 2, 2},
+                                   {4, 2, 4, 2, 2}, {2, 2, 5, 2, 1}};
 constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_tile_count() { return kTileCount; }
 
-int gemm_tile_shape(int tile, int* rg, int* ku) {
+int gemm_tile_shape(int tile, int* rg, int* ku, int* mb) {
     if (tile < 0 || tile >= kTileCount) return -1;
     *rg = kTiles[tile].rg;
     *ku = kTiles[tile].ku;
+    *mb = kTiles[tile].mb;
     return 0;
 }
 
@@ -339,9 +366,12 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     ga.n_kc = gemm_fwd_kchunks(ga.pitch);
     if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs);
     switch (tile) {
-        case 0: return launch_tile<true, 2, 4>(ga, fhat, scales, Xq, Yp, st);
-        case 1: return launch_tile<true, 2, 2>(ga, fhat, scales, Xq, Yp, st);
-        default: return launch_tile<true, 4, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 1: return launch_tile<true, 2, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 2: return launch_tile<true, 4, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 3: return launch_tile<true, 2, 2, 4, 2, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 4: return launch_tile<true, 4, 2, 4, 2, 2>(ga, fhat, scales, Xq, Yp, st);
+        default: return launch_tile<true, 2, 2, 5, 2, 1>(ga, fhat, scales, Xq, Yp, st);
     }
 }
 
@@ -353,9 +383,12 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
     ga.n_kc = 1;
     if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs);
     switch (tile) {
-        case 0: return launch_tile<false, 2, 4>(ga, fhat, scales, Yq, Xp, st);
-        case 1: return launch_tile<false, 2, 2>(ga, fhat, scales, Yq, Xp, st);
-        default: return launch_tile<false, 4, 2>(ga, fhat, scales, Yq, Xp, st);
+        case 0: return launch_tile<false, 2, 4, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
+        case 1: return launch_tile<false, 2, 2, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
+        case 2: return launch_tile<false, 4, 2, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
+        case 3: return launch_tile<false, 2, 2, 4, 2, 2>(ga, fhat, scales, Yq, Xp, st);
+        case 4: return launch_tile<false, 4, 2, 4, 2, 2>(ga, fhat, scales, Yq, Xp, st);
+        default: return launch_tile<false, 2, 2, 5, 2, 1>(ga, fhat, scales, Yq, Xp, st);
     }
 }
 

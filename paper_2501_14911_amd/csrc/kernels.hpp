@@ -87,7 +87,7 @@ hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int 
 int gemm_fwd_kchunks(int pitch);
 int gemm_data_pitch(int Nd);   // row length of data-side quad spectra read by the adjoint (Nd rounded up to 8)
 int gemm_tile_count();
-int gemm_tile_shape(int tile, int* row_groups, int* substeps);
+int gemm_tile_shape(int tile, int* row_groups, int* substeps, int* blocks);
 int gemm_default_tile(int nrhs);
 // tile: a variant index, or -1 for the built-in choice
 hipError_t launch_gemm_fwd(const GemmArgs& ga, int tile, const void* fhat, const float* scales, const void* Xq,

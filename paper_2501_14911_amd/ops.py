@@ -282,13 +282,15 @@ def misfit(m: torch.Tensor, op: P2OOperator, d_obs: torch.Tensor, noise_var, nt_
 
 
 def gemm_tiles() -> list:
-    """Matrix-core tile variants: [(row_groups, substeps, rhs_per_group), ...]."""
+    """Matrix-core tile variants: [(row_groups, substeps, blocks, rhs_per_group), ...]
+    (32 * row_groups * blocks output rows per workgroup)."""
     out = []
     while True:
-        rg, ku, nr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        if lib.p2o_gemm_tile_info(len(out), ctypes.byref(rg), ctypes.byref(ku), ctypes.byref(nr)) != 0:
+        rg, ku, mb, nr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        if lib.p2o_gemm_tile_info(len(out), ctypes.byref(rg), ctypes.byref(ku), ctypes.byref(mb),
+                                  ctypes.byref(nr)) != 0:
             return out
-        out.append((rg.value, ku.value, nr.value))
+        out.append((rg.value, ku.value, mb.value, nr.value))
 
 
 def bandwidth_probe(nbytes: int = 8 << 30, reps: int = 10, device="cuda", blocks: int = 8192) -> dict:
