@@ -82,8 +82,10 @@ p2o_status p2o_create(p2o_plan** out, int64_t Nd, int64_t Nm, int64_t Nt,
 p2o_status p2o_destroy(p2o_plan* plan);
 
 /* Derived sizes: circulant length L, number of stored frequencies L/2+1,
- * row pitch of the stored spectrum in complex elements (Nm rounded up to 8),
- * and the number of 4096-column scale blocks.  Any pointer may be NULL. */
+ * row pitch of the stored spectrum in complex elements (the smallest value
+ * >= Nm that is 32 mod 64, so that rows start an odd number of 128-byte
+ * lines apart; columns past Nm hold zeros), and the number of 4096-column
+ * scale blocks.  Any pointer may be NULL. */
 p2o_status p2o_get_layout(const p2o_plan* plan, int64_t* L, int64_t* nfreq,
                           int64_t* pitch, int64_t* nscale_blocks);
 

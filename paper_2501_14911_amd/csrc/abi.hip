@@ -153,6 +153,10 @@ bool f64_plan(const p2o_plan* p) { return p->prec == kFP64; }
 const void* tw_of(const p2o_plan* p) { return p->fhat + (f64_plan(p) ? p->off_tw64 : p->off_tw32); }
 const float* scales_of(const p2o_plan* p) { return reinterpret_cast<const float*>(p->fhat + p->off_scales); }
 
+// Spectrum columns that can be nonzero (Nm rounded up to 8); the rest of a
+// row is zero padding that the products skip.
+int64_t live_cols(const p2o_plan* p) { return (p->Nm + 7) / 8 * 8; }
+
 void layout(p2o_plan* p) {
     const size_t nfreq = (size_t)p->nfreq;
     const size_t spec = nfreq * (size_t)p->Nd * (size_t)p->pitch * (size_t)p->elem_bytes;
@@ -169,7 +173,7 @@ void layout(p2o_plan* p) {
     if (p->prec == kBF16) {
         // matrix-core path: forward partials per 4096-column chunk, and data
         // spectra in quad storage with rows padded to a multiple of 8
-        ylen = std::max(ylen, (size_t)gemm_fwd_kchunks((int)p->pitch) * nfreq * R * (size_t)p->Nd);
+        ylen = std::max(ylen, (size_t)gemm_fwd_kchunks((int)live_cols(p)) * nfreq * R * (size_t)p->Nd);
         ylen = std::max(ylen, nfreq * R * (size_t)gemm_data_pitch((int)p->Nd));
     }
     p->off_X = 0;
@@ -228,6 +232,7 @@ GemvArgs gemv_args(const p2o_plan* p, int64_t nrhs, bool fwd) {
     GemvArgs ga{};
     ga.Nd = (int)p->Nd;
     ga.pitch = (int)p->pitch;
+    ga.ncols = (int)live_cols(p);
     ga.nfreq = (int)p->nfreq;
     ga.nrhs = (int)nrhs;
     ga.nblk = (int)p->nblk;
@@ -250,7 +255,7 @@ bool mfma_on(const p2o_plan* p, int64_t nrhs) {
 }
 
 int fwd_parts(const p2o_plan* p, int64_t nrhs) {
-    return mfma_on(p, nrhs) ? gemm_fwd_kchunks((int)p->pitch) : p->fwd_chunks;
+    return mfma_on(p, nrhs) ? gemm_fwd_kchunks((int)live_cols(p)) : p->fwd_chunks;
 }
 
 int adj_parts(const p2o_plan* p, int64_t nrhs) { return mfma_on(p, nrhs) ? 1 : p->adj_nslab; }
@@ -259,6 +264,7 @@ GemmArgs gemm_args(const p2o_plan* p, int64_t nrhs) {
     GemmArgs ga{};
     ga.Nd = (int)p->Nd;
     ga.pitch = (int)p->pitch;
+    ga.ncols = (int)live_cols(p);
     ga.nfreq = (int)p->nfreq;
     ga.nrhs = (int)nrhs;
     ga.nblk = (int)p->nblk;
@@ -391,14 +397,18 @@ p2o_status p2o_create(p2o_plan** out, int64_t Nd, int64_t Nm, int64_t Nt, int32_
         p->fft = fp;
         p->L = 2 * M;
         p->nfreq = M + 1;
-        p->pitch = (Nm + 7) / 8 * 8;
+        // Rows start an odd number of 128-byte lines apart (pitch = 32 mod 64
+        // entries): with a power-of-two pitch every row of a tile maps to the
+        // same L2 sets, and rows read a part of a line at a time lose their
+        // lines before the rest is read.
+        p->pitch = (Nm + 31) / 64 * 64 + 32;
         p->nblk = (Nm + kScaleBlock - 1) / kScaleBlock;
         p->elem_bytes = precision == P2O_FP64 ? 16 : precision == P2O_FP32 ? 8 : 4;
         p->cbytes = precision == P2O_FP64 ? 16 : 8;
         p->io_bytes = precision == P2O_FP64 ? 8 : 4;
         p->fwd_rows = 64;
         p->fwd_nslab = (int)((Nd + p->fwd_rows - 1) / p->fwd_rows);
-        p->fwd_chunks = gemv_fwd_chunks(precision, (int)p->pitch);
+        p->fwd_chunks = gemv_fwd_chunks(precision, (int)((Nm + 7) / 8 * 8));
         p->adj_nslab = 1;
         p->adj_rows = (int)Nd;
         p->c2r_nd_blocks = c2r_grid_x(fp, precision == P2O_FP64, (int)Nd);

@@ -141,7 +141,7 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
     const int m0 = mt * T::MROWS;                      // first output row (sensor or column) of the tile
     // K range: forward columns [kbeg, kend) of the chunk, adjoint sensors [0, ldb)
     const int kbeg = FWD ? kc * ga.kchunk : 0;
-    const int kend = FWD ? min(ga.pitch, kbeg + ga.kchunk) : ga.ldb;
+    const int kend = FWD ? min(ga.ncols, kbeg + ga.kchunk) : ga.ldb;
     const int nst = (kend - kbeg + T::KC - 1) / T::KC;
     const uint32_t* Fw = reinterpret_cast<const uint32_t*>(fhat) + (long long)w * ga.Nd * ga.pitch;
     const uint8_t* brows = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
@@ -301,19 +301,19 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const int jb = m0 + (rg * MB + mb) * 32;        // an m block lies in one 4096-column scale block
-            if (jb >= ga.pitch) continue;
+            if (jb >= ga.ncols) continue;
             const float sc = scales[(long long)w * ga.nblk + jb / kScaleBlock];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int j = jb + 8 * (v >> 2) + 4 * kg + (v & 3);
-                if (j < ga.pitch) out[j] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+                if (j < ga.ncols) out[j] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------- host launchers
-int gemm_fwd_kchunks(int pitch) { return (pitch + kScaleBlock - 1) / kScaleBlock; }
+int gemm_fwd_kchunks(int ncols) { return (ncols + kScaleBlock - 1) / kScaleBlock; }
 
 int gemm_data_pitch(int Nd) { return (Nd + 7) / 8 * 8; }
 
@@ -321,7 +321,7 @@ template <bool FWD, int RG, int KU, int MB, int WPE, int PF>
 static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
                               hipStream_t st) {
     using T = Tile<FWD, RG, KU, MB>;
-    ga.n_mt = ((FWD ? ga.Nd : ga.pitch) + T::MROWS - 1) / T::MROWS;
+    ga.n_mt = ((FWD ? ga.Nd : ga.ncols) + T::MROWS - 1) / T::MROWS;
     ga.n_bg = (ga.nrhs + T::RHS - 1) / T::RHS;
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
@@ -363,7 +363,7 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     GemmArgs ga = in;
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
-    ga.n_kc = gemm_fwd_kchunks(ga.pitch);
+    ga.n_kc = gemm_fwd_kchunks(ga.ncols);
     if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs);
     switch (tile) {
         case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);

@@ -5,7 +5,7 @@
 // (forward) or its conjugate transpose (adjoint), both from one stored copy.
 //
 // Layout: Fhat is [nfreq][Nd][pitch], complex, real part first, the
-// parameter index fastest (pitch = Nm rounded up to 8, zero padded).  Both
+// parameter index fastest (pitch >= Nm, a multiple of 32; zero padded).  Both
 // directions then stream Fhat once with unit-stride, 32-byte-per-lane loads:
 //  - forward, y_w[i] = sum_j Fhat_w[i, j] x_w[j]: row dot products.  A lane
 //    keeps its V entries of x_w in registers and reuses them across every
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_fwd(const uint8_t* __rest
     const int slab = blockIdx.z - b * ga.nslab;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = (blockIdx.x * 4 + wave) * (64 * V) + lane * V;
-    const bool live = col < ga.pitch;
+    const bool live = col < ga.ncols;
 
     CT xr[V], xi[V];
     if (live) {
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_adj(const uint8_t* __rest
     const int b = blockIdx.z / ga.nslab;
     const int slab = blockIdx.z - b * ga.nslab;
     const int col = blockIdx.x * (kGemvThreads * V) + threadIdx.x * V;
-    const bool live = col < ga.pitch;
+    const bool live = col < ga.ncols;
     const int r0 = slab * ga.rows_per_wg;
     const int r1 = min(ga.Nd, r0 + ga.rows_per_wg);
 
@@ -217,9 +217,9 @@ int gemv_cols_per_lane(int prec) {
     }
 }
 
-int gemv_fwd_chunks(int prec, int pitch) {
+int gemv_fwd_chunks(int prec, int ncols) {
     const int w = 4 * 64 * gemv_cols_per_lane(prec);
-    return (pitch + w - 1) / w;
+    return (ncols + w - 1) / w;
 }
 
 // Rows in flight per lane: 8 x 32 bytes, except FP64 where the wider
@@ -230,7 +230,7 @@ template <int P>
 static void fwd_launch(const GemvArgs& ga, const void* fhat, const float* scales, const void* X, void* Yp,
                        hipStream_t st) {
     using Z = cplx<typename Fmt<P>::CT>;
-    dim3 grid(gemv_fwd_chunks(P, ga.pitch), ga.nfreq, ga.nslab * ga.nrhs);
+    dim3 grid(gemv_fwd_chunks(P, ga.ncols), ga.nfreq, ga.nslab * ga.nrhs);
     hipLaunchKernelGGL((k_gemv_fwd<P, fwd_unroll<P>()>), grid, dim3(kGemvThreads), 0, st, (const uint8_t*)fhat, scales,
                        (const Z*)X, (Z*)Yp, ga);
 }
@@ -240,7 +240,7 @@ static void adj_launch(const GemvArgs& ga, const void* fhat, const float* scales
                        hipStream_t st) {
     using Z = cplx<typename Fmt<P>::CT>;
     const int w = kGemvThreads * Fmt<P>::V;
-    dim3 grid((ga.pitch + w - 1) / w, ga.nfreq, ga.nslab * ga.nrhs);
+    dim3 grid((ga.ncols + w - 1) / w, ga.nfreq, ga.nslab * ga.nrhs);
     hipLaunchKernelGGL((k_gemv_adj<P, 8>), grid, dim3(kGemvThreads), 0, st, (const uint8_t*)fhat, scales,
                        (const Z*)Y, (Z*)Xp, ga);
 }

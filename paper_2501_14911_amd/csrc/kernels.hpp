@@ -8,7 +8,8 @@ namespace p2o {
 
 struct GemvArgs {
     int Nd;
-    int pitch;            // complex entries per stored row (>= Nm, multiple of 8)
+    int pitch;            // complex entries per stored row (>= Nm, multiple of 32): row stride
+    int ncols;            // columns that can be nonzero (Nm rounded up to 8): the column extent
     int nfreq;
     int nrhs;
     int nblk;             // scale blocks per row
@@ -19,7 +20,8 @@ struct GemvArgs {
 
 struct GemmArgs {
     int Nd;
-    int pitch;
+    int pitch;            // complex entries per stored spectrum row (row stride)
+    int ncols;            // columns that can be nonzero (Nm rounded up to 8): K extent / adjoint outputs
     int nfreq;
     int nrhs;
     int nblk;
@@ -74,7 +76,7 @@ bool launch_fixed_project(bool f64, const FftPlan& pl, const SeriesIO& io, void*
 
 // gemv.hip
 int gemv_cols_per_lane(int prec);
-int gemv_fwd_chunks(int prec, int pitch);
+int gemv_fwd_chunks(int prec, int ncols);
 hipError_t launch_gemv_fwd(int prec, const GemvArgs& ga, const void* fhat, const float* scales, const void* X,
                            void* Yp, hipStream_t st);
 hipError_t launch_gemv_adj(int prec, const GemvArgs& ga, const void* fhat, const float* scales, const void* Y,
@@ -84,7 +86,7 @@ hipError_t launch_gemv_adj(int prec, const GemvArgs& ga, const void* fhat, const
 hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int blocks, hipStream_t st);
 
 // gemm_mfma.hip
-int gemm_fwd_kchunks(int pitch);
+int gemm_fwd_kchunks(int ncols);
 int gemm_data_pitch(int Nd);   // row length of data-side quad spectra read by the adjoint (Nd rounded up to 8)
 int gemm_tile_count();
 int gemm_tile_shape(int tile, int* row_groups, int* substeps, int* blocks);

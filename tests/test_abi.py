@@ -71,7 +71,18 @@ def test_transform_length_is_twice_7smooth(Nt, L):
     Lv, nf, pitch, nblk = c_int64(), c_int64(), c_int64(), c_int64()
     assert lib.p2o_get_layout(plan, byref(Lv), byref(nf), byref(pitch), byref(nblk)) == OK
     assert Lv.value == L and nf.value == L // 2 + 1 and Lv.value >= 2 * Nt - 1
-    assert pitch.value == 8 and nblk.value == 1
+    assert pitch.value == 32 and nblk.value == 1
+    lib.p2o_destroy(plan)
+
+
+@pytest.mark.parametrize("Nm,pitch", [(1, 32), (32, 32), (33, 96), (1003, 1056), (16384, 16416), (16416, 16416),
+                                      (16417, 16480), (65536, 65568)])
+def test_spectrum_rows_start_an_odd_number_of_lines_apart(Nm, pitch):
+    st, plan = create(Nd=3, Nm=Nm, Nt=16, prec=2)
+    assert st == OK
+    p = c_int64()
+    assert lib.p2o_get_layout(plan, None, None, byref(p), None) == OK
+    assert p.value == pitch and p.value >= Nm and p.value % 64 == 32
     lib.p2o_destroy(plan)
 
 
@@ -81,7 +92,7 @@ def test_required_bytes_cover_the_spectrum(prec, elem):
     assert st == OK
     fb, wb = c_size_t(), c_size_t()
     assert lib.p2o_required_bytes(plan, byref(fb), byref(wb)) == OK
-    spec = 421 * 600 * 16384 * elem
+    spec = 421 * 600 * 16416 * elem            # pitch 16416: the smallest >= 16384 that is 32 mod 64
     assert spec <= fb.value <= spec + 421 * 4 * 4 + 840 * 24 + 4096
     # workspace: one spectrum of the parameter series at least
     assert wb.value >= 421 * 16384 * (16 if prec == 0 else 8)
