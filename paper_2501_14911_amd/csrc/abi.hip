@@ -478,11 +478,13 @@ p2o_status p2o_autotune(p2o_plan* p, int64_t nrhs, int32_t reps, int32_t* fwd_ti
         if (reps < 1 || reps > 100) return fail(P2O_ERR_ARG, "reps=%d not in [1, 100]", (int)reps);
         if (!mfma_on(p, nrhs)) return fail(P2O_ERR_DTYPE, "calls with nrhs=%lld do not use the matrix cores on this plan", (long long)nrhs);
         if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
-        // Operands: the workspace's spectra regions, cleared (their values do not
-        // change the timing; clearing keeps them finite).
+        // Operands: the workspace's spectra regions, filled with finite random
+        // BF16 words (on zeros the matrix cores run cooler and faster than on
+        // real data, which would skew the comparison).  The adjoint's operand
+        // is refilled after the forward launches have written over it.
         void* X = p->ws + p->off_X;
         void* Y = p->ws + p->off_Y;
-        p2o_status s = check_hip(hipMemsetAsync(p->ws, 0, p->off_D, p->stream), "autotune operand clear");
+        p2o_status s = check_hip(launch_fill_bf16(X, p->off_D - p->off_X, 0x5EEDu, p->stream), "autotune operand fill");
         if (s) return s;
         hipEvent_t a = nullptr, b = nullptr;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -493,6 +495,7 @@ p2o_status p2o_autotune(p2o_plan* p, int64_t nrhs, int32_t reps, int32_t* fwd_ti
         double best[2] = {1e300, 1e300};
         int pick[2] = {-1, -1};
         for (int dir = 0; dir < 2 && !s; ++dir) {
+            if (dir == 1) s = check_hip(launch_fill_bf16(Y, p->off_D - p->off_Y, 0xADu, p->stream), "autotune operand fill");
             for (int t = 0; t < gemm_tile_count() && !s; ++t) {
                 auto run = [&]() {
                     return dir == 0 ? launch_gemm_fwd(ga, t, p->fhat, scales_of(p), X, Y, p->stream)

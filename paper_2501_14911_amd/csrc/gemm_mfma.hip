@@ -312,6 +312,26 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
     }
 }
 
+// Operand filler for timing runs: words of two BF16 values with magnitudes in
+// [1/2, 1) and hashed signs and mantissas.  The matrix cores draw much more
+// power on such data than on zeros, and the power limit sets their clock, so
+// tiles are compared on data like the real operands.
+__global__ void k_fill_bf16(uint32_t* __restrict__ p, size_t n, uint32_t seed) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 0x9E3779B1u ^ seed;
+        h ^= h >> 15; h *= 0x85EBCA77u; h ^= h >> 13; h *= 0xC2B2AE3Du; h ^= h >> 16;
+        const uint32_t a = (h & 0x807Fu) | (126u << 7), b = ((h >> 16) & 0x807Fu) | (126u << 7);
+        p[i] = a | (b << 16);
+    }
+}
+
+hipError_t launch_fill_bf16(void* p, size_t bytes, uint32_t seed, hipStream_t st) {
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_bf16, dim3(2048), dim3(256), 0, st, (uint32_t*)p, n, seed);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- host launchers
 int gemm_fwd_kchunks(int ncols) { return (ncols + kScaleBlock - 1) / kScaleBlock; }
 
