@@ -250,19 +250,42 @@ def main():
 
 # HBM traffic per launch of the timed kernels, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs of this benchmark (copy-kernel calibration: fetched KiB x 2,
-# written KiB x 1; see profiles/).  Valid only for the kernel source it was
-# measured on: keyed by the SHA-1 of that file and the tile variant.
-_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "c6a47c11420ef01d87749be6446e79dd8524d0ab")
-_GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "fd80bdf513763482c5e0e531d01284b78a223d99")
-TRAFFIC = {
-    # (kernel, tile): (source file, sha1, fetch bytes, write bytes, workload)
-    ("gemm_fwd_64", 0): (*_GEMM, 21500095473, 523757480, "paper_time"),
-    ("gemm_adj_64", 1): (*_GEMM, 17084969105, 3531955480, "paper_time"),
-    ("gemm_fwd_32", 2): (*_GEMM, 24577390028, 267290431, "paper_time"),
-    ("gemm_adj_32", 2): (*_GEMM, 16696744945, 1766560097, "paper_time"),
-    ("gemv_fwd", None): (*_GEMV, 17222871392, 16166400, "paper_time"),
-    ("gemv_adj", None): (*_GEMV, 17021801913, 55183274, "paper_time"),
+# written KiB x 1; see profiles/), on the paper_time workload.  The matrix-core
+# rows come from the autotuner's launches, which run every tile variant on the
+# benchmark's shapes.  Valid only for the kernel source it was measured on:
+# keyed by the SHA-1 of that file.
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "8981bdd33c1129a7a07ae20d8d6207afce4d8fab")
+_GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "8700f29c070cba1fa0fc7f82ba82cb8d950b3ab7")
+# (kernel, tile): (fetch bytes, write bytes); GEMM rows from the autotuner's launches of every tile
+_MEASURED = {
+    ("gemm_adj_32", 0): (16789330525, 1765812795),
+    ("gemm_adj_32", 1): (16808384302, 1765813339),
+    ("gemm_adj_32", 2): (16734786507, 1766839483),
+    ("gemm_adj_32", 3): (16720434751, 1765884475),
+    ("gemm_adj_32", 4): (16713822419, 1768543547),
+    ("gemm_adj_32", 5): (16782698225, 1788292731),
+    ("gemm_adj_64", 0): (16981149937, 3537807670),
+    ("gemm_adj_64", 1): (17051798073, 3535844054),
+    ("gemm_adj_64", 2): (31900924258, 3535294134),
+    ("gemm_adj_64", 3): (16961275691, 3533632182),
+    ("gemm_adj_64", 4): (33469519767, 3538251574),
+    ("gemm_adj_64", 5): (16996586735, 3556158358),
+    ("gemm_fwd_32", 0): (18401672044, 260653535),
+    ("gemm_fwd_32", 1): (18388160470, 261647743),
+    ("gemm_fwd_32", 2): (19167905353, 261044319),
+    ("gemm_fwd_32", 3): (20603521670, 260940671),
+    ("gemm_fwd_32", 4): (19953750640, 261939135),
+    ("gemm_fwd_32", 5): (20373218070, 260121407),
+    ("gemm_fwd_64", 0): (20305905700, 523240703),
+    ("gemm_fwd_64", 1): (20283216193, 523042303),
+    ("gemm_fwd_64", 2): (20642436893, 524284447),
+    ("gemm_fwd_64", 3): (25224146195, 519632575),
+    ("gemm_fwd_64", 4): (23997123159, 521608351),
+    ("gemm_fwd_64", 5): (23616160461, 519851423),
+    ("gemv_adj", None): (17025396890, 55183040),
+    ("gemv_fwd", None): (17229186840, 16166400),
 }
+TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
 
 def measured_traffic(kernel, tile, w):
