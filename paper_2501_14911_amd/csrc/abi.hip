@@ -459,13 +459,13 @@ p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
 
 p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* blocks,
                               int32_t* rhs_per_group) {
-    int rg = 0, ku = 0, mb = 0;
-    if (gemm_tile_shape(tile, &rg, &ku, &mb))
+    int rg = 0, ku = 0, mb = 0, nr = 0;
+    if (gemm_tile_shape(tile, &rg, &ku, &mb, &nr))
         return fail(P2O_ERR_ARG, "tile variant %d not in [0, %d)", (int)tile, gemm_tile_count());
     if (row_groups) *row_groups = rg;
     if (substeps) *substeps = ku;
     if (blocks) *blocks = mb;
-    if (rhs_per_group) *rhs_per_group = 32 * (4 / rg);
+    if (rhs_per_group) *rhs_per_group = nr;
     return P2O_OK;
 }
 

@@ -16,9 +16,10 @@
 // accumulation.  The per-(frequency, 4096-column block) power-of-two scale of
 // the stored spectrum multiplies finished outputs (exact).
 //
-// Work.  A workgroup is 4 wavefronts: RG row groups x (4 / RG) halves of the
-// right-hand sides, each wavefront computing MB (4 or 5) blocks of 32 output
-// rows (forward: sensors; adjoint: parameter columns) for 32 right-hand sides.
+// Work.  A workgroup is NW (4 or 8) wavefronts: RG row groups x (NW / RG)
+// halves of the right-hand sides, each wavefront computing MB (4 or 5) blocks
+// of 32 output rows (forward: sensors; adjoint: parameter columns) for 32
+// right-hand sides.
 // Each K step (KU substeps of 8 complex entries) the workgroup stages its
 // spectrum tile and right-hand-side tile in LDS, loaded cooperatively with
 // whole 128-byte lines per 8 lanes: forward rows in runs of 32 (or 16)
@@ -43,7 +44,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));   // native vector: staged copies stay in registers
 
-constexpr int kGemmThreads = 256;
 
 __device__ __forceinline__ f32x16 mfma32(uint4 a, uint4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
@@ -79,20 +79,21 @@ __device__ __forceinline__ void lds_barrier() {
 // consecutive rows hit distinct banks).  ADJ: KC sensor rows x MROWS columns,
 // row stride A_RS with 4 A_RS / 4 = 32 (mod 64) banks, so the two sensor
 // quartets a fragment read covers fall in different bank halves.
-template <bool FWD, int RG, int KU, int MB_>
+template <bool FWD, int RG, int KU, int MB_, int NW>
 struct Tile {
+    static constexpr int THREADS = 64 * NW;            // NW wavefronts = RG row groups x NH halves
     static constexpr int MB = MB_;                     // 32-row blocks per wavefront
-    static constexpr int NH = 4 / RG;                  // right-hand-side halves of 32
+    static constexpr int NH = NW / RG;                 // right-hand-side halves of 32
     static constexpr int MROWS = RG * 32 * MB;         // output rows per workgroup
     static constexpr int KC = 8 * KU;                  // complex K entries per step
     static constexpr int RHS = 32 * NH;
     static constexpr int A_RS = FWD ? KC * 4 + 16 : MROWS * 4 + 32;
     static constexpr int A_BYTES = FWD ? MROWS * A_RS : KC * A_RS;
     static constexpr int A_CPR = FWD ? KC / 4 : MROWS / 4;   // 16-byte chunks per stored row
-    static constexpr int A_PT = MROWS * KC / 4 / kGemmThreads;
-    static constexpr int B_PT = RHS * KC / 2 / kGemmThreads;  // 16-byte hi or lo chunks
-    static_assert(A_PT * kGemmThreads * 4 == MROWS * KC, "A chunks per thread");
-    static_assert(B_PT * kGemmThreads * 2 == RHS * KC, "B chunks per thread");
+    static constexpr int A_PT = MROWS * KC / 4 / THREADS;
+    static constexpr int B_PT = RHS * KC / 2 / THREADS;    // 16-byte hi or lo chunks
+    static_assert(A_PT * THREADS * 4 == MROWS * KC, "A chunks per thread");
+    static_assert(B_PT * THREADS * 2 == RHS * KC, "B chunks per thread");
 };
 
 // LDS slot of lane L's B fragment in plane (substep u, hi/lo hl): the low 4
@@ -115,11 +116,11 @@ struct Staged {
 // PF: steps staged in registers ahead of the LDS double buffer (2, or 1 to
 // fit two wavefronts per SIMD; the other workgroup on the CU then covers the
 // shorter lead).
-template <bool FWD, int RG, int KU, int MB_, int WPE, int PF>
-__global__ __launch_bounds__(kGemmThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
+template <bool FWD, int RG, int KU, int MB_, int WPE, int PF, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq, float2* __restrict__ out_base,
             GemmArgs ga) {
-    using T = Tile<FWD, RG, KU, MB_>;
+    using T = Tile<FWD, RG, KU, MB_, NW>;
     constexpr int MB = MB_;
     __shared__ __align__(16) uint8_t as[2][T::A_BYTES];
     __shared__ __align__(16) v4u bfr[2][KU][T::NH][2][64];
@@ -158,7 +159,7 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
         const int sa = min(st, nst - 1);
 #pragma unroll
         for (int i = 0; i < T::A_PT; ++i) {
-            const int c = tid + i * kGemmThreads;
+            const int c = tid + i * T::THREADS;
             const int row = c / T::A_CPR, cc = c % T::A_CPR;
             long long off;
             if constexpr (FWD) {
@@ -175,7 +176,7 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
         }
 #pragma unroll
         for (int i = 0; i < T::B_PT; ++i) {
-            const int c = tid + i * kGemmThreads;
+            const int c = tid + i * T::THREADS;
             const int p = c >> 1, hl = c & 1;
             const int g = p % (T::KC / 4), bl = min(p / (T::KC / 4), nb_valid - 1);
             const int gi = (kbeg + st * T::KC) / 4 + g;
@@ -187,13 +188,13 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
     auto store = [&](const S& sg, int buf) {
 #pragma unroll
         for (int i = 0; i < T::A_PT; ++i) {
-            const int c = tid + i * kGemmThreads;
+            const int c = tid + i * T::THREADS;
             const int row = c / T::A_CPR, cc = c % T::A_CPR;
             *reinterpret_cast<v4u*>(&as[buf][row * T::A_RS + cc * 16]) = sg.a[i];
         }
 #pragma unroll
         for (int i = 0; i < T::B_PT; ++i) {
-            const int c = tid + i * kGemmThreads;
+            const int c = tid + i * T::THREADS;
             const int p = c >> 1, hl = c & 1;
             const int g = p % (T::KC / 4), bl = p / (T::KC / 4);
             // The empty asm pins the first use of the loaded chunk here: left
@@ -337,22 +338,25 @@ int gemm_fwd_kchunks(int ncols) { return (ncols + kScaleBlock - 1) / kScaleBlock
 
 int gemm_data_pitch(int Nd) { return (Nd + 7) / 8 * 8; }
 
-template <bool FWD, int RG, int KU, int MB, int WPE, int PF>
+template <bool FWD, int RG, int KU, int MB, int WPE, int PF, int NW = 4>
 static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
                               hipStream_t st) {
-    using T = Tile<FWD, RG, KU, MB>;
+    using T = Tile<FWD, RG, KU, MB, NW>;
     ga.n_mt = ((FWD ? ga.Nd : ga.ncols) + T::MROWS - 1) / T::MROWS;
     ga.n_bg = (ga.nrhs + T::RHS - 1) / T::RHS;
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
-    hipLaunchKernelGGL((k_gemm<FWD, RG, KU, MB, WPE, PF>), dim3(8 * ga.Q), dim3(kGemmThreads), 0, st, (const uint8_t*)fhat,
+    hipLaunchKernelGGL((k_gemm<FWD, RG, KU, MB, WPE, PF, NW>), dim3(8 * ga.Q), dim3(T::THREADS), 0, st, (const uint8_t*)fhat,
                        scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
 }
 
 // Tile variants (row groups RG, substeps per step KU, 32-row blocks per
-// wavefront MB, wavefronts per SIMD WPE): 32 (4 / RG) right-hand sides and
-// 32 MB RG output rows per workgroup, K steps of 8 KU entries.  MB = 5 fits
+// wavefront MB, wavefronts per SIMD WPE, staged steps PF, wavefronts per
+// workgroup NW): 32 (NW / RG) right-hand sides and 32 MB RG output rows per
+// workgroup, K steps of 8 KU entries.  NW = 8 with RG = 4 covers 600 sensors
+// and 64 right-hand sides in one workgroup, so the right-hand sides are read
+// once per K chunk instead of once per 320-row tile.  MB = 5 fits
 // 600-sensor forward tiles (two of 320 or one of 640 rows); MB = 4 keeps the
 // accumulators at 128 registers so that two workgroups share a CU, which
 // lets one workgroup's loads run under another's prologue and epilogue (the
@@ -360,19 +364,20 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
 // built-in choice takes 64-wide groups for 33 or more right-hand sides; a
 // plan's autotuner may pick another.
 struct TileShape {
-    int rg, ku, mb, wpe, pf;
+    int rg, ku, mb, wpe, pf, nw;
 };
-static const TileShape kTiles[] = {{2, 4, 5, 1, 2}, {2, 2, 5, 1, 2}, {4, 2, 5, 1, 2}, {2, 2, 4, 2, 2},
-                                   {4, 2, 4, 2, 2}, {2, 2, 5, 2, 1}};
+static const TileShape kTiles[] = {{2, 4, 5, 1, 2, 4}, {2, 2, 5, 1, 2, 4}, {4, 2, 5, 1, 2, 4}, {2, 2, 4, 2, 2, 4},
+                                   {4, 2, 4, 2, 2, 4}, {2, 2, 5, 2, 1, 4}, {4, 2, 5, 2, 1, 8}};
 constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_tile_count() { return kTileCount; }
 
-int gemm_tile_shape(int tile, int* rg, int* ku, int* mb) {
+int gemm_tile_shape(int tile, int* rg, int* ku, int* mb, int* rhs) {
     if (tile < 0 || tile >= kTileCount) return -1;
     *rg = kTiles[tile].rg;
     *ku = kTiles[tile].ku;
     *mb = kTiles[tile].mb;
+    *rhs = 32 * kTiles[tile].nw / kTiles[tile].rg;
     return 0;
 }
 
@@ -391,7 +396,8 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
         case 2: return launch_tile<true, 4, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 3: return launch_tile<true, 2, 2, 4, 2, 2>(ga, fhat, scales, Xq, Yp, st);
         case 4: return launch_tile<true, 4, 2, 4, 2, 2>(ga, fhat, scales, Xq, Yp, st);
-        default: return launch_tile<true, 2, 2, 5, 2, 1>(ga, fhat, scales, Xq, Yp, st);
+        case 5: return launch_tile<true, 2, 2, 5, 2, 1>(ga, fhat, scales, Xq, Yp, st);
+        default: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
     }
 }
 
@@ -408,7 +414,8 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
         case 2: return launch_tile<false, 4, 2, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
         case 3: return launch_tile<false, 2, 2, 4, 2, 2>(ga, fhat, scales, Yq, Xp, st);
         case 4: return launch_tile<false, 4, 2, 4, 2, 2>(ga, fhat, scales, Yq, Xp, st);
-        default: return launch_tile<false, 2, 2, 5, 2, 1>(ga, fhat, scales, Yq, Xp, st);
+        case 5: return launch_tile<false, 2, 2, 5, 2, 1>(ga, fhat, scales, Yq, Xp, st);
+        default: return launch_tile<false, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Yq, Xp, st);
     }
 }
 
