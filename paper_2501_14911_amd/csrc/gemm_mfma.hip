@@ -360,9 +360,8 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
 // 600-sensor forward tiles (two of 320 or one of 640 rows); MB = 4 keeps the
 // accumulators at 128 registers so that two workgroups share a CU, which
 // lets one workgroup's loads run under another's prologue and epilogue (the
-// adjoint's 256-column tiles also divide 4096-column blocks evenly).  The
-// built-in choice takes 64-wide groups for 33 or more right-hand sides; a
-// plan's autotuner may pick another.
+// adjoint's 256-column tiles also divide 4096-column blocks evenly).  A
+// plan's autotuner may replace the built-in choice (gemm_default_tile).
 struct TileShape {
     int rg, ku, mb, wpe, pf, nw;
 };
@@ -381,7 +380,9 @@ int gemm_tile_shape(int tile, int* rg, int* ku, int* mb, int* rhs) {
     return 0;
 }
 
-int gemm_default_tile(int nrhs) { return nrhs > 32 ? 0 : 2; }
+// Built-in choice without autotuning: the variants measured fastest on the
+// 600 x 16384 x 420 workload (random operands) for each width.
+int gemm_default_tile(int nrhs, bool fwd) { return nrhs > 32 ? (fwd ? 6 : 3) : 2; }
 
 hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Xq,
                            void* Yp, hipStream_t st) {
@@ -389,7 +390,7 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.ncols);
-    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs);
+    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs, true);
     switch (tile) {
         case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 1: return launch_tile<true, 2, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
@@ -407,7 +408,7 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = gemm_data_pitch(ga.Nd);
     ga.kchunk = 0;
     ga.n_kc = 1;
-    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs);
+    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs, false);
     switch (tile) {
         case 0: return launch_tile<false, 2, 4, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
         case 1: return launch_tile<false, 2, 2, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);

@@ -90,7 +90,7 @@ int gemm_fwd_kchunks(int ncols);
 int gemm_data_pitch(int Nd);   // row length of data-side quad spectra read by the adjoint (Nd rounded up to 8)
 int gemm_tile_count();
 int gemm_tile_shape(int tile, int* row_groups, int* substeps, int* blocks, int* rhs_per_group);
-int gemm_default_tile(int nrhs);
+int gemm_default_tile(int nrhs, bool fwd);
 hipError_t launch_fill_bf16(void* p, size_t bytes, uint32_t seed, hipStream_t st);   // timing operands
 // tile: a variant index, or -1 for the built-in choice
 hipError_t launch_gemm_fwd(const GemmArgs& ga, int tile, const void* fhat, const float* scales, const void* Xq,
