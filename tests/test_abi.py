@@ -167,3 +167,14 @@ def test_gemm_tile_table_and_autotune_checks():
     assert lib.p2o_autotune(plan, 2, 3, None, None, None, None) == STATE      # not loaded
     assert lib.p2o_autotune(None, 2, 3, None, None, None, None) == ARG
     lib.p2o_destroy(plan)
+
+
+def test_fixed_length_fft_switch():
+    st, plan = create(Nd=4, Nm=64, Nt=420, prec=1, max_rhs=2)
+    assert st == OK
+    for v in (0, 1):
+        assert lib.p2o_set_option(plan, 2, v) == OK
+    for v in (-1, 2):
+        assert lib.p2o_set_option(plan, 2, v) == ARG
+    assert lib.p2o_set_option(plan, 3, 0) == ARG          # no such option
+    lib.p2o_destroy(plan)
