@@ -497,6 +497,7 @@ p2o_status p2o_autotune(p2o_plan* p, int64_t nrhs, int32_t reps, int32_t* fwd_ti
         for (int dir = 0; dir < 2 && !s; ++dir) {
             if (dir == 1) s = check_hip(launch_fill_bf16(Y, p->off_D - p->off_Y, 0xADu, p->stream), "autotune operand fill");
             for (int t = 0; t < gemm_tile_count() && !s; ++t) {
+                if (!gemm_tile_has(t, dir == 0)) continue;
                 auto run = [&]() {
                     return dir == 0 ? launch_gemm_fwd(ga, t, p->fhat, scales_of(p), X, Y, p->stream)
                                     : launch_gemm_adj(ga, t, p->fhat, scales_of(p), Y, X, p->stream);

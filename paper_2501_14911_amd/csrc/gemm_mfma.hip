@@ -313,6 +313,162 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
     }
 }
 
+// ---------------------------------------------------------------- forward, LDS ring
+// Forward product with the operands streamed straight into a ring of RING
+// K steps in LDS by direct-to-LDS loads (global_load_lds_dwordx4: each lane
+// moves 16 bytes to ring base + 16 x lane), so that RING - 1 steps are in
+// flight without holding registers.  4 NH wavefronts = 4 row groups x NH
+// halves of 32 NH right-hand sides; 5 blocks of 32 rows per wavefront (640
+// rows: all sensors of a 600-sensor tile, so the right-hand sides are read
+// once per K chunk).  A step is 16 complex columns.
+//   A: 640 rows x 64 bytes, rows packed (a load instruction fills 16 rows);
+//      the 16-byte chunk c of row r sits in slot c ^ ((r / 4) mod 4), so that
+//      16 lanes reading one chunk of 16 consecutive rows hit distinct banks.
+//   B: one plane per (substep, half, hi/lo), lane L's fragment in slot L.
+// The K range is rounded up to whole steps; that stays inside the row pitch
+// (a multiple of 32 entries >= Nm), where spectrum and right-hand sides
+// are zero past Nm, so no step needs masking.
+constexpr int kRingSteps = 3;
+
+// Wait until at most n vector-memory loads of this wavefront are in flight
+// and its LDS operations are done (expcnt not waited on).
+template <int n>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+    static_assert(n >= 0 && n < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((n & 0xF) | (0x7 << 4) | (0x0 << 8) | ((n >> 4) << 14));
+}
+
+// Barrier without a memory fence (the fence would wait for every load in
+// flight); the caller's waits make the LDS contents visible.
+__device__ __forceinline__ void bare_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// One direct-to-LDS load (wavefront-uniform LDS base).  Inline assembly, so
+// that the compiler does not wait for it before every LDS access; the kernel
+// waits for these loads itself.
+__device__ __forceinline__ void dma16(const void* src, const void* lds_base) {
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)lds_base);
+    asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(src), "{m0}"(m0) : "memory");
+}
+
+template <int NH>
+__global__ __launch_bounds__(256 * NH) __attribute__((amdgpu_waves_per_eu(NH)))
+void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
+                     float2* __restrict__ out_base, GemmArgs ga) {
+    constexpr int RG = 4, MB = 5, KU = 2, RING = kRingSteps;
+    constexpr int MROWS = RG * 32 * MB, RHS = 32 * NH;
+    constexpr int AI = MROWS / 16 / (RG * NH);            // A loads (16 rows each) per wavefront per step
+    static_assert(AI * 16 * RG * NH == MROWS, "A rows per wavefront");
+    constexpr int A_STEP = MROWS * 64;                    // bytes of A per step
+    constexpr int B_STEP = KU * NH * 2 * 1024;            // bytes of B per step (one plane per wavefront)
+    constexpr int G = AI + 1;                             // loads per wavefront per step
+    __shared__ __align__(16) uint8_t ring_a[RING][A_STEP];
+    __shared__ __align__(16) uint8_t ring_b[RING][B_STEP];
+
+    const int q = xcd_item(blockIdx.x, ga.Q);
+    if (q >= ga.items) return;
+    int t = q;
+    const int mt = t % ga.n_mt; t /= ga.n_mt;
+    const int bg = t % ga.n_bg; t /= ga.n_bg;
+    const int kc = t % ga.n_kc; t /= ga.n_kc;
+    const int w = t;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rg = wave % RG, nh = wave / RG;
+    const int r = lane & 31, kg = lane >> 5;
+    const int b0 = bg * RHS;
+    const int nb_valid = min(RHS, ga.nrhs - b0);
+    const int m0 = mt * MROWS;
+    const int kbeg = kc * ga.kchunk;
+    const int kend = min((ga.ncols + 15) / 16 * 16, kbeg + ga.kchunk);
+    const int nst = (kend - kbeg) / 16;
+
+    // Per-lane sources at step 0.  A instruction i of this wavefront fills
+    // rows 16 (AI wave + i) .. + 15; lane L takes row L / 4 of those and puts
+    // chunk (L % 4) ^ (L / 16 % 4) of it in its slot.
+    const uint8_t* asrc[AI];
+    {
+        const int swz = (lane >> 4) & 3, c = (lane & 3) ^ swz;
+#pragma unroll
+        for (int i = 0; i < AI; ++i) {
+            const int row = 16 * (AI * wave + i) + (lane >> 2);
+            const int sr = min(m0 + row, ga.Nd - 1);
+            asrc[i] = fhat + (((long long)w * ga.Nd + sr) * ga.pitch + kbeg + 4 * c) * 4;
+        }
+    }
+    // B plane of this wavefront, plane = (u NH + h) 2 + hl: substep u, half h, hi/lo hl
+    const int phl = wave & 1, ph = (wave >> 1) % NH, pu = wave / (2 * NH);
+    const uint8_t* bsrc;
+    {
+        const int bl = min(ph * 32 + (lane & 31), nb_valid - 1);
+        const int g = 2 * pu + (lane >> 5);
+        bsrc = Bq + ((long long)w * ga.nrhs + b0 + bl) * ga.ldb * 8 + (long long)(kbeg / 4 + g) * 32 + phl * 16;
+    }
+    auto issue = [&](int st, int slot) {
+        const long long sa = st < nst ? st : nst - 1;       // past the end: repeat the last step (unused)
+#pragma unroll
+        for (int i = 0; i < AI; ++i) dma16(asrc[i] + sa * 64, &ring_a[slot][(AI * wave + i) * 1024]);
+        dma16(bsrc + sa * 128, &ring_b[slot][wave * 1024]);
+    };
+
+    f32x16 accr[MB], acci[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) accr[mb] = acci[mb] = f32x16{};
+
+    auto compute = [&](int slot) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const uint4 bh = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 0) * 1024 + lane * 16]);
+            const uint4 bl = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 1) * 1024 + lane * 16]);
+            const int cs = ((2 * u + kg) ^ ((r >> 2) & 3)) * 16;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int mrow = (rg * MB + mb) * 32 + r;
+                const uint4 a = *reinterpret_cast<const uint4*>(&ring_a[slot][mrow * 64 + cs]);
+                const uint4 a1 = f_conj(a), a2 = f_swap(a);
+                accr[mb] = mfma32(a1, bh, accr[mb]);
+                acci[mb] = mfma32(a2, bh, acci[mb]);
+                accr[mb] = mfma32(a1, bl, accr[mb]);
+                acci[mb] = mfma32(a2, bl, acci[mb]);
+            }
+        }
+    };
+
+    // Step st: wait for its loads (RING - 2 later steps stay in flight) and
+    // for this wavefront's LDS reads; barrier (every wavefront's loads of
+    // step st have landed, every wavefront is done with step st - 1); load
+    // step st + RING - 1 into the slot step st - 1 used; compute step st.
+#pragma unroll
+    for (int d = 0; d < RING - 1; ++d) issue(d, d);
+    int slot = 0;
+    for (int st = 0; st < nst; ++st) {
+        wait_vm_lgkm0<(RING - 2) * G>();
+        bare_barrier();
+        const int ns = slot == 0 ? RING - 1 : slot - 1;
+        issue(st + RING - 1, ns);
+        compute(slot);
+        slot = slot + 1 == RING ? 0 : slot + 1;
+    }
+    wait_vm_lgkm0<0>();                                   // no load may land after the workgroup ends
+
+    const int b = b0 + 32 * nh + r;
+    if (b >= ga.nrhs) return;
+    const float sc = scales[(long long)w * ga.nblk + kbeg / kScaleBlock];
+    float2* out = out_base + (long long)kc * ga.part_stride + ((long long)w * ga.nrhs + b) * ga.Nd;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = m0 + (rg * MB + mb) * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
+            if (row < ga.Nd) out[row] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+        }
+}
+
 // Operand filler for timing runs: words of two BF16 values with magnitudes in
 // [1/2, 1) and hashed signs and mantissas.  The matrix cores draw much more
 // power on such data than on zeros, and the power limit sets their clock, so
@@ -362,14 +518,32 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
 // lets one workgroup's loads run under another's prologue and epilogue (the
 // adjoint's 256-column tiles also divide 4096-column blocks evenly).  A
 // plan's autotuner may replace the built-in choice (gemm_default_tile).
+// Variants 7 and 8 are the forward LDS-ring kernel (k_gemm_fwd_ring, pf = 0
+// marks the ring) for 64 and 32 right-hand sides per group; they have no
+// adjoint, which then takes its built-in choice.
 struct TileShape {
     int rg, ku, mb, wpe, pf, nw;
 };
 static const TileShape kTiles[] = {{2, 4, 5, 1, 2, 4}, {2, 2, 5, 1, 2, 4}, {4, 2, 5, 1, 2, 4}, {2, 2, 4, 2, 2, 4},
-                                   {4, 2, 4, 2, 2, 4}, {2, 2, 5, 2, 1, 4}, {4, 2, 5, 2, 1, 8}};
+                                   {4, 2, 4, 2, 2, 4}, {2, 2, 5, 2, 1, 4}, {4, 2, 5, 2, 1, 8}, {4, 2, 5, 2, 0, 8},
+                                   {4, 2, 5, 1, 0, 4}};
 constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_tile_count() { return kTileCount; }
+
+bool gemm_tile_has(int tile, bool fwd) { return tile >= 0 && tile < kTileCount && (fwd || kTiles[tile].pf != 0); }
+
+template <int NH>
+static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
+                              hipStream_t st) {
+    ga.n_mt = (ga.Nd + 639) / 640;
+    ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
+    ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
+    ga.Q = (ga.items + 7) / 8;
+    hipLaunchKernelGGL(k_gemm_fwd_ring<NH>, dim3(8 * ga.Q), dim3(256 * NH), 0, st, (const uint8_t*)fhat, scales,
+                       (const uint8_t*)Bq, (float2*)out, ga);
+    return hipGetLastError();
+}
 
 int gemm_tile_shape(int tile, int* rg, int* ku, int* mb, int* rhs) {
     if (tile < 0 || tile >= kTileCount) return -1;
@@ -398,7 +572,9 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
         case 3: return launch_tile<true, 2, 2, 4, 2, 2>(ga, fhat, scales, Xq, Yp, st);
         case 4: return launch_tile<true, 4, 2, 4, 2, 2>(ga, fhat, scales, Xq, Yp, st);
         case 5: return launch_tile<true, 2, 2, 5, 2, 1>(ga, fhat, scales, Xq, Yp, st);
-        default: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
+        case 6: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
+        case 7: return launch_ring<2>(ga, fhat, scales, Xq, Yp, st);
+        default: return launch_ring<1>(ga, fhat, scales, Xq, Yp, st);
     }
 }
 
@@ -408,7 +584,7 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = gemm_data_pitch(ga.Nd);
     ga.kchunk = 0;
     ga.n_kc = 1;
-    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs, false);
+    if (!gemm_tile_has(tile, false)) tile = gemm_default_tile(ga.nrhs, false);
     switch (tile) {
         case 0: return launch_tile<false, 2, 4, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
         case 1: return launch_tile<false, 2, 2, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
