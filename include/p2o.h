@@ -236,10 +236,11 @@ p2o_status p2o_profile_read_nrhs(p2o_plan* plan, int32_t stage, int64_t nrhs, do
                                  int64_t* launches);
 
 /* Streaming probe for roofline context (not part of the operator): mode 0
- * reads `bytes` from `src` (32-byte non-temporal loads per lane; `dst`
- * receives one 32-bit word per workgroup, at least `blocks` words), mode 1
- * copies `bytes` from `src` to `dst` (16 bytes per lane).  bytes must be a
- * multiple of 32, blocks in [1, 65536].  Enqueued on `stream`. */
+ * reads `bytes` from `src` (non-temporal; each wavefront reads 2 KB chunks,
+ * one contiguous kilobyte per load instruction; `dst` receives one 32-bit
+ * word per workgroup, at least `blocks` words), mode 1 copies `bytes` from
+ * `src` to `dst` (16 bytes per lane).  bytes must be a multiple of 2048 for
+ * mode 0 and of 32 for mode 1, blocks in [1, 65536].  Enqueued on `stream`. */
 p2o_status p2o_bandwidth_probe(int32_t mode, const void* src, void* dst, size_t bytes,
                                int32_t blocks, void* stream);
 

@@ -425,7 +425,8 @@ p2o_status p2o_bandwidth_probe(int32_t mode, const void* src, void* dst, size_t 
                                void* stream) {
     if (mode != 0 && mode != 1) return fail(P2O_ERR_ARG, "probe mode must be 0 (read) or 1 (copy)");
     if (!src || !dst) return fail(P2O_ERR_ARG, "probe buffer is NULL");
-    if (bytes == 0 || bytes % 32) return fail(P2O_ERR_ARG, "probe size must be a positive multiple of 32");
+    if (bytes == 0 || bytes % (mode == 0 ? 2048 : 32))
+        return fail(P2O_ERR_ARG, "probe size must be a positive multiple of %d", mode == 0 ? 2048 : 32);
     if (blocks < 1 || blocks > 65536) return fail(P2O_ERR_ARG, "probe blocks must be in [1, 65536]");
     if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 32)
         return fail(P2O_ERR_ARG, "probe buffers must be 32-byte aligned");

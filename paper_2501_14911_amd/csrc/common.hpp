@@ -76,6 +76,20 @@ __device__ __forceinline__ void unpack(const Raw32& r, typename Fmt<P>::CT* re, 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // 32-byte streaming load (non-temporal: the spectrum is read once per call).
+// 32 bytes of a lane as two 16-byte halves 1 KB apart (half h only if lh):
+// with lane L at base + 16 L, each load instruction of a wavefront covers one
+// contiguous kilobyte, i.e. whole cache lines.
+__device__ __forceinline__ Raw32 load32_split(const void* p, bool l0, bool l1) {
+    const u32x4* q = reinterpret_cast<const u32x4*>(p);
+    u32x4 a = {0u, 0u, 0u, 0u}, b = {0u, 0u, 0u, 0u};
+    if (l0) a = __builtin_nontemporal_load(q);
+    if (l1) b = __builtin_nontemporal_load(q + 64);
+    Raw32 r;
+    r.a = make_uint4(a.x, a.y, a.z, a.w);
+    r.b = make_uint4(b.x, b.y, b.z, b.w);
+    return r;
+}
+
 __device__ __forceinline__ Raw32 load32(const void* p) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
     const u32x4 a = __builtin_nontemporal_load(q);

@@ -6,7 +6,9 @@
 //
 // Layout: Fhat is [nfreq][Nd][pitch], complex, real part first, the
 // parameter index fastest (pitch >= Nm, a multiple of 32; zero padded).  Both
-// directions then stream Fhat once with unit-stride, 32-byte-per-lane loads:
+// directions then stream Fhat once, each lane loading 32 bytes per row as two
+// 16-byte halves 1 KB apart (one wavefront load instruction = one contiguous
+// kilobyte, whole cache lines; a lane's columns are two runs of V/2):
 //  - forward, y_w[i] = sum_j Fhat_w[i, j] x_w[j]: row dot products.  A lane
 //    keeps its V entries of x_w in registers and reuses them across every
 //    row of the workgroup's slab; partial row sums are reduced across the
@@ -15,7 +17,7 @@
 //    column chunk writes its own partial y (no atomics); the inverse FFT
 //    that follows adds the partials in a fixed order.
 //  - adjoint, x'_w[j] = sum_i conj(Fhat_w[i, j]) y_w[i]: column AXPYs.  A
-//    lane owns V adjacent columns and walks the rows; y_w[i] is the same for
+//    lane owns its V columns and walks the rows; y_w[i] is the same for
 //    the whole workgroup (scalar loads).  No cross-lane reduction at all.
 // Quantised formats carry one power-of-two multiplier per (frequency,
 // 4096-column block).  Forward folds it into x (exact: a power of two);
@@ -89,19 +91,22 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_fwd(const uint8_t* __rest
     const int b = blockIdx.z / ga.nslab;
     const int slab = blockIdx.z - b * ga.nslab;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = (blockIdx.x * 4 + wave) * (64 * V) + lane * V;
-    const bool live = col < ga.ncols;
+    // lane columns: col .. col + V/2 - 1 and col + 32 V .. (split 32-byte loads)
+    const int col = (blockIdx.x * 4 + wave) * (64 * V) + lane * (V / 2);
+    const bool live0 = col < ga.ncols, live1 = col + 32 * V < ga.ncols;
 
     CT xr[V], xi[V];
-    if (live) {
+    {
         const Z* xp = X + ((long long)w * ga.nrhs + b) * ga.pitch + col;
         CT sc = CT(1);
-        if constexpr (Fmt<P>::scaled) sc = scales[(long long)w * ga.nblk + col / kScaleBlock];
+        if constexpr (Fmt<P>::scaled) sc = live0 ? scales[(long long)w * ga.nblk + col / kScaleBlock] : CT(0);
 #pragma unroll
-        for (int v = 0; v < V; ++v) { const Z x = xp[v]; xr[v] = x.x * sc; xi[v] = x.y * sc; }
-    } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) { xr[v] = CT(0); xi[v] = CT(0); }
+        for (int v = 0; v < V; ++v) {
+            const bool lv = v < V / 2 ? live0 : live1;
+            const Z x = lv ? xp[v < V / 2 ? v : 32 * V + v - V / 2] : Z{CT(0), CT(0)};
+            xr[v] = x.x * sc;
+            xi[v] = x.y * sc;
+        }
     }
 
     const long long rowb = (long long)ga.pitch * B;
@@ -113,8 +118,8 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_fwd(const uint8_t* __rest
         Raw32 raw[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (live && r + u < r1) raw[u] = load32(Fw + (long long)(r + u) * rowb);
-            else raw[u] = Raw32{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+            const bool ok = r + u < r1;
+            raw[u] = load32_split(Fw + (long long)(r + u) * rowb, ok && live0, ok && live1);
         }
         CT acc[2 * U];
 #pragma unroll
@@ -164,8 +169,9 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_adj(const uint8_t* __rest
     const int w = blockIdx.y;
     const int b = blockIdx.z / ga.nslab;
     const int slab = blockIdx.z - b * ga.nslab;
-    const int col = blockIdx.x * (kGemvThreads * V) + threadIdx.x * V;
-    const bool live = col < ga.ncols;
+    // lane columns: col .. col + V/2 - 1 and col + 32 V .. (split 32-byte loads)
+    const int col = blockIdx.x * (kGemvThreads * V) + (threadIdx.x >> 6) * (64 * V) + (threadIdx.x & 63) * (V / 2);
+    const bool live0 = col < ga.ncols, live1 = col + 32 * V < ga.ncols;
     const int r0 = slab * ga.rows_per_wg;
     const int r1 = min(ga.Nd, r0 + ga.rows_per_wg);
 
@@ -184,8 +190,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_adj(const uint8_t* __rest
         for (int u = 0; u < U; ++u) {
             const bool ok = r + u < r1;
             y[u] = ok ? yw[r + u] : Z{CT(0), CT(0)};
-            if (ok && live) raw[u] = load32(Fw + (long long)(r + u) * rowb);
-            else raw[u] = Raw32{make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+            raw[u] = load32_split(Fw + (long long)(r + u) * rowb, ok && live0, ok && live1);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -198,12 +203,15 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv_adj(const uint8_t* __rest
             }
         }
     }
-    if (live) {
+    if (live0) {
         CT sc = CT(1);
         if constexpr (Fmt<P>::scaled) sc = scales[(long long)w * ga.nblk + col / kScaleBlock];
         Z* out = Xp + (long long)slab * ga.part_stride + ((long long)w * ga.nrhs + b) * ga.pitch + col;
 #pragma unroll
-        for (int v = 0; v < V; ++v) out[v] = Z{accr[v] * sc, acci[v] * sc};
+        for (int v = 0; v < V / 2; ++v) out[v] = Z{accr[v] * sc, acci[v] * sc};
+        if (live1)
+#pragma unroll
+            for (int v = V / 2; v < V; ++v) out[32 * V + v - V / 2] = Z{accr[v] * sc, acci[v] * sc};
     }
 }
 

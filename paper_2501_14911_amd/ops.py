@@ -297,7 +297,7 @@ def bandwidth_probe(nbytes: int = 8 << 30, reps: int = 10, device="cuda", blocks
     """Measured streaming read and copy bandwidth (GB/s) of the device, with
     the library's probe kernels, for roofline context."""
     dev = torch.device(device)
-    nbytes = nbytes // 32 * 32
+    nbytes = nbytes // 2048 * 2048                 # the read probe moves whole 2 KB chunks
     src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     src.fill_(1)
     sink = torch.empty(blocks, dtype=torch.int32, device=dev)

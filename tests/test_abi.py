@@ -178,3 +178,12 @@ def test_fixed_length_fft_switch():
         assert lib.p2o_set_option(plan, 2, v) == ARG
     assert lib.p2o_set_option(plan, 3, 0) == ARG          # no such option
     lib.p2o_destroy(plan)
+
+
+def test_bandwidth_probe_argument_checks():
+    fake = c_void_p(1 << 20)                    # aligned, never dereferenced: every call fails before a launch
+    assert lib.p2o_bandwidth_probe(0, fake, fake, 1024, 8, None) == ARG    # read probe: whole 2 KB chunks
+    assert lib.p2o_bandwidth_probe(1, fake, fake, 48, 8, None) == ARG      # copy probe: multiples of 32
+    assert lib.p2o_bandwidth_probe(2, fake, fake, 2048, 8, None) == ARG
+    assert lib.p2o_bandwidth_probe(0, fake, fake, 2048, 0, None) == ARG
+    assert lib.p2o_bandwidth_probe(0, None, fake, 2048, 8, None) == ARG
