@@ -5,11 +5,13 @@
 // complex GEMM per frequency, done with v_mfma_f32_32x32x16_bf16 (on gfx950
 // the 32x32 shape sustains about 1.5x the rate of the 16x16x32 one, and
 // does so with one wavefront per SIMD).  K runs over (index, re/im) pairs in
-// their stored interleaved order, so a complex product is two real ones
-// against forms of the spectrum fragment, each 32-bit word (re, im) being
-// rewritten by one or two VALU operations:
-//   forward  y_r = (a_r, -a_i) . (x_r, x_i)   y_i = (a_i, a_r) . (x_r, x_i)
-//   adjoint  x_r = (a_r,  a_i) . (y_r, y_i)   x_i = (-a_i, a_r) . (y_r, y_i)
+// their stored interleaved order, so a complex product is two real ones of
+// the stored spectrum fragment against forms of the right-hand-side
+// fragment, each 32-bit word (re, im) being rewritten by one or two VALU
+// operations (a right-hand-side fragment serves MB spectrum fragments, so
+// the forms cost a fraction of what forms of the spectrum would):
+//   forward  y_r = (a_r, a_i) . (x_r, -x_i)   y_i = (a_r, a_i) . (x_i, x_r)
+//   adjoint  x_r = (a_r, a_i) . (y_r,  y_i)   x_i = (a_r, a_i) . (y_i, -y_r)
 // (the adjoint takes conj(F)^T).  Right-hand sides arrive as quad BF16 hi/lo
 // storage (written by the FFT that produced them); hi and lo each go through
 // the matrix cores, giving about 16 significant bits of x with FP32
@@ -58,8 +60,9 @@ __device__ __forceinline__ uint4 f_conj(uint4 a) {                       // (re,
 __device__ __forceinline__ uint4 f_swap(uint4 a) {                       // (im, re)
     return make_uint4(w_swap(a.x), w_swap(a.y), w_swap(a.z), w_swap(a.w));
 }
-__device__ __forceinline__ uint4 f_jrot(uint4 a) {                       // (-im, re)
-    return make_uint4(w_swap(a.x) ^ 0x8000u, w_swap(a.y) ^ 0x8000u, w_swap(a.z) ^ 0x8000u, w_swap(a.w) ^ 0x8000u);
+__device__ __forceinline__ uint4 f_nswap(uint4 a) {                      // (im, -re)
+    return make_uint4(w_swap(a.x) ^ 0x80000000u, w_swap(a.y) ^ 0x80000000u, w_swap(a.z) ^ 0x80000000u,
+                      w_swap(a.w) ^ 0x80000000u);
 }
 
 __device__ __forceinline__ int xcd_item(int id, int Q) { return (id & 7) * Q + (id >> 3); }
@@ -231,15 +234,15 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
         for (int u = 0; u < KU; ++u) {
             const v4u vh = bfr[buf][u][nh][0][b_slot(lane, u, 0)], vl = bfr[buf][u][nh][1][b_slot(lane, u, 1)];
             const uint4 bh = make_uint4(vh.x, vh.y, vh.z, vh.w), bl = make_uint4(vl.x, vl.y, vl.z, vl.w);
+            const uint4 bh_r = FWD ? f_conj(bh) : bh, bl_r = FWD ? f_conj(bl) : bl;
+            const uint4 bh_i = FWD ? f_swap(bh) : f_nswap(bh), bl_i = FWD ? f_swap(bl) : f_nswap(bl);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const uint4 a = frag(buf, mb, u);
-                const uint4 a1 = FWD ? f_conj(a) : a;
-                const uint4 a2 = FWD ? f_swap(a) : f_jrot(a);
-                accr[mb] = mfma32(a1, bh, accr[mb]);
-                acci[mb] = mfma32(a2, bh, acci[mb]);
-                accr[mb] = mfma32(a1, bl, accr[mb]);
-                acci[mb] = mfma32(a2, bl, acci[mb]);
+                accr[mb] = mfma32(a, bh_r, accr[mb]);
+                acci[mb] = mfma32(a, bh_i, acci[mb]);
+                accr[mb] = mfma32(a, bl_r, accr[mb]);
+                acci[mb] = mfma32(a, bl_i, acci[mb]);
             }
         }
     };
@@ -425,16 +428,16 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         for (int u = 0; u < KU; ++u) {
             const uint4 bh = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 0) * 1024 + lane * 16]);
             const uint4 bl = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 1) * 1024 + lane * 16]);
+            const uint4 bh_r = f_conj(bh), bh_i = f_swap(bh), bl_r = f_conj(bl), bl_i = f_swap(bl);
             const int cs = ((2 * u + kg) ^ ((r >> 2) & 3)) * 16;
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const int mrow = (rg * MB + mb) * 32 + r;
                 const uint4 a = *reinterpret_cast<const uint4*>(&ring_a[slot][mrow * 64 + cs]);
-                const uint4 a1 = f_conj(a), a2 = f_swap(a);
-                accr[mb] = mfma32(a1, bh, accr[mb]);
-                acci[mb] = mfma32(a2, bh, acci[mb]);
-                accr[mb] = mfma32(a1, bl, accr[mb]);
-                acci[mb] = mfma32(a2, bl, acci[mb]);
+                accr[mb] = mfma32(a, bh_r, accr[mb]);
+                acci[mb] = mfma32(a, bh_i, acci[mb]);
+                accr[mb] = mfma32(a, bl_r, accr[mb]);
+                acci[mb] = mfma32(a, bl_i, acci[mb]);
             }
         }
     };
