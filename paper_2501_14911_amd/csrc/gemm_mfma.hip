@@ -349,13 +349,18 @@ __device__ __forceinline__ void bare_barrier() {
     asm volatile("" ::: "memory");
 }
 
-// One direct-to-LDS load (wavefront-uniform LDS base).  Inline assembly, so
-// that the compiler does not wait for it before every LDS access; the kernel
-// waits for these loads itself.
-__device__ __forceinline__ void dma16(const void* src, const void* lds_base) {
-    const uint32_t m0 = __builtin_amdgcn_readfirstlane(
-        (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)lds_base);
-    asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(src), "{m0}"(m0) : "memory");
+// LDS byte address of a shared-memory location.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// One direct-to-LDS load: 16 bytes per lane from base + off (base
+// wavefront-uniform, off a per-lane 32-bit byte offset) to LDS byte address
+// lds + 16 x lane (lds wavefront-uniform).  Inline assembly, so that the
+// compiler does not wait for it before every LDS access; the kernel waits
+// for these loads itself.
+__device__ __forceinline__ void dma16(const uint8_t* base, uint32_t off, uint32_t lds) {
+    asm volatile("global_load_lds_dwordx4 %0, %1" : : "v"(off), "s"(base), "{m0}"(lds) : "memory");
 }
 
 template <int NH>
@@ -391,70 +396,89 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
     const int kend = min((ga.ncols + 15) / 16 * 16, kbeg + ga.kchunk);
     const int nst = (kend - kbeg) / 16;
 
-    // Per-lane sources at step 0.  A instruction i of this wavefront fills
-    // rows 16 (AI wave + i) .. + 15; lane L takes row L / 4 of those and puts
-    // chunk (L % 4) ^ (L / 16 % 4) of it in its slot.
-    const uint8_t* asrc[AI];
+    // Per-lane byte offsets from wavefront-uniform bases that advance by a
+    // step (64 bytes of spectrum row, 128 bytes of right-hand-side row) per
+    // step; the launcher checks that the offsets fit 32 bits.  A instruction
+    // i of this wavefront fills rows 16 (AI wave + i) .. + 15; lane L takes
+    // row L / 4 of those and puts chunk (L % 4) ^ (L / 16 % 4) of it in its
+    // slot.
+    const uint8_t* const abase = fhat + ((long long)w * ga.Nd * ga.pitch + kbeg) * 4;
+    uint32_t aoff[AI];
     {
         const int swz = (lane >> 4) & 3, c = (lane & 3) ^ swz;
 #pragma unroll
         for (int i = 0; i < AI; ++i) {
             const int row = 16 * (AI * wave + i) + (lane >> 2);
             const int sr = min(m0 + row, ga.Nd - 1);
-            asrc[i] = fhat + (((long long)w * ga.Nd + sr) * ga.pitch + kbeg + 4 * c) * 4;
+            aoff[i] = ((uint32_t)sr * (uint32_t)ga.pitch + 4u * (uint32_t)c) * 4u;
         }
     }
     // B plane of this wavefront, plane = (u NH + h) 2 + hl: substep u, half h, hi/lo hl
     const int phl = wave & 1, ph = (wave >> 1) % NH, pu = wave / (2 * NH);
-    const uint8_t* bsrc;
+    const uint8_t* const bbase = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8 + (long long)kbeg * 8 + phl * 16;
+    uint32_t boff;
     {
         const int bl = min(ph * 32 + (lane & 31), nb_valid - 1);
         const int g = 2 * pu + (lane >> 5);
-        bsrc = Bq + ((long long)w * ga.nrhs + b0 + bl) * ga.ldb * 8 + (long long)(kbeg / 4 + g) * 32 + phl * 16;
+        boff = (uint32_t)bl * (uint32_t)ga.ldb * 8u + (uint32_t)g * 32u;
     }
+    const uint32_t la = lds_addr(&ring_a[0][0]) + AI * wave * 1024, lb = lds_addr(&ring_b[0][0]) + wave * 1024;
     auto issue = [&](int st, int slot) {
         const long long sa = st < nst ? st : nst - 1;       // past the end: repeat the last step (unused)
+        const uint8_t* const ab = abase + sa * 64;
 #pragma unroll
-        for (int i = 0; i < AI; ++i) dma16(asrc[i] + sa * 64, &ring_a[slot][(AI * wave + i) * 1024]);
-        dma16(bsrc + sa * 128, &ring_b[slot][wave * 1024]);
+        for (int i = 0; i < AI; ++i) dma16(ab, aoff[i], la + slot * A_STEP + i * 1024);
+        dma16(bbase + sa * 128, boff, lb + slot * B_STEP);
     };
 
     f32x16 accr[MB], acci[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) accr[mb] = acci[mb] = f32x16{};
 
-    auto compute = [&](int slot) {
+    struct Frags {
+        uint4 a[MB], bh, bl;
+    };
+    auto read = [&](Frags& f, int slot, int u) {
+        f.bh = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 0) * 1024 + lane * 16]);
+        f.bl = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 1) * 1024 + lane * 16]);
+        const int cs = ((2 * u + kg) ^ ((r >> 2) & 3)) * 16;
 #pragma unroll
-        for (int u = 0; u < KU; ++u) {
-            const uint4 bh = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 0) * 1024 + lane * 16]);
-            const uint4 bl = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 1) * 1024 + lane * 16]);
-            const uint4 bh_r = f_conj(bh), bh_i = f_swap(bh), bl_r = f_conj(bl), bl_i = f_swap(bl);
-            const int cs = ((2 * u + kg) ^ ((r >> 2) & 3)) * 16;
+        for (int mb = 0; mb < MB; ++mb)
+            f.a[mb] = *reinterpret_cast<const uint4*>(&ring_a[slot][((rg * MB + mb) * 32 + r) * 64 + cs]);
+    };
+    auto mfmas = [&](const Frags& f) {
+        const uint4 bh_r = f_conj(f.bh), bh_i = f_swap(f.bh), bl_r = f_conj(f.bl), bl_i = f_swap(f.bl);
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int mrow = (rg * MB + mb) * 32 + r;
-                const uint4 a = *reinterpret_cast<const uint4*>(&ring_a[slot][mrow * 64 + cs]);
-                accr[mb] = mfma32(a, bh_r, accr[mb]);
-                acci[mb] = mfma32(a, bh_i, acci[mb]);
-                accr[mb] = mfma32(a, bl_r, accr[mb]);
-                acci[mb] = mfma32(a, bl_i, acci[mb]);
-            }
+        for (int mb = 0; mb < MB; ++mb) {
+            accr[mb] = mfma32(f.a[mb], bh_r, accr[mb]);
+            acci[mb] = mfma32(f.a[mb], bh_i, acci[mb]);
+            accr[mb] = mfma32(f.a[mb], bl_r, accr[mb]);
+            acci[mb] = mfma32(f.a[mb], bl_i, acci[mb]);
         }
     };
 
     // Step st: wait for its loads (RING - 2 later steps stay in flight) and
     // for this wavefront's LDS reads; barrier (every wavefront's loads of
-    // step st have landed, every wavefront is done with step st - 1); load
-    // step st + RING - 1 into the slot step st - 1 used; compute step st.
+    // step st have landed, every wavefront is done with step st - 1); read
+    // the first substep's fragments, so that the matrix cores start as soon
+    // as the LDS answers; load step st + RING - 1 into the slot step st - 1
+    // used; compute step st.
 #pragma unroll
     for (int d = 0; d < RING - 1; ++d) issue(d, d);
     int slot = 0;
     for (int st = 0; st < nst; ++st) {
         wait_vm_lgkm0<(RING - 2) * G>();
         bare_barrier();
+        Frags f;
+        read(f, slot, 0);
         const int ns = slot == 0 ? RING - 1 : slot - 1;
         issue(st + RING - 1, ns);
-        compute(slot);
+        mfmas(f);
+#pragma unroll
+        for (int u = 1; u < KU; ++u) {
+            read(f, slot, u);
+            mfmas(f);
+        }
         slot = slot + 1 == RING ? 0 : slot + 1;
     }
     wait_vm_lgkm0<0>();                                   // no load may land after the workgroup ends
@@ -539,6 +563,11 @@ bool gemm_tile_has(int tile, bool fwd) { return tile >= 0 && tile < kTileCount &
 template <int NH>
 static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
                               hipStream_t st) {
+    // the ring kernel addresses a frequency's spectrum and a group's
+    // right-hand-side rows with 32-bit byte offsets; larger shapes take the
+    // register-staged 640-row tile
+    if ((long long)ga.Nd * ga.pitch * 4 >= (1LL << 32) || 32LL * NH * ga.ldb * 8 >= (1LL << 32))
+        return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Bq, out, st);
     ga.n_mt = (ga.Nd + 639) / 640;
     ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
