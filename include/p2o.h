@@ -176,7 +176,9 @@ typedef enum {
 typedef enum {
     P2O_OPT_BATCHED = 0,     /* value: p2o_batched_mode                      */
     P2O_OPT_GEMM_TILE = 1,   /* value: matrix-core tile variant in [0, p2o_gemm_tile_info's count), or -1
-                                (default) for the autotuned or built-in choice; both directions */
+                                (default) for the autotuned or built-in choice; both directions (a
+                                variant built for one direction only leaves the other at its
+                                built-in choice) */
     P2O_OPT_FFT_FIXED = 2    /* value: 1 (default) runs the time-axis FFTs (section 4's circulant
                                 embedding) with kernels compiled for the plan's transform length when
                                 the library has them (lengths L = 32, 256, 840), 0 always with the
@@ -202,7 +204,9 @@ p2o_status p2o_set_option(p2o_plan* plan, int32_t option, int64_t value);
  * products as complex GEMMs, one per frequency).  Variant `tile` assigns
  * 32 * row_groups * blocks output rows (sensors, or parameter columns for the
  * adjoint) and rhs_per_group right-hand sides to a workgroup and stages K in
- * steps of 8 * substeps entries.  Returns P2O_ERR_ARG for an unknown variant;
+ * steps of 8 * substeps entries.  Some variants exist for one direction
+ * only (the LDS-ring kernels); the autotuner times each variant in the
+ * directions it exists for.  Returns P2O_ERR_ARG for an unknown variant;
  * variants are numbered from 0 without gaps, so the first index that fails
  * is the count.  Any output pointer may be NULL. */
 p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* substeps, int32_t* blocks,

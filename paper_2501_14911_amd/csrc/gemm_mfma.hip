@@ -496,6 +496,157 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         }
 }
 
+// ---------------------------------------------------------------- adjoint, LDS ring
+// Adjoint product with both operands streamed into a RING-step LDS ring by
+// direct-to-LDS loads, as in the forward ring.  RG NH wavefronts = RG column
+// groups x NH halves of 32 NH right-hand sides; MB blocks of 32 output
+// columns per wavefront (MROWS = 32 RG MB columns per workgroup).  A step is
+// 16 sensors (two substeps of 8).
+//   A: 16 sensor rows x MROWS columns; a load instruction moves 256 columns
+//      of one row (1 KB, whole lines); rows A_RS = 4 MROWS + 32 bytes apart,
+//      so the two sensor quartets a fragment gathers (rows 4 apart) fall in
+//      different halves of the 64 banks.
+//   B: one plane per (substep, half, hi/lo), lane L's fragment in slot L.
+// Sensor rows past Nd read row Nd - 1 and columns past the pitch read its
+// last entries (valid addresses); a substep that starts at or past the
+// padded data row (ldb, a multiple of 8) is skipped, and inside one the data
+// rows past Nd are zero.
+template <int RG, int MB, int NH>
+__global__ __launch_bounds__(64 * RG * NH) __attribute__((amdgpu_waves_per_eu(2)))
+void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
+                     float2* __restrict__ out_base, GemmArgs ga) {
+    constexpr int KU = 2, RING = kRingSteps, NW = RG * NH;
+    constexpr int MROWS = 32 * RG * MB, RHS = 32 * NH;
+    constexpr int NCP = MROWS / 256;                      // load instructions per sensor row
+    constexpr int AI = 16 * NCP / NW;                     // A loads per wavefront per step
+    constexpr int BI = KU * NH * 2 / NW;                  // B loads per wavefront per step
+    static_assert(MROWS % 256 == 0 && AI * NW == 16 * NCP && BI * NW == KU * NH * 2, "loads per wavefront");
+    constexpr int A_RS = 4 * MROWS + 32;
+    constexpr int A_STEP = 16 * A_RS;
+    constexpr int B_STEP = KU * NH * 2 * 1024;
+    constexpr int G = AI + BI;
+    __shared__ __align__(16) uint8_t ring_a[RING][A_STEP];
+    __shared__ __align__(16) uint8_t ring_b[RING][B_STEP];
+
+    const int q = xcd_item(blockIdx.x, ga.Q);
+    if (q >= ga.items) return;
+    int t = q;
+    const int mt = t % ga.n_mt; t /= ga.n_mt;
+    const int bg = t % ga.n_bg; t /= ga.n_bg;
+    const int w = t;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rg = wave % RG, nh = wave / RG;
+    const int r = lane & 31, kg = lane >> 5;
+    const int b0 = bg * RHS;
+    const int nb_valid = min(RHS, ga.nrhs - b0);
+    const int m0 = mt * MROWS;                            // first output column of the tile
+    const int nst = (ga.ldb + 15) / 16;
+
+    // A instruction i of this wavefront: sensor row k = a / NCP of the step,
+    // columns m0 + 256 (a % NCP) + 4 lane .. + 3 (a = AI wave + i)
+    const uint8_t* const arows = fhat + (long long)w * ga.Nd * ga.pitch * 4;
+    uint32_t aoff[AI];
+#pragma unroll
+    for (int i = 0; i < AI; ++i) {
+        const int a = AI * wave + i;
+        aoff[i] = (uint32_t)min(m0 + 256 * (a % NCP) + 4 * lane, ga.pitch - 4) * 4u;
+    }
+    // B plane p = (u NH + h) 2 + hl of instruction i: right-hand side
+    // h 32 + lane % 32, group 2 u + lane / 32 of the step, hi/lo hl
+    const uint8_t* const brows = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
+    uint32_t boff[BI];
+#pragma unroll
+    for (int i = 0; i < BI; ++i) {
+        const int pl = BI * wave + i, h = (pl >> 1) % NH;
+        const int bl = min(h * 32 + (lane & 31), nb_valid - 1);
+        boff[i] = (uint32_t)bl * (uint32_t)ga.ldb * 8u + (uint32_t)(lane >> 5) * 32u + (uint32_t)(pl & 1) * 16u;
+    }
+    const uint32_t la = lds_addr(&ring_a[0][0]), lb = lds_addr(&ring_b[0][0]) + BI * wave * 1024;
+    const int glast = ga.ldb / 4 - 2;                     // last whole substep's first group
+    auto issue = [&](int st, int slot) {
+        const int sa = st < nst ? st : nst - 1;           // past the end: repeat the last step (unused)
+#pragma unroll
+        for (int i = 0; i < AI; ++i) {
+            const int a = AI * wave + i, k = a / NCP;
+            const int row = min(16 * sa + k, ga.Nd - 1);
+            dma16(arows + (long long)row * ga.pitch * 4, aoff[i], la + slot * A_STEP + k * A_RS + (a % NCP) * 1024);
+        }
+#pragma unroll
+        for (int i = 0; i < BI; ++i) {
+            const int pl = BI * wave + i, u = pl / (2 * NH);
+            const int g = min(4 * sa + 2 * u, glast);
+            dma16(brows + (long long)g * 32, boff[i], lb + slot * B_STEP + i * 1024);
+        }
+    };
+
+    f32x16 accr[MB], acci[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) accr[mb] = acci[mb] = f32x16{};
+
+    // lane (r, kg) of block mb, substep u: sensors 8 u + 4 kg .. + 3 of the
+    // step for column (rg MB + mb) 32 + r
+    struct Frags {
+        uint4 a[MB], bh, bl;
+    };
+    auto read = [&](Frags& f, int slot, int u) {
+        f.bh = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 0) * 1024 + lane * 16]);
+        f.bl = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 1) * 1024 + lane * 16]);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const uint8_t* p = &ring_a[slot][(8 * u + 4 * kg) * A_RS + ((rg * MB + mb) * 32 + r) * 4];
+            f.a[mb] = make_uint4(*reinterpret_cast<const uint32_t*>(p), *reinterpret_cast<const uint32_t*>(p + A_RS),
+                                 *reinterpret_cast<const uint32_t*>(p + 2 * A_RS),
+                                 *reinterpret_cast<const uint32_t*>(p + 3 * A_RS));
+        }
+    };
+    auto mfmas = [&](const Frags& f) {
+        const uint4 bh_i = f_nswap(f.bh), bl_i = f_nswap(f.bl);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            accr[mb] = mfma32(f.a[mb], f.bh, accr[mb]);
+            acci[mb] = mfma32(f.a[mb], bh_i, acci[mb]);
+            accr[mb] = mfma32(f.a[mb], f.bl, accr[mb]);
+            acci[mb] = mfma32(f.a[mb], bl_i, acci[mb]);
+        }
+    };
+
+#pragma unroll
+    for (int d = 0; d < RING - 1; ++d) issue(d, d);
+    int slot = 0;
+    for (int st = 0; st < nst; ++st) {
+        wait_vm_lgkm0<(RING - 2) * G>();
+        bare_barrier();
+        Frags f;
+        read(f, slot, 0);                                 // first fragments before the next loads
+        const int ns = slot == 0 ? RING - 1 : slot - 1;
+        issue(st + RING - 1, ns);
+        mfmas(f);
+        if (16 * st + 8 < ga.ldb) {
+            read(f, slot, 1);
+            mfmas(f);
+        }
+        slot = slot + 1 == RING ? 0 : slot + 1;
+    }
+    wait_vm_lgkm0<0>();                                   // no load may land after the workgroup ends
+
+    const int b = b0 + 32 * nh + r;
+    if (b >= ga.nrhs) return;
+    float2* out = out_base + ((long long)w * ga.nrhs + b) * ga.pitch;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const int jb = m0 + (rg * MB + mb) * 32;            // an m block lies in one 4096-column scale block
+        if (jb >= ga.ncols) continue;
+        const float sc = scales[(long long)w * ga.nblk + jb / kScaleBlock];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int j = jb + 8 * (v >> 2) + 4 * kg + (v & 3);
+            if (j < ga.ncols) out[j] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+        }
+    }
+}
+
 // Operand filler for timing runs: words of two BF16 values with magnitudes in
 // [1/2, 1) and hashed signs and mantissas.  The matrix cores draw much more
 // power on such data than on zeros, and the power limit sets their clock, so
@@ -546,19 +697,24 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
 // adjoint's 256-column tiles also divide 4096-column blocks evenly).  A
 // plan's autotuner may replace the built-in choice (gemm_default_tile).
 // Variants 7 and 8 are the forward LDS-ring kernel (k_gemm_fwd_ring, pf = 0
-// marks the ring) for 64 and 32 right-hand sides per group; they have no
-// adjoint, which then takes its built-in choice.
+// marks a ring) for 64 and 32 right-hand sides per group, 9 and 10 the
+// adjoint one (k_gemm_adj_ring) for 64 and 32; a direction a variant lacks
+// takes its built-in choice.
 struct TileShape {
     int rg, ku, mb, wpe, pf, nw;
+    int dirs;   // 1: forward, 2: adjoint, 3: both
 };
-static const TileShape kTiles[] = {{2, 4, 5, 1, 2, 4}, {2, 2, 5, 1, 2, 4}, {4, 2, 5, 1, 2, 4}, {2, 2, 4, 2, 2, 4},
-                                   {4, 2, 4, 2, 2, 4}, {2, 2, 5, 2, 1, 4}, {4, 2, 5, 2, 1, 8}, {4, 2, 5, 2, 0, 8},
-                                   {4, 2, 5, 1, 0, 4}};
+static const TileShape kTiles[] = {{2, 4, 5, 1, 2, 4, 3}, {2, 2, 5, 1, 2, 4, 3}, {4, 2, 5, 1, 2, 4, 3},
+                                   {2, 2, 4, 2, 2, 4, 3}, {4, 2, 4, 2, 2, 4, 3}, {2, 2, 5, 2, 1, 4, 3},
+                                   {4, 2, 5, 2, 1, 8, 3}, {4, 2, 5, 2, 0, 8, 1}, {4, 2, 5, 1, 0, 4, 1},
+                                   {2, 2, 4, 2, 0, 4, 2}, {4, 2, 4, 1, 0, 4, 2}};
 constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_tile_count() { return kTileCount; }
 
-bool gemm_tile_has(int tile, bool fwd) { return tile >= 0 && tile < kTileCount && (fwd || kTiles[tile].pf != 0); }
+bool gemm_tile_has(int tile, bool fwd) {
+    return tile >= 0 && tile < kTileCount && (kTiles[tile].dirs & (fwd ? 1 : 2)) != 0;
+}
 
 template <int NH>
 static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
@@ -574,6 +730,22 @@ static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales
     ga.Q = (ga.items + 7) / 8;
     hipLaunchKernelGGL(k_gemm_fwd_ring<NH>, dim3(8 * ga.Q), dim3(256 * NH), 0, st, (const uint8_t*)fhat, scales,
                        (const uint8_t*)Bq, (float2*)out, ga);
+    return hipGetLastError();
+}
+
+template <int RG, int MB, int NH>
+static hipError_t launch_adj_ring(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
+                                  hipStream_t st) {
+    // 32-bit lane offsets within a spectrum row and a group's right-hand-side rows
+    if ((long long)ga.pitch * 4 >= (1LL << 32) || 32LL * NH * ga.ldb * 8 >= (1LL << 32))
+        return launch_tile<false, 2, 2, 4, 2, 2>(ga, fhat, scales, Bq, out, st);
+    constexpr int MROWS = 32 * RG * MB;
+    ga.n_mt = (ga.ncols + MROWS - 1) / MROWS;
+    ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
+    ga.items = ga.nfreq * ga.n_bg * ga.n_mt;
+    ga.Q = (ga.items + 7) / 8;
+    hipLaunchKernelGGL((k_gemm_adj_ring<RG, MB, NH>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                       (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
 }
 
@@ -596,7 +768,7 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.ncols);
-    if (tile < 0 || tile >= kTileCount) tile = gemm_default_tile(ga.nrhs, true);
+    if (!gemm_tile_has(tile, true)) tile = gemm_default_tile(ga.nrhs, true);
     switch (tile) {
         case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 1: return launch_tile<true, 2, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
@@ -606,7 +778,8 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
         case 5: return launch_tile<true, 2, 2, 5, 2, 1>(ga, fhat, scales, Xq, Yp, st);
         case 6: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
         case 7: return launch_ring<2>(ga, fhat, scales, Xq, Yp, st);
-        default: return launch_ring<1>(ga, fhat, scales, Xq, Yp, st);
+        case 8: return launch_ring<1>(ga, fhat, scales, Xq, Yp, st);
+        default: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
     }
 }
 
@@ -624,7 +797,9 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
         case 3: return launch_tile<false, 2, 2, 4, 2, 2>(ga, fhat, scales, Yq, Xp, st);
         case 4: return launch_tile<false, 4, 2, 4, 2, 2>(ga, fhat, scales, Yq, Xp, st);
         case 5: return launch_tile<false, 2, 2, 5, 2, 1>(ga, fhat, scales, Yq, Xp, st);
-        default: return launch_tile<false, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Yq, Xp, st);
+        case 6: return launch_tile<false, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Yq, Xp, st);
+        case 9: return launch_adj_ring<2, 4, 2>(ga, fhat, scales, Yq, Xp, st);
+        default: return launch_adj_ring<4, 4, 1>(ga, fhat, scales, Yq, Xp, st);
     }
 }
 
