@@ -238,6 +238,12 @@ def main():
     log(f"[bench] streaming probe: read {probe['read_GBs']:.0f} GB/s, copy {probe['copy_GBs']:.0f} GB/s; "
         f"{dom} at {dk['GBs']:.0f} GB/s = {roof['frac']:.1%} of 8 TB/s, {roof['frac_of_measured_read']:.1%} of read probe")
 
+    result["calls"] = call_stats(op, w, m, d_obs, E, spec_bytes, vec_bytes, probe["read_GBs"], dev, torch, np, synth)
+    for k, v in result["calls"].items():
+        log(f"[bench] {k:5s} median {v['median_ms']:.3f} ms (p10 {v['p10_ms']:.3f}, p90 {v['p90_ms']:.3f}; "
+            f"{v['calls']} calls): {v['matvecs_per_s']:.0f} matvecs/s, spectrum {v['spectrum_GBs']:.0f} GB/s "
+            f"= {v['spectrum_frac_of_peak']:.1%} of 8 TB/s")
+
     if not args.no_accuracy:
         result["accuracy"] = accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np)
     if not args.no_fp64:
@@ -254,44 +260,48 @@ def main():
 # rows come from the autotuner's launches, which run every tile variant on the
 # benchmark's shapes.  Valid only for the kernel source it was measured on:
 # keyed by the SHA-1 of that file.
-_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "067485f38484f490ef9d801a98988cf07e853d0f")
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "0dfaaffb52614c37055b0a0eec0e8d8203e91109")
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile): (fetch bytes, write bytes); GEMM rows from the autotuner's launches of every tile
 _MEASURED = {
-    ("gemm_adj_32", 0): (16778408219, 1765815021),
-    ("gemm_adj_32", 1): (16789485004, 1765818029),
-    ("gemm_adj_32", 2): (16737138476, 1766875533),
-    ("gemm_adj_32", 3): (16714261266, 1765891469),
-    ("gemm_adj_32", 4): (16720406979, 1768741197),
-    ("gemm_adj_32", 5): (16784355278, 1788284301),
-    ("gemm_adj_32", 6): (16827608739, 1878621292),
-    ("gemm_adj_64", 0): (16938949134, 3537686874),
-    ("gemm_adj_64", 1): (17082004002, 3535211514),
-    ("gemm_adj_64", 2): (31943716563, 3535124410),
-    ("gemm_adj_64", 3): (16970642807, 3533772794),
-    ("gemm_adj_64", 4): (33475245324, 3538248570),
-    ("gemm_adj_64", 5): (17007680860, 3556046585),
-    ("gemm_adj_64", 6): (16985396346, 3692048056),
-    ("gemm_fwd_32", 0): (18402959145, 260626333),
-    ("gemm_fwd_32", 1): (18390164749, 261660669),
-    ("gemm_fwd_32", 2): (19172060314, 261006365),
-    ("gemm_fwd_32", 3): (20632175335, 260940957),
-    ("gemm_fwd_32", 4): (19950791952, 261911069),
-    ("gemm_fwd_32", 5): (20335546694, 260193021),
-    ("gemm_fwd_32", 6): (18688278363, 260850685),
-    ("gemm_fwd_32", 7): (18585415619, 261026653),
-    ("gemm_fwd_32", 8): (18928489360, 260973789),
-    ("gemm_fwd_64", 0): (20322346160, 523254586),
-    ("gemm_fwd_64", 1): (20316012737, 522977498),
-    ("gemm_fwd_64", 2): (20642864798, 524476666),
-    ("gemm_fwd_64", 3): (25246601682, 519833338),
-    ("gemm_fwd_64", 4): (24005814598, 521689658),
-    ("gemm_fwd_64", 5): (23652567868, 519937754),
-    ("gemm_fwd_64", 6): (20530881147, 534578362),
-    ("gemm_fwd_64", 7): (20614938565, 530416314),
-    ("gemm_fwd_64", 8): (20641011126, 526148378),
-    ("gemv_adj", None): (16586662349, 55187157),
-    ("gemv_fwd", None): (17107136138, 16166400),
+    ('gemm_adj_32', 0): (16772207160, 1765822194),
+    ('gemm_adj_32', 1): (16792382772, 1765810258),
+    ('gemm_adj_32', 2): (16749196257, 1766830962),
+    ('gemm_adj_32', 3): (16713222896, 1765912018),
+    ('gemm_adj_32', 4): (16739690715, 1782183506),
+    ('gemm_adj_32', 5): (16786786748, 1810713457),
+    ('gemm_adj_32', 6): (16757287288, 1811572465),
+    ('gemm_adj_32', 9): (16705675601, 1766092530),
+    ('gemm_adj_32', 10): (16712840437, 1766209938),
+    ('gemm_adj_64', 0): (16939243920, 3536616451),
+    ('gemm_adj_64', 1): (17092504538, 3535069635),
+    ('gemm_adj_64', 2): (31232469192, 3534523203),
+    ('gemm_adj_64', 3): (16970799738, 3534076451),
+    ('gemm_adj_64', 4): (33507215952, 3564624067),
+    ('gemm_adj_64', 5): (17029553925, 3577898147),
+    ('gemm_adj_64', 6): (16958563351, 3669566754),
+    ('gemm_adj_64', 9): (16928717720, 3533524259),
+    ('gemm_adj_64', 10): (33474523829, 3532261603),
+    ('gemm_fwd_32', 0): (18400483208, 261088478),
+    ('gemm_fwd_32', 1): (18471507445, 261768542),
+    ('gemm_fwd_32', 2): (18778127750, 260775710),
+    ('gemm_fwd_32', 3): (20873382806, 260977182),
+    ('gemm_fwd_32', 4): (19966620023, 262117118),
+    ('gemm_fwd_32', 5): (19943633824, 260445822),
+    ('gemm_fwd_32', 6): (18601664232, 260665886),
+    ('gemm_fwd_32', 7): (18910002596, 260507870),
+    ('gemm_fwd_32', 8): (19094367772, 260716286),
+    ('gemm_fwd_64', 0): (20278307400, 522828988),
+    ('gemm_fwd_64', 1): (20888497619, 522508572),
+    ('gemm_fwd_64', 2): (20642311415, 523859836),
+    ('gemm_fwd_64', 3): (25525170558, 519417276),
+    ('gemm_fwd_64', 4): (24021757222, 522083356),
+    ('gemm_fwd_64', 5): (23008131048, 519588060),
+    ('gemm_fwd_64', 6): (20519558948, 534532700),
+    ('gemm_fwd_64', 7): (21133802043, 530037756),
+    ('gemm_fwd_64', 8): (20653168619, 524529340),
+    ('gemv_adj', None): (16586660411, 55189129),
+    ('gemv_fwd', None): (17106877945, 16166400),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
@@ -312,6 +322,41 @@ def measured_traffic(kernel, tile, w):
     if cur != sha:
         return None
     return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "source": src, "sha1": sha}
+
+
+def call_stats(op, w, m, d_obs, E, spec_bytes, vec_bytes, read_GBs, dev, torch, np, synth, calls=20, warm=3):
+    """Whole calls of F and F* (FFTs and products), separately, at one and at
+    64 right-hand sides: 3 warm-ups, then the median and 10th / 90th
+    percentiles of `calls` calls, each bracketed by HIP events on the plan's
+    stream.  Spectrum GB/s counts the spectrum bytes once per call."""
+    m64 = synth.param_series(w, N_HESS, seed_offset=41, backend="torch", device=dev).float()
+    d1 = d_obs.unsqueeze(0)
+    out = {"F_1": (lambda o: op.apply_F(m.unsqueeze(0), out=o), (1, w.Nt, w.Nd), 1),
+           "Ft_1": (lambda o: op.apply_Ft(d1, out=o), (1, w.Nt, w.Nm), 1),
+           "F_64": (lambda o: op.apply_F(m64, out=o), (N_HESS, w.Nt, w.Nd), N_HESS),
+           "Ft_64": (lambda o: op.apply_Ft(E, out=o), (N_HESS, w.Nt, w.Nm), N_HESS)}
+    res = {}
+    for name, (fn, shape, nrhs) in out.items():
+        o = torch.empty(shape, dtype=torch.float32, device=dev)
+        for _ in range(warm):
+            fn(o)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        for a, b in evs:
+            a.record()
+            fn(o)
+            b.record()
+        torch.cuda.synchronize()
+        ts = np.array([a.elapsed_time(b) for a, b in evs])
+        med = float(np.median(ts))
+        res[name] = {"nrhs": nrhs, "calls": calls, "median_ms": med, "p10_ms": float(np.percentile(ts, 10)),
+                     "p90_ms": float(np.percentile(ts, 90)), "matvecs_per_s": nrhs / (med * 1e-3),
+                     "spectrum_GBs": spec_bytes / (med * 1e-3) / 1e9,
+                     "spectrum_frac_of_peak": spec_bytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "spectrum_frac_of_measured_read": spec_bytes / (med * 1e-3) / 1e9 / read_GBs,
+                     "algorithmic_GBs": (spec_bytes + vec_bytes(nrhs)) / (med * 1e-3) / 1e9}
+        del o
+    del m64
+    return res
 
 
 def accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np):
