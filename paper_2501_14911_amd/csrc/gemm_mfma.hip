@@ -327,7 +327,10 @@ void k_gemm(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t
 //   A: 640 rows x 64 bytes, rows packed (a load instruction fills 16 rows);
 //      the 16-byte chunk c of row r sits in slot c ^ ((r / 4) mod 4), so that
 //      16 lanes reading one chunk of 16 consecutive rows hit distinct banks.
-//   B: one plane per (substep, half, hi/lo), lane L's fragment in slot L.
+//   B: right-hand side b's 128 bytes of the step (4 groups x hi/lo) as 8
+//      16-byte parts, part p in slot p ^ ((b / 2) mod 8), so that a load
+//      instruction moves 8 whole 128-byte lines (8 right-hand sides) and
+//      the 16 lanes of a fragment read (consecutive b) hit distinct banks.
 // The K range is rounded up to whole steps; that stays inside the row pitch
 // (a multiple of 32 entries >= Nm), where spectrum and right-hand sides
 // are zero past Nm, so no step needs masking.
@@ -372,7 +375,8 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
     constexpr int AI = MROWS / 16 / (RG * NH);            // A loads (16 rows each) per wavefront per step
     static_assert(AI * 16 * RG * NH == MROWS, "A rows per wavefront");
     constexpr int A_STEP = MROWS * 64;                    // bytes of A per step
-    constexpr int B_STEP = KU * NH * 2 * 1024;            // bytes of B per step (one plane per wavefront)
+    constexpr int B_STEP = RHS * 128;                     // bytes of B per step (8 right-hand sides per wavefront)
+    static_assert(8 * RG * NH == RHS, "one B load per wavefront per step");
     constexpr int G = AI + 1;                             // loads per wavefront per step
     __shared__ __align__(16) uint8_t ring_a[RING][A_STEP];
     __shared__ __align__(16) uint8_t ring_b[RING][B_STEP];
@@ -413,14 +417,15 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
             aoff[i] = ((uint32_t)sr * (uint32_t)ga.pitch + 4u * (uint32_t)c) * 4u;
         }
     }
-    // B plane of this wavefront, plane = (u NH + h) 2 + hl: substep u, half h, hi/lo hl
-    const int phl = wave & 1, ph = (wave >> 1) % NH, pu = wave / (2 * NH);
-    const uint8_t* const bbase = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8 + (long long)kbeg * 8 + phl * 16;
+    // B rows 8 wave .. + 7 of the group: lane L moves part
+    // (L % 8) ^ ((b / 2) mod 8) of right-hand side b = 8 wave + L / 8 into
+    // slot L % 8 of that right-hand side's 128 bytes
+    const uint8_t* const bbase = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8 + (long long)kbeg * 8;
     uint32_t boff;
     {
-        const int bl = min(ph * 32 + (lane & 31), nb_valid - 1);
-        const int g = 2 * pu + (lane >> 5);
-        boff = (uint32_t)bl * (uint32_t)ga.ldb * 8u + (uint32_t)g * 32u;
+        const int b = 8 * wave + (lane >> 3);
+        const int part = (lane & 7) ^ ((b >> 1) & 7);
+        boff = (uint32_t)min(b, nb_valid - 1) * (uint32_t)ga.ldb * 8u + (uint32_t)part * 16u;
     }
     const uint32_t la = lds_addr(&ring_a[0][0]) + AI * wave * 1024, lb = lds_addr(&ring_b[0][0]) + wave * 1024;
     auto issue = [&](int st, int slot) {
@@ -439,8 +444,10 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         uint4 a[MB], bh, bl;
     };
     auto read = [&](Frags& f, int slot, int u) {
-        f.bh = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 0) * 1024 + lane * 16]);
-        f.bl = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 1) * 1024 + lane * 16]);
+        // right-hand side 32 nh + r, group 2 u + kg: parts 2 (2 u + kg) (hi) and + 1 (lo)
+        const int rb = 32 * nh + r, sw = (rb >> 1) & 7, ph = 2 * (2 * u + kg);
+        f.bh = *reinterpret_cast<const uint4*>(&ring_b[slot][rb * 128 + ((ph ^ sw) * 16)]);
+        f.bl = *reinterpret_cast<const uint4*>(&ring_b[slot][rb * 128 + (((ph + 1) ^ sw) * 16)]);
         const int cs = ((2 * u + kg) ^ ((r >> 2) & 3)) * 16;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
