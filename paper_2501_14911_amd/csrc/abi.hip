@@ -172,7 +172,7 @@ void layout(p2o_plan* p) {
     size_t ylen = yparts * nfreq * R * (size_t)p->Nd;
     if (p->prec == kBF16) {
         // matrix-core path: forward partials per 4096-column chunk, and data
-        // spectra in quad storage with rows padded to a multiple of 8
+        // spectra in quad storage with rows padded to a multiple of 16
         ylen = std::max(ylen, (size_t)gemm_fwd_kchunks((int)live_cols(p)) * nfreq * R * (size_t)p->Nd);
         ylen = std::max(ylen, nfreq * R * (size_t)gemm_data_pitch((int)p->Nd));
     }

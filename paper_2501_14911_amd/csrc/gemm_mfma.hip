@@ -513,11 +513,12 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
 //      of one row (1 KB, whole lines); rows A_RS = 4 MROWS + 32 bytes apart,
 //      so the two sensor quartets a fragment gathers (rows 4 apart) fall in
 //      different halves of the 64 banks.
-//   B: one plane per (substep, half, hi/lo), lane L's fragment in slot L.
-// Sensor rows past Nd read row Nd - 1 and columns past the pitch read its
-// last entries (valid addresses); a substep that starts at or past the
-// padded data row (ldb, a multiple of 8) is skipped, and inside one the data
-// rows past Nd are zero.
+//   B: as in the forward ring, right-hand side b's 128 bytes of the step
+//      (4 sensor groups x hi/lo) in 8 parts, part p in slot p ^ ((b / 2) mod 8).
+// The data rows are padded with zeros to a multiple of 16 sensors (ldb), so
+// every step is whole; sensor rows past Nd read row Nd - 1 and columns past
+// the pitch read its last entries (valid addresses), and a substep that
+// starts at or past Nd is skipped (its data rows are zero).
 template <int RG, int MB, int NH>
 __global__ __launch_bounds__(64 * RG * NH) __attribute__((amdgpu_waves_per_eu(2)))
 void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
@@ -526,11 +527,11 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
     constexpr int MROWS = 32 * RG * MB, RHS = 32 * NH;
     constexpr int NCP = MROWS / 256;                      // load instructions per sensor row
     constexpr int AI = 16 * NCP / NW;                     // A loads per wavefront per step
-    constexpr int BI = KU * NH * 2 / NW;                  // B loads per wavefront per step
-    static_assert(MROWS % 256 == 0 && AI * NW == 16 * NCP && BI * NW == KU * NH * 2, "loads per wavefront");
+    constexpr int BI = RHS / 8 / NW;                      // B loads (8 right-hand sides each) per wavefront per step
+    static_assert(MROWS % 256 == 0 && AI * NW == 16 * NCP && BI * 8 * NW == RHS, "loads per wavefront");
     constexpr int A_RS = 4 * MROWS + 32;
     constexpr int A_STEP = 16 * A_RS;
-    constexpr int B_STEP = KU * NH * 2 * 1024;
+    constexpr int B_STEP = RHS * 128;
     constexpr int G = AI + BI;
     __shared__ __align__(16) uint8_t ring_a[RING][A_STEP];
     __shared__ __align__(16) uint8_t ring_b[RING][B_STEP];
@@ -549,7 +550,7 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
     const int b0 = bg * RHS;
     const int nb_valid = min(RHS, ga.nrhs - b0);
     const int m0 = mt * MROWS;                            // first output column of the tile
-    const int nst = (ga.ldb + 15) / 16;
+    const int nst = ga.ldb / 16;                          // ldb is a multiple of 16
 
     // A instruction i of this wavefront: sensor row k = a / NCP of the step,
     // columns m0 + 256 (a % NCP) + 4 lane .. + 3 (a = AI wave + i)
@@ -560,18 +561,17 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         const int a = AI * wave + i;
         aoff[i] = (uint32_t)min(m0 + 256 * (a % NCP) + 4 * lane, ga.pitch - 4) * 4u;
     }
-    // B plane p = (u NH + h) 2 + hl of instruction i: right-hand side
-    // h 32 + lane % 32, group 2 u + lane / 32 of the step, hi/lo hl
+    // B instruction i: right-hand sides 8 (BI wave + i) .. + 7, lane L
+    // moving part (L % 8) ^ ((b / 2) mod 8) of b = 8 (BI wave + i) + L / 8
     const uint8_t* const brows = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8;
     uint32_t boff[BI];
 #pragma unroll
     for (int i = 0; i < BI; ++i) {
-        const int pl = BI * wave + i, h = (pl >> 1) % NH;
-        const int bl = min(h * 32 + (lane & 31), nb_valid - 1);
-        boff[i] = (uint32_t)bl * (uint32_t)ga.ldb * 8u + (uint32_t)(lane >> 5) * 32u + (uint32_t)(pl & 1) * 16u;
+        const int b = 8 * (BI * wave + i) + (lane >> 3);
+        const int part = (lane & 7) ^ ((b >> 1) & 7);
+        boff[i] = (uint32_t)min(b, nb_valid - 1) * (uint32_t)ga.ldb * 8u + (uint32_t)part * 16u;
     }
     const uint32_t la = lds_addr(&ring_a[0][0]), lb = lds_addr(&ring_b[0][0]) + BI * wave * 1024;
-    const int glast = ga.ldb / 4 - 2;                     // last whole substep's first group
     auto issue = [&](int st, int slot) {
         const int sa = st < nst ? st : nst - 1;           // past the end: repeat the last step (unused)
 #pragma unroll
@@ -581,11 +581,7 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
             dma16(arows + (long long)row * ga.pitch * 4, aoff[i], la + slot * A_STEP + k * A_RS + (a % NCP) * 1024);
         }
 #pragma unroll
-        for (int i = 0; i < BI; ++i) {
-            const int pl = BI * wave + i, u = pl / (2 * NH);
-            const int g = min(4 * sa + 2 * u, glast);
-            dma16(brows + (long long)g * 32, boff[i], lb + slot * B_STEP + i * 1024);
-        }
+        for (int i = 0; i < BI; ++i) dma16(brows + (long long)sa * 128, boff[i], lb + slot * B_STEP + i * 1024);
     };
 
     f32x16 accr[MB], acci[MB];
@@ -598,8 +594,10 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         uint4 a[MB], bh, bl;
     };
     auto read = [&](Frags& f, int slot, int u) {
-        f.bh = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 0) * 1024 + lane * 16]);
-        f.bl = *reinterpret_cast<const uint4*>(&ring_b[slot][((u * NH + nh) * 2 + 1) * 1024 + lane * 16]);
+        // right-hand side 32 nh + r, group 2 u + kg: parts 2 (2 u + kg) (hi) and + 1 (lo)
+        const int rb = 32 * nh + r, sw = (rb >> 1) & 7, ph = 2 * (2 * u + kg);
+        f.bh = *reinterpret_cast<const uint4*>(&ring_b[slot][rb * 128 + ((ph ^ sw) * 16)]);
+        f.bl = *reinterpret_cast<const uint4*>(&ring_b[slot][rb * 128 + (((ph + 1) ^ sw) * 16)]);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const uint8_t* p = &ring_a[slot][(8 * u + 4 * kg) * A_RS + ((rg * MB + mb) * 32 + r) * 4];
@@ -630,7 +628,7 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         const int ns = slot == 0 ? RING - 1 : slot - 1;
         issue(st + RING - 1, ns);
         mfmas(f);
-        if (16 * st + 8 < ga.ldb) {
+        if (16 * st + 8 < ga.Nd) {
             read(f, slot, 1);
             mfmas(f);
         }
@@ -677,7 +675,7 @@ hipError_t launch_fill_bf16(void* p, size_t bytes, uint32_t seed, hipStream_t st
 // ---------------------------------------------------------------- host launchers
 int gemm_fwd_kchunks(int ncols) { return (ncols + kScaleBlock - 1) / kScaleBlock; }
 
-int gemm_data_pitch(int Nd) { return (Nd + 7) / 8 * 8; }
+int gemm_data_pitch(int Nd) { return (Nd + 15) / 16 * 16; }
 
 template <bool FWD, int RG, int KU, int MB, int WPE, int PF, int NW = 4>
 static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
@@ -766,8 +764,9 @@ int gemm_tile_shape(int tile, int* rg, int* ku, int* mb, int* rhs) {
 }
 
 // Built-in choice without autotuning: the variants measured fastest on the
-// 600 x 16384 x 420 workload (random operands) for each width.
-int gemm_default_tile(int nrhs, bool fwd) { return nrhs > 32 ? (fwd ? 6 : 3) : 2; }
+// 600 x 16384 x 420 workload (random operands) for each width (the LDS
+// rings 7 / 9 above 32 right-hand sides, ring 8 and tile 4 at most 32).
+int gemm_default_tile(int nrhs, bool fwd) { return nrhs > 32 ? (fwd ? 7 : 9) : (fwd ? 8 : 4); }
 
 hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Xq,
                            void* Yp, hipStream_t st) {

@@ -87,7 +87,7 @@ hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int 
 
 // gemm_mfma.hip
 int gemm_fwd_kchunks(int ncols);
-int gemm_data_pitch(int Nd);   // row length of data-side quad spectra read by the adjoint (Nd rounded up to 8)
+int gemm_data_pitch(int Nd);   // row length of data-side quad spectra read by the adjoint (Nd rounded up to 16)
 int gemm_tile_count();
 bool gemm_tile_has(int tile, bool fwd);   // variant exists for that direction (others take the built-in choice)
 int gemm_tile_shape(int tile, int* row_groups, int* substeps, int* blocks, int* rhs_per_group);
