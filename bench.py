@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-call-stats", action="store_true")
     return ap.parse_args()
 
 
@@ -238,8 +239,10 @@ def main():
     log(f"[bench] streaming probe: read {probe['read_GBs']:.0f} GB/s, copy {probe['copy_GBs']:.0f} GB/s; "
         f"{dom} at {dk['GBs']:.0f} GB/s = {roof['frac']:.1%} of 8 TB/s, {roof['frac_of_measured_read']:.1%} of read probe")
 
-    result["calls"] = call_stats(op, w, m, d_obs, E, spec_bytes, vec_bytes, probe["read_GBs"], dev, torch, np, synth)
-    for k, v in result["calls"].items():
+    if not args.no_call_stats:
+        result["calls"] = call_stats(op, w, m, d_obs, E, spec_bytes, vec_bytes, probe["read_GBs"], dev, torch, np,
+                                     synth)
+    for k, v in result.get("calls", {}).items():
         log(f"[bench] {k:5s} median {v['median_ms']:.3f} ms (p10 {v['p10_ms']:.3f}, p90 {v['p90_ms']:.3f}; "
             f"{v['calls']} calls): {v['matvecs_per_s']:.0f} matvecs/s, spectrum {v['spectrum_GBs']:.0f} GB/s "
             f"= {v['spectrum_frac_of_peak']:.1%} of 8 TB/s")
