@@ -534,11 +534,16 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
     constexpr int B_STEP = RHS * 128;
     constexpr int G = AI + BI;
     // Output staging (after the K loop, over the ring): 32 right-hand sides x
-    // MROWS columns of complex FP32 at a time, rows OS_RS bytes apart (16 bytes
-    // of padding shift consecutive rows across the banks).
-    constexpr int OS_RS = MROWS * 8 + 16;
-    constexpr bool STAGE = 32 * OS_RS <= RING * (A_STEP + B_STEP);
-    __shared__ __align__(16) uint8_t lds[RING * (A_STEP + B_STEP)];
+    // CW columns of complex FP32 at a time (CW: MROWS or the largest part of
+    // it that fits, in whole wavefront column ranges), rows OS_RS bytes apart
+    // (16 bytes of padding shift consecutive rows across the banks).
+    constexpr int LDS_BYTES = RING * (A_STEP + B_STEP);
+    constexpr int CW = 32 * (MROWS * 8 + 16) <= LDS_BYTES       ? MROWS
+                       : 32 * (MROWS / 2 * 8 + 16) <= LDS_BYTES ? MROWS / 2
+                                                                : MROWS / 4;
+    constexpr int OS_RS = CW * 8 + 16;
+    constexpr bool STAGE = 32 * OS_RS <= LDS_BYTES && CW % (32 * MB) == 0;
+    __shared__ __align__(16) uint8_t lds[LDS_BYTES];
     uint8_t (*ring_a)[A_STEP] = reinterpret_cast<uint8_t (*)[A_STEP]>(lds);
     uint8_t (*ring_b)[B_STEP] = reinterpret_cast<uint8_t (*)[B_STEP]>(lds + RING * A_STEP);
 
@@ -643,20 +648,21 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
     wait_vm_lgkm0<0>();                                   // no load may land after the workgroup ends
 
     if constexpr (STAGE) {
-        // Each half of the right-hand sides in turn: its wavefronts write
-        // their scaled products to LDS, then the whole workgroup stores rows
-        // of MROWS columns (16 bytes per lane, whole lines) instead of the
-        // accumulators' 8-byte pieces spread over 32 rows.
-        for (int h = 0; h < NH; ++h) {
-            bare_barrier();                               // ring (or previous half) reads done
-            if (nh == h) {
+        // Each (half of the right-hand sides, column part) in turn: its
+        // wavefronts write their scaled products to LDS, then the whole
+        // workgroup stores rows of CW columns (16 bytes per lane, whole lines)
+        // instead of the accumulators' 8-byte pieces spread over 32 rows.
+        for (int ch = 0; ch < NH * (MROWS / CW); ++ch) {
+            const int h = ch / (MROWS / CW), c0 = (ch % (MROWS / CW)) * CW;
+            bare_barrier();                               // ring (or previous part) reads done
+            if (nh == h && rg * MB * 32 / CW == c0 / CW) {
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
                     const int cb = (rg * MB + mb) * 32;   // an m block lies in one 4096-column scale block
                     const float sc = scales[(long long)w * ga.nblk + min(m0 + cb, ga.ncols - 1) / kScaleBlock];
 #pragma unroll
                     for (int v = 0; v < 16; ++v) {
-                        const int c = cb + 8 * (v >> 2) + 4 * kg + (v & 3);
+                        const int c = cb - c0 + 8 * (v >> 2) + 4 * kg + (v & 3);
                         *reinterpret_cast<float2*>(&lds[r * OS_RS + c * 8]) =
                             make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
                     }
@@ -665,9 +671,9 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
             __syncthreads();
             constexpr int PER = 64 * NW * 2;              // complex values stored per pass
 #pragma unroll 4
-            for (int e = tid * 2; e < 32 * MROWS; e += PER) {
-                const int row = e / MROWS, c = e % MROWS;
-                const int b = b0 + 32 * h + row, j = m0 + c;
+            for (int e = tid * 2; e < 32 * CW; e += PER) {
+                const int row = e / CW, c = e % CW;
+                const int b = b0 + 32 * h + row, j = m0 + c0 + c;
                 const float4 v = *reinterpret_cast<const float4*>(&lds[row * OS_RS + c * 8]);
                 if (b < ga.nrhs && j < ga.ncols) {
                     float2* o = out_base + ((long long)w * ga.nrhs + b) * ga.pitch + j;
