@@ -815,8 +815,8 @@ int gemm_tile_shape(int tile, int* rg, int* ku, int* mb, int* rhs) {
 
 // Built-in choice without autotuning: the variants measured fastest on the
 // 600 x 16384 x 420 workload (random operands) for each width (the LDS
-// rings 7 / 9 above 32 right-hand sides, ring 8 and tile 4 at most 32).
-int gemm_default_tile(int nrhs, bool fwd) { return nrhs > 32 ? (fwd ? 7 : 9) : (fwd ? 8 : 4); }
+// rings: 7 / 9 above 32 right-hand sides, 8 / 10 for at most 32).
+int gemm_default_tile(int nrhs, bool fwd) { return nrhs > 32 ? (fwd ? 7 : 9) : (fwd ? 8 : 10); }
 
 hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Xq,
                            void* Yp, hipStream_t st) {
