@@ -267,44 +267,44 @@ _GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "4e49592b915a185825d87538e60
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile): (fetch bytes, write bytes); GEMM rows from the autotuner's launches of every tile
 _MEASURED = {
-    ('gemm_adj_32', 0): (16769814153, 1765815862),
-    ('gemm_adj_32', 1): (16786040313, 1765808502),
-    ('gemm_adj_32', 2): (16749780490, 1766827638),
-    ('gemm_adj_32', 3): (16720485314, 1765907670),
-    ('gemm_adj_32', 4): (16761291638, 1782826582),
-    ('gemm_adj_32', 5): (16807640355, 1810711126),
-    ('gemm_adj_32', 6): (16762970273, 1811483862),
-    ('gemm_adj_32', 9): (16743741207, 1765801974),
-    ('gemm_adj_32', 10): (16681967664, 1765801974),
-    ('gemm_adj_64', 0): (16945410235, 3536703981),
-    ('gemm_adj_64', 1): (17078432272, 3535350861),
-    ('gemm_adj_64', 2): (31829087635, 3534388109),
-    ('gemm_adj_64', 3): (17006702953, 3533805837),
-    ('gemm_adj_64', 4): (33583443679, 3566254669),
-    ('gemm_adj_64', 5): (17070054012, 3577847277),
-    ('gemm_adj_64', 6): (16973043673, 3669068140),
-    ('gemm_adj_64', 9): (16928442069, 3531603949),
-    ('gemm_adj_64', 10): (33344115295, 3531603949),
-    ('gemm_fwd_32', 0): (18402676909, 261043135),
-    ('gemm_fwd_32', 1): (18452803625, 261526143),
-    ('gemm_fwd_32', 2): (18775016962, 260816287),
-    ('gemm_fwd_32', 3): (20869712191, 260863935),
-    ('gemm_fwd_32', 4): (19968494253, 262102111),
-    ('gemm_fwd_32', 5): (19924156710, 260415231),
-    ('gemm_fwd_32', 6): (18589376273, 260831103),
-    ('gemm_fwd_32', 7): (18723568150, 260585631),
-    ('gemm_fwd_32', 8): (19055309365, 260898559),
-    ('gemm_fwd_64', 0): (20278889565, 522856701),
-    ('gemm_fwd_64', 1): (20684421961, 522632253),
-    ('gemm_fwd_64', 2): (20642115944, 524626557),
-    ('gemm_fwd_64', 3): (25480482584, 519379069),
-    ('gemm_fwd_64', 4): (24048526626, 522061789),
-    ('gemm_fwd_64', 5): (22856498661, 519864157),
-    ('gemm_fwd_64', 6): (20518285277, 534661021),
-    ('gemm_fwd_64', 7): (20699071117, 531496765),
-    ('gemm_fwd_64', 8): (20646746668, 525122109),
-    ('gemv_adj', None): (16586662434, 55188394),
-    ('gemv_fwd', None): (17107135200, 16166421),
+    ('gemm_adj_32', 0): (16772458607, 1765821787),
+    ('gemm_adj_32', 1): (16804539540, 1765806683),
+    ('gemm_adj_32', 2): (16743988956, 1766859003),
+    ('gemm_adj_32', 3): (16710257421, 1765889723),
+    ('gemm_adj_32', 4): (16760095502, 1782700827),
+    ('gemm_adj_32', 5): (16814357270, 1810695675),
+    ('gemm_adj_32', 6): (16760124557, 1811674075),
+    ('gemm_adj_32', 9): (16742552239, 1765801979),
+    ('gemm_adj_32', 10): (16682149749, 1765801979),
+    ('gemm_adj_64', 0): (16944033047, 3536715574),
+    ('gemm_adj_64', 1): (17094762697, 3535301814),
+    ('gemm_adj_64', 2): (31632449519, 3534996726),
+    ('gemm_adj_64', 3): (17001029308, 3533602742),
+    ('gemm_adj_64', 4): (33573840363, 3566086230),
+    ('gemm_adj_64', 5): (17071117305, 3577718518),
+    ('gemm_adj_64', 6): (16941742324, 3669809622),
+    ('gemm_adj_64', 9): (16936387321, 3531603958),
+    ('gemm_adj_64', 10): (33346708813, 3531603958),
+    ('gemm_fwd_32', 0): (18394497131, 261075295),
+    ('gemm_fwd_32', 1): (18438627253, 261595999),
+    ('gemm_fwd_32', 2): (18769871005, 260691487),
+    ('gemm_fwd_32', 3): (20819688938, 260865791),
+    ('gemm_fwd_32', 4): (19964150983, 262093407),
+    ('gemm_fwd_32', 5): (19913171797, 260377631),
+    ('gemm_fwd_32', 6): (18591976966, 260727487),
+    ('gemm_fwd_32', 7): (18671581257, 260341759),
+    ('gemm_fwd_32', 8): (18988930147, 260779423),
+    ('gemm_fwd_64', 0): (20280652780, 522825407),
+    ('gemm_fwd_64', 1): (20720127079, 522592127),
+    ('gemm_fwd_64', 2): (20642274510, 524529887),
+    ('gemm_fwd_64', 3): (25411040802, 519310655),
+    ('gemm_fwd_64', 4): (24041855483, 522030207),
+    ('gemm_fwd_64', 5): (22751659871, 519716255),
+    ('gemm_fwd_64', 6): (20531625497, 534807039),
+    ('gemm_fwd_64', 7): (20687919684, 531371743),
+    ('gemm_fwd_64', 8): (20645101993, 525195263),
+    ('gemv_adj', None): (16586662142, 55186773),
+    ('gemv_fwd', None): (17107136277, 16166400),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
