@@ -25,9 +25,12 @@
 // Each K step (KU substeps of 8 complex entries) the workgroup stages its
 // spectrum tile and right-hand-side tile in LDS, loaded cooperatively with
 // whole 128-byte lines per 8 lanes: forward rows in runs of 32 (or 16)
-// columns, adjoint sensor rows of 256 to 640 contiguous columns.  Loads
-// run two steps ahead through registers into a double buffer, and one
-// barrier per step separates staging from the matrix-core work.  Fragments
+// columns, adjoint sensor rows of 256 to 640 contiguous columns.  In the
+// register-staged kernel (k_gemm) loads run two steps ahead through
+// registers into a double buffer; the LDS-ring kernels (k_gemm_fwd_ring,
+// k_gemm_adj_ring, the built-in choice) load straight into a 3-step ring in
+// LDS.  One barrier per step separates staging from the matrix-core work.
+// Fragments
 // come from padded LDS rows without bank conflicts: forward lanes read 16
 // bytes of a row, adjoint lanes gather 4 sensors of a column as 4-byte words.
 // Every spectrum byte is read once per launch.  Forward workgroups own
