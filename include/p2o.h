@@ -188,9 +188,12 @@ typedef enum {
 /* How calls with several right-hand sides do the per-frequency products.
  * AUTO: matrix cores (one launch for up to 64 right-hand sides per group,
  * BF16 spectrum x BF16 hi+lo split of the FP32 right-hand sides, FP32
- * accumulation) when the spectrum is BF16 and nrhs >= 2, otherwise one
- * streaming matrix-vector pass per right-hand side.  GEMV forces the latter;
- * MFMA forces the former (BF16 plans only, P2O_ERR_DTYPE otherwise). */
+ * accumulation; an FP16 spectrum enters as the exact sum of two BF16 parts)
+ * when the spectrum is BF16 or FP16 and nrhs >= 2, otherwise one streaming
+ * matrix-vector pass per right-hand side.  GEMV forces the latter; MFMA
+ * forces the former (BF16 plans, and FP16 plans whose one-frequency spectrum
+ * is under 4 GiB; P2O_ERR_DTYPE otherwise).  FP16 plans use the LDS-ring
+ * tile variants only (a forced other variant takes the built-in choice). */
 typedef enum {
     P2O_BATCHED_AUTO = 0,
     P2O_BATCHED_GEMV = 1,

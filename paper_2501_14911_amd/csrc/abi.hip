@@ -170,7 +170,7 @@ void layout(p2o_plan* p) {
     const size_t xparts = (size_t)(p->adj_nslab > 1 ? p->adj_nslab : 1);
     size_t yparts = (size_t)(p->fwd_chunks > 1 ? p->fwd_chunks : 1);
     size_t ylen = yparts * nfreq * R * (size_t)p->Nd;
-    if (p->prec == kBF16) {
+    if (p->prec == kBF16 || p->prec == kFP16) {
         // matrix-core path: forward partials per 4096-column chunk, and data
         // spectra in quad storage with rows padded to a multiple of 16
         ylen = std::max(ylen, (size_t)gemm_fwd_kchunks((int)live_cols(p)) * nfreq * R * (size_t)p->Nd);
@@ -243,11 +243,16 @@ GemvArgs gemv_args(const p2o_plan* p, int64_t nrhs, bool fwd) {
 }
 
 // enqueue sequences ----------------------------------------------------------
-// Several right-hand sides with a BF16 spectrum go to the matrix cores.  Their
+// Several right-hand sides with a BF16 (or FP16, on the LDS-ring kernels,
+// for shapes they can address) spectrum go to the matrix cores.  Their
 // operands are written by the FFTs in quad storage, in place by the F F*
 // projection, whose tiles must then span whole groups of 4 series.
+bool mfma_capable(const p2o_plan* p) {
+    return p->prec == kBF16 || (p->prec == kFP16 && gemm_f16_fits((int)p->Nd, (int)p->pitch));
+}
+
 bool mfma_on(const p2o_plan* p, int64_t nrhs) {
-    if (p->prec != kBF16) return false;
+    if (!mfma_capable(p)) return false;
     if (fft_tile_shift(p->fft.M, false) < 2) return false;
     if (p->batched_mode == P2O_BATCHED_MFMA) return true;
     if (p->batched_mode == P2O_BATCHED_GEMV) return false;
@@ -269,6 +274,7 @@ GemmArgs gemm_args(const p2o_plan* p, int64_t nrhs) {
     ga.nrhs = (int)nrhs;
     ga.nblk = (int)p->nblk;
     ga.part_stride = p->nfreq * nrhs * p->Nd;
+    ga.a_f16 = p->prec == kFP16;
     return ga;
 }
 
@@ -439,8 +445,8 @@ p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
     if (option == P2O_OPT_BATCHED) {
         if (value < P2O_BATCHED_AUTO || value > P2O_BATCHED_MFMA)
             return fail(P2O_ERR_ARG, "batched mode %lld unknown", (long long)value);
-        if (value == P2O_BATCHED_MFMA && p->prec != kBF16)
-            return fail(P2O_ERR_DTYPE, "the matrix-core path needs a BF16 spectrum");
+        if (value == P2O_BATCHED_MFMA && !mfma_capable(p))
+            return fail(P2O_ERR_DTYPE, "the matrix-core path needs a BF16 or FP16 spectrum");
         p->batched_mode = (int)value;
         return P2O_OK;
     }
@@ -498,7 +504,7 @@ p2o_status p2o_autotune(p2o_plan* p, int64_t nrhs, int32_t reps, int32_t* fwd_ti
         for (int dir = 0; dir < 2 && !s; ++dir) {
             if (dir == 1) s = check_hip(launch_fill_bf16(Y, p->off_D - p->off_Y, 0xADu, p->stream), "autotune operand fill");
             for (int t = 0; t < gemm_tile_count() && !s; ++t) {
-                if (!gemm_tile_has(t, dir == 0)) continue;
+                if (!gemm_tile_has(t, dir == 0) || (ga.a_f16 && !gemm_tile_is_ring(t))) continue;
                 auto run = [&]() {
                     return dir == 0 ? launch_gemm_fwd(ga, t, p->fhat, scales_of(p), X, Y, p->stream)
                                     : launch_gemm_adj(ga, t, p->fhat, scales_of(p), Y, X, p->stream);

@@ -68,6 +68,22 @@ __device__ __forceinline__ uint4 f_nswap(uint4 a) {                      // (im,
                       w_swap(a.w) ^ 0x80000000u);
 }
 
+// An FP16 spectrum fragment (words of (re, im) FP16) as the exact sum of two
+// BF16 fragments: FP16 carries 11 significant bits, the BF16 rounding of an
+// entry keeps 8 and the remainder (at most 3 more) is exact in BF16.
+__device__ __forceinline__ uint32_t w_f16_hi(uint32_t w, uint32_t& lo) {
+    const float re = f16lo(w), im = f16hi(w);
+    const uint32_t hi = pack_bf16_rne(re, im);
+    lo = pack_bf16_rne(re - __uint_as_float(hi << 16), im - __uint_as_float(hi & 0xffff0000u));
+    return hi;
+}
+__device__ __forceinline__ void f_split_f16(uint4 a, uint4& hi, uint4& lo) {
+    hi.x = w_f16_hi(a.x, lo.x);
+    hi.y = w_f16_hi(a.y, lo.y);
+    hi.z = w_f16_hi(a.z, lo.z);
+    hi.w = w_f16_hi(a.w, lo.w);
+}
+
 __device__ __forceinline__ int xcd_item(int id, int Q) { return (id & 7) * Q + (id >> 3); }
 
 // Workgroup barrier that waits for this wavefront's LDS operations but not
@@ -369,7 +385,10 @@ __device__ __forceinline__ void dma16(const uint8_t* base, uint32_t off, uint32_
     asm volatile("global_load_lds_dwordx4 %0, %1" : : "v"(off), "s"(base), "{m0}"(lds) : "memory");
 }
 
-template <int NH>
+// F16A: the spectrum is stored in FP16; each fragment is split into BF16
+// hi + lo and takes three products per right-hand-side form (the lo x lo
+// term is below the FP32 accumulation's rounding).
+template <int NH, bool F16A>
 __global__ __launch_bounds__(256 * NH) __attribute__((amdgpu_waves_per_eu(NH)))
 void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
                      float2* __restrict__ out_base, GemmArgs ga) {
@@ -460,10 +479,16 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         const uint4 bh_r = f_conj(f.bh), bh_i = f_swap(f.bh), bl_r = f_conj(f.bl), bl_i = f_swap(f.bl);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-            accr[mb] = mfma32(f.a[mb], bh_r, accr[mb]);
-            acci[mb] = mfma32(f.a[mb], bh_i, acci[mb]);
-            accr[mb] = mfma32(f.a[mb], bl_r, accr[mb]);
-            acci[mb] = mfma32(f.a[mb], bl_i, acci[mb]);
+            uint4 a = f.a[mb], al;
+            if constexpr (F16A) f_split_f16(f.a[mb], a, al);
+            accr[mb] = mfma32(a, bh_r, accr[mb]);
+            acci[mb] = mfma32(a, bh_i, acci[mb]);
+            accr[mb] = mfma32(a, bl_r, accr[mb]);
+            acci[mb] = mfma32(a, bl_i, acci[mb]);
+            if constexpr (F16A) {
+                accr[mb] = mfma32(al, bh_r, accr[mb]);
+                acci[mb] = mfma32(al, bh_i, acci[mb]);
+            }
         }
     };
 
@@ -522,7 +547,7 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
 // every step is whole; sensor rows past Nd read row Nd - 1 and columns past
 // the pitch read its last entries (valid addresses), and a substep that
 // starts at or past Nd is skipped (its data rows are zero).
-template <int RG, int MB, int NH>
+template <int RG, int MB, int NH, bool F16A>
 __global__ __launch_bounds__(64 * RG * NH) __attribute__((amdgpu_waves_per_eu(2)))
 void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
                      float2* __restrict__ out_base, GemmArgs ga) {
@@ -624,10 +649,16 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         const uint4 bh_i = f_nswap(f.bh), bl_i = f_nswap(f.bl);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-            accr[mb] = mfma32(f.a[mb], f.bh, accr[mb]);
-            acci[mb] = mfma32(f.a[mb], bh_i, acci[mb]);
-            accr[mb] = mfma32(f.a[mb], f.bl, accr[mb]);
-            acci[mb] = mfma32(f.a[mb], bl_i, acci[mb]);
+            uint4 a = f.a[mb], al;
+            if constexpr (F16A) f_split_f16(f.a[mb], a, al);
+            accr[mb] = mfma32(a, f.bh, accr[mb]);
+            acci[mb] = mfma32(a, bh_i, acci[mb]);
+            accr[mb] = mfma32(a, f.bl, accr[mb]);
+            acci[mb] = mfma32(a, bl_i, acci[mb]);
+            if constexpr (F16A) {
+                accr[mb] = mfma32(al, f.bh, accr[mb]);
+                acci[mb] = mfma32(al, bh_i, acci[mb]);
+            }
         }
     };
 
@@ -780,14 +811,20 @@ static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales
     // the ring kernel addresses a frequency's spectrum and a group's
     // right-hand-side rows with 32-bit byte offsets; larger shapes take the
     // register-staged 640-row tile
-    if ((long long)ga.Nd * ga.pitch * 4 >= (1LL << 32) || 32LL * NH * ga.ldb * 8 >= (1LL << 32))
+    if ((long long)ga.Nd * ga.pitch * 4 >= (1LL << 32) || 32LL * NH * ga.ldb * 8 >= (1LL << 32)) {
+        if (ga.a_f16) return hipErrorInvalidValue;        // callers check gemm_f16_fits first
         return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Bq, out, st);
+    }
     ga.n_mt = (ga.Nd + 639) / 640;
     ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
-    hipLaunchKernelGGL(k_gemm_fwd_ring<NH>, dim3(8 * ga.Q), dim3(256 * NH), 0, st, (const uint8_t*)fhat, scales,
-                       (const uint8_t*)Bq, (float2*)out, ga);
+    if (ga.a_f16)
+        hipLaunchKernelGGL((k_gemm_fwd_ring<NH, true>), dim3(8 * ga.Q), dim3(256 * NH), 0, st, (const uint8_t*)fhat,
+                           scales, (const uint8_t*)Bq, (float2*)out, ga);
+    else
+        hipLaunchKernelGGL((k_gemm_fwd_ring<NH, false>), dim3(8 * ga.Q), dim3(256 * NH), 0, st, (const uint8_t*)fhat,
+                           scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
 }
 
@@ -795,16 +832,31 @@ template <int RG, int MB, int NH>
 static hipError_t launch_adj_ring(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
                                   hipStream_t st) {
     // 32-bit lane offsets within a spectrum row and a group's right-hand-side rows
-    if ((long long)ga.pitch * 4 >= (1LL << 32) || 32LL * NH * ga.ldb * 8 >= (1LL << 32))
+    if ((long long)ga.pitch * 4 >= (1LL << 32) || 32LL * NH * ga.ldb * 8 >= (1LL << 32)) {
+        if (ga.a_f16) return hipErrorInvalidValue;        // callers check gemm_f16_fits first
         return launch_tile<false, 2, 2, 4, 2, 2>(ga, fhat, scales, Bq, out, st);
+    }
     constexpr int MROWS = 32 * RG * MB;
     ga.n_mt = (ga.ncols + MROWS - 1) / MROWS;
     ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
     ga.items = ga.nfreq * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
-    hipLaunchKernelGGL((k_gemm_adj_ring<RG, MB, NH>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
-                       (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
+    if (ga.a_f16)
+        hipLaunchKernelGGL((k_gemm_adj_ring<RG, MB, NH, true>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                           (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
+    else
+        hipLaunchKernelGGL((k_gemm_adj_ring<RG, MB, NH, false>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                           (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
+}
+
+bool gemm_tile_is_ring(int tile) { return tile >= 0 && tile < kTileCount && kTiles[tile].pf == 0; }
+
+// FP16 spectra run on the LDS-ring kernels only, whose 32-bit lane offsets
+// must cover a frequency's spectrum and a group's right-hand-side rows.
+bool gemm_f16_fits(int Nd, int pitch) {
+    const long long ldb = gemm_data_pitch(Nd);
+    return (long long)Nd * pitch * 4 < (1LL << 32) && 64LL * pitch * 8 < (1LL << 32) && 64LL * ldb * 8 < (1LL << 32);
 }
 
 int gemm_tile_shape(int tile, int* rg, int* ku, int* mb, int* rhs) {
@@ -827,7 +879,7 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.ncols);
-    if (!gemm_tile_has(tile, true)) tile = gemm_default_tile(ga.nrhs, true);
+    if (!gemm_tile_has(tile, true) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, true);
     switch (tile) {
         case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 1: return launch_tile<true, 2, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
@@ -848,7 +900,7 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = gemm_data_pitch(ga.Nd);
     ga.kchunk = 0;
     ga.n_kc = 1;
-    if (!gemm_tile_has(tile, false)) tile = gemm_default_tile(ga.nrhs, false);
+    if (!gemm_tile_has(tile, false) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, false);
     switch (tile) {
         case 0: return launch_tile<false, 2, 4, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
         case 1: return launch_tile<false, 2, 2, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);

@@ -26,6 +26,7 @@ struct GemmArgs {
     int nrhs;
     int nblk;
     long long part_stride;  // complex elements between forward partial outputs
+    int a_f16;              // spectrum words are FP16 (re, im) pairs (BF16 otherwise); LDS-ring tiles only
     // filled in by the launcher
     int ldb;                // complex values per right-hand-side row of the quad B operand
     int kchunk;             // complex columns per forward K chunk
@@ -92,6 +93,8 @@ int gemm_tile_count();
 bool gemm_tile_has(int tile, bool fwd);   // variant exists for that direction (others take the built-in choice)
 int gemm_tile_shape(int tile, int* row_groups, int* substeps, int* blocks, int* rhs_per_group);
 int gemm_default_tile(int nrhs, bool fwd);
+bool gemm_tile_is_ring(int tile);           // an LDS-ring variant (the only ones for FP16 spectra)
+bool gemm_f16_fits(int Nd, int pitch);      // shapes the FP16-spectrum ring kernels can address
 hipError_t launch_fill_bf16(void* p, size_t bytes, uint32_t seed, hipStream_t st);   // timing operands
 // tile: a variant index, or -1 for the built-in choice
 hipError_t launch_gemm_fwd(const GemmArgs& ga, int tile, const void* fhat, const float* scales, const void* Xq,

@@ -91,7 +91,7 @@ class P2OOperator:
     def set_batched(self, mode: str = "auto"):
         """Per-frequency products for several right-hand sides: "auto",
         "gemv" (one streaming pass per right-hand side) or "mfma" (matrix
-        cores, BF16 spectra only)."""
+        cores, BF16 and FP16 spectra only)."""
         check(lib.p2o_set_option(self._plan, 0, BATCHED[mode]))
 
     def set_gemm_tile(self, tile: int = -1):

@@ -135,6 +135,38 @@ def test_every_tile_variant(w):
         assert worst <= TOL_BF16
 
 
+@pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
+def test_fp16_spectrum_on_matrix_cores(w):
+    """FP16-stored spectrum on the matrix cores (each entry split exactly into
+    BF16 hi + lo, LDS-ring tiles): every ring variant and the built-in choice
+    against the oracle, at a full and a ragged right-hand-side group, within
+    the FP16 bound; and against the same plan's streaming FP16 path."""
+    nrhs = 70
+    F = synth.operator_blocks(w)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp16", max_rhs=nrhs, device=DEV)
+    Ft = torch.from_numpy(F).to(DEV)
+    op.load(lambda c0, n: Ft[:, :, c0:c0 + n])
+    m = synth.param_series(w, nrhs)
+    d = synth.data_series(w, nrhs)
+    yo, so = oracle.apply_F(F, m), oracle.apply_Ft(F, d)
+    from paper_2501_14911_amd import gemm_tiles
+    rings = [t for t, shape in enumerate(gemm_tiles()) if t >= 7]
+    for t in [-1] + rings:
+        op.set_gemm_tile(t)
+        y = host(op.apply_F(dev(m)))
+        s = host(op.apply_Ft(dev(d)))
+        worst = max(max(oracle.rel_l2(y[b], yo[b]), oracle.rel_l2(s[b], so[b])) for b in range(nrhs))
+        note(f"[batched] fp16 {w.name} tile {t}: worst rel-L2 {worst:.3e}")
+        assert worst <= TOL_BF16
+    op.set_gemm_tile(-1)
+    op.set_batched("gemv")
+    y1, s1 = host(op.apply_F(dev(m[:3]))), host(op.apply_Ft(dev(d[:3])))
+    op.set_batched("auto")
+    y2, s2 = host(op.apply_F(dev(m[:3]))), host(op.apply_Ft(dev(d[:3])))
+    for b in range(3):
+        assert oracle.rel_l2(y2[b], y1[b]) <= 1e-4 and oracle.rel_l2(s2[b], s1[b]) <= 1e-4
+
+
 def test_autotune_then_apply():
     w = SHAPES[0]
     nrhs = 40
@@ -155,7 +187,7 @@ def test_autotune_then_apply():
         op.autotune(nrhs + 1)                    # beyond max_rhs
 
 
-def test_mfma_option_needs_bf16():
+def test_mfma_option_needs_a_16_bit_spectrum():
     w = synth.CONFIGS["tiny"]
     op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp32", max_rhs=2, device=DEV)
     from paper_2501_14911_amd import P2OError
