@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-call-stats", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
     return ap.parse_args()
 
 
@@ -249,6 +250,8 @@ def main():
 
     if not args.no_accuracy:
         result["accuracy"] = accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np)
+    if not args.no_fp16:
+        result["fp16"] = fp16_leg(w, dev, torch, np, synth, P2OOperator, m, d_obs, E, args.no_accuracy)
     if not args.no_fp64:
         result["fp64_plain"] = fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var,
                                           args.no_accuracy, result)
@@ -267,44 +270,44 @@ _GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "7199a5286c99f5aefcbeb78c705
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile): (fetch bytes, write bytes); GEMM rows from the autotuner's launches of every tile
 _MEASURED = {
-    ('gemm_adj_32', 0): (16767016140, 1765822454),
-    ('gemm_adj_32', 1): (16792839743, 1765809302),
-    ('gemm_adj_32', 2): (16748095871, 1766809078),
-    ('gemm_adj_32', 3): (16710726688, 1765926006),
-    ('gemm_adj_32', 4): (16759219248, 1783275222),
-    ('gemm_adj_32', 5): (16812069064, 1810704438),
-    ('gemm_adj_32', 6): (16759237104, 1811677462),
-    ('gemm_adj_32', 9): (16738823094, 1765801974),
-    ('gemm_adj_32', 10): (16679029112, 1765801974),
-    ('gemm_adj_64', 0): (16942790390, 3536594445),
-    ('gemm_adj_64', 1): (17112191666, 3535598445),
-    ('gemm_adj_64', 2): (32051534362, 3534609421),
-    ('gemm_adj_64', 3): (16987236282, 3534089165),
-    ('gemm_adj_64', 4): (33569778251, 3566763981),
-    ('gemm_adj_64', 5): (17062491698, 3577859277),
-    ('gemm_adj_64', 6): (16950006489, 3669420844),
-    ('gemm_adj_64', 9): (16935419925, 3531603949),
-    ('gemm_adj_64', 10): (33391777662, 3531603949),
-    ('gemm_fwd_32', 0): (18398426957, 261028511),
-    ('gemm_fwd_32', 1): (18485047283, 261504671),
-    ('gemm_fwd_32', 2): (18766394447, 260746527),
-    ('gemm_fwd_32', 3): (20875416015, 260869983),
-    ('gemm_fwd_32', 4): (19966593404, 262087199),
-    ('gemm_fwd_32', 5): (19943848801, 260452927),
-    ('gemm_fwd_32', 6): (18579691249, 260852031),
-    ('gemm_fwd_32', 7): (18742985596, 260530783),
-    ('gemm_fwd_32', 8): (19075781826, 260871423),
-    ('gemm_fwd_64', 0): (20278766924, 522891677),
-    ('gemm_fwd_64', 1): (20661735436, 522533341),
-    ('gemm_fwd_64', 2): (20641927499, 524621245),
-    ('gemm_fwd_64', 3): (25547484414, 519578941),
-    ('gemm_fwd_64', 4): (24021456241, 522100157),
-    ('gemm_fwd_64', 5): (22907790953, 519880413),
-    ('gemm_fwd_64', 6): (20507422606, 534519133),
-    ('gemm_fwd_64', 7): (20791128459, 531402621),
-    ('gemm_fwd_64', 8): (20647021002, 525227293),
-    ('gemv_adj', None): (16586661724, 55188565),
-    ('gemv_fwd', None): (17107132212, 16166400),
+    ('gemm_adj_32', 0): (16768916678, 1765821595),
+    ('gemm_adj_32', 1): (16800078712, 1765811099),
+    ('gemm_adj_32', 2): (16747575447, 1766837819),
+    ('gemm_adj_32', 3): (16721608483, 1765895067),
+    ('gemm_adj_32', 4): (16763789192, 1782897371),
+    ('gemm_adj_32', 5): (16814063237, 1810694459),
+    ('gemm_adj_32', 6): (16761001579, 1811694779),
+    ('gemm_adj_32', 9): (16737854099, 1765801979),
+    ('gemm_adj_32', 10): (16684835769, 1765801979),
+    ('gemm_adj_64', 0): (16952011041, 3537111734),
+    ('gemm_adj_64', 1): (17071207469, 3535810102),
+    ('gemm_adj_64', 2): (32457111877, 3534912246),
+    ('gemm_adj_64', 3): (16982867927, 3533839190),
+    ('gemm_adj_64', 4): (33574256827, 3566616630),
+    ('gemm_adj_64', 5): (17050211450, 3577760502),
+    ('gemm_adj_64', 6): (16932340573, 3670009462),
+    ('gemm_adj_64', 9): (16919524673, 3531603958),
+    ('gemm_adj_64', 10): (33353343939, 3531603958),
+    ('gemm_fwd_32', 0): (18397930027, 261020991),
+    ('gemm_fwd_32', 1): (18449910610, 261535935),
+    ('gemm_fwd_32', 2): (18759615643, 260724127),
+    ('gemm_fwd_32', 3): (20813418312, 260850847),
+    ('gemm_fwd_32', 4): (19964104051, 262083615),
+    ('gemm_fwd_32', 5): (19929158834, 260336255),
+    ('gemm_fwd_32', 6): (18581436609, 260754367),
+    ('gemm_fwd_32', 7): (18728610983, 260552511),
+    ('gemm_fwd_32', 8): (19034864092, 260919615),
+    ('gemm_fwd_64', 0): (20272753353, 522875903),
+    ('gemm_fwd_64', 1): (20711815515, 522553439),
+    ('gemm_fwd_64', 2): (20641582685, 524484831),
+    ('gemm_fwd_64', 3): (25466162858, 519329535),
+    ('gemm_fwd_64', 4): (24029962852, 522096895),
+    ('gemm_fwd_64', 5): (22905637899, 519834719),
+    ('gemm_fwd_64', 6): (20512511248, 534636383),
+    ('gemm_fwd_64', 7): (20722395220, 531308415),
+    ('gemm_fwd_64', 8): (20646713884, 524907615),
+    ('gemv_adj', None): (16586663286, 55188267),
+    ('gemv_fwd', None): (17107136589, 16166400),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
@@ -402,6 +405,56 @@ def accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np):
     out["ragged_F_4x_8rows"] = max(errs)
     log("[bench] sampled rel-L2 vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
     out["tolerance"] = 2e-3
+    return out
+
+
+def fp16_leg(w, dev, torch, np, synth, P2OOperator, m, d_obs, E, no_acc, calls=10):
+    """The same operator with an FP16 spectrum: F and F* at one right-hand
+    side (streaming path) and at 64 (matrix cores, FP16 entries split into
+    BF16 hi + lo), medians of `calls` whole calls, and rel-L2 against the FP64
+    oracle on sampled rows / columns."""
+    import oracle
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp16", max_rhs=N_HESS, device=dev)
+    op.load(lambda c0, n: gpu_blocks(w, c0, n, dev, torch, synth))
+    tuned = op.autotune(N_HESS, reps=2)
+    m64 = synth.param_series(w, N_HESS, seed_offset=41, backend="torch", device=dev).float()
+    runs = {"F_1": lambda: op.apply_F(m.unsqueeze(0)), "Ft_1": lambda: op.apply_Ft(d_obs.unsqueeze(0)),
+            "F_64": lambda: op.apply_F(m64), "Ft_64": lambda: op.apply_Ft(E)}
+    out = {"autotune_64": {"fwd_tile": tuned["fwd"][0], "adj_tile": tuned["adj"][0]}}
+    for name, fn in runs.items():
+        for _ in range(2):
+            fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        med = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        nr = N_HESS if name.endswith("64") else 1
+        out[name] = {"median_ms": med, "matvecs_per_s": nr / (med * 1e-3), "calls": calls}
+    if not no_acc:
+        rng = np.random.default_rng(1)
+        rows = np.sort(rng.choice(w.Nd, 8, replace=False))
+        cols = np.sort(rng.choice(w.Nm, 64, replace=False))
+        Fr = synth.operator_rows_cols(w, range(w.Nt), rows=rows, backend="torch").numpy()
+        Fc = synth.operator_rows_cols(w, range(w.Nt), cols=cols, backend="torch").numpy()
+        d1 = op.apply_F(m.unsqueeze(0))[0].double().cpu().numpy()
+        out["rel_l2_single_F_8rows"] = oracle.rel_l2(d1[:, rows], oracle.apply_F(Fr, m.double().cpu().numpy()))
+        s1 = op.apply_Ft(d_obs.unsqueeze(0))[0].double().cpu().numpy()
+        out["rel_l2_single_Ft_64cols"] = oracle.rel_l2(s1[:, cols], oracle.apply_Ft(Fc, d_obs.double().cpu().numpy()))
+        y = op.apply_F(m64).double().cpu().numpy()
+        mh = m64[:4].double().cpu().numpy()
+        out["rel_l2_batched_F_4x_8rows"] = max(oracle.rel_l2(y[b][:, rows], oracle.apply_F(Fr, mh[b]))
+                                               for b in range(4))
+        out["tolerance"] = 2e-3
+    log("[bench] FP16 spectrum: " + ", ".join(f"{k} {v['median_ms']:.3f} ms" for k, v in out.items()
+                                              if isinstance(v, dict) and "median_ms" in v)
+        + ("" if no_acc else ", rel-L2 " + ", ".join(f"{k[7:]} {v:.2e}" for k, v in out.items()
+                                                      if k.startswith("rel_l2"))))
+    op.close()
+    del op, m64
+    torch.cuda.empty_cache()
     return out
 
 
