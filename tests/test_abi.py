@@ -169,6 +169,18 @@ def test_gemm_tile_table_and_autotune_checks():
     lib.p2o_destroy(plan)
 
 
+def test_matrix_core_option_needs_a_16_bit_spectrum():
+    """P2O_BATCHED_MFMA is accepted for BF16 and FP16 spectra (FP16 entries are
+    split into BF16 hi + lo on the matrix cores) and refused for FP32 / FP64."""
+    for prec, want in ((0, DTYPE), (1, DTYPE), (2, OK), (3, OK)):
+        st, plan = create(Nd=4, Nm=64, Nt=16, prec=prec, max_rhs=4)
+        assert st == OK
+        assert lib.p2o_set_option(plan, 0, 2) == want, prec
+        assert lib.p2o_set_option(plan, 0, 1) == OK
+        assert lib.p2o_set_option(plan, 0, 3) == ARG
+        lib.p2o_destroy(plan)
+
+
 def test_fixed_length_fft_switch():
     st, plan = create(Nd=4, Nm=64, Nt=420, prec=1, max_rhs=2)
     assert st == OK
