@@ -157,7 +157,9 @@ def spectrum(F: np.ndarray, L: int) -> np.ndarray:
 
 
 def rel_l2(y, y_ref) -> float:
-    """||y - y_ref||_2 / ||y_ref||_2 in float64 over the whole array."""
+    """||y - y_ref||_2 / ||y_ref||_2 in float64 over the whole array (all
+    right-hand sides together; pass one right-hand side for a per-RHS error).
+    With an all-zero reference it returns the absolute norm ||y||_2."""
     y = np.asarray(y, dtype=np.float64)
     y_ref = np.asarray(y_ref, dtype=np.float64)
     den = np.linalg.norm(y_ref.ravel())

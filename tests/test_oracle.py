@@ -315,6 +315,45 @@ def test_hand_worked_examples():
     np.testing.assert_array_equal(oracle.apply_Ft(F, np.array(blk["adj_in"])), np.array(blk["adj_out"]))
 
 
+def test_rel_l2_hand_worked():
+    """The error metric every parity verdict goes through, on hand-computed
+    cases whose value differs from its square, the max-norm ratio, the ratio
+    over the result's norm and per-right-hand-side maxima or means."""
+    g = json.load(open(GOLDEN))
+    for key in ("rel_l2", "rel_l2_batched", "rel_l2_zero_reference"):
+        c = g[key]
+        assert abs(oracle.rel_l2(np.array(c["y"]), np.array(c["y_ref"])) - c["value"]) <= 1e-15, key
+
+
+def _broken_rel_l2_variants():
+    def squared(y, y_ref):
+        return float(np.sum((y - y_ref) ** 2) / np.sum(y_ref ** 2))
+
+    def max_norm(y, y_ref):
+        return float(np.max(abs(y - y_ref)) / np.max(abs(y_ref)))
+
+    def over_result(y, y_ref):
+        return float(np.linalg.norm((y - y_ref).ravel()) / np.linalg.norm(y.ravel()))
+
+    def worst_rhs(y, y_ref):
+        return max(float(np.linalg.norm(y[b] - y_ref[b]) / np.linalg.norm(y_ref[b])) for b in range(len(y)))
+
+    return [squared, max_norm, over_result, worst_rhs]
+
+
+@pytest.mark.parametrize("broken", _broken_rel_l2_variants(), ids=lambda f: f.__name__)
+def test_rel_l2_pins_catch_planted_mistakes(broken):
+    g = json.load(open(GOLDEN))
+    caught = False
+    for key in ("rel_l2", "rel_l2_batched"):
+        c = g[key]
+        y, y_ref = np.array(c["y"]), np.array(c["y_ref"])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            got = broken(y, y_ref)
+        caught |= not abs(got - c["value"]) <= 1e-15
+    assert caught
+
+
 # ---------------------------------------------------------------- planted mistakes
 def _broken_forward_variants():
     def dropped_last_lag(F, m, nt_active=None):
