@@ -1,22 +1,25 @@
 """Benchmark of the FFT-based block-Toeplitz p2o path on one MI355X.
 
 Workload: Nd = 600 sensors, Nm = 16384 parameters per step, Nt = 420 steps
-(circulant length 840), BF16 spectrum with FP32 accumulation, synthetic
-blocks F_k = exp(-k/100) N(0,1)/sqrt(Nm).
+(circulant length 840), synthetic blocks F_k = exp(-k/100) N(0,1)/sqrt(Nm),
+half spectrum stored in 16 bits with FP32 accumulation.
 
 One step is one pass over every use of the hot path:
   1. a data-misfit gradient on one right-hand side (r2c FFT of m, streaming
      forward products, inverse FFT fused with the residual and the FP64
      misfit reduction, r2c, streaming adjoint products, inverse FFT):
-     one F and one F^* matvec;
+     one F and one F^* matvec, BF16 spectrum;
   2. 64 data-space operator columns h_j = F F^* e_j in one call (batched
      adjoint and forward products on the matrix cores, truncate-and-repad
-     between them): 128 matvecs;
+     between them): 128 matvecs, FP16 spectrum -- the storage precision
+     whose columns meet 2e-3 on the whole output (with a BF16 spectrum the
+     columns of early spikes do not);
   3. F and F^* on 32 right-hand sides whose active lengths are drawn from
-     U{64..420} (batched, ragged): 64 matvecs.
+     U{64..420} (batched, ragged): 64 matvecs, BF16 spectrum.
 ``value`` = matvecs per second over the step (194 per step).  The plain FP64
 single-right-hand-side path on an FP64 spectrum of the same operator is timed
-beside it for the batched-mixed-precision speedup.
+beside it for the batched-mixed-precision speedup, and so are the FP32
+spectrum and the 600 x 65536 x 420 one-GPU share (BF16, 66 GB).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build targets one
 GPU (the operator's column share on that GPU).
@@ -49,7 +52,8 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-call-stats", action="store_true")
-    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-largest", action="store_true")
     return ap.parse_args()
 
 
@@ -85,23 +89,28 @@ def main():
     torch.cuda.set_device(dev)
     log(f"[bench] workload {w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt}")
 
-    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=N_HESS, device=dev)
-    t0 = time.perf_counter()
-    op.profile(True)
-    op.load(lambda c0, n: gpu_blocks(w, c0, n, dev, torch, synth))
-    load_ms = op.stage_times()["load"][0]
-    op.profile(False)
-    log(f"[bench] BF16 spectrum loaded ({op.fhat_bytes / 1e9:.2f} GB) in {time.perf_counter() - t0:.1f} s "
-        f"(load kernels {load_ms:.1f} ms)")
+    def loaded(precision, max_rhs, wl=w):
+        o = P2OOperator(wl.Nd, wl.Nm, wl.Nt, precision, max_rhs=max_rhs, device=dev)
+        t0 = time.perf_counter()
+        o.profile(True)
+        o.load(lambda c0, n: gpu_blocks(wl, c0, n, dev, torch, synth))
+        ms = o.stage_times()["load"][0]
+        o.profile(False)
+        log(f"[bench] {precision.upper()} spectrum of {wl.name} loaded ({o.fhat_bytes / 1e9:.2f} GB) in "
+            f"{time.perf_counter() - t0:.1f} s (load kernels {ms:.1f} ms)")
+        return o, ms
 
-    # matrix-core tile variants for the two batched widths (autotuner, before timing)
+    op, load_ms = loaded("bf16", N_HESS)        # gradient, ragged right-hand sides
+    op16, load16_ms = loaded("fp16", N_HESS)    # data-space columns
+
+    # matrix-core tile variants for the batched widths (autotuner, before timing)
     from paper_2501_14911_amd import gemm_tiles
     tiles = gemm_tiles()
     tuned = {}
-    for nr in (N_HESS, N_RAGGED):
-        r = op.autotune(nr, reps=2)
-        tuned[nr] = {d: {"tile": r[d][0], "shape": tiles[r[d][0]], "ms": r[d][1]} for d in ("fwd", "adj")}
-        log(f"[bench] autotune nrhs={nr}: fwd tile {r['fwd'][0]} {tiles[r['fwd'][0]]} {r['fwd'][1]:.3f} ms, "
+    for name, o, nr in (("bf16", op, N_RAGGED), ("bf16", op, N_HESS), ("fp16", op16, N_HESS)):
+        r = o.autotune(nr, reps=2)
+        tuned[f"{name}_{nr}"] = {d: {"tile": r[d][0], "shape": tiles[r[d][0]], "ms": r[d][1]} for d in ("fwd", "adj")}
+        log(f"[bench] autotune {name} nrhs={nr}: fwd tile {r['fwd'][0]} {tiles[r['fwd'][0]]} {r['fwd'][1]:.3f} ms, "
             f"adj tile {r['adj'][0]} {tiles[r['adj'][0]]} {r['adj'][1]:.3f} ms")
 
     # inputs
@@ -124,7 +133,7 @@ def main():
         op.misfit_grad(m, d_obs, var)
         if evs:
             evs[1].record()
-        op.apply_FFt(E, out=H)
+        op16.apply_FFt(E, out=H)
         if evs:
             evs[2].record()
         op.apply_F(m_r, nt_active=nt_r_dev, out=Y_r)
@@ -136,6 +145,7 @@ def main():
         step()
     torch.cuda.synchronize()
     op.profile(True)
+    op16.profile(True)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -148,61 +158,76 @@ def main():
     wall = time.perf_counter() - wall0
     ms_step = ev0.elapsed_time(ev1) / args.steps
     part_ms = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps for i in range(3)]
-    stages = op.stage_times()
-    st1, st64, st32 = op.stage_times(1), op.stage_times(N_HESS), op.stage_times(N_RAGGED)
+    st1, st32, st64 = op.stage_times(1), op.stage_times(N_RAGGED), op16.stage_times(N_HESS)
     op.profile(False)
+    op16.profile(False)
     matvecs = 2 + 2 * N_HESS + 2 * N_RAGGED
     log(f"[bench] {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}): single-RHS gradient "
         f"{part_ms[0]:.3f} ms, 64 F F* columns {part_ms[1]:.3f} ms, 32 ragged F + F* {part_ms[2]:.3f} ms")
-    for nr, st in ((1, st1), (N_HESS, st64), (N_RAGGED, st32)):
+    for label, st in (("bf16 nrhs= 1", st1), ("fp16 nrhs=64", st64), ("bf16 nrhs=32", st32)):
         for k, (tot, n) in st.items():
             if n:
-                log(f"[bench]   nrhs={nr:2d} {k:9s} {tot / n * 1e3:9.1f} us x {n / args.steps:.0f}/step")
+                log(f"[bench]   {label} {k:9s} {tot / n * 1e3:9.1f} us x {n / args.steps:.0f}/step")
 
-    # roofline bookkeeping (algorithmic bytes: spectrum once + series spectra in/out)
+    # Roofline bookkeeping.  The per-unit figure is the stored spectrum: one
+    # pass over it, (Nt+1) Nd Nm complex values of 4 bytes (BF16 or FP16),
+    # is what a launch of the products must read whatever its right-hand-side
+    # count; the right-hand-side and result spectra (8 bytes per bin and
+    # series value) are reported beside it, not in it.
     spec_bytes = op.nfreq * w.Nd * w.Nm * op.elem_bytes
 
-    def avg_us(k, st=stages):
+    def avg_us(st, k):
         tot, n = st[k]
         return tot / n * 1e3 if n else 0.0
 
     def vec_bytes(nrhs):
         return op.nfreq * nrhs * (w.Nm + w.Nd) * 8
 
-    def gemm_flop(nrhs):        # real-equivalent flops of one BF16 pass (x2 issued for the hi+lo split)
+    def gemm_flop(nrhs):        # real-equivalent flops of one pass
         return 2.0 * op.nfreq * w.Nd * (2 * w.Nm) * (2 * nrhs)
 
-    kern = {
-        "gemv_fwd": {"us": avg_us("gemv_fwd", st1), "bytes": spec_bytes + vec_bytes(1), "nrhs": 1},
-        "gemv_adj": {"us": avg_us("gemv_adj", st1), "bytes": spec_bytes + vec_bytes(1), "nrhs": 1},
-        "gemm_fwd_64": {"us": avg_us("gemm_fwd", st64), "bytes": spec_bytes + vec_bytes(N_HESS),
-                        "flop": gemm_flop(N_HESS), "nrhs": N_HESS},
-        "gemm_adj_64": {"us": avg_us("gemm_adj", st64), "bytes": spec_bytes + vec_bytes(N_HESS),
-                        "flop": gemm_flop(N_HESS), "nrhs": N_HESS},
-        "gemm_fwd_32": {"us": avg_us("gemm_fwd", st32), "bytes": spec_bytes + vec_bytes(N_RAGGED),
-                        "flop": gemm_flop(N_RAGGED), "nrhs": N_RAGGED},
-        "gemm_adj_32": {"us": avg_us("gemm_adj", st32), "bytes": spec_bytes + vec_bytes(N_RAGGED),
-                        "flop": gemm_flop(N_RAGGED), "nrhs": N_RAGGED},
+    # kernel: (stage times, stage, spectrum precision, right-hand sides, products issued per real-equivalent flop)
+    kdefs = {
+        "gemv_fwd": (st1, "gemv_fwd", "bf16", 1, None), "gemv_adj": (st1, "gemv_adj", "bf16", 1, None),
+        "gemm_fwd_64": (st64, "gemm_fwd", "fp16", N_HESS, 3), "gemm_adj_64": (st64, "gemm_adj", "fp16", N_HESS, 3),
+        "project_64": (st64, "project", "fp16", N_HESS, None),
+        "gemm_fwd_32": (st32, "gemm_fwd", "bf16", N_RAGGED, 2), "gemm_adj_32": (st32, "gemm_adj", "bf16", N_RAGGED, 2),
     }
-    for k, v in kern.items():
-        v["GBs"] = v["bytes"] / (v["us"] * 1e-6) / 1e9 if v["us"] else 0.0
-        if "flop" in v and v["us"]:
-            v["TFLOPs_issued"] = 2 * v["flop"] / (v["us"] * 1e-6) / 1e12
-    # dominant kernel: largest share of the step
-    share = {"gemv_fwd": st1["gemv_fwd"][0], "gemv_adj": st1["gemv_adj"][0],
-             "gemm_fwd_64": st64["gemm_fwd"][0], "gemm_adj_64": st64["gemm_adj"][0],
-             "gemm_fwd_32": st32["gemm_fwd"][0], "gemm_adj_32": st32["gemm_adj"][0]}
-    dom = max(share, key=share.get)
+    kern = {}
+    for k, (st, stage, prec, nr, issue) in kdefs.items():
+        us = avg_us(st, stage)
+        v = {"us": us, "spectrum": prec, "nrhs": nr, "launches_per_step": st[stage][1] / args.steps}
+        if k.startswith("project"):
+            # truncate-and-repad: reads the adjoint products and writes the forward operand, 8 B each per value
+            v["bytes"] = 2 * op.nfreq * nr * w.Nm * 8
+            v["GBs"] = v["bytes"] / (us * 1e-6) / 1e9 if us else 0.0
+        else:
+            v["spectrum_bytes"] = spec_bytes
+            v["rhs_bytes"] = vec_bytes(nr)
+            v["GBs"] = spec_bytes / (us * 1e-6) / 1e9 if us else 0.0
+            v["GBs_incl_rhs"] = (spec_bytes + vec_bytes(nr)) / (us * 1e-6) / 1e9 if us else 0.0
+        if issue and us:
+            v["TFLOPs_real_equiv"] = gemm_flop(nr) / (us * 1e-6) / 1e12
+            v["TFLOPs_issued"] = issue * gemm_flop(nr) / (us * 1e-6) / 1e12
+        kern[k] = v
+    share = {k: kdefs[k][0][kdefs[k][1]][0] for k in kdefs}
+    dom = max((k for k in share if not k.startswith("project")), key=share.get)
     dk = kern[dom]
     dom_tile = None
     if dom.startswith("gemm_"):
-        dom_tile = tuned[int(dom.rsplit("_", 1)[1])][dom.split("_")[1]]["tile"]
-    traffic = measured_traffic(dom, dom_tile, w)
+        nr = int(dom.rsplit("_", 1)[1])
+        dom_tile = tuned[f"{dk['spectrum']}_{nr}"][dom.split("_")[1]]["tile"]
+    traffic = measured_traffic(dom, dom_tile, dk["spectrum"], w)
     roof = {"bound": "hbm", "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dk["GBs"] / HBM_PEAK_GBS,
             "traffic": traffic["bytes"] if traffic else None, "traffic_unit": "bytes/launch",
-            "traffic_detail": traffic, "kernel": dom, "tile": dom_tile,
-            "algorithmic_bytes_per_launch": dk["bytes"], "avg_launch_us": dk["us"]}
+            "traffic_detail": traffic, "kernel": dom, "tile": dom_tile, "spectrum": dk["spectrum"],
+            "algorithmic_bytes_per_launch": spec_bytes, "avg_launch_us": dk["us"],
+            "achieved_incl_rhs": dk.get("GBs_incl_rhs"), "frac_incl_rhs": (dk.get("GBs_incl_rhs") or 0) / HBM_PEAK_GBS,
+            "rhs_bytes_per_launch": dk.get("rhs_bytes")}
+    if "TFLOPs_issued" in dk:
+        roof["mfma_TFLOPs_issued"] = dk["TFLOPs_issued"]
+        roof["mfma_frac_issued"] = dk["TFLOPs_issued"] / BF16_MFMA_PEAK_TFLOPS
 
     result = {
         "metric": "F/F* matvecs/s + HBM GB/s vs peak",
@@ -215,22 +240,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "bf16+fp16",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt} L={op.L}, BF16 spectrum + FP32 "
-                               f"accumulation; step = misfit gradient on 1 RHS + 64 F F* columns + F and F* "
-                               f"on 32 ragged RHS ({matvecs} matvecs)",
-                   "Nd": w.Nd, "Nm": w.Nm, "Nt": w.Nt, "spectrum": "bf16", "matvecs_per_step": matvecs},
+        "config": {"workload": f"{w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt} L={op.L}; step = misfit gradient on 1 RHS "
+                               f"(BF16 spectrum) + 64 F F* columns (FP16 spectrum) + F and F* on 32 ragged RHS "
+                               f"(BF16 spectrum), FP32 accumulation ({matvecs} matvecs)",
+                   "Nd": w.Nd, "Nm": w.Nm, "Nt": w.Nt, "spectrum": {"gradient": "bf16", "hessian_columns": "fp16",
+                                                                   "ragged": "bf16"},
+                   "matvecs_per_step": matvecs},
         "roofline": roof,
         "parts_ms": {"single_rhs_gradient": part_ms[0], "hessian_64_columns": part_ms[1],
                      "ragged_32_F_and_Ft": part_ms[2]},
         "single_rhs_matvecs_per_s": 2.0 / (part_ms[0] * 1e-3),
         "batched_matvecs_per_s": 2.0 * N_HESS / (part_ms[1] * 1e-3),
         "kernels": kern,
-        "kernels_us_by_nrhs": {str(n): {k: avg_us(k, st) for k in st if st[k][1]}
-                               for n, st in ((1, st1), (N_HESS, st64), (N_RAGGED, st32))},
-        "load_ms": load_ms,
-        "autotune": {str(k): v for k, v in tuned.items()},
+        "kernels_us": {lbl: {k: avg_us(st, k) for k in st if st[k][1]}
+                       for lbl, st in (("bf16_1", st1), ("fp16_64", st64), ("bf16_32", st32))},
+        "load_ms": {"bf16": load_ms, "fp16": load16_ms},
+        "autotune": tuned,
     }
 
     from paper_2501_14911_amd import bandwidth_probe
@@ -238,23 +265,32 @@ def main():
     result["measured_stream"] = probe
     roof["frac_of_measured_read"] = dk["GBs"] / probe["read_GBs"]
     log(f"[bench] streaming probe: read {probe['read_GBs']:.0f} GB/s, copy {probe['copy_GBs']:.0f} GB/s; "
-        f"{dom} at {dk['GBs']:.0f} GB/s = {roof['frac']:.1%} of 8 TB/s, {roof['frac_of_measured_read']:.1%} of read probe")
+        f"{dom} ({dk['spectrum']}) at {dk['GBs']:.0f} GB/s of spectrum = {roof['frac']:.1%} of 8 TB/s, "
+        f"{roof['frac_of_measured_read']:.1%} of read probe")
 
     if not args.no_call_stats:
-        result["calls"] = call_stats(op, w, m, d_obs, E, spec_bytes, vec_bytes, probe["read_GBs"], dev, torch, np,
-                                     synth)
+        result["calls"] = {}
+        for name, o in (("bf16", op), ("fp16", op16)):
+            cs = call_stats(o, w, m, d_obs, E, spec_bytes, probe["read_GBs"], dev, torch, np, synth)
+            result["calls"].update({f"{name}_{k}": v for k, v in cs.items()})
     for k, v in result.get("calls", {}).items():
-        log(f"[bench] {k:5s} median {v['median_ms']:.3f} ms (p10 {v['p10_ms']:.3f}, p90 {v['p90_ms']:.3f}; "
+        log(f"[bench] {k:10s} median {v['median_ms']:.3f} ms (p10 {v['p10_ms']:.3f}, p90 {v['p90_ms']:.3f}; "
             f"{v['calls']} calls): {v['matvecs_per_s']:.0f} matvecs/s, spectrum {v['spectrum_GBs']:.0f} GB/s "
             f"= {v['spectrum_frac_of_peak']:.1%} of 8 TB/s")
 
     if not args.no_accuracy:
-        result["accuracy"] = accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np)
-    if not args.no_fp16:
-        result["fp16"] = fp16_leg(w, dev, torch, np, synth, P2OOperator, m, d_obs, E, args.no_accuracy)
+        result["accuracy"] = accuracy_sample(op, op16, w, m, H, hidx, m_r, Y_r, nt_r, dev, torch, np)
+    op.close()
+    op16.close()
+    del op, op16, H, Y_r, S_r, E
+    torch.cuda.empty_cache()
+    if not args.no_fp32:
+        result["fp32"] = single_rhs_leg(w, "fp32", dev, torch, np, synth, P2OOperator, args.no_accuracy)
     if not args.no_fp64:
         result["fp64_plain"] = fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var,
                                           args.no_accuracy, result)
+    if not args.no_largest:
+        result["largest"] = largest_leg(dev, torch, np, synth, P2OOperator, args.no_accuracy)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_cols, np)
     print(json.dumps(result), flush=True)
@@ -312,9 +348,9 @@ _MEASURED = {
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
 
-def measured_traffic(kernel, tile, w):
+def measured_traffic(kernel, tile, precision, w):
     import hashlib
-    ent = TRAFFIC.get((kernel, tile))
+    ent = TRAFFIC.get((kernel, tile, precision))
     if not ent:
         return None
     src, sha, fetch, write, workload = ent
@@ -330,7 +366,7 @@ def measured_traffic(kernel, tile, w):
     return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "source": src, "sha1": sha}
 
 
-def call_stats(op, w, m, d_obs, E, spec_bytes, vec_bytes, read_GBs, dev, torch, np, synth, calls=20, warm=3):
+def call_stats(op, w, m, d_obs, E, spec_bytes, read_GBs, dev, torch, np, synth, calls=20, warm=3):
     """Whole calls of F and F* (FFTs and products), separately, at one and at
     64 right-hand sides: 3 warm-ups, then the median and 10th / 90th
     percentiles of `calls` calls, each bracketed by HIP events on the plan's
@@ -358,70 +394,85 @@ def call_stats(op, w, m, d_obs, E, spec_bytes, vec_bytes, read_GBs, dev, torch, 
                      "p90_ms": float(np.percentile(ts, 90)), "matvecs_per_s": nrhs / (med * 1e-3),
                      "spectrum_GBs": spec_bytes / (med * 1e-3) / 1e9,
                      "spectrum_frac_of_peak": spec_bytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "spectrum_frac_of_measured_read": spec_bytes / (med * 1e-3) / 1e9 / read_GBs,
-                     "algorithmic_GBs": (spec_bytes + vec_bytes(nrhs)) / (med * 1e-3) / 1e9}
+                     "spectrum_frac_of_measured_read": spec_bytes / (med * 1e-3) / 1e9 / read_GBs}
         del o
     del m64
     return res
 
 
-def accuracy_sample(op, w, m, E, H, hidx, m_r, Y_r, nt_r, dev, torch, np):
-    """rel-L2 against the FP64 oracle on sampled sensor rows / parameter
-    columns of the same outputs (the oracle regenerates those rows or
-    columns of every block)."""
+def column_error_estimate(w, h_col, j, k_other, rng, np):
+    """Relative L2 error of one data-space column h = F F* e_j over all
+    Nd x Nt outputs against the FP64 oracle, estimated without the whole
+    operator: the spike's own sensor row s exactly, plus (Nd - 1) / k times
+    the squared error and squared norm of k other sensor rows drawn at random
+    (F* e_j needs row s of the blocks only, so a sampled output row r costs
+    rows r and s of every block).  Returns (estimate, spike row alone)."""
+    import oracle
+    import synth
+    t0, sidx = divmod(int(j), w.Nd)
+    others = np.sort(rng.choice(np.setdiff1d(np.arange(w.Nd), [sidx]), k_other, replace=False))
+    rs = np.concatenate([[sidx], others])
+    Frs = synth.operator_rows_cols(w, range(w.Nt), rows=rs, backend="torch").numpy()
+    e = np.zeros((w.Nt, len(rs)))
+    e[t0, 0] = 1.0
+    href = oracle.apply_F(Frs, oracle.apply_Ft(Frs, e))
+    err2 = ((h_col[:, rs] - href) ** 2).sum(axis=0)
+    ref2 = (href ** 2).sum(axis=0)
+    scale = (w.Nd - 1) / k_other
+    est = np.sqrt((err2[0] + scale * err2[1:].sum()) / (ref2[0] + scale * ref2[1:].sum()))
+    return float(est), float(np.sqrt(err2[0] / ref2[0]))
+
+
+def accuracy_sample(op, op16, w, m, H, hidx, m_r, Y_r, nt_r, dev, torch, np):
+    """rel-L2 against the FP64 oracle.  F m and F* d on N(0, 1) inputs: on
+    random sensor rows / parameter columns of the outputs (an unbiased sample:
+    the inputs have no structure).  Data-space columns: the whole-output
+    estimate of column_error_estimate for the columns whose spikes sit at
+    t = 0 (the hardest case: output concentrated near lag 0) and t = Nt - 1."""
     import oracle
     import synth
     rng = np.random.default_rng(1)
     rows = np.sort(rng.choice(w.Nd, 8, replace=False))
     cols = np.sort(rng.choice(w.Nm, 64, replace=False))
-    out = {}
-    d = op.apply_F(m).double().cpu().numpy()
     Fr = synth.operator_rows_cols(w, range(w.Nt), rows=rows, backend="torch").numpy()
-    out["single_F_8rows"] = oracle.rel_l2(d[:, rows], oracle.apply_F(Fr, m.double().cpu().numpy()))
-    din = synth.data_series(w, 1)[0]
-    s = op.apply_Ft(torch.from_numpy(din).to(dev, torch.float32)).double().cpu().numpy()
     Fc = synth.operator_rows_cols(w, range(w.Nt), cols=cols, backend="torch").numpy()
-    out["single_Ft_64cols"] = oracle.rel_l2(s[:, cols], oracle.apply_Ft(Fc, din))
-    # data-space columns: F^T e_(t0, s) needs sensor row s of the blocks only
+    mh = m.double().cpu().numpy()
+    din = synth.data_series(w, 1)[0]
+    out = {}
+    for name, o in (("bf16", op), ("fp16", op16)):
+        d = o.apply_F(m).double().cpu().numpy()
+        out[f"{name}_single_F_8rows"] = oracle.rel_l2(d[:, rows], oracle.apply_F(Fr, mh))
+        s = o.apply_Ft(torch.from_numpy(din).to(dev, torch.float32)).double().cpu().numpy()
+        out[f"{name}_single_Ft_64cols"] = oracle.rel_l2(s[:, cols], oracle.apply_Ft(Fc, din))
     h = H.double().cpu().numpy()
-    errs = []
-    for c in range(4):
-        j = int(hidx[c])
-        t0, sidx = divmod(j, w.Nd)
-        rs = np.unique(np.concatenate([rows, [sidx]]))
-        Frs = synth.operator_rows_cols(w, range(w.Nt), rows=rs, backend="torch").numpy()
-        e = np.zeros((w.Nt, len(rs)))
-        e[t0, np.searchsorted(rs, sidx)] = 1.0
-        mt = oracle.apply_Ft(Frs, e)
-        href = oracle.apply_F(Frs, mt)
-        errs.append(oracle.rel_l2(h[c][:, rs], href))
-    out["hessian_columns_4x_rows"] = max(errs)
+    crng = np.random.default_rng(2)
+    for c in (0, 1):
+        est, spike = column_error_estimate(w, h[c], hidx[c], 8, crng, np)
+        t0 = int(hidx[c]) // w.Nd
+        out[f"fp16_hessian_column_t{t0}_whole_output_estimate"] = est
+        out[f"fp16_hessian_column_t{t0}_spike_row"] = spike
     y = Y_r.double().cpu().numpy()
     mr = m_r.double().cpu().numpy()
-    errs = []
-    for b in range(4):
-        yo = oracle.apply_F(Fr, mr[b:b + 1], nt_r[b:b + 1])[0]
-        errs.append(oracle.rel_l2(y[b][:, rows], yo))
-    out["ragged_F_4x_8rows"] = max(errs)
-    log("[bench] sampled rel-L2 vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
+    out["bf16_ragged_F_4x_8rows"] = max(oracle.rel_l2(y[b][:, rows], oracle.apply_F(Fr, mr[b:b + 1], nt_r[b:b + 1])[0])
+                                        for b in range(4))
+    log("[bench] rel-L2 vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
     out["tolerance"] = 2e-3
     return out
 
 
-def fp16_leg(w, dev, torch, np, synth, P2OOperator, m, d_obs, E, no_acc, calls=10):
-    """The same operator with an FP16 spectrum: F and F* at one right-hand
-    side (streaming path) and at 64 (matrix cores, FP16 entries split into
-    BF16 hi + lo), medians of `calls` whole calls, and rel-L2 against the FP64
-    oracle on sampled rows / columns."""
+def single_rhs_leg(w, precision, dev, torch, np, synth, P2OOperator, no_acc, calls=10):
+    """F and F* on one right-hand side (streaming products) with a spectrum
+    in `precision`: medians of `calls` whole calls, spectrum GB/s, and
+    rel-L2 against the FP64 oracle on random rows / columns."""
     import oracle
-    op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp16", max_rhs=N_HESS, device=dev)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, precision, max_rhs=1, device=dev)
     op.load(lambda c0, n: gpu_blocks(w, c0, n, dev, torch, synth))
-    tuned = op.autotune(N_HESS, reps=2)
-    m64 = synth.param_series(w, N_HESS, seed_offset=41, backend="torch", device=dev).float()
-    runs = {"F_1": lambda: op.apply_F(m.unsqueeze(0)), "Ft_1": lambda: op.apply_Ft(d_obs.unsqueeze(0)),
-            "F_64": lambda: op.apply_F(m64), "Ft_64": lambda: op.apply_Ft(E)}
-    out = {"autotune_64": {"fwd_tile": tuned["fwd"][0], "adj_tile": tuned["adj"][0]}}
-    for name, fn in runs.items():
+    dt = op.dtype
+    m = synth.param_series(w, 1, backend="torch", device=dev)[0].to(dt)
+    d = synth.data_series(w, 1, backend="torch", device=dev)[0].to(dt)
+    spec = op.nfreq * w.Nd * w.Nm * op.elem_bytes
+    out = {"spectrum_bytes": spec}
+    for name, fn in (("F_1", lambda: op.apply_F(m)), ("Ft_1", lambda: op.apply_Ft(d))):
         for _ in range(2):
             fn()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
@@ -431,29 +482,82 @@ def fp16_leg(w, dev, torch, np, synth, P2OOperator, m, d_obs, E, no_acc, calls=1
             b.record()
         torch.cuda.synchronize()
         med = float(np.median([a.elapsed_time(b) for a, b in evs]))
-        nr = N_HESS if name.endswith("64") else 1
-        out[name] = {"median_ms": med, "matvecs_per_s": nr / (med * 1e-3), "calls": calls}
+        out[name] = {"median_ms": med, "matvecs_per_s": 1e3 / med, "spectrum_GBs": spec / (med * 1e-3) / 1e9,
+                     "spectrum_frac_of_peak": spec / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, "calls": calls}
     if not no_acc:
-        rng = np.random.default_rng(1)
-        rows = np.sort(rng.choice(w.Nd, 8, replace=False))
-        cols = np.sort(rng.choice(w.Nm, 64, replace=False))
+        rng = np.random.default_rng(3)
+        rows = np.sort(rng.choice(w.Nd, 6, replace=False))
+        cols = np.sort(rng.choice(w.Nm, 48, replace=False))
         Fr = synth.operator_rows_cols(w, range(w.Nt), rows=rows, backend="torch").numpy()
         Fc = synth.operator_rows_cols(w, range(w.Nt), cols=cols, backend="torch").numpy()
-        d1 = op.apply_F(m.unsqueeze(0))[0].double().cpu().numpy()
-        out["rel_l2_single_F_8rows"] = oracle.rel_l2(d1[:, rows], oracle.apply_F(Fr, m.double().cpu().numpy()))
-        s1 = op.apply_Ft(d_obs.unsqueeze(0))[0].double().cpu().numpy()
-        out["rel_l2_single_Ft_64cols"] = oracle.rel_l2(s1[:, cols], oracle.apply_Ft(Fc, d_obs.double().cpu().numpy()))
-        y = op.apply_F(m64).double().cpu().numpy()
-        mh = m64[:4].double().cpu().numpy()
-        out["rel_l2_batched_F_4x_8rows"] = max(oracle.rel_l2(y[b][:, rows], oracle.apply_F(Fr, mh[b]))
-                                               for b in range(4))
-        out["tolerance"] = 2e-3
-    log("[bench] FP16 spectrum: " + ", ".join(f"{k} {v['median_ms']:.3f} ms" for k, v in out.items()
-                                              if isinstance(v, dict) and "median_ms" in v)
-        + ("" if no_acc else ", rel-L2 " + ", ".join(f"{k[7:]} {v:.2e}" for k, v in out.items()
-                                                      if k.startswith("rel_l2"))))
+        y = op.apply_F(m).double().cpu().numpy()
+        s = op.apply_Ft(d).double().cpu().numpy()
+        out["rel_l2_F_6rows"] = oracle.rel_l2(y[:, rows], oracle.apply_F(Fr, m.double().cpu().numpy()))
+        out["rel_l2_Ft_48cols"] = oracle.rel_l2(s[:, cols], oracle.apply_Ft(Fc, d.double().cpu().numpy()))
+        out["tolerance"] = {"fp64": 1e-12, "fp32": 1e-5}.get(precision, 2e-3)
+    log(f"[bench] {precision.upper()} spectrum: " + ", ".join(
+        f"{k} {v['median_ms']:.3f} ms ({v['spectrum_frac_of_peak']:.1%} of 8 TB/s)" for k, v in out.items()
+        if isinstance(v, dict)) + ("" if no_acc else f", rel-L2 F {out['rel_l2_F_6rows']:.2e}, "
+                                                      f"F* {out['rel_l2_Ft_48cols']:.2e}"))
     op.close()
-    del op, m64
+    del op
+    torch.cuda.empty_cache()
+    return out
+
+
+def largest_leg(dev, torch, np, synth, P2OOperator, no_acc, calls=10, nrhs=16):
+    """The 600 x 65536 x 420 one-GPU share, BF16 spectrum (66 GB): F and F*
+    at one and at 16 right-hand sides (medians of `calls` whole calls) and
+    the misfit gradient at m_true (d = F m_true + 0.01 eps), with the
+    gradient against the FP64 oracle on random parameter columns there (the
+    residual is minus the noise, so the oracle needs those columns only)."""
+    import oracle
+    w = synth.CONFIGS["largest"]
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=nrhs, device=dev)
+    t0 = time.perf_counter()
+    op.load(lambda c0, n: gpu_blocks(w, c0, n, dev, torch, synth))
+    log(f"[bench] largest: BF16 spectrum ({op.fhat_bytes / 1e9:.1f} GB) loaded in {time.perf_counter() - t0:.1f} s")
+    r = op.autotune(nrhs, reps=2)
+    spec = op.nfreq * w.Nd * w.Nm * op.elem_bytes
+    m_true = synth.param_series(w, 1, backend="torch", device=dev, smooth=True)[0].float()
+    noise = torch.from_numpy(synth.noise(w, 1)[0]).to(dev, torch.float32)
+    with torch.no_grad():
+        d_obs = op.apply_F(m_true) + noise
+    var = torch.tensor([w.sigma ** 2], dtype=torch.float64, device=dev)
+    m16 = synth.param_series(w, nrhs, backend="torch", device=dev, smooth=True).float()
+    d16 = synth.data_series(w, nrhs, backend="torch", device=dev).float()
+    out = {"workload": f"{w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt}, BF16 spectrum", "spectrum_bytes": spec,
+           "autotune_16": {"fwd_tile": r["fwd"][0], "adj_tile": r["adj"][0]}}
+    runs = {"F_1": (lambda: op.apply_F(m_true), 1), "Ft_1": (lambda: op.apply_Ft(d_obs), 1),
+            "F_16": (lambda: op.apply_F(m16), nrhs), "Ft_16": (lambda: op.apply_Ft(d16), nrhs),
+            "misfit_grad_1": (lambda: op.misfit_grad(m_true, d_obs, var), 2)}
+    for name, (fn, nmv) in runs.items():
+        for _ in range(2):
+            fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        med = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        passes = 2 if name.startswith("misfit") else 1
+        out[name] = {"median_ms": med, "matvecs_per_s": nmv / (med * 1e-3),
+                     "spectrum_GBs": passes * spec / (med * 1e-3) / 1e9,
+                     "spectrum_frac_of_peak": passes * spec / (med * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if not no_acc:
+        cols = np.sort(np.random.default_rng(14).choice(w.Nm, 32, replace=False))
+        _, g = op.misfit_grad(m_true, d_obs, var)
+        g = g.double().cpu().numpy()
+        Fc = synth.operator_rows_cols(w, range(w.Nt), cols=cols, backend="torch").numpy()
+        g_ref = -oracle.apply_Ft(Fc, synth.noise(w, 1)[0]) / w.sigma ** 2
+        out["rel_l2_gradient_at_m_true_32cols"] = oracle.rel_l2(g[:, cols], g_ref)
+        out["tolerance"] = 2e-3
+    log("[bench] largest: " + ", ".join(f"{k} {v['median_ms']:.3f} ms ({v['spectrum_frac_of_peak']:.1%})"
+                                        for k, v in out.items() if isinstance(v, dict) and "median_ms" in v)
+        + ("" if no_acc else f", gradient rel-L2 {out['rel_l2_gradient_at_m_true_32cols']:.2e}"))
+    op.close()
+    del op, m16, d16
     torch.cuda.empty_cache()
     return out
 
@@ -499,11 +603,17 @@ def cpu_baseline(w, cols, np):
     time is scaled by Nm / cols to a full-size matvec rate."""
     import oracle
     import synth
+    # The oracle's BLAS pool uses the threads the job is given (OMP_NUM_THREADS,
+    # 16 per GPU on the benchmark boxes); the host's own count is reported beside it.
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
     except Exception:
-        cores = os.cpu_count()
+        cores = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = None
     cols = min(cols, w.Nm)
     F = synth.operator_rows_cols(w, range(w.Nt), cols=np.arange(cols), backend="torch").numpy()
     m = synth.param_series(w.with_(Nm=cols, grid=None), 1)[0]
@@ -520,6 +630,7 @@ def cpu_baseline(w, cols, np):
     log(f"[bench] oracle on {cols} columns x {reps}: F {t_f / reps:.2f} s, F* {t_t / reps:.2f} s "
         f"({cores} BLAS threads)")
     return {"value": 2.0 / full, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+            "host_os_cpu_count": os.cpu_count(), "host_affinity_cpus": affinity,
             "sample": f"F and F* on parameter columns 0..{cols - 1} of {w.Nm} (all {w.Nd} sensors, "
                       f"{w.Nt} steps), FP64 numpy block-Toeplitz sums, repeated {reps} times; time per "
                       f"matvec scaled by {w.Nm}/{cols}",

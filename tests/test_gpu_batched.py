@@ -1,8 +1,8 @@
 """GPU parity of the batched (many right-hand sides) path on the matrix
 cores against the FP64 oracle, and against the per-right-hand-side streaming
-path on the same plan.  BF16 spectrum; right-hand sides enter the MFMA as a
-BF16 hi + lo pair, so the batched and streaming results differ only by
-that split (relative 2^-16) and by summation order."""
+path on the same plan.  BF16 spectrum (FP16 where stated); right-hand sides
+enter the MFMA as a hi + lo pair, so the batched and streaming results differ
+only by that split (relative 2^-16) and by summation order."""
 import sys
 
 import numpy as np
@@ -20,19 +20,16 @@ import synth  # noqa: E402
 from paper_2501_14911_amd import P2OOperator  # noqa: E402
 
 DEV = "cuda"
-TOL_BF16 = 2e-3
-# F F^* e applies two operators each within 2e-3; to first order their
-# relative errors add.
-TOL_BF16_COMPOSED = 2 * TOL_BF16
+TOL_BF16 = 2e-3        # BF16 or FP16 spectrum, FP32 accumulation
 
 
 def note(msg):
     print(msg, flush=True)
 
 
-def build(w, max_rhs):
+def build(w, max_rhs, precision="bf16"):
     F = synth.operator_blocks(w)
-    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=max_rhs, device=DEV)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, precision, max_rhs=max_rhs, device=DEV)
     Ft = torch.from_numpy(F).to(DEV)
     op.load(lambda c0, n: Ft[:, :, c0:c0 + n])
     return op, F
@@ -92,15 +89,24 @@ def test_batched_medium_64_and_ragged():
 
 
 def test_batched_data_space_columns():
+    """64 columns F F* e_j in one call on an FP16 spectrum (the precision that
+    meets 2e-3 on every column; a BF16 spectrum does not on early spikes),
+    each column against the oracle, plain and with ragged lengths."""
     w = synth.CONFIGS["medium"]
     idx = synth.hessian_column_indices(w, 64)
     e = synth.unit_data_vectors(w, idx)
-    op, F = build(w, 64)
-    h = host(op.apply_FFt(dev(e)))
-    ho = oracle.data_space_hessian(F, e)
-    worst = max(oracle.rel_l2(h[b], ho[b]) for b in range(64))
-    note(f"[batched] F F* columns worst rel-L2 {worst:.3e}")
-    assert worst <= TOL_BF16_COMPOSED
+    op, F = build(w, 64, "fp16")
+    n = synth.ragged_lengths(w, 64, lo=1)
+    for nt in (None, n):
+        h = host(op.apply_FFt(dev(e), nt_active=nt))
+        ho = oracle.data_space_hessian(F, e, nt)
+        errs = [oracle.rel_l2(h[b], ho[b]) for b in range(64) if np.any(ho[b])]
+        note(f"[batched] fp16 F F* columns{' ragged' if nt is not None else ''}: worst rel-L2 {max(errs):.3e} "
+             f"(t = 0 column {errs[0]:.3e})")
+        assert max(errs) <= TOL_BF16
+        if nt is not None:
+            for b in range(64):
+                assert np.all(h[b, nt[b]:] == 0.0)
 
 
 def test_batched_misfit_gradient():

@@ -1,7 +1,7 @@
 """Full-size GPU parity in the launch configurations the benchmark times.
 
-The 600 x 16384 x 420 workload (BF16 spectrum, 16.5 GB) and the
-600 x 65536 x 420 one-GPU share (BF16, 66 GB).  Blocks are drawn on the GPU
+The 600 x 16384 x 420 workload (BF16 and FP16 spectra, 16.5 GB each; FP32,
+33 GB; FP64, 66 GB) and the 600 x 65536 x 420 one-GPU share (BF16, 66 GB).  Blocks are drawn on the GPU
 with the counter-based generator; the FP64 oracle regenerates on the CPU
 only the sensor rows (for F m and F F* e) or parameter columns (for F* d) it
 checks, and computes those outputs exactly.  Where the oracle would need
@@ -50,51 +50,54 @@ def cols_of_blocks(w, cols):
     return synth.operator_rows_cols(w, range(w.Nt), cols=np.asarray(cols), backend="torch").numpy()
 
 
-@pytest.fixture(scope="module")
-def paper_time():
-    w = synth.CONFIGS["paper_time"]
-    note(f"[fullsize] loading {w.name}")
-    op = P2OOperator(w.Nd, w.Nm, w.Nt, "bf16", max_rhs=64, device=DEV)
+def load_op(w, precision, max_rhs):
+    note(f"[fullsize] loading {w.name} {precision}")
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, precision, max_rhs=max_rhs, device=DEV)
     op.load(lambda c0, n: gpu_blocks(w, c0, n))
-    yield w, op
+    return op
+
+
+def close_op(op):
     op.close()
     del op
     torch.cuda.empty_cache()
 
 
-def test_paper_time_single_rhs(paper_time):
-    w, op = paper_time
-    rng = np.random.default_rng(11)
-    rows = np.sort(rng.choice(w.Nd, 6, replace=False))
-    cols = np.sort(rng.choice(w.Nm, 48, replace=False))
+@pytest.fixture(scope="module")
+def paper_time():
+    w = synth.CONFIGS["paper_time"]
+    op = load_op(w, "bf16", 64)
+    yield w, op
+    close_op(op)
+
+
+def single_rhs_errors(w, op, nrows=6, ncols=48, seed=11):
+    """F m on random sensor rows and F* d on random parameter columns of the
+    outputs, against the oracle on those rows / columns of every block.  The
+    inputs are N(0, 1) series with no structure, so the sampled error is an
+    unbiased estimate of the whole output's."""
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(w.Nd, nrows, replace=False))
+    cols = np.sort(rng.choice(w.Nm, ncols, replace=False))
     m = synth.param_series(w, 1)[0]
     d = synth.data_series(w, 1)[0]
-    y = op.apply_F(torch.from_numpy(m).to(DEV, torch.float32)).double().cpu().numpy()
-    s = op.apply_Ft(torch.from_numpy(d).to(DEV, torch.float32)).double().cpu().numpy()
+    y = op.apply_F(torch.from_numpy(m).to(DEV, op.dtype)).double().cpu().numpy()
+    s = op.apply_Ft(torch.from_numpy(d).to(DEV, op.dtype)).double().cpu().numpy()
     ey = oracle.rel_l2(y[:, rows], oracle.apply_F(rows_of_blocks(w, rows), m))
     es = oracle.rel_l2(s[:, cols], oracle.apply_Ft(cols_of_blocks(w, cols), d))
-    note(f"  single: F rows {ey:.3e}, F* columns {es:.3e}")
+    return ey, es
+
+
+def test_paper_time_single_rhs(paper_time):
+    w, op = paper_time
+    ey, es = single_rhs_errors(w, op)
+    note(f"  bf16 single: F rows {ey:.3e}, F* columns {es:.3e}")
     assert ey <= TOL and es <= TOL
 
 
-def test_paper_time_hessian_columns_and_ragged(paper_time):
+def test_paper_time_ragged(paper_time):
     w, op = paper_time
-    idx = synth.hessian_column_indices(w, 64)
-    E = torch.from_numpy(synth.unit_data_vectors(w, idx)).to(DEV, torch.float32)
-    h = op.apply_FFt(E).double().cpu().numpy()
     rows = np.sort(np.random.default_rng(12).choice(w.Nd, 4, replace=False))
-    worst = 0.0
-    for c in (0, 1, 17, 63):                         # includes t = 0 and t = Nt - 1
-        t0, sidx = divmod(int(idx[c]), w.Nd)
-        rs = np.unique(np.concatenate([rows, [sidx]]))
-        Frs = rows_of_blocks(w, rs)
-        e = np.zeros((w.Nt, len(rs)))
-        e[t0, np.searchsorted(rs, sidx)] = 1.0
-        href = oracle.apply_F(Frs, oracle.apply_Ft(Frs, e))
-        worst = max(worst, oracle.rel_l2(h[c][:, rs], href))
-    note(f"  64 F F* columns: worst sampled rel-L2 {worst:.3e}")
-    assert worst <= 2 * TOL                          # two quantised operators composed
-    # 32 ragged right-hand sides
     n = synth.ragged_lengths(w, 32)
     m = synth.param_series(w, 32, seed_offset=21)
     y = op.apply_F(torch.from_numpy(m).to(DEV, torch.float32), nt_active=n).double().cpu().numpy()
@@ -103,6 +106,82 @@ def test_paper_time_hessian_columns_and_ragged(paper_time):
         assert np.all(y[b, n[b]:] == 0.0)
         yo = oracle.apply_F(Fr, m[b:b + 1], n[b:b + 1])[0]
         assert oracle.rel_l2(y[b][:, rows], yo) <= TOL
+
+
+def column_error_estimate(w, h_col, j, k_other, rng):
+    """Relative L2 error of one data-space column h = F F* e_j over all Nd x Nt
+    outputs, estimated without the whole operator: the spike's own sensor row
+    s exactly, plus (Nd - 1) / k times the squared error and squared norm of
+    k other sensor rows drawn at random.  F* e_j needs row s of the blocks
+    only, so each sampled row r of h costs rows r and s of every block."""
+    t0, sidx = divmod(int(j), w.Nd)
+    others = np.sort(rng.choice(np.setdiff1d(np.arange(w.Nd), [sidx]), k_other, replace=False))
+    rs = np.concatenate([[sidx], others])
+    Frs = rows_of_blocks(w, rs)
+    e = np.zeros((w.Nt, len(rs)))
+    e[t0, 0] = 1.0
+    href = oracle.apply_F(Frs, oracle.apply_Ft(Frs, e))          # [Nt, 1 + k]
+    err2 = ((h_col[:, rs] - href) ** 2).sum(axis=0)
+    ref2 = (href ** 2).sum(axis=0)
+    scale = (w.Nd - 1) / k_other
+    est = np.sqrt((err2[0] + scale * err2[1:].sum()) / (ref2[0] + scale * ref2[1:].sum()))
+    spike_only = np.sqrt(err2[0] / ref2[0])
+    return float(est), float(spike_only)
+
+
+@pytest.fixture(scope="module")
+def paper_time_fp16():
+    w = synth.CONFIGS["paper_time"]
+    op = load_op(w, "fp16", 64)
+    yield w, op
+    close_op(op)
+
+
+def test_paper_time_fp16_single_rhs(paper_time_fp16):
+    w, op = paper_time_fp16
+    ey, es = single_rhs_errors(w, op)
+    note(f"  fp16 single: F rows {ey:.3e}, F* columns {es:.3e}")
+    assert ey <= TOL and es <= TOL
+
+
+def test_paper_time_hessian_columns(paper_time_fp16):
+    """64 data-space columns in one call (FP16 spectrum, matrix cores); the
+    columns with spikes at t = 0 and t = Nt - 1 and two others, each by the
+    whole-output estimate of column_error_estimate."""
+    w, op = paper_time_fp16
+    idx = synth.hessian_column_indices(w, 64)
+    E = torch.from_numpy(synth.unit_data_vectors(w, idx)).to(DEV, torch.float32)
+    h = op.apply_FFt(E).double().cpu().numpy()
+    rng = np.random.default_rng(12)
+    for c in (0, 1, 17, 63):
+        est, spike = column_error_estimate(w, h[c], idx[c], 12, rng)
+        note(f"  F F* column {c} (t0 = {int(idx[c]) // w.Nd}): whole-output estimate {est:.3e} "
+             f"(spike row alone {spike:.3e})")
+        assert est <= TOL
+
+
+def test_paper_time_fp32():
+    """FP32 spectrum (33 GB) at the same shape: F and F* within 1e-5."""
+    w = synth.CONFIGS["paper_time"]
+    op = load_op(w, "fp32", 1)
+    try:
+        ey, es = single_rhs_errors(w, op, seed=21)
+        note(f"  fp32 single: F rows {ey:.3e}, F* columns {es:.3e}")
+        assert ey <= 1e-5 and es <= 1e-5
+    finally:
+        close_op(op)
+
+
+def test_paper_time_fp64():
+    """FP64 spectrum (66 GB) at the same shape: F and F* within 1e-12."""
+    w = synth.CONFIGS["paper_time"]
+    op = load_op(w, "fp64", 1)
+    try:
+        ey, es = single_rhs_errors(w, op, nrows=4, ncols=32, seed=22)
+        note(f"  fp64 single: F rows {ey:.3e}, F* columns {es:.3e}")
+        assert ey <= 1e-12 and es <= 1e-12
+    finally:
+        close_op(op)
 
 
 @pytest.fixture(scope="module")
@@ -167,6 +246,17 @@ def test_largest_misfit_gradient_autograd(largest):
         gv = float((g * v.double()).sum())
         note(f"  misfit {float(phi.detach()):.6e}: directional derivative {gv:.6e}, central difference {fd:.6e}")
         assert abs(fd - gv) <= 1e-3 * abs(gv)
+    # At m_true the residual F m_true - d_obs is minus the noise, so the
+    # gradient is -F* noise / sigma^2: against the oracle on sampled columns.
+    cols = np.sort(np.random.default_rng(14).choice(w.Nm, 32, replace=False))
+    m = m_true.clone().requires_grad_(True)
+    misfit(m, op, d_obs, sig2).backward()
+    g_true = m.grad.double().cpu().numpy()
+    noise = synth.noise(w, 1)[0]
+    g_ref = -oracle.apply_Ft(cols_of_blocks(w, cols), noise) / sig2
+    eg = oracle.rel_l2(g_true[:, cols], g_ref)
+    note(f"  gradient at m_true vs oracle on 32 columns: {eg:.3e}")
+    assert eg <= TOL
     # at m_true the residual is the noise: misfit ~ chi-square / 2 with Nd*Nt dof
     with torch.no_grad():
         phi_true = float(misfit(m_true, op, d_obs, sig2))

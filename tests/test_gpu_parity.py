@@ -24,12 +24,6 @@ import synth  # noqa: E402
 from paper_2501_14911_amd import P2O, P2OT, P2OOperator, misfit  # noqa: E402
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 2e-3, "fp16": 2e-3}
-# With fewer than 64 terms per output the relative L2 error of a BF16/FP16
-# product is not concentrated near its mean (about 1.1e-3 for BF16 with
-# round-to-nearest-even); such shapes are held to the BF16 unit roundoff 2^-8.
-# That every stored code is the correctly rounded spectrum value is checked
-# separately (test_quantised_spectrum_is_nearest_rounding).
-TOL_FEW_TERMS = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 2.0 ** -8, "fp16": 2e-3}
 DEV = "cuda"
 
 
@@ -67,20 +61,28 @@ SMALL = [
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("w", SMALL, ids=lambda w: w.name)
 def test_forward_and_adjoint_small(w, precision):
+    """16 right-hand sides, on the batched path (matrix cores for BF16 / FP16)
+    and on the streaming one.  Several of these shapes give an output only a
+    handful of terms (5 sensors x 8 parameters at N_t = 1), where a single
+    output's relative error is not concentrated near its mean; the error is
+    therefore taken over all 16 right-hand sides together (hundreds of
+    outputs), at the same tolerance as everywhere else."""
     note(f"[parity] {w.name} {precision}")
-    op, F = build_op(w, precision, max_rhs=2)
-    m = synth.param_series(w, 2)
-    d = synth.data_series(w, 2)
-    y = host(op.apply_F(to_dev(m, op)))
-    s = host(op.apply_Ft(to_dev(d, op)))
-    ey = oracle.rel_l2(y, oracle.apply_F(F, m))
-    es = oracle.rel_l2(s, oracle.apply_Ft(F, d))
-    note(f"  rel-L2 F {ey:.3e}  F* {es:.3e}")
-    tol = TOL if min(w.Nm, w.Nd * w.Nt) >= 64 else TOL_FEW_TERMS
-    assert ey <= tol[precision] and es <= tol[precision]
+    nrhs = 16
+    op, F = build_op(w, precision, max_rhs=nrhs)
+    m = synth.param_series(w, nrhs)
+    d = synth.data_series(w, nrhs)
+    yo, so = oracle.apply_F(F, m), oracle.apply_Ft(F, d)
+    for mode in ("auto", "gemv"):
+        op.set_batched(mode)
+        y = host(op.apply_F(to_dev(m, op)))
+        s = host(op.apply_Ft(to_dev(d, op)))
+        ey, es = oracle.rel_l2(y, yo), oracle.rel_l2(s, so)
+        note(f"  {mode}: rel-L2 F {ey:.3e}  F* {es:.3e}")
+        assert ey <= TOL[precision] and es <= TOL[precision], (mode, ey, es)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16"])
 def test_medium_workload(precision):
     w = synth.CONFIGS["medium"]
     note(f"[parity] medium {precision}")
@@ -113,20 +115,26 @@ def test_ragged_right_hand_sides():
             assert oracle.rel_l2(s[b], so[b]) <= 1e-12
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
 def test_data_space_operator_columns(precision):
+    """Columns F F* e_j, each checked on its own (the first has its spike at
+    t = 0, the second at t = Nt - 1).  A BF16 spectrum does not meet 2e-3 on
+    early-spike columns (test_bf16_data_space_columns_at_L840); FP16 does."""
     w = synth.CONFIGS["medium"]
     note(f"[parity] F F* columns medium {precision}")
     idx = synth.hessian_column_indices(w, 4)
     e = synth.unit_data_vectors(w, idx)
     n = np.array([128, 128, 77, 128], dtype=np.int32)
     op, F = build_op(w, precision, max_rhs=4)
-    h = host(op.apply_FFt(to_dev(e, op)))
-    ho = oracle.data_space_hessian(F, e)
-    assert oracle.rel_l2(h, ho) <= TOL[precision]
-    h = host(op.apply_FFt(to_dev(e, op), nt_active=n))
-    ho = oracle.data_space_hessian(F, e, n)
-    assert oracle.rel_l2(h, ho) <= TOL[precision]
+    for nt in (None, n):
+        h = host(op.apply_FFt(to_dev(e, op), nt_active=nt))
+        ho = oracle.data_space_hessian(F, e, nt)
+        errs = [oracle.rel_l2(h[b], ho[b]) for b in range(len(idx))]
+        note("  per column " + " ".join(f"{x:.2e}" for x in errs))
+        assert max(errs) <= TOL[precision], errs
+    # one column alone takes the streaming path
+    h1 = host(op.apply_FFt(to_dev(e[:1], op)))
+    assert oracle.rel_l2(h1[0], oracle.data_space_hessian(F, e[:1])[0]) <= TOL[precision]
 
 
 # L = 840 (the paper's time shape): the length the library has compiled FFT
@@ -134,17 +142,14 @@ def test_data_space_operator_columns(precision):
 PAPER_T = synth.Workload("paper_t_small", Nd=5, Nm=203, Nt=420, tau=100.0)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
-def test_fixed_and_runtime_length_ffts(precision):
-    """Both FFT paths (kernels compiled for L = 840, and the runtime-length
-    ones) against the oracle on F, F*, F F* (truncate-and-repad), ragged
-    active lengths and the misfit epilogue; with a BF16 spectrum the batched
-    calls take the matrix cores and quad-stored spectra, and the two paths
-    must then also agree with each other to FP32 rounding."""
+def _l840_runs(precision):
+    """F, F*, ragged F and F*, F F* (truncate-and-repad) with its spikes at
+    t = 0, 419, 347, 350, ragged F F* and the misfit epilogue at L = 840, on
+    both FFT paths (kernels compiled for L = 840 and the runtime-length ones),
+    with the oracle's results."""
     w = PAPER_T
-    note(f"[parity] fixed vs runtime-length FFTs, {w.name} {precision}")
     n = np.array([420, 301, 64, 0], dtype=np.int32)
-    nh = np.array([300, 420, 400, 351], dtype=np.int32)   # the unit spikes sit at t = 0, 419, 347, 350
+    nh = np.array([300, 420, 400, 351], dtype=np.int32)
     op, F = build_op(w, precision, max_rhs=4)
     m = synth.param_series(w, 4)
     d = synth.data_series(w, 4)
@@ -154,7 +159,7 @@ def test_fixed_and_runtime_length_ffts(precision):
     ref = {"F": oracle.apply_F(F, m), "Ft": oracle.apply_Ft(F, d),
            "F_ragged": oracle.apply_F(F, m, n), "Ft_ragged": oracle.apply_Ft(F, d, n),
            "FFt": oracle.data_space_hessian(F, e), "FFt_ragged": oracle.data_space_hessian(F, e, nh)}
-    phi_o, g_o = oracle.misfit_and_grad(F, m[:2], d_obs, var)
+    ref["phi"], ref["grad"] = oracle.misfit_and_grad(F, m[:2], d_obs, var)
     got = {}
     for fixed in (True, False):
         op.set_fixed_fft(fixed)
@@ -166,34 +171,76 @@ def test_fixed_and_runtime_length_ffts(precision):
         r["phi"], r["grad"] = host(phi), host(g)
         got[fixed] = r
     for fixed, r in got.items():
-        for key, want in ref.items():
-            err = oracle.rel_l2(r[key], want)
+        for key in ("F", "Ft", "F_ragged", "Ft_ragged", "FFt", "FFt_ragged", "grad"):
+            want = ref[key]
             per_rhs = " ".join(f"{oracle.rel_l2(r[key][b], want[b]):.2e}" if np.any(want[b]) else "-"
-                               for b in range(len(n)))
-            note(f"  fixed={fixed} {key}: rel-L2 {err:.3e}  per rhs {per_rhs}")
-    # F F* chains two products: with a BF16 spectrum a single column at this
-    # size (5 sensors, 203 parameters) is not held to the one-product bound,
-    # as in test_data_space_operator_columns; the two paths must still agree.
-    checked = [k for k in ref if precision != "bf16" or not k.startswith("FFt")]
+                               for b in range(len(want)))
+            note(f"  fixed={fixed} {key}: per rhs {per_rhs}")
+    lens = {"F_ragged": n, "Ft_ragged": n, "FFt_ragged": nh}
+    return ref, got, lens
+
+
+def _per_rhs_errors(r, want):
+    return [oracle.rel_l2(r[b], want[b]) for b in range(len(want)) if np.any(want[b])]
+
+
+def _check_l840(precision, ref, got, lens, keys):
     for fixed, r in got.items():
-        for key in checked:
-            err = oracle.rel_l2(r[key], ref[key])
-            assert err <= TOL[precision], (key, fixed, err)
-        for key, lens in (("F_ragged", n), ("Ft_ragged", n), ("FFt_ragged", nh)):
-            for b, nb in enumerate(lens):
+        for key in keys:
+            errs = _per_rhs_errors(r[key], ref[key])
+            assert max(errs) <= TOL[precision], (key, fixed, errs)
+        for key, nl in lens.items():
+            for b, nb in enumerate(nl):
                 assert np.all(r[key][b, nb:] == 0.0), (key, fixed, b)
         for b in range(2):
-            assert abs(r["phi"][b] - phi_o[b]) <= TOL[precision] * phi_o[b]
-            assert oracle.rel_l2(r["grad"][b], g_o[b]) <= TOL[precision]
-    if precision == "bf16":
+            assert abs(r["phi"][b] - ref["phi"][b]) <= TOL[precision] * ref["phi"][b]
+            assert oracle.rel_l2(r["grad"][b], ref["grad"][b]) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_fixed_and_runtime_length_ffts(precision):
+    """Both FFT paths against the oracle on every result at L = 840, each
+    right-hand side (each F F* column) on its own; with an FP16 spectrum the
+    batched calls take the matrix cores, and the two paths must then also
+    agree with each other to FP32 rounding."""
+    note(f"[parity] fixed vs runtime-length FFTs, {PAPER_T.name} {precision}")
+    ref, got, lens = _l840_runs(precision)
+    _check_l840(precision, ref, got, lens, ("F", "Ft", "F_ragged", "Ft_ragged", "FFt", "FFt_ragged"))
+    if precision == "fp16":
         for key in got[True]:
-            agree = oracle.rel_l2(got[True][key], got[False][key])
-            note(f"  fixed vs runtime-length {key}: {agree:.3e}")
-            assert agree <= 1e-5, (key, agree)
+            assert oracle.rel_l2(got[True][key], got[False][key]) <= 1e-5, key
+
+
+def test_bf16_spectrum_at_L840():
+    """BF16 spectrum: F, F* (plain and ragged) and the misfit gradient meet
+    2e-3 per right-hand side on both FFT paths, and every result, the F F*
+    columns included, agrees between the two paths to FP32 rounding.  Its
+    F F* columns' error against the oracle is test_bf16_data_space_columns."""
+    note(f"[parity] fixed vs runtime-length FFTs, {PAPER_T.name} bf16")
+    ref, got, lens = _l840_runs("bf16")
+    _check_l840("bf16", ref, got, lens, ("F", "Ft", "F_ragged", "Ft_ragged"))
+    for key in got[True]:
+        agree = oracle.rel_l2(got[True][key], got[False][key])
+        note(f"  fixed vs runtime-length {key}: {agree:.3e}")
+        assert agree <= 1e-5, (key, agree)
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "A BF16 spectrum's rounding noise is spread evenly over all L lags of the operator, while the column "
+    "F F* e_j of a spike at t = 0 is concentrated near lag 0: its relative error grows like the square root "
+    "of the decay time (measured 6.3e-3 at tau = 100, L = 840).  Data-space columns meet 2e-3 with an FP16 "
+    "spectrum (test_fixed_and_runtime_length_ffts[fp16])."))
+def test_bf16_data_space_columns():
+    note(f"[parity] F F* columns {PAPER_T.name} bf16 (known to exceed 2e-3)")
+    ref, got, lens = _l840_runs("bf16")
+    for fixed, r in got.items():
+        for key in ("FFt", "FFt_ragged"):
+            errs = _per_rhs_errors(r[key], ref[key])
+            assert max(errs) <= TOL["bf16"], (key, fixed, errs)
 
 
 @pytest.mark.parametrize("var_kind", ["scalar", "sensor", "full"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16"])
 def test_misfit_and_gradient(precision, var_kind):
     w = synth.CONFIGS["medium"]
     note(f"[parity] misfit medium {precision} {var_kind}")
