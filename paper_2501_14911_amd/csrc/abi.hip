@@ -66,8 +66,22 @@ struct p2o_plan {
     int io_bytes = 0;          // element of m and d
     // spectrum store layout (bytes)
     size_t off_scales = 0, off_tw64 = 0, off_tw32 = 0, off_flag = 0, fhat_total = 0;
-    // workspace layout (bytes)
-    size_t off_X = 0, off_Y = 0, off_D = 0, off_P = 0, ws_total = 0;
+    // workspace layout (bytes), for max_rhs right-hand sides
+    struct Carve {
+        size_t off_X = 0, off_Y = 0, off_D = 0, off_P = 0, ws_total = 0;
+        // FP16 matrix-core operands: wavefront maxima and right-hand-side scales of X and Y
+        size_t off_A = 0, off_SX = 0, off_SY = 0;
+        int amax_slots = 0;
+    } carve;
+    size_t& off_X = carve.off_X;
+    size_t& off_Y = carve.off_Y;
+    size_t& off_D = carve.off_D;
+    size_t& off_P = carve.off_P;
+    size_t& ws_total = carve.ws_total;
+    size_t& off_A = carve.off_A;
+    size_t& off_SX = carve.off_SX;
+    size_t& off_SY = carve.off_SY;
+    int& amax_slots = carve.amax_slots;
     // kernel configuration
     int fwd_rows = 64, fwd_nslab = 1, fwd_chunks = 1;
     int adj_rows = 1, adj_nslab = 1;
@@ -181,6 +195,13 @@ void layout(p2o_plan* p) {
     p->off_D = align_up(p->off_Y + ylen * p->cbytes);
     p->off_P = align_up(p->off_D + R * (size_t)p->Nt * (size_t)p->Nd * p->io_bytes);
     p->ws_total = align_up(p->off_P + R * (size_t)p->c2r_nd_blocks * sizeof(double));
+    if (p->prec == kFP16) {
+        p->amax_slots = fft_amax_slots((int)std::max<int64_t>(p->pitch, gemm_data_pitch((int)p->Nd)));
+        p->off_A = p->ws_total;
+        p->off_SX = align_up(p->off_A + R * (size_t)p->amax_slots * sizeof(float));
+        p->off_SY = align_up(p->off_SX + R * sizeof(float));
+        p->ws_total = align_up(p->off_SY + R * sizeof(float));
+    }
 }
 
 p2o_status ready_for_apply(const p2o_plan* p, const void* a, const void* b, int64_t nrhs) {
@@ -275,7 +296,26 @@ GemmArgs gemm_args(const p2o_plan* p, int64_t nrhs) {
     ga.nblk = (int)p->nblk;
     ga.part_stride = p->nfreq * nrhs * p->Nd;
     ga.a_f16 = p->prec == kFP16;
+    ga.rhs_scale = nullptr;
     return ga;
+}
+
+float* scale_X(const p2o_plan* p) { return reinterpret_cast<float*>(p->ws + p->off_SX); }
+float* scale_Y(const p2o_plan* p) { return reinterpret_cast<float*>(p->ws + p->off_SY); }
+
+// Operands of the matrix-core products written by a transform: quad BF16
+// hi/lo for a BF16 spectrum; complex FP32 with wavefront maxima and
+// per-right-hand-side scales (into `scale`) for an FP16 spectrum.
+void rhs_operand(const p2o_plan* p, int64_t nrhs, SeriesIO& io, float* scale) {
+    if (!mfma_on(p, nrhs)) return;
+    if (p->prec == kFP16) {
+        io.quad = 0;
+        io.amax_part = reinterpret_cast<float*>(p->ws + p->off_A);
+        io.amax_slots = p->amax_slots;
+        io.rhs_scale = scale;
+    } else {
+        io.quad = 1;
+    }
 }
 
 // matrix-core tile variant for a call with nrhs right-hand sides
@@ -289,8 +329,9 @@ int gemm_tile_for(const p2o_plan* p, const std::map<int64_t, int>& tuned, int64_
 p2o_status enqueue_fwd_products(p2o_plan* p, const void* X, void* Y, int64_t nrhs) {
     if (mfma_on(p, nrhs))
         return staged(p, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores)", [&] {
-            return launch_gemm_fwd(gemm_args(p, nrhs), gemm_tile_for(p, p->tuned_fwd, nrhs), p->fhat, scales_of(p), X,
-                                   Y, p->stream);
+            GemmArgs ga = gemm_args(p, nrhs);
+            ga.rhs_scale = scale_X(p);
+            return launch_gemm_fwd(ga, gemm_tile_for(p, p->tuned_fwd, nrhs), p->fhat, scales_of(p), X, Y, p->stream);
         });
     return staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
         return launch_gemv_fwd(p->prec, gemv_args(p, nrhs, true), p->fhat, scales_of(p), X, Y, p->stream);
@@ -301,23 +342,25 @@ p2o_status enqueue_fwd_products(p2o_plan* p, const void* X, void* Y, int64_t nrh
 p2o_status enqueue_adj_products(p2o_plan* p, const void* Y, void* X, int64_t nrhs) {
     if (mfma_on(p, nrhs))
         return staged(p, P2O_STAGE_GEMM_ADJ, "adjoint per-frequency products (matrix cores)", [&] {
-            return launch_gemm_adj(gemm_args(p, nrhs), gemm_tile_for(p, p->tuned_adj, nrhs), p->fhat, scales_of(p), Y,
-                                   X, p->stream);
+            GemmArgs ga = gemm_args(p, nrhs);
+            ga.rhs_scale = scale_Y(p);
+            return launch_gemm_adj(ga, gemm_tile_for(p, p->tuned_adj, nrhs), p->fhat, scales_of(p), Y, X, p->stream);
         });
     return staged(p, P2O_STAGE_GEMV_ADJ, "adjoint per-frequency products", [&] {
         return launch_gemv_adj(p->prec, gemv_args(p, nrhs, false), p->fhat, scales_of(p), Y, X, p->stream);
     });
 }
 
-// parameter spectra for the products: quad storage on the matrix-core path
+// parameter spectra for the forward products (matrix-core operand form on
+// that path)
 SeriesIO io_param_rhs(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active, int nparts) {
     SeriesIO io = io_param(p, nrhs, nt_active, nparts);
-    io.quad = mfma_on(p, nrhs) ? 1 : 0;
+    rhs_operand(p, nrhs, io, scale_X(p));
     return io;
 }
 
-// data spectra for the adjoint products: on the matrix-core path in quad
-// storage, rows padded with zeros to gemm_data_pitch(Nd)
+// data spectra for the adjoint products: on the matrix-core path in operand
+// form, rows padded with zeros to gemm_data_pitch(Nd)
 SeriesIO io_data_rhs(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active) {
     SeriesIO io = io_data(p, nrhs, nt_active, 1);
     if (mfma_on(p, nrhs)) {
@@ -326,7 +369,7 @@ SeriesIO io_data_rhs(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active) 
         io.f_outer = ld;
         io.f_part = p->nfreq * nrhs * ld;
         io.S_pad = ld;
-        io.quad = 1;
+        rhs_operand(p, nrhs, io, scale_Y(p));
     }
     return io;
 }
@@ -349,6 +392,16 @@ p2o_status enqueue_adjoint_to_X(p2o_plan* p, const void* d, int64_t nrhs, const 
     });
     if (s) return s;
     return enqueue_adj_products(p, Y, X, nrhs);
+}
+
+p2o_status enqueue_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const int32_t* nt_active) {
+    p->cur_nrhs = nrhs;
+    p2o_status s = enqueue_forward_to_Y(p, m, nrhs, nt_active);
+    if (s) return s;
+    return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
+        return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, d,
+                          tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
+    });
 }
 
 }  // namespace
@@ -493,21 +546,31 @@ p2o_status p2o_autotune(p2o_plan* p, int64_t nrhs, int32_t reps, int32_t* fwd_ti
         void* Y = p->ws + p->off_Y;
         p2o_status s = check_hip(launch_fill_bf16(X, p->off_D - p->off_X, 0x5EEDu, p->stream), "autotune operand fill");
         if (s) return s;
+        if (p->prec == kFP16) {
+            // FP16 plans read the operands as complex FP32 (the words above are
+            // finite, magnitudes in [1/2, 1)) with unit right-hand-side scales
+            s = check_hip(launch_fill_f32(scale_X(p), (size_t)p->max_rhs, 1.f, p->stream), "autotune scale fill");
+            if (!s) s = check_hip(launch_fill_f32(scale_Y(p), (size_t)p->max_rhs, 1.f, p->stream), "autotune scale fill");
+            if (s) return s;
+        }
         hipEvent_t a = nullptr, b = nullptr;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
             if (a) (void)hipEventDestroy(a);
             return fail(P2O_ERR_HIP, "event creation failed");
         }
-        const GemmArgs ga = gemm_args(p, nrhs);
+        GemmArgs gf = gemm_args(p, nrhs), gb = gemm_args(p, nrhs);
+        gf.rhs_scale = scale_X(p);                      // the forward reads X, the adjoint Y
+        gb.rhs_scale = scale_Y(p);
+        const bool a_f16 = gf.a_f16 != 0;
         double best[2] = {1e300, 1e300};
         int pick[2] = {-1, -1};
         for (int dir = 0; dir < 2 && !s; ++dir) {
             if (dir == 1) s = check_hip(launch_fill_bf16(Y, p->off_D - p->off_Y, 0xADu, p->stream), "autotune operand fill");
             for (int t = 0; t < gemm_tile_count() && !s; ++t) {
-                if (!gemm_tile_has(t, dir == 0) || (ga.a_f16 && !gemm_tile_is_ring(t))) continue;
+                if (!gemm_tile_has(t, dir == 0) || (a_f16 && !gemm_tile_is_ring(t))) continue;
                 auto run = [&]() {
-                    return dir == 0 ? launch_gemm_fwd(ga, t, p->fhat, scales_of(p), X, Y, p->stream)
-                                    : launch_gemm_adj(ga, t, p->fhat, scales_of(p), Y, X, p->stream);
+                    return dir == 0 ? launch_gemm_fwd(gf, t, p->fhat, scales_of(p), X, Y, p->stream)
+                                    : launch_gemm_adj(gb, t, p->fhat, scales_of(p), Y, X, p->stream);
                 };
                 s = check_hip(run(), "autotune warm-up launch");
                 if (s) break;
@@ -717,13 +780,7 @@ p2o_status p2o_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const 
     try {
         p2o_status s = ready_for_apply(p, m, d, nrhs);
         if (s) return s;
-        p->cur_nrhs = nrhs;
-        s = enqueue_forward_to_Y(p, m, nrhs, nt_active);
-        if (s) return s;
-        return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, d,
-                              tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
-        });
+        return enqueue_apply_F(p, m, d, nrhs, nt_active);
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_apply_F");
     }

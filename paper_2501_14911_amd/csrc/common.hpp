@@ -183,6 +183,21 @@ struct SeriesIO {
     int Nt;                  // time steps
     int outer_count;
     const int* nt_active;    // per outer index, or nullptr
+    // Right-hand-side scales of the FP16 matrix-core products (FP32 spectra
+    // only, or nullptr): the producing transform writes the largest |re|,
+    // |im| it stores per (outer index, tile, wavefront) to amax_part (at most
+    // amax_slots slots per outer index), then rhs_scale[outer] receives the
+    // power of two that maps that outer index's maximum into (2^14, 2^15].
+    float* amax_part;
+    float* rhs_scale;
+    int amax_slots;
 };
+
+// Largest |re|, |im| of a wavefront's values, written by lane 0 to slot[wave].
+__device__ __forceinline__ void wave_amax_store(float v, float* slot) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = v;
+}
 
 }  // namespace p2o

@@ -216,7 +216,7 @@ __device__ __forceinline__ void load_spec(cplx<T>* buf, int twsh, int M, const c
 // with io.quad (FP32 only), in quad BF16 hi/lo storage.
 template <typename T>
 __device__ __forceinline__ void store_half_spectra(const cplx<T>* buf, int twsh, int M, const cplx<T>* tw,
-                                                   const SeriesIO& io, cplx<T>* row, int s0) {
+                                                   const SeriesIO& io, cplx<T>* row, int s0, float* amax_slot) {
     using Z = cplx<T>;
     if constexpr (sizeof(T) == sizeof(float)) {
         if (io.quad) {
@@ -228,9 +228,51 @@ __device__ __forceinline__ void store_half_spectra(const cplx<T>* buf, int twsh,
         }
     }
     Z* dst = row + s0;
+    float vmax = 0.f;
     r2c_post<T>(buf, twsh, M, tw, [&](int k, int s, Z X) {
-        if (s0 + s < io.S_pad) dst[(long long)k * io.f_stride + s] = X;
+        if (s0 + s < io.S_pad) {
+            dst[(long long)k * io.f_stride + s] = X;
+            if constexpr (sizeof(T) == sizeof(float)) vmax = fmaxf(vmax, fmaxf(fabsf(X.x), fabsf(X.y)));
+        }
     });
+    // FP16 matrix-core operands: each wavefront's largest |re|, |im|
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (amax_slot) wave_amax_store(vmax, amax_slot);
+    }
+}
+
+__device__ __forceinline__ float* amax_slots_of(const SeriesIO& io, int outer, int tile) {
+    return io.amax_part ? io.amax_part + (long long)outer * io.amax_slots + tile * (kFftThreads / 64) : nullptr;
+}
+
+// Right-hand-side scales from the wavefront maxima of one transform: block b
+// reduces the `slots` maxima of outer index b and writes the power of two
+// 2^(15 - ceil(log2 max)) (1 for an all-zero or non-finite maximum; the
+// exponent is clamped to the FP32 range), so that max * scale lies in
+// (2^14, 2^15]: every scaled value then fits FP16, and values far below the
+// maximum keep an absolute precision of 2^-25 of the scaled unit.
+__global__ void k_rhs_scale(const float* __restrict__ part, int slots, int stride, float* __restrict__ scale) {
+    __shared__ float red[256];
+    const float* p = part + (long long)blockIdx.x * stride;
+    float v = 0.f;
+    for (int i = threadIdx.x; i < slots; i += 256) v = fmaxf(v, p[i]);
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float a = red[0];
+        float sc = 1.f;
+        if (a > 0.f && a <= 3.0e38f) {
+            int e;
+            const float f = frexpf(a, &e);                 // a = f 2^e, f in [1/2, 1)
+            const int c = f == 0.5f ? e - 1 : e;           // ceil(log2 a)
+            sc = ldexpf(1.f, max(-126, min(126, 15 - c)));
+        }
+        scale[blockIdx.x] = sc;
+    }
 }
 
 // ---------------------------------------------------------------- kernels
@@ -251,7 +293,8 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c(FftPlan pl, SeriesIO io, co
     load_time<T, TIN>(buf, twsh, pl.M, in + (long long)outer * io.t_outer, io.t_stride, io.S, s0, nt);
     __syncthreads();
     fft_tile<T, false>(buf, twsh, pl, tw);
-    store_half_spectra<T>(buf, twsh, pl.M, tw, io, out + (long long)outer * io.f_outer, s0);
+    store_half_spectra<T>(buf, twsh, pl.M, tw, io, out + (long long)outer * io.f_outer, s0,
+                          amax_slots_of(io, outer, tile));
 }
 
 // c2r: half spectra (sum of nparts partials) -> time series, truncated to Nt
@@ -355,7 +398,7 @@ __global__ __launch_bounds__(kFftThreads) void k_project(FftPlan pl, SeriesIO io
     }
     __syncthreads();
     fft_tile<T, false>(buf, twsh, pl, tw);
-    store_half_spectra<T>(buf, twsh, pl.M, tw, io, base, s0);
+    store_half_spectra<T>(buf, twsh, pl.M, tw, io, base, s0, amax_slots_of(io, outer, tile));
 }
 
 // Fixed-order sum of the misfit partials: misfit[b] = 1/2 sum_x partials[b][x].
@@ -531,12 +574,29 @@ hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
-                      const void* tw, hipStream_t st) {
+// After a transform that recorded wavefront maxima: the per-outer scales,
+// from the slots of its tiles (tile shift sh, four wavefronts per tile on
+// both the compiled-length and the runtime-length kernels).
+static hipError_t rhs_scales(const SeriesIO& io, int sh, hipError_t err, hipStream_t st) {
+    if (err != hipSuccess || !io.amax_part || io.outer_count == 0) return err;
+    static_assert(kFftThreads == 256, "four wavefronts per tile");
+    const int used = ((io.S_pad + (1 << sh) - 1) >> sh) * 4;
+    hipLaunchKernelGGL(k_rhs_scale, dim3(io.outer_count), dim3(256), 0, st, (const float*)io.amax_part, used,
+                       io.amax_slots, io.rhs_scale);
+    return hipGetLastError();
+}
+
+// Wavefront-maximum slots per outer index that the transforms of S_pad
+// series need at most (tiles of at least 4 series, 256-thread workgroups).
+int fft_amax_slots(int S_pad) { return (S_pad + 3) / 4 * (kFftThreads / 64); }
+
+static hipError_t r2c_transform(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in,
+                                void* out, const void* tw, hipStream_t st) {
     const int sh = fft_tile_shift(pl.M, f64);
     hipError_t err;
     if (launch_fixed_r2c(f64, in_f64, pl, io, in, out, tw, sh, st, &err)) return err;
     const ItemMap im = item_map(io.S_pad, sh, io.outer_count);
+    if (io.amax_part && (long long)im.ntiles * (kFftThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
     dim3 grid(8 * im.Q);
     if (f64) {
         const size_t lds = fft_lds(pl.M, sh, sizeof(double2));
@@ -547,6 +607,11 @@ hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& 
         hipLaunchKernelGGL((k_r2c<float, float>), grid, dim3(kFftThreads), lds, st, pl, io, (const float*)in, (float2*)out, (const float2*)tw, sh, im);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
+                      const void* tw, hipStream_t st) {
+    return rhs_scales(io, fft_tile_shift(pl.M, f64), r2c_transform(f64, in_f64, pl, io, in, out, tw, st), st);
 }
 
 hipError_t launch_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
@@ -577,16 +642,22 @@ int c2r_grid_x(const FftPlan& pl, bool f64, int S) {
     return (S + (1 << sh) - 1) >> sh;
 }
 
-hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
-                          hipStream_t st) {
+static hipError_t project_transform(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
+                                    hipStream_t st) {
     const int sh = fft_tile_shift(pl.M, f64);
     hipError_t err;
     if (launch_fixed_project(f64, pl, io, in_out, tw, sh, st, &err)) return err;
     const ItemMap im = item_map(io.S_pad, sh, io.outer_count);
+    if (io.amax_part && (long long)im.ntiles * (kFftThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
     dim3 grid(8 * im.Q);
     if (f64) hipLaunchKernelGGL((k_project<double>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(double2)), st, pl, io, (double2*)in_out, (const double2*)tw, sh, im);
     else hipLaunchKernelGGL((k_project<float>), grid, dim3(kFftThreads), fft_lds(pl.M, sh, sizeof(float2)), st, pl, io, (float2*)in_out, (const float2*)tw, sh, im);
     return hipGetLastError();
+}
+
+hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
+                          hipStream_t st) {
+    return rhs_scales(io, fft_tile_shift(pl.M, f64), project_transform(f64, pl, io, in_out, tw, st), st);
 }
 
 hipError_t launch_misfit_reduce(const double* partials, int nper, double* misfit, int nrhs, hipStream_t st) {

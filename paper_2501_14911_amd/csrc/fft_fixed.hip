@@ -326,9 +326,11 @@ __device__ __forceinline__ void load_pre(cplx<T>* buf, const cplx<T>* twq, const
 // bytes per lane, a quarter of the store instructions of per-word stores
 // (measured: r2c at 64 RHS 8 % faster; the re-pad, whose time is its
 // arithmetic, 1 % slower, so it stores per word).
+// With amax_slot (FP32 complex output only), each wavefront's largest |re|,
+// |im| of the values it stores goes to amax_slot[wavefront].
 template <typename T, int M, int SH, bool STAGED>
 __device__ __forceinline__ void post_store(cplx<T>* buf, const cplx<T>* twq, const SeriesIO& io, cplx<T>* row,
-                                           int s0, int s, int j0) {
+                                           int s0, int s, int j0, float* amax_slot) {
     using Z = cplx<T>;
     using G = Geo<M, SH>;
     constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
@@ -396,8 +398,10 @@ __device__ __forceinline__ void post_store(cplx<T>* buf, const cplx<T>* twq, con
     // bins k = j0 + u JS and M - k from base rows u JS and M - (JS - 1) - u JS
     uint32_t oa = (uint32_t)j0 * fs + lo_, ob = (uint32_t)(JS - 1 - j0) * fs + lo_;
     asm volatile("" : "+v"(oa), "+v"(ob));
+    float vmax = 0.f;
     auto put = [&](Z* rbase, uint32_t off, Z X) {
         if constexpr (sizeof(T) == sizeof(float)) {
+            vmax = fmaxf(vmax, fmaxf(fabsf(X.x), fabsf(X.y)));
             if (quad) {
                 const uint32_t hi = pack_bf16_rne(X.x, X.y);
                 const uint32_t lo = pack_bf16_rne(X.x - __uint_as_float(hi << 16), X.y - __uint_as_float(hi & 0xffff0000u));
@@ -424,6 +428,16 @@ __device__ __forceinline__ void post_store(cplx<T>* buf, const cplx<T>* twq, con
             }
         }
     }
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (amax_slot) wave_amax_store(vmax, amax_slot);
+    }
+}
+
+static_assert(kFxThreads == 256, "four wavefront-maximum slots per tile, as in the runtime-length kernels");
+
+// Slots of this tile's wavefront maxima, or nullptr.
+__device__ __forceinline__ float* amax_slots_of(const SeriesIO& io, int outer, int tile) {
+    return io.amax_part ? io.amax_part + (long long)outer * io.amax_slots + tile * (kFxThreads / 64) : nullptr;
 }
 
 // ---------------------------------------------------------------- kernels
@@ -457,7 +471,8 @@ __global__ __launch_bounds__(kFxThreads) void k_r2c_fx(SeriesIO io, const TIN* _
         first_pass_from_time<T, TIN, M, SH>(buf, in + (long long)outer * io.t_outer + s0, io.t_stride,
                                             s0 + s < io.S, nt, s, j0);
         static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
-        post_store<T, M, SH, true>(buf, twq, io, out + (long long)outer * io.f_outer, s0, s, j0);
+        post_store<T, M, SH, true>(buf, twq, io, out + (long long)outer * io.f_outer, s0, s, j0,
+                                   amax_slots_of(io, outer, tile));
         __syncthreads();
     }
 }
@@ -628,7 +643,7 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>*
         }
         __syncthreads();
         static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
-        post_store<T, M, SH, false>(buf, twq, io, base, s0, s, j0);
+        post_store<T, M, SH, false>(buf, twq, io, base, s0, s, j0, amax_slots_of(io, outer, tile));
         __syncthreads();
     }
 }
@@ -669,6 +684,7 @@ template <typename T, int M, int SH>
 hipError_t fx_r2c(bool in_f64, const SeriesIO& io, const void* in, void* out, const void* tw, hipStream_t st) {
     const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
+    if (io.amax_part && (long long)im.ntiles * (kFxThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
     const size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 1);
     if (in_f64) {
         constexpr auto k = k_r2c_fx<T, double, M, SH>;
@@ -705,6 +721,7 @@ template <typename T, int M, int SH>
 hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStream_t st) {
     const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
+    if (io.amax_part && (long long)im.ntiles * (kFxThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
     const size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 2);
     constexpr auto k = k_project_fx<T, M, SH>;
     hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (cplx<T>*)in_out, (const cplx<T>*)tw, im);

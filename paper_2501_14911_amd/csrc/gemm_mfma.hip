@@ -12,11 +12,18 @@
 // the forms cost a fraction of what forms of the spectrum would):
 //   forward  y_r = (a_r, a_i) . (x_r, -x_i)   y_i = (a_r, a_i) . (x_i, x_r)
 //   adjoint  x_r = (a_r, a_i) . (y_r,  y_i)   x_i = (a_r, a_i) . (y_i, -y_r)
-// (the adjoint takes conj(F)^T).  Right-hand sides arrive as quad BF16 hi/lo
-// storage (written by the FFT that produced them); hi and lo each go through
-// the matrix cores, giving about 16 significant bits of x with FP32
-// accumulation.  The per-(frequency, 4096-column block) power-of-two scale of
-// the stored spectrum multiplies finished outputs (exact).
+// (the adjoint takes conj(F)^T).  With a BF16 spectrum the right-hand sides
+// arrive as quad BF16 hi/lo storage (written by the FFT that produced them);
+// hi and lo each go through the matrix cores, giving about 16 significant
+// bits of x with FP32 accumulation.  With an FP16 spectrum (LDS-ring kernels
+// only) they arrive as complex FP32, and each fragment is rounded to FP16
+// after multiplying by its right-hand side's power-of-two scale (which maps
+// that right-hand side's largest entry into (2^14, 2^15]), one
+// v_mfma_f32_32x32x16_f16 per form: half the matrix-core work of the BF16
+// hi + lo products, at FP16's 11 significant bits on both operands.  The
+// per-(frequency, 4096-column block) power-of-two scale of the stored
+// spectrum, and the inverse right-hand-side scale, multiply finished outputs
+// (exact).
 //
 // Work.  A workgroup is NW (4 or 8) wavefronts: RG row groups x (NW / RG)
 // halves of the right-hand sides, each wavefront computing MB (4 or 5) blocks
@@ -68,20 +75,23 @@ __device__ __forceinline__ uint4 f_nswap(uint4 a) {                      // (im,
                       w_swap(a.w) ^ 0x80000000u);
 }
 
-// An FP16 spectrum fragment (words of (re, im) FP16) as the exact sum of two
-// BF16 fragments: FP16 carries 11 significant bits, the BF16 rounding of an
-// entry keeps 8 and the remainder (at most 3 more) is exact in BF16.
-__device__ __forceinline__ uint32_t w_f16_hi(uint32_t w, uint32_t& lo) {
-    const float re = f16lo(w), im = f16hi(w);
-    const uint32_t hi = pack_bf16_rne(re, im);
-    lo = pack_bf16_rne(re - __uint_as_float(hi << 16), im - __uint_as_float(hi & 0xffff0000u));
-    return hi;
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f32x16 mfma32h(uint4 a, uint4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0,
+                                                  0);
 }
-__device__ __forceinline__ void f_split_f16(uint4 a, uint4& hi, uint4& lo) {
-    hi.x = w_f16_hi(a.x, lo.x);
-    hi.y = w_f16_hi(a.y, lo.y);
-    hi.z = w_f16_hi(a.z, lo.z);
-    hi.w = w_f16_hi(a.w, lo.w);
+
+// (re, im) FP32 -> one word of two FP16 (nearest even, one v_cvt_pk_f16_f32),
+// after multiplying by the right-hand side's scale s (a power of two: exact).
+__device__ __forceinline__ uint32_t w_f16(uint32_t re, uint32_t im, float s) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{__uint_as_float(re) * s,
+                                                                        __uint_as_float(im) * s}, f16x2));
+}
+// Four consecutive complex FP32 values (two 16-byte parts) as an FP16 fragment.
+__device__ __forceinline__ uint4 f_rhs_f16(uint4 p0, uint4 p1, float s) {
+    return make_uint4(w_f16(p0.x, p0.y, s), w_f16(p0.z, p0.w, s), w_f16(p1.x, p1.y, s), w_f16(p1.z, p1.w, s));
 }
 
 __device__ __forceinline__ int xcd_item(int id, int Q) { return (id & 7) * Q + (id >> 3); }
@@ -385,10 +395,10 @@ __device__ __forceinline__ void dma16(const uint8_t* base, uint32_t off, uint32_
     asm volatile("global_load_lds_dwordx4 %0, %1" : : "v"(off), "s"(base), "{m0}"(lds) : "memory");
 }
 
-// F16A: the spectrum is stored in FP16; each fragment is split into BF16
-// hi + lo and takes three products per right-hand-side form (the lo x lo
-// term is below the FP32 accumulation's rounding).
-template <int NH, bool F16A>
+// F16: the spectrum is stored in FP16 and the right-hand sides in complex
+// FP32 with per-right-hand-side scales (rhs_scale); fragments are rounded to
+// FP16 in registers and take one FP16 product per form.
+template <int NH, bool F16>
 __global__ __launch_bounds__(256 * NH) __attribute__((amdgpu_waves_per_eu(NH)))
 void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
                      float2* __restrict__ out_base, GemmArgs ga) {
@@ -475,19 +485,27 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         for (int mb = 0; mb < MB; ++mb)
             f.a[mb] = *reinterpret_cast<const uint4*>(&ring_a[slot][((rg * MB + mb) * 32 + r) * 64 + cs]);
     };
+    // FP16: this lane's right-hand side 32 nh + r (its B fragments, and its outputs)
+    float rs = 1.f;
+    if constexpr (F16) rs = ga.rhs_scale[min(b0 + 32 * nh + r, ga.nrhs - 1)];
     auto mfmas = [&](const Frags& f) {
-        const uint4 bh_r = f_conj(f.bh), bh_i = f_swap(f.bh), bl_r = f_conj(f.bl), bl_i = f_swap(f.bl);
+        if constexpr (F16) {
+            // parts ph and ph + 1 hold entries 4 g .. 4 g + 3 as complex FP32
+            const uint4 bx = f_rhs_f16(f.bh, f.bl, rs);
+            const uint4 b_r = f_conj(bx), b_i = f_swap(bx);
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            uint4 a = f.a[mb], al;
-            if constexpr (F16A) f_split_f16(f.a[mb], a, al);
-            accr[mb] = mfma32(a, bh_r, accr[mb]);
-            acci[mb] = mfma32(a, bh_i, acci[mb]);
-            accr[mb] = mfma32(a, bl_r, accr[mb]);
-            acci[mb] = mfma32(a, bl_i, acci[mb]);
-            if constexpr (F16A) {
-                accr[mb] = mfma32(al, bh_r, accr[mb]);
-                acci[mb] = mfma32(al, bh_i, acci[mb]);
+            for (int mb = 0; mb < MB; ++mb) {
+                accr[mb] = mfma32h(f.a[mb], b_r, accr[mb]);
+                acci[mb] = mfma32h(f.a[mb], b_i, acci[mb]);
+            }
+        } else {
+            const uint4 bh_r = f_conj(f.bh), bh_i = f_swap(f.bh), bl_r = f_conj(f.bl), bl_i = f_swap(f.bl);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                accr[mb] = mfma32(f.a[mb], bh_r, accr[mb]);
+                acci[mb] = mfma32(f.a[mb], bh_i, acci[mb]);
+                accr[mb] = mfma32(f.a[mb], bl_r, accr[mb]);
+                acci[mb] = mfma32(f.a[mb], bl_i, acci[mb]);
             }
         }
     };
@@ -520,7 +538,7 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
 
     const int b = b0 + 32 * nh + r;
     if (b >= ga.nrhs) return;
-    const float sc = scales[(long long)w * ga.nblk + kbeg / kScaleBlock];
+    const float sc = scales[(long long)w * ga.nblk + kbeg / kScaleBlock] / rs;
     float2* out = out_base + (long long)kc * ga.part_stride + ((long long)w * ga.nrhs + b) * ga.Nd;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -547,7 +565,7 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
 // every step is whole; sensor rows past Nd read row Nd - 1 and columns past
 // the pitch read its last entries (valid addresses), and a substep that
 // starts at or past Nd is skipped (its data rows are zero).
-template <int RG, int MB, int NH, bool F16A>
+template <int RG, int MB, int NH, bool F16>
 __global__ __launch_bounds__(64 * RG * NH) __attribute__((amdgpu_waves_per_eu(2)))
 void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
                      float2* __restrict__ out_base, GemmArgs ga) {
@@ -645,22 +663,30 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
                                  *reinterpret_cast<const uint32_t*>(p + 3 * A_RS));
         }
     };
+    // FP16: this lane's right-hand side 32 nh + r (its B fragments, and its outputs)
+    float rs = 1.f;
+    if constexpr (F16) rs = ga.rhs_scale[min(b0 + 32 * nh + r, ga.nrhs - 1)];
     auto mfmas = [&](const Frags& f) {
-        const uint4 bh_i = f_nswap(f.bh), bl_i = f_nswap(f.bl);
+        if constexpr (F16) {
+            const uint4 bx = f_rhs_f16(f.bh, f.bl, rs);
+            const uint4 b_i = f_nswap(bx);
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            uint4 a = f.a[mb], al;
-            if constexpr (F16A) f_split_f16(f.a[mb], a, al);
-            accr[mb] = mfma32(a, f.bh, accr[mb]);
-            acci[mb] = mfma32(a, bh_i, acci[mb]);
-            accr[mb] = mfma32(a, f.bl, accr[mb]);
-            acci[mb] = mfma32(a, bl_i, acci[mb]);
-            if constexpr (F16A) {
-                accr[mb] = mfma32(al, f.bh, accr[mb]);
-                acci[mb] = mfma32(al, bh_i, acci[mb]);
+            for (int mb = 0; mb < MB; ++mb) {
+                accr[mb] = mfma32h(f.a[mb], bx, accr[mb]);
+                acci[mb] = mfma32h(f.a[mb], b_i, acci[mb]);
+            }
+        } else {
+            const uint4 bh_i = f_nswap(f.bh), bl_i = f_nswap(f.bl);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                accr[mb] = mfma32(f.a[mb], f.bh, accr[mb]);
+                acci[mb] = mfma32(f.a[mb], bh_i, acci[mb]);
+                accr[mb] = mfma32(f.a[mb], f.bl, accr[mb]);
+                acci[mb] = mfma32(f.a[mb], bl_i, acci[mb]);
             }
         }
     };
+    const float irs = 1.f / rs;                           // exact: rs is a power of two
 
 #pragma unroll
     for (int d = 0; d < RING - 1; ++d) issue(d, d);
@@ -693,7 +719,7 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
                     const int cb = (rg * MB + mb) * 32;   // an m block lies in one 4096-column scale block
-                    const float sc = scales[(long long)w * ga.nblk + min(m0 + cb, ga.ncols - 1) / kScaleBlock];
+                    const float sc = scales[(long long)w * ga.nblk + min(m0 + cb, ga.ncols - 1) / kScaleBlock] * irs;
 #pragma unroll
                     for (int v = 0; v < 16; ++v) {
                         const int c = cb - c0 + 8 * (v >> 2) + 4 * kg + (v & 3);
@@ -726,7 +752,7 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         for (int mb = 0; mb < MB; ++mb) {
             const int jb = m0 + (rg * MB + mb) * 32;        // an m block lies in one 4096-column scale block
             if (jb >= ga.ncols) continue;
-            const float sc = scales[(long long)w * ga.nblk + jb / kScaleBlock];
+            const float sc = scales[(long long)w * ga.nblk + jb / kScaleBlock] * irs;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int j = jb + 8 * (v >> 2) + 4 * kg + (v & 3);
@@ -753,6 +779,16 @@ hipError_t launch_fill_bf16(void* p, size_t bytes, uint32_t seed, hipStream_t st
     const size_t n = bytes / 4;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_bf16, dim3(2048), dim3(256), 0, st, (uint32_t*)p, n, seed);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, size_t n, float v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)std::min<size_t>(1024, (n + 255) / 256)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 
@@ -875,6 +911,7 @@ int gemm_default_tile(int nrhs, bool fwd) { return nrhs > 32 ? (fwd ? 7 : 9) : (
 
 hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Xq,
                            void* Yp, hipStream_t st) {
+    if (in.a_f16 && !in.rhs_scale) return hipErrorInvalidValue;      // FP16 products read per-RHS scales
     GemmArgs ga = in;
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
@@ -896,6 +933,7 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
 
 hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Yq,
                            void* Xp, hipStream_t st) {
+    if (in.a_f16 && !in.rhs_scale) return hipErrorInvalidValue;      // FP16 products read per-RHS scales
     GemmArgs ga = in;
     ga.ldb = gemm_data_pitch(ga.Nd);
     ga.kchunk = 0;

@@ -27,6 +27,7 @@ struct GemmArgs {
     int nblk;
     long long part_stride;  // complex elements between forward partial outputs
     int a_f16;              // spectrum words are FP16 (re, im) pairs (BF16 otherwise); LDS-ring tiles only
+    const float* rhs_scale; // FP16 spectra: per-right-hand-side power-of-two scales of the complex FP32 operand
     // filled in by the launcher
     int ldb;                // complex values per right-hand-side row of the quad B operand
     int kchunk;             // complex columns per forward K chunk
@@ -63,6 +64,7 @@ hipError_t launch_load(int prec, bool in_f64, const FftPlan& pl, const LoadArgs&
                        const void* tw64, hipStream_t st);
 hipError_t launch_zero_pad(void* fhat, long long rows, int pitch, int Nm, int bytes, hipStream_t st);
 int load_tile_shift(int M);
+int fft_amax_slots(int S_pad);   // wavefront-maximum slots per outer index a transform of S_pad series needs
 
 // fft_fixed.hip: kernels compiled for fixed transform lengths.  Each returns
 // false when there is none for (M, tile shift, precision) or the plan turned
@@ -96,6 +98,7 @@ int gemm_default_tile(int nrhs, bool fwd);
 bool gemm_tile_is_ring(int tile);           // an LDS-ring variant (the only ones for FP16 spectra)
 bool gemm_f16_fits(int Nd, int pitch);      // shapes the FP16-spectrum ring kernels can address
 hipError_t launch_fill_bf16(void* p, size_t bytes, uint32_t seed, hipStream_t st);   // timing operands
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
 // tile: a variant index, or -1 for the built-in choice
 hipError_t launch_gemm_fwd(const GemmArgs& ga, int tile, const void* fhat, const float* scales, const void* Xq,
                            void* Yp, hipStream_t st);

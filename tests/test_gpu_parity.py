@@ -207,8 +207,11 @@ def test_fixed_and_runtime_length_ffts(precision):
     ref, got, lens = _l840_runs(precision)
     _check_l840(precision, ref, got, lens, ("F", "Ft", "F_ragged", "Ft_ragged", "FFt", "FFt_ragged"))
     if precision == "fp16":
+        # the two paths' FP32 rounding can move a right-hand side's value
+        # across an FP16 rounding boundary (or its scale across a power of
+        # two) in the matrix-core operands: agreement to the operand rounding
         for key in got[True]:
-            assert oracle.rel_l2(got[True][key], got[False][key]) <= 1e-5, key
+            assert oracle.rel_l2(got[True][key], got[False][key]) <= 2.0 ** -11, key
 
 
 def test_bf16_spectrum_at_L840():
