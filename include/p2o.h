@@ -130,6 +130,22 @@ p2o_status p2o_load_finalize(p2o_plan* plan);
 p2o_status p2o_apply_F(p2o_plan* plan, const void* m, void* d, int64_t nrhs,
                        const int32_t* nt_active);
 
+/* d = F m exactly as p2o_apply_F, for callers that cannot allocate device
+ * memory or must not touch the bound workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * workspace for nrhs right-hand sides is taken from a fixed scratch array in
+ * device memory that the library holds on each GPU it runs on (128 MiB per
+ * device, kept until the process ends), never from the plan's workspace,
+ * and nothing is allocated or freed.  The spectrum must be on the current
+ * device.  Every call on one GPU shares that GPU's scratch array: calls that
+ * overlap on one GPU (other streams, other threads, other plans) race and
+ * must be serialised by the caller.  Returns P2O_ERR_ARG, before anything
+ * is enqueued, when nrhs right-hand sides need more than the array holds
+ * (the message gives the size), P2O_ERR_HIP if the array's address cannot
+ * be obtained; otherwise as p2o_apply_F. */
+p2o_status p2o_apply_F_noalloc(p2o_plan* plan, const void* m, void* d, int64_t nrhs,
+                               const int32_t* nt_active);
+
 /* m = F^* d, the adjoint (section 2, F^* in equation mmap-problem; section 4,
  * conjugate-transposed Fourier blocks).  d: [nrhs][Nt][Nd] in,
  * m: [nrhs][Nt][Nm] out.  nt_active as for p2o_apply_F. */

@@ -54,6 +54,7 @@ def _load():
         "p2o_load_blocks": [pv, pv, c_int64, c_int64, c_int32],
         "p2o_load_finalize": [pv],
         "p2o_apply_F": [pv, pv, pv, c_int64, pv],
+        "p2o_apply_F_noalloc": [pv, pv, pv, c_int64, pv],
         "p2o_apply_Ft": [pv, pv, pv, c_int64, pv],
         "p2o_apply_FFt": [pv, pv, pv, c_int64, pv],
         "p2o_misfit_grad": [pv, pv, pv, pv, c_int64, pv, pv, c_int64, pv],

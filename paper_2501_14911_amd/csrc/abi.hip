@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -404,6 +405,51 @@ p2o_status enqueue_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, co
     });
 }
 
+// ---------------------------------------------------------------- scratch of the allocation-free entry point
+// p2o_apply_F_noalloc's workspace: a fixed array in device memory (each GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never uses the array's name as an address: its device address, taken once
+// per device with hipGetSymbolAddress while that device is current, is kept
+// in g_scratch and used for every access.  Every call on a device shares
+// that device's array: calls that overlap on one GPU race.  Nothing in it
+// needs to start at zero (the transforms and products write every value
+// they later read).
+constexpr size_t kScratchBytes = size_t(128) << 20;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch;
+
+p2o_status scratch_on_current_device(const p2o_plan* p, void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(P2O_ERR_HIP, "hipGetDevice failed");
+    }
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p->fhat) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(P2O_ERR_HIP, "cannot query the spectrum's device");
+    }
+    if (at.device != dev)
+        return fail(P2O_ERR_ARG, "the plan's spectrum is on device %d but device %d is current", at.device, dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return P2O_OK;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(P2O_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    }
+    g_scratch[dev] = ptr;
+    *out = ptr;
+    return P2O_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -783,6 +829,43 @@ p2o_status p2o_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const 
         return enqueue_apply_F(p, m, d, nrhs, nt_active);
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_apply_F");
+    }
+}
+
+p2o_status p2o_apply_F_noalloc(p2o_plan* p, const void* m, void* d, int64_t nrhs, const int32_t* nt_active) {
+    try {
+        p2o_status s = ready_for_apply(p, m, d, nrhs);
+        if (s) return s;
+        // the workspace layout for exactly nrhs right-hand sides, carved from
+        // this device's scratch array for the duration of the call
+        p2o_plan::Carve saved = p->carve;
+        const int64_t saved_rhs = p->max_rhs;
+        p->max_rhs = nrhs;
+        layout(p);
+        const size_t need = p->ws_total;
+        char* const saved_ws = p->ws;
+        auto restore = [&] {
+            p->max_rhs = saved_rhs;
+            p->carve = saved;
+            p->ws = saved_ws;
+        };
+        if (need > kScratchBytes) {
+            restore();
+            return fail(P2O_ERR_ARG, "p2o_apply_F_noalloc: %lld right-hand sides need %zu bytes of scratch, more than "
+                        "its %zu", (long long)nrhs, need, kScratchBytes);
+        }
+        void* scr = nullptr;
+        s = scratch_on_current_device(p, &scr);
+        if (s) {
+            restore();
+            return s;
+        }
+        p->ws = static_cast<char*>(scr);
+        s = enqueue_apply_F(p, m, d, nrhs, nt_active);
+        restore();
+        return s;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_apply_F_noalloc");
     }
 }
 
