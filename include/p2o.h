@@ -174,6 +174,66 @@ p2o_status p2o_misfit_grad(p2o_plan* plan, const void* m, const void* d_obs,
                            void* grad, double* misfit, int64_t nrhs,
                            const int32_t* nt_active);
 
+/* ---------------------------------------------------------------------------
+ * Offline and online phases on top of the map (section 4, Phases 2-4), with
+ * the stand-in prior Gamma_prior = prior_var * I, so that
+ * G^* := Gamma_prior F^* = prior_var F^* is the same block Toeplitz map as
+ * F^* (the paper precomputes G^* as its own block Toeplitz matrix; with this
+ * prior it needs no second spectrum).  The data-space matrix
+ * K = Gamma_noise + F G^* (equations woodbury and fast-Hessian-matvec) is
+ * dense, N x N with N = Nt * Nd, FP64, column-major with leading dimension
+ * ldk >= N (entry (i, j) at K[j * ldk + i]), the data index being
+ * j = t * Nd + s (the order of the data series [Nt][Nd]).  noise_var is a
+ * device double array of 1, Nd or Nt * Nd variances as for p2o_misfit_grad.
+ * ------------------------------------------------------------------------- */
+
+/* Columns [j0, j0 + ncols) of K = Gamma_noise + prior_var F F^* (the
+ * column-by-column assembly of section 4, Phase 2): one batched F F^* call on
+ * prior_var times the unit vectors e_j (matrix cores for BF16 / FP16 plans),
+ * the result widened to FP64 into the columns, the noise variance added on
+ * the diagonal.  K is a device pointer; 1 <= ncols <= max_rhs,
+ * j0 + ncols <= N.  Uses the workspace; asynchronous on the plan's stream. */
+p2o_status p2o_assemble_K(p2o_plan* plan, double prior_var, const double* noise_var,
+                          int64_t noise_var_len, double* K, int64_t ldk, int64_t j0,
+                          int64_t ncols);
+
+/* In-place Cholesky factorisation A = L L^T of a symmetric positive definite
+ * n x n FP64 matrix on the device (column-major, lda >= n; section 4,
+ * Phase 2: K is factorised offline): on return the lower triangle (i >= j)
+ * holds L; the strict upper triangle is neither read nor written.  *info
+ * (device int32) receives 0, or k + 1 when the k-th pivot was not positive
+ * (the factor is then not usable).  Blocked right-looking algorithm (blocks
+ * of 64; trailing updates on the FP64 matrix cores).  Asynchronous on
+ * `stream` (a hipStream_t, NULL = default stream). */
+p2o_status p2o_cholesky(double* A, int64_t n, int64_t lda, int32_t* info, void* stream);
+
+/* X <- K^{-1} X with K = L L^T from p2o_cholesky: the two triangular solves
+ * of the online phase (section 4, Phase 4), L y = x then L^T x = y, for
+ * nrhs right-hand sides, X column-major n x nrhs with leading dimension
+ * ldx >= n (device FP64).  Asynchronous on `stream`. */
+p2o_status p2o_cholesky_solve(const double* L, int64_t n, int64_t lda, double* X, int64_t nrhs,
+                              int64_t ldx, void* stream);
+
+/* MAP point with zero prior mean by equation real-time-parameter (section 4,
+ * Phase 4): m_map = (I - G^* K^{-1} F) G^* Gamma_noise^{-1} d_obs with
+ * G^* = prior_var F^*, computed as u = G^* Gamma_noise^{-1} d_obs,
+ * z = K^{-1} F u (two triangular solves with L, the factor of K from
+ * p2o_assemble_K and p2o_cholesky), m_map = G^* (Gamma_noise^{-1} d_obs - z):
+ * two adjoint and one forward application of the map.  d_obs: [nrhs][Nt][Nd],
+ * m_map: [nrhs][Nt][Nm] (I/O type), L: N x N with leading dimension ldl.
+ * Uses the workspace; asynchronous on the plan's stream. */
+p2o_status p2o_map_point(p2o_plan* plan, double prior_var, const double* noise_var,
+                         int64_t noise_var_len, const double* L, int64_t ldl, const void* d_obs,
+                         void* m_map, int64_t nrhs);
+
+/* Posterior covariance action out = Gamma_post v by equation
+ * fast-Hessian-matvec (section 4, Phase 2): Gamma_post = (I - G^* K^{-1} F)
+ * Gamma_prior, i.e. w = prior_var v, out = w - G^* K^{-1} F w.  v, out:
+ * [nrhs][Nt][Nm] (I/O type, distinct buffers); L as for p2o_map_point.
+ * Uses the workspace; asynchronous on the plan's stream. */
+p2o_status p2o_posterior_cov_apply(p2o_plan* plan, double prior_var, const double* L,
+                                   int64_t ldl, const void* v, void* out, int64_t nrhs);
+
 /* Stages of the calls above, for per-stage timing. */
 typedef enum {
     P2O_STAGE_R2C = 0,       /* zero-padded real FFT along time              */

@@ -58,6 +58,11 @@ def _load():
         "p2o_apply_Ft": [pv, pv, pv, c_int64, pv],
         "p2o_apply_FFt": [pv, pv, pv, c_int64, pv],
         "p2o_misfit_grad": [pv, pv, pv, pv, c_int64, pv, pv, c_int64, pv],
+        "p2o_assemble_K": [pv, c_double, pv, c_int64, pv, c_int64, c_int64, c_int64],
+        "p2o_cholesky": [pv, c_int64, c_int64, pv, pv],
+        "p2o_cholesky_solve": [pv, c_int64, c_int64, pv, c_int64, c_int64, pv],
+        "p2o_map_point": [pv, c_double, pv, c_int64, pv, c_int64, pv, pv, c_int64],
+        "p2o_posterior_cov_apply": [pv, c_double, pv, c_int64, pv, pv, c_int64],
         "p2o_profile_enable": [pv, c_int32],
         "p2o_set_option": [pv, c_int32, c_int64],
         "p2o_profile_read_nrhs": [pv, c_int32, c_int64, POINTER(c_double), POINTER(c_int64)],

@@ -73,6 +73,8 @@ struct p2o_plan {
         // FP16 matrix-core operands: wavefront maxima and right-hand-side scales of X and Y
         size_t off_A = 0, off_SX = 0, off_SY = 0;
         int amax_slots = 0;
+        // online phase: a second data series buffer (I/O type) and FP64 data vectors
+        size_t off_D2 = 0, off_Z = 0;
     } carve;
     size_t& off_X = carve.off_X;
     size_t& off_Y = carve.off_Y;
@@ -83,6 +85,8 @@ struct p2o_plan {
     size_t& off_SX = carve.off_SX;
     size_t& off_SY = carve.off_SY;
     int& amax_slots = carve.amax_slots;
+    size_t& off_D2 = carve.off_D2;
+    size_t& off_Z = carve.off_Z;
     // kernel configuration
     int fwd_rows = 64, fwd_nslab = 1, fwd_chunks = 1;
     int adj_rows = 1, adj_nslab = 1;
@@ -195,7 +199,9 @@ void layout(p2o_plan* p) {
     p->off_Y = align_up(p->off_X + xparts * nfreq * R * (size_t)p->pitch * p->cbytes);
     p->off_D = align_up(p->off_Y + ylen * p->cbytes);
     p->off_P = align_up(p->off_D + R * (size_t)p->Nt * (size_t)p->Nd * p->io_bytes);
-    p->ws_total = align_up(p->off_P + R * (size_t)p->c2r_nd_blocks * sizeof(double));
+    p->off_D2 = align_up(p->off_P + R * (size_t)p->c2r_nd_blocks * sizeof(double));
+    p->off_Z = align_up(p->off_D2 + R * (size_t)p->Nt * (size_t)p->Nd * p->io_bytes);
+    p->ws_total = align_up(p->off_Z + R * (size_t)p->Nt * (size_t)p->Nd * sizeof(double));
     if (p->prec == kFP16) {
         p->amax_slots = fft_amax_slots((int)std::max<int64_t>(p->pitch, gemm_data_pitch((int)p->Nd)));
         p->off_A = p->ws_total;
@@ -393,6 +399,43 @@ p2o_status enqueue_adjoint_to_X(p2o_plan* p, const void* d, int64_t nrhs, const 
     });
     if (s) return s;
     return enqueue_adj_products(p, Y, X, nrhs);
+}
+
+p2o_status noise_mode(const p2o_plan* p, int64_t len, int* mode) {
+    if (len == 1) *mode = 0;
+    else if (len == p->Nd) *mode = 1;
+    else if (len == p->Nd * p->Nt) *mode = 2;
+    else
+        return fail(P2O_ERR_ARG, "noise_var_len=%lld must be 1, Nd=%lld or Nt*Nd=%lld", (long long)len,
+                    (long long)p->Nd, (long long)(p->Nd * p->Nt));
+    return P2O_OK;
+}
+
+p2o_status enqueue_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, const int32_t* nt_active) {
+    p->cur_nrhs = nrhs;
+    p2o_status s = enqueue_adjoint_to_X(p, d, nrhs, nt_active);
+    if (s) return s;
+    return staged(p, P2O_STAGE_C2R, "c2r (parameters)", [&] {
+        return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, adj_parts(p, nrhs)), p->ws + p->off_X, m,
+                          tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
+    });
+}
+
+p2o_status enqueue_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, const int32_t* nt_active) {
+    p->cur_nrhs = nrhs;
+    p2o_status s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
+    if (s) return s;
+    s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
+        return launch_project(f64_plan(p), p->fft, io_param_rhs(p, nrhs, nt_active, adj_parts(p, nrhs)),
+                              p->ws + p->off_X, tw_of(p), p->stream);
+    });
+    if (s) return s;
+    s = enqueue_fwd_products(p, p->ws + p->off_X, p->ws + p->off_Y, nrhs);
+    if (s) return s;
+    return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
+        return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, h,
+                          tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
+    });
 }
 
 p2o_status enqueue_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const int32_t* nt_active) {
@@ -873,13 +916,7 @@ p2o_status p2o_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, const
     try {
         p2o_status s = ready_for_apply(p, d, m, nrhs);
         if (s) return s;
-        p->cur_nrhs = nrhs;
-        s = enqueue_adjoint_to_X(p, d, nrhs, nt_active);
-        if (s) return s;
-        return staged(p, P2O_STAGE_C2R, "c2r (parameters)", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_param(p, nrhs, nt_active, adj_parts(p, nrhs)), p->ws + p->off_X, m,
-                              tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
-        });
+        return enqueue_apply_Ft(p, d, m, nrhs, nt_active);
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_apply_Ft");
     }
@@ -889,22 +926,126 @@ p2o_status p2o_apply_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, cons
     try {
         p2o_status s = ready_for_apply(p, e, h, nrhs);
         if (s) return s;
-        p->cur_nrhs = nrhs;
-        s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
-        if (s) return s;
-        s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
-            return launch_project(f64_plan(p), p->fft, io_param_rhs(p, nrhs, nt_active, adj_parts(p, nrhs)),
-                                  p->ws + p->off_X, tw_of(p), p->stream);
-        });
-        if (s) return s;
-        s = enqueue_fwd_products(p, p->ws + p->off_X, p->ws + p->off_Y, nrhs);
-        if (s) return s;
-        return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
-            return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, h,
-                              tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
-        });
+        return enqueue_FFt(p, e, h, nrhs, nt_active);
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_apply_FFt");
+    }
+}
+
+p2o_status p2o_assemble_K(p2o_plan* p, double prior_var, const double* noise_var, int64_t noise_var_len, double* K,
+                          int64_t ldk, int64_t j0, int64_t ncols) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (!K || !noise_var) return fail(P2O_ERR_ARG, "K or noise_var is NULL");
+        int var_mode;
+        p2o_status s = noise_mode(p, noise_var_len, &var_mode);
+        if (s) return s;
+        if (!(prior_var > 0.0) || prior_var > 1e300) return fail(P2O_ERR_ARG, "prior_var must be positive and finite");
+        const int64_t N = p->Nt * p->Nd;
+        if (ldk < N) return fail(P2O_ERR_ARG, "ldk=%lld < Nt*Nd=%lld", (long long)ldk, (long long)N);
+        if (j0 < 0 || ncols < 1 || j0 + ncols > N)
+            return fail(P2O_ERR_ARG, "columns [%lld, %lld) outside [0, %lld)", (long long)j0, (long long)(j0 + ncols),
+                        (long long)N);
+        s = ready_for_apply(p, K, K, ncols);
+        if (s) return s;
+        p->cur_nrhs = ncols;
+        void* E = p->ws + p->off_D;
+        void* H = p->ws + p->off_D2;
+        const bool f64 = f64_plan(p);
+        // gamma e_j: F (gamma F* e_j) is the column of F G* with G* = gamma F*
+        s = check_hip(launch_unit_vectors(f64, E, N, j0, (int)ncols, prior_var, p->stream), "unit vectors");
+        if (s) return s;
+        s = enqueue_FFt(p, E, H, ncols, nullptr);
+        if (s) return s;
+        return check_hip(launch_K_columns(f64, H, N, K, ldk, j0, (int)ncols, noise_var, var_mode, (int)p->Nd, p->stream),
+                         "K columns");
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_assemble_K");
+    }
+}
+
+p2o_status p2o_cholesky(double* A, int64_t n, int64_t lda, int32_t* info, void* stream) {
+    if (!A || !info) return fail(P2O_ERR_ARG, "A or info is NULL");
+    if (n < 1 || n > (1LL << 31) - 1 || lda < n) return fail(P2O_ERR_ARG, "n=%lld or lda=%lld invalid", (long long)n, (long long)lda);
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return check_hip(launch_cholesky(A, n, lda, info, static_cast<hipStream_t>(stream)), "Cholesky factorisation");
+}
+
+p2o_status p2o_cholesky_solve(const double* L, int64_t n, int64_t lda, double* X, int64_t nrhs, int64_t ldx,
+                              void* stream) {
+    if (!L || !X) return fail(P2O_ERR_ARG, "L or X is NULL");
+    if (n < 1 || n > (1LL << 31) - 1 || lda < n || ldx < n)
+        return fail(P2O_ERR_ARG, "n=%lld, lda=%lld or ldx=%lld invalid", (long long)n, (long long)lda, (long long)ldx);
+    if (nrhs < 1 || nrhs > 65535) return fail(P2O_ERR_ARG, "nrhs=%lld outside [1, 65535]", (long long)nrhs);
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return check_hip(launch_cholesky_solve(L, n, lda, X, (int)nrhs, ldx, static_cast<hipStream_t>(stream)),
+                     "Cholesky solve");
+}
+
+p2o_status p2o_map_point(p2o_plan* p, double prior_var, const double* noise_var, int64_t noise_var_len,
+                         const double* L, int64_t ldl, const void* d_obs, void* m_map, int64_t nrhs) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (!L || !noise_var) return fail(P2O_ERR_ARG, "L or noise_var is NULL");
+        int var_mode;
+        p2o_status s = noise_mode(p, noise_var_len, &var_mode);
+        if (s) return s;
+        if (!(prior_var > 0.0) || prior_var > 1e300) return fail(P2O_ERR_ARG, "prior_var must be positive and finite");
+        const int64_t N = p->Nt * p->Nd;
+        if (ldl < N) return fail(P2O_ERR_ARG, "ldl=%lld < Nt*Nd=%lld", (long long)ldl, (long long)N);
+        s = ready_for_apply(p, d_obs, m_map, nrhs);
+        if (s) return s;
+        p->cur_nrhs = nrhs;
+        const bool f64 = f64_plan(p);
+        void* D = p->ws + p->off_D;
+        void* D2 = p->ws + p->off_D2;
+        double* Z = reinterpret_cast<double*>(p->ws + p->off_Z);
+        // w = gamma Gamma_noise^{-1} d; u = F* w (= G* Gamma_noise^{-1} d)
+        s = check_hip(launch_weight_data(f64, d_obs, D, N, (int)nrhs, noise_var, var_mode, (int)p->Nd, prior_var,
+                                         p->stream), "noise weighting");
+        if (!s) s = enqueue_apply_Ft(p, D, m_map, nrhs, nullptr);
+        // z = K^{-1} F u
+        if (!s) s = enqueue_apply_F(p, m_map, D2, nrhs, nullptr);
+        if (!s) s = check_hip(launch_to_f64(f64, D2, Z, N, (int)nrhs, N, p->stream), "data vectors to FP64");
+        if (!s) s = check_hip(launch_cholesky_solve(L, N, ldl, Z, (int)nrhs, N, p->stream), "K solve");
+        // m_map = G* (Gamma_noise^{-1} d - z) = F* (w - gamma z)
+        if (!s) s = check_hip(launch_combine(f64, D, Z, N, (int)nrhs, N, 1.0, -prior_var, p->stream), "w - gamma z");
+        if (!s) s = enqueue_apply_Ft(p, D, m_map, nrhs, nullptr);
+        return s;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_map_point");
+    }
+}
+
+p2o_status p2o_posterior_cov_apply(p2o_plan* p, double prior_var, const double* L, int64_t ldl, const void* v,
+                                   void* out, int64_t nrhs) {
+    try {
+        if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
+        if (!L) return fail(P2O_ERR_ARG, "L is NULL");
+        if (!(prior_var > 0.0) || prior_var > 1e300) return fail(P2O_ERR_ARG, "prior_var must be positive and finite");
+        const int64_t N = p->Nt * p->Nd;
+        if (ldl < N) return fail(P2O_ERR_ARG, "ldl=%lld < Nt*Nd=%lld", (long long)ldl, (long long)N);
+        p2o_status s = ready_for_apply(p, v, out, nrhs);
+        if (s) return s;
+        if (v == out) return fail(P2O_ERR_ARG, "v and out must not be the same buffer");
+        p->cur_nrhs = nrhs;
+        const bool f64 = f64_plan(p);
+        const long long nm = (long long)nrhs * p->Nt * p->Nm;
+        void* D = p->ws + p->off_D;
+        void* D2 = p->ws + p->off_D2;
+        double* Z = reinterpret_cast<double*>(p->ws + p->off_Z);
+        // w = gamma v (Gamma_prior v); z = K^{-1} F w
+        s = check_hip(launch_axpby(f64, v, out, nm, 0.0, prior_var, p->stream), "gamma v");
+        if (!s) s = enqueue_apply_F(p, out, D2, nrhs, nullptr);
+        if (!s) s = check_hip(launch_to_f64(f64, D2, Z, N, (int)nrhs, N, p->stream), "data vectors to FP64");
+        if (!s) s = check_hip(launch_cholesky_solve(L, N, ldl, Z, (int)nrhs, N, p->stream), "K solve");
+        // out = w - G* z = F* (-gamma z) + gamma v
+        if (!s) s = check_hip(launch_combine(f64, D, Z, N, (int)nrhs, N, 0.0, -prior_var, p->stream), "-gamma z");
+        if (!s) s = enqueue_apply_Ft(p, D, out, nrhs, nullptr);
+        if (!s) s = check_hip(launch_axpby(f64, v, out, nm, 1.0, prior_var, p->stream), "+ gamma v");
+        return s;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_posterior_cov_apply");
     }
 }
 
@@ -914,13 +1055,9 @@ p2o_status p2o_misfit_grad(p2o_plan* p, const void* m, const void* d_obs, const 
         if (!p) return fail(P2O_ERR_ARG, "plan is NULL");
         if (!d_obs || !noise_var || !misfit) return fail(P2O_ERR_ARG, "d_obs, noise_var or misfit is NULL");
         int var_mode;
-        if (noise_var_len == 1) var_mode = 0;
-        else if (noise_var_len == p->Nd) var_mode = 1;
-        else if (noise_var_len == p->Nd * p->Nt) var_mode = 2;
-        else
-            return fail(P2O_ERR_ARG, "noise_var_len=%lld must be 1, Nd=%lld or Nt*Nd=%lld", (long long)noise_var_len,
-                        (long long)p->Nd, (long long)(p->Nd * p->Nt));
-        p2o_status s = ready_for_apply(p, m, grad, nrhs);
+        p2o_status s = noise_mode(p, noise_var_len, &var_mode);
+        if (s) return s;
+        s = ready_for_apply(p, m, grad, nrhs);
         if (s) return s;
         p->cur_nrhs = nrhs;
         s = enqueue_forward_to_Y(p, m, nrhs, nt_active);

@@ -398,18 +398,22 @@ __device__ __forceinline__ void dma16(const uint8_t* base, uint32_t off, uint32_
 // F16: the spectrum is stored in FP16 and the right-hand sides in complex
 // FP32 with per-right-hand-side scales (rhs_scale); fragments are rounded to
 // FP16 in registers and take one FP16 product per form.
-template <int NH, bool F16>
-__global__ __launch_bounds__(256 * NH) __attribute__((amdgpu_waves_per_eu(NH)))
+// RG row groups x MB blocks of 32 rows (640 rows: all sensors of a 600-sensor
+// operator; 64 or 128 rows for operators with few sensors, where a 640-row
+// tile would do the matrix work of its padding rows).
+template <int RG, int MB, int NH, bool F16>
+__global__ __launch_bounds__(64 * RG * NH) __attribute__((amdgpu_waves_per_eu(NH)))
 void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
                      float2* __restrict__ out_base, GemmArgs ga) {
-    constexpr int RG = 4, MB = 5, KU = 2, RING = kRingSteps;
-    constexpr int MROWS = RG * 32 * MB, RHS = 32 * NH;
-    constexpr int AI = MROWS / 16 / (RG * NH);            // A loads (16 rows each) per wavefront per step
-    static_assert(AI * 16 * RG * NH == MROWS, "A rows per wavefront");
+    constexpr int KU = 2, RING = kRingSteps;
+    constexpr int MROWS = RG * 32 * MB, RHS = 32 * NH, NW = RG * NH;
+    constexpr int AI = MROWS / 16 / NW;                   // A loads (16 rows each) per wavefront per step
+    static_assert(AI >= 1 && AI * 16 * NW == MROWS, "A rows per wavefront");
     constexpr int A_STEP = MROWS * 64;                    // bytes of A per step
-    constexpr int B_STEP = RHS * 128;                     // bytes of B per step (8 right-hand sides per wavefront)
-    static_assert(8 * RG * NH == RHS, "one B load per wavefront per step");
-    constexpr int G = AI + 1;                             // loads per wavefront per step
+    constexpr int B_STEP = RHS * 128;                     // bytes of B per step (8 right-hand sides per load)
+    constexpr int BI = RHS / 8 / NW;                      // B loads per wavefront per step
+    static_assert(BI >= 1 && 8 * BI * NW == RHS, "B loads per wavefront");
+    constexpr int G = AI + BI;                            // loads per wavefront per step
     __shared__ __align__(16) uint8_t ring_a[RING][A_STEP];
     __shared__ __align__(16) uint8_t ring_b[RING][B_STEP];
 
@@ -449,23 +453,25 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
             aoff[i] = ((uint32_t)sr * (uint32_t)ga.pitch + 4u * (uint32_t)c) * 4u;
         }
     }
-    // B rows 8 wave .. + 7 of the group: lane L moves part
-    // (L % 8) ^ ((b / 2) mod 8) of right-hand side b = 8 wave + L / 8 into
-    // slot L % 8 of that right-hand side's 128 bytes
+    // B instruction i of this wavefront: right-hand sides 8 (BI wave + i) .. + 7
+    // of the group; lane L moves part (L % 8) ^ ((b / 2) mod 8) of right-hand
+    // side b = 8 (BI wave + i) + L / 8 into slot L % 8 of its 128 bytes
     const uint8_t* const bbase = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8 + (long long)kbeg * 8;
-    uint32_t boff;
-    {
-        const int b = 8 * wave + (lane >> 3);
+    uint32_t boff[BI];
+#pragma unroll
+    for (int i = 0; i < BI; ++i) {
+        const int b = 8 * (BI * wave + i) + (lane >> 3);
         const int part = (lane & 7) ^ ((b >> 1) & 7);
-        boff = (uint32_t)min(b, nb_valid - 1) * (uint32_t)ga.ldb * 8u + (uint32_t)part * 16u;
+        boff[i] = (uint32_t)min(b, nb_valid - 1) * (uint32_t)ga.ldb * 8u + (uint32_t)part * 16u;
     }
-    const uint32_t la = lds_addr(&ring_a[0][0]) + AI * wave * 1024, lb = lds_addr(&ring_b[0][0]) + wave * 1024;
+    const uint32_t la = lds_addr(&ring_a[0][0]) + AI * wave * 1024, lb = lds_addr(&ring_b[0][0]) + BI * wave * 1024;
     auto issue = [&](int st, int slot) {
         const long long sa = st < nst ? st : nst - 1;       // past the end: repeat the last step (unused)
         const uint8_t* const ab = abase + sa * 64;
 #pragma unroll
         for (int i = 0; i < AI; ++i) dma16(ab, aoff[i], la + slot * A_STEP + i * 1024);
-        dma16(bbase + sa * 128, boff, lb + slot * B_STEP);
+#pragma unroll
+        for (int i = 0; i < BI; ++i) dma16(bbase + sa * 128, boff[i], lb + slot * B_STEP + i * 1024);
     };
 
     f32x16 accr[MB], acci[MB];
@@ -822,9 +828,10 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
 // adjoint's 256-column tiles also divide 4096-column blocks evenly).  A
 // plan's autotuner may replace the built-in choice (gemm_default_tile).
 // Variants 7 and 8 are the forward LDS-ring kernel (k_gemm_fwd_ring, pf = 0
-// marks a ring) for 64 and 32 right-hand sides per group, 9 and 10 the
-// adjoint one (k_gemm_adj_ring) for 64 and 32; a direction a variant lacks
-// takes its built-in choice.
+// marks a ring) with 640-row tiles for 64 and 32 right-hand sides per group,
+// 11 and 12 the same kernel with 64- and 128-row tiles (64 right-hand sides),
+// 9 and 10 the adjoint one (k_gemm_adj_ring) for 64 and 32; a direction a
+// variant lacks takes its built-in choice.
 struct TileShape {
     int rg, ku, mb, wpe, pf, nw;
     int dirs;   // 1: forward, 2: adjoint, 3: both
@@ -832,7 +839,8 @@ struct TileShape {
 static const TileShape kTiles[] = {{2, 4, 5, 1, 2, 4, 3}, {2, 2, 5, 1, 2, 4, 3}, {4, 2, 5, 1, 2, 4, 3},
                                    {2, 2, 4, 2, 2, 4, 3}, {4, 2, 4, 2, 2, 4, 3}, {2, 2, 5, 2, 1, 4, 3},
                                    {4, 2, 5, 2, 1, 8, 3}, {4, 2, 5, 2, 0, 8, 1}, {4, 2, 5, 1, 0, 4, 1},
-                                   {2, 2, 4, 2, 0, 4, 2}, {4, 2, 4, 1, 0, 4, 2}};
+                                   {2, 2, 4, 2, 0, 4, 2}, {4, 2, 4, 1, 0, 4, 2}, {2, 2, 1, 2, 0, 4, 1},
+                                   {4, 2, 1, 2, 0, 8, 1}};
 constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_tile_count() { return kTileCount; }
@@ -841,7 +849,7 @@ bool gemm_tile_has(int tile, bool fwd) {
     return tile >= 0 && tile < kTileCount && (kTiles[tile].dirs & (fwd ? 1 : 2)) != 0;
 }
 
-template <int NH>
+template <int RG, int MB, int NH>
 static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
                               hipStream_t st) {
     // the ring kernel addresses a frequency's spectrum and a group's
@@ -851,16 +859,17 @@ static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales
         if (ga.a_f16) return hipErrorInvalidValue;        // callers check gemm_f16_fits first
         return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Bq, out, st);
     }
-    ga.n_mt = (ga.Nd + 639) / 640;
+    constexpr int MROWS = 32 * RG * MB;
+    ga.n_mt = (ga.Nd + MROWS - 1) / MROWS;
     ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
     if (ga.a_f16)
-        hipLaunchKernelGGL((k_gemm_fwd_ring<NH, true>), dim3(8 * ga.Q), dim3(256 * NH), 0, st, (const uint8_t*)fhat,
-                           scales, (const uint8_t*)Bq, (float2*)out, ga);
+        hipLaunchKernelGGL((k_gemm_fwd_ring<RG, MB, NH, true>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                           (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     else
-        hipLaunchKernelGGL((k_gemm_fwd_ring<NH, false>), dim3(8 * ga.Q), dim3(256 * NH), 0, st, (const uint8_t*)fhat,
-                           scales, (const uint8_t*)Bq, (float2*)out, ga);
+        hipLaunchKernelGGL((k_gemm_fwd_ring<RG, MB, NH, false>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                           (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
 }
 
@@ -906,8 +915,14 @@ int gemm_tile_shape(int tile, int* rg, int* ku, int* mb, int* rhs) {
 
 // Built-in choice without autotuning: the variants measured fastest on the
 // 600 x 16384 x 420 workload (random operands) for each width (the LDS
-// rings: 7 / 9 above 32 right-hand sides, 8 / 10 for at most 32).
-int gemm_default_tile(int nrhs, bool fwd) { return nrhs > 32 ? (fwd ? 7 : 9) : (fwd ? 8 : 10); }
+// rings: 7 / 9 above 32 right-hand sides, 8 / 10 for at most 32); forward
+// products of operators with at most 64 or 128 sensors take the 64- or
+// 128-row ring tiles 11 / 12 (64 right-hand sides per group).
+int gemm_default_tile(int nrhs, bool fwd, int Nd) {
+    if (fwd && Nd <= 64) return 11;
+    if (fwd && Nd <= 128) return 12;
+    return nrhs > 32 ? (fwd ? 7 : 9) : (fwd ? 8 : 10);
+}
 
 hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const float* scales, const void* Xq,
                            void* Yp, hipStream_t st) {
@@ -916,7 +931,7 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = ga.pitch;
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.ncols);
-    if (!gemm_tile_has(tile, true) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, true);
+    if (!gemm_tile_has(tile, true) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, true, ga.Nd);
     switch (tile) {
         case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 1: return launch_tile<true, 2, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
@@ -925,8 +940,10 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
         case 4: return launch_tile<true, 4, 2, 4, 2, 2>(ga, fhat, scales, Xq, Yp, st);
         case 5: return launch_tile<true, 2, 2, 5, 2, 1>(ga, fhat, scales, Xq, Yp, st);
         case 6: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
-        case 7: return launch_ring<2>(ga, fhat, scales, Xq, Yp, st);
-        case 8: return launch_ring<1>(ga, fhat, scales, Xq, Yp, st);
+        case 7: return launch_ring<4, 5, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 8: return launch_ring<4, 5, 1>(ga, fhat, scales, Xq, Yp, st);
+        case 11: return launch_ring<2, 1, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 12: return launch_ring<4, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         default: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
     }
 }
@@ -938,7 +955,7 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
     ga.ldb = gemm_data_pitch(ga.Nd);
     ga.kchunk = 0;
     ga.n_kc = 1;
-    if (!gemm_tile_has(tile, false) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, false);
+    if (!gemm_tile_has(tile, false) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, false, ga.Nd);
     switch (tile) {
         case 0: return launch_tile<false, 2, 4, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);
         case 1: return launch_tile<false, 2, 2, 5, 1, 2>(ga, fhat, scales, Yq, Xp, st);

@@ -94,7 +94,7 @@ int gemm_data_pitch(int Nd);   // row length of data-side quad spectra read by t
 int gemm_tile_count();
 bool gemm_tile_has(int tile, bool fwd);   // variant exists for that direction (others take the built-in choice)
 int gemm_tile_shape(int tile, int* row_groups, int* substeps, int* blocks, int* rhs_per_group);
-int gemm_default_tile(int nrhs, bool fwd);
+int gemm_default_tile(int nrhs, bool fwd, int Nd);
 bool gemm_tile_is_ring(int tile);           // an LDS-ring variant (the only ones for FP16 spectra)
 bool gemm_f16_fits(int Nd, int pitch);      // shapes the FP16-spectrum ring kernels can address
 hipError_t launch_fill_bf16(void* p, size_t bytes, uint32_t seed, hipStream_t st);   // timing operands
@@ -104,5 +104,21 @@ hipError_t launch_gemm_fwd(const GemmArgs& ga, int tile, const void* fhat, const
                            void* Yp, hipStream_t st);
 hipError_t launch_gemm_adj(const GemmArgs& ga, int tile, const void* fhat, const float* scales, const void* Yq,
                            void* Xp, hipStream_t st);
+
+// posterior.hip: data-space matrix, Cholesky factorisation and solves, and
+// the elementwise steps of the online phase (dense matrices FP64,
+// column-major; f64 selects FP64 series, FP32 otherwise)
+hipError_t launch_unit_vectors(bool f64, void* E, long long N, long long j0, int ncols, double value, hipStream_t st);
+hipError_t launch_K_columns(bool f64, const void* H, long long N, double* K, long long ldk, long long j0, int ncols,
+                            const double* var, int var_mode, int Nd, hipStream_t st);
+hipError_t launch_weight_data(bool f64, const void* d, void* D, long long N, int nrhs, const double* var, int var_mode,
+                              int Nd, double gamma, hipStream_t st);
+hipError_t launch_to_f64(bool f64, const void* Y, double* Z, long long N, int nrhs, long long ldz, hipStream_t st);
+hipError_t launch_combine(bool f64, void* D, const double* Z, long long N, int nrhs, long long ldz, double a0, double a1,
+                          hipStream_t st);
+hipError_t launch_axpby(bool f64, const void* v, void* out, long long n, double a0, double a1, hipStream_t st);
+hipError_t launch_cholesky(double* A, long long n, long long lda, int* info, hipStream_t st);
+hipError_t launch_cholesky_solve(const double* L, long long n, long long lda, double* X, int nrhs, long long ldx,
+                                 hipStream_t st);
 
 }  // namespace p2o

@@ -1,0 +1,418 @@
+// Kernels of the offline and online phases built on the p2o map (section 4,
+// Phases 2-4): assembly of the data-space matrix K = Gamma_noise + F G*
+// from batched operator columns, its Cholesky factorisation K = L L^T, the
+// triangular solves with L, and the small elementwise steps of the MAP point
+// and posterior-covariance actions.
+//
+// Dense matrices are FP64 and column-major with a leading dimension: entry
+// (i, j) at A[j * lda + i].  The data-space index is j = t * Nd + s (the
+// time-major order of the data series).
+//
+// Cholesky (right-looking, blocks of kNB = 64):
+//   for each diagonal block k: factor it in LDS (one workgroup); solve the
+//   panel below it against L_kk^T (one row per lane, L_kk in LDS); subtract
+//   P P^T from the lower tiles of the trailing matrix with
+//   v_mfma_f64_16x16x4f64 (64 x 64 tiles, panel columns staged in LDS).
+// The strict upper triangle is never read or written.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace p2o {
+
+namespace {
+
+constexpr int kNB = 64;                 // Cholesky / solve block size
+constexpr int kLP = kNB + 2;            // padded LDS row (doubles)
+
+__device__ __forceinline__ double noise_var_at(const double* var, int mode, long long i, int Nd) {
+    return mode == 0 ? var[0] : mode == 1 ? var[i % Nd] : var[i];
+}
+
+// ---------------------------------------------------------------- K assembly
+// E[b][i] = value at i = j0 + b, zero elsewhere (b < ncols, i < N).
+template <typename T>
+__global__ void k_unit_vectors(T* __restrict__ E, long long N, long long j0, int ncols, T value) {
+    const long long n = N * ncols;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / N, i = e - b * N;
+        E[e] = (i == j0 + b) ? value : T(0);
+    }
+}
+
+// K[:, j0 + b] = H[b] + Gamma_noise e_{j0+b}: the operator columns (FP32 or
+// FP64) widened to FP64, the noise variance added on the diagonal.
+template <typename T>
+__global__ void k_K_columns(const T* __restrict__ H, long long N, double* __restrict__ K, long long ldk, long long j0,
+                            int ncols, const double* __restrict__ var, int var_mode, int Nd) {
+    const long long n = N * ncols;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / N, i = e - b * N;
+        double v = (double)H[e];
+        if (i == j0 + b) v += noise_var_at(var, var_mode, i, Nd);
+        K[(j0 + b) * ldk + i] = v;
+    }
+}
+
+// ---------------------------------------------------------------- elementwise steps of the online phase
+// D = gamma d / var (nrhs data series of N values).
+template <typename T>
+__global__ void k_weight_data(const T* __restrict__ d, T* __restrict__ D, long long N, int nrhs,
+                              const double* __restrict__ var, int var_mode, int Nd, double gamma) {
+    const long long n = N * nrhs;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e % N;
+        D[e] = (T)(gamma * (double)d[e] / noise_var_at(var, var_mode, i, Nd));
+    }
+}
+
+// Z[b][i] = Y[b][i] widened to FP64 (Z rows ldz apart).
+template <typename T>
+__global__ void k_to_f64(const T* __restrict__ Y, double* __restrict__ Z, long long N, int nrhs, long long ldz) {
+    const long long n = N * nrhs;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / N, i = e - b * N;
+        Z[b * ldz + i] = (double)Y[e];
+    }
+}
+
+// D[b][i] = a0 * D[b][i] + a1 * Z[b][i]   (Z rows ldz apart).
+// (a0 = 0 does not read D, so stale contents never reach the result.)
+template <typename T>
+__global__ void k_combine(T* __restrict__ D, const double* __restrict__ Z, long long N, int nrhs, long long ldz,
+                          double a0, double a1) {
+    const long long n = N * nrhs;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / N, i = e - b * N;
+        const double z = a1 * Z[b * ldz + i];
+        D[e] = (T)(a0 == 0.0 ? z : a0 * (double)D[e] + z);
+    }
+}
+
+// out = a0 * out + a1 * v (a0 = 0 does not read out).
+template <typename T>
+__global__ void k_axpby(const T* __restrict__ v, T* __restrict__ out, long long n, double a0, double a1) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const double y = a1 * (double)v[e];
+        out[e] = (T)(a0 == 0.0 ? y : a0 * (double)out[e] + y);
+    }
+}
+
+// ---------------------------------------------------------------- Cholesky
+// Factor the nb x nb diagonal block at (k, k) in place (nb <= kNB), one
+// workgroup: column j is scaled by 1 / sqrt(a_jj), then its outer product
+// leaves the trailing part of the block.  A pivot that is not positive (or
+// not a number) records k + j + 1 in *info if nothing was recorded before.
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, long long lda, int k, int nb,
+                                                    int* __restrict__ info) {
+    __shared__ double a[kNB][kLP];                     // a[col][row]
+    const int tid = threadIdx.x;
+    if (k == 0 && tid == 0 && info) *info = 0;        // read back only by this thread, in stream order
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int c = e / nb, r = e - c * nb;
+        if (r >= c) a[c][r] = A[(long long)(k + c) * lda + k + r];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+            const double d = a[j][j];
+            if (!(d > 0.0) && info && *info == 0) *info = k + j + 1;
+            a[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        const double dj = a[j][j];
+        for (int r = j + 1 + tid; r < nb; r += 256) a[j][r] /= dj;
+        __syncthreads();
+        const int m = nb - j - 1;
+        for (int e = tid; e < m * m; e += 256) {
+            const int c = j + 1 + e / m, r = j + 1 + e % m;
+            if (r >= c) a[c][r] -= a[j][r] * a[j][c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int c = e / nb, r = e - c * nb;
+        if (r >= c) A[(long long)(k + c) * lda + k + r] = a[c][r];
+    }
+}
+
+// Rows r in [k + kNB, n) of the panel: x L_kk^T = a for each row (forward
+// substitution along the row), one row per lane, L_kk staged in LDS.
+__global__ __launch_bounds__(256) void k_trsm_panel(double* __restrict__ A, long long lda, int n, int k) {
+    __shared__ double l[kNB][kLP];                     // l[col][row] = L_kk(row, col)
+    for (int e = threadIdx.x; e < kNB * kNB; e += 256) {
+        const int c = e / kNB, r = e - c * kNB;
+        l[c][r] = r >= c ? A[(long long)(k + c) * lda + k + r] : 0.0;
+    }
+    __syncthreads();
+    const long long r = (long long)k + kNB + blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    double x[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) x[c] = A[(long long)(k + c) * lda + r];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) {
+        double s = x[j];
+#pragma unroll
+        for (int c = 0; c < j; ++c) s -= x[c] * l[c][j];
+        x[j] = s / l[j][j];
+    }
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) A[(long long)(k + c) * lda + r] = x[c];
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Trailing update A[t0 + i, t0 + j] -= sum_c P[i, c] P[j, c] over the lower
+// 64 x 64 tiles (tile row >= tile column), P = A[t0:n, k:k + kNB], t0 =
+// k + kNB.  Workgroup = one tile, 4 wavefronts of 32 x 32 (2 x 2 blocks of
+// 16 x 16 on the matrix cores).  The products are taken as the transposed
+// block P_j P_i^T so that lane l of a block holds rows l % 16 of four
+// columns: stores cover 128 contiguous bytes per 16 lanes.
+__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, long long lda, int n, int k) {
+    __shared__ double pi[kNB][kLP], pj[kNB][kLP];     // [panel column][tile row]
+    const int t0 = k + kNB;
+    const int m = n - t0;
+    // tile (ti, tj), tj <= ti, from the linear index ti (ti + 1) / 2 + tj
+    const long long q = blockIdx.x;
+    int ti = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+    while ((long long)(ti + 1) * (ti + 2) / 2 <= q) ++ti;
+    while ((long long)ti * (ti + 1) / 2 > q) --ti;
+    const int tj = (int)(q - (long long)ti * (ti + 1) / 2);
+    const int ri = ti * 64, rj = tj * 64;              // first rows (tile-local to t0)
+    for (int e = threadIdx.x; e < 64 * kNB; e += 256) {
+        const int c = e / 64, r = e % 64;
+        const double* col = A + (long long)(k + c) * lda + t0;
+        pi[c][r] = ri + r < m ? col[ri + r] : 0.0;
+        pj[c][r] = rj + r < m ? col[rj + r] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // sub-tile: rows wr (of i), columns wc (of j)
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+    for (int c0 = 0; c0 < kNB; c0 += 4) {
+        double vi[2], vj[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) vi[a] = pi[c0 + lk][wr + 16 * a + li];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) vj[b] = pj[c0 + lk][wc + 16 * b + li];
+        // block (a, b) of P_j P_i^T: rows = tile columns wc + 16 b + ., columns = tile rows wr + 16 a + .
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vj[b], vi[a], acc[a][b], 0, 0, 0);
+    }
+    // lane l holds D[4 v + l / 16][l % 16] of each block in item v (measured
+    // on gfx950 with an in-bounds probe): D row = j offset, D column = i offset
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = ri + wr + 16 * a + li;              // row of A (tile-local to t0)
+                const int gj = rj + wc + 16 * b + 4 * v + lk;      // column of A
+                if (gi < m && gj < m && gi >= gj) {
+                    double* p = A + (long long)(t0 + gj) * lda + t0 + gi;
+                    *p -= acc[a][b][v];
+                }
+            }
+}
+
+// ---------------------------------------------------------------- triangular solves with L
+// Forward, diagonal block k (nb rows): X[b][k:k+nb] = L_kk^{-1} X[b][k:k+nb].
+// One wavefront per right-hand side; L_kk in LDS.
+__global__ __launch_bounds__(64) void k_trsv_fwd_diag(const double* __restrict__ L, long long lda, int k, int nb,
+                                                      double* __restrict__ X, long long ldx) {
+    __shared__ double l[kNB][kLP];
+    __shared__ double s[kNB];
+    const int i = threadIdx.x;
+    for (int c = 0; c < nb; ++c) l[c][i] = (i < nb && i >= c) ? L[(long long)(k + c) * lda + k + i] : 0.0;
+    double* x = X + blockIdx.x * ldx + k;
+    double xi = i < nb ? x[i] : 0.0;
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (i == j) {
+            xi /= l[j][j];
+            s[j] = xi;
+        }
+        __syncthreads();
+        if (i > j && i < nb) xi -= l[j][i] * s[j];
+    }
+    if (i < nb) x[i] = xi;
+}
+
+// Forward, rows below block k: X[b][r] -= sum_c L[r, k + c] X[b][k + c]
+// for r in [k + nb, n); one row per lane, all right-hand sides per lane.
+__global__ __launch_bounds__(256) void k_trsv_fwd_update(const double* __restrict__ L, long long lda, int n, int k,
+                                                         double* __restrict__ X, long long ldx, int nrhs) {
+    __shared__ double xs[8][kNB];
+    const long long r = (long long)k + kNB + blockIdx.x * 256 + threadIdx.x;
+    double lr[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) lr[c] = r < n ? L[(long long)(k + c) * lda + r] : 0.0;
+    for (int b0 = 0; b0 < nrhs; b0 += 8) {
+        const int nb = min(8, nrhs - b0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * kNB; e += 256) xs[e / kNB][e % kNB] = X[(long long)(b0 + e / kNB) * ldx + k + e % kNB];
+        __syncthreads();
+        if (r < n) {
+            for (int b = 0; b < nb; ++b) {
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < kNB; ++c) acc += lr[c] * xs[b][c];
+                X[(long long)(b0 + b) * ldx + r] -= acc;
+            }
+        }
+    }
+}
+
+// Backward, diagonal block k: X[b][k:k+nb] = L_kk^{-T} X[b][k:k+nb].
+__global__ __launch_bounds__(64) void k_trsv_bwd_diag(const double* __restrict__ L, long long lda, int k, int nb,
+                                                      double* __restrict__ X, long long ldx) {
+    __shared__ double l[kNB][kLP];
+    __shared__ double s[kNB];
+    const int i = threadIdx.x;
+    for (int c = 0; c < nb; ++c) l[c][i] = (i < nb && i >= c) ? L[(long long)(k + c) * lda + k + i] : 0.0;
+    double* x = X + blockIdx.x * ldx + k;
+    double xi = i < nb ? x[i] : 0.0;
+    __syncthreads();
+    for (int j = nb - 1; j >= 0; --j) {
+        if (i == j) {
+            xi /= l[j][j];
+            s[j] = xi;
+        }
+        __syncthreads();
+        if (i < j) xi -= l[i][j] * s[j];                 // L^T(i, j) = L(j, i)
+    }
+    if (i < nb) x[i] = xi;
+}
+
+// Backward, columns left of block k: X[b][c] -= sum_{r in block} L[r, c] X[b][r]
+// for c < k; a workgroup stages 64 columns' rows of the block in LDS (whole
+// 512-byte runs per column) and each lane sums one column.
+__global__ __launch_bounds__(64) void k_trsv_bwd_update(const double* __restrict__ L, long long lda, int k, int nb,
+                                                        double* __restrict__ X, long long ldx, int nrhs) {
+    __shared__ double t[kNB][kLP];                     // t[col][row in block]
+    __shared__ double xs[kNB];
+    const int c0 = blockIdx.x * 64, lane = threadIdx.x;
+    for (int cc = 0; cc < 64; ++cc) {
+        const int c = c0 + cc;
+        t[cc][lane] = (c < k && lane < nb) ? L[(long long)c * lda + k + lane] : 0.0;
+    }
+    for (int b = 0; b < nrhs; ++b) {
+        __syncthreads();
+        xs[lane] = lane < nb ? X[(long long)b * ldx + k + lane] : 0.0;
+        __syncthreads();
+        const int c = c0 + lane;
+        if (c < k) {
+            double acc = 0.0;
+#pragma unroll 8
+            for (int r = 0; r < kNB; ++r) acc += t[lane][r] * xs[r];
+            X[(long long)b * ldx + c] -= acc;
+        }
+    }
+}
+
+dim3 grid_for(long long n) { return dim3((unsigned)std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256))); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_unit_vectors(bool f64, void* E, long long N, long long j0, int ncols, double value, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_unit_vectors<double>, grid_for(N * ncols), dim3(256), 0, st, (double*)E, N, j0, ncols, value);
+    else
+        hipLaunchKernelGGL(k_unit_vectors<float>, grid_for(N * ncols), dim3(256), 0, st, (float*)E, N, j0, ncols,
+                           (float)value);
+    return hipGetLastError();
+}
+
+hipError_t launch_K_columns(bool f64, const void* H, long long N, double* K, long long ldk, long long j0, int ncols,
+                            const double* var, int var_mode, int Nd, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_K_columns<double>, grid_for(N * ncols), dim3(256), 0, st, (const double*)H, N, K, ldk, j0,
+                           ncols, var, var_mode, Nd);
+    else
+        hipLaunchKernelGGL(k_K_columns<float>, grid_for(N * ncols), dim3(256), 0, st, (const float*)H, N, K, ldk, j0,
+                           ncols, var, var_mode, Nd);
+    return hipGetLastError();
+}
+
+hipError_t launch_weight_data(bool f64, const void* d, void* D, long long N, int nrhs, const double* var, int var_mode,
+                              int Nd, double gamma, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_weight_data<double>, grid_for(N * nrhs), dim3(256), 0, st, (const double*)d, (double*)D, N,
+                           nrhs, var, var_mode, Nd, gamma);
+    else
+        hipLaunchKernelGGL(k_weight_data<float>, grid_for(N * nrhs), dim3(256), 0, st, (const float*)d, (float*)D, N,
+                           nrhs, var, var_mode, Nd, gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f64(bool f64, const void* Y, double* Z, long long N, int nrhs, long long ldz, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_to_f64<double>, grid_for(N * nrhs), dim3(256), 0, st, (const double*)Y, Z, N, nrhs, ldz);
+    else
+        hipLaunchKernelGGL(k_to_f64<float>, grid_for(N * nrhs), dim3(256), 0, st, (const float*)Y, Z, N, nrhs, ldz);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(bool f64, void* D, const double* Z, long long N, int nrhs, long long ldz, double a0, double a1,
+                          hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_combine<double>, grid_for(N * nrhs), dim3(256), 0, st, (double*)D, Z, N, nrhs, ldz, a0, a1);
+    else
+        hipLaunchKernelGGL(k_combine<float>, grid_for(N * nrhs), dim3(256), 0, st, (float*)D, Z, N, nrhs, ldz, a0, a1);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(bool f64, const void* v, void* out, long long n, double a0, double a1, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_axpby<double>, grid_for(n), dim3(256), 0, st, (const double*)v, (double*)out, n, a0, a1);
+    else
+        hipLaunchKernelGGL(k_axpby<float>, grid_for(n), dim3(256), 0, st, (const float*)v, (float*)out, n, a0, a1);
+    return hipGetLastError();
+}
+
+hipError_t launch_cholesky(double* A, long long n, long long lda, int* info, hipStream_t st) {
+    for (long long k = 0; k < n; k += kNB) {
+        const int nb = (int)std::min<long long>(kNB, n - k);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, A, lda, (int)k, nb, info);
+        const long long below = n - k - nb;
+        if (below <= 0) break;
+        hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, st, A, lda, (int)n, (int)k);
+        const long long T = (below + 63) / 64;
+        hipLaunchKernelGGL(k_syrk_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, st, A, lda, (int)n, (int)k);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cholesky_solve(const double* L, long long n, long long lda, double* X, int nrhs, long long ldx,
+                                 hipStream_t st) {
+    for (long long k = 0; k < n; k += kNB) {
+        const int nb = (int)std::min<long long>(kNB, n - k);
+        hipLaunchKernelGGL(k_trsv_fwd_diag, dim3(nrhs), dim3(64), 0, st, L, lda, (int)k, nb, X, ldx);
+        const long long below = n - k - nb;
+        if (below > 0)
+            hipLaunchKernelGGL(k_trsv_fwd_update, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, st, L, lda,
+                               (int)n, (int)k, X, ldx, nrhs);
+    }
+    for (long long k = (n - 1) / kNB * kNB; k >= 0; k -= kNB) {
+        const int nb = (int)std::min<long long>(kNB, n - k);
+        hipLaunchKernelGGL(k_trsv_bwd_diag, dim3(nrhs), dim3(64), 0, st, L, lda, (int)k, nb, X, ldx);
+        if (k > 0)
+            hipLaunchKernelGGL(k_trsv_bwd_update, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, st, L, lda, (int)k, nb, X,
+                               ldx, nrhs);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace p2o

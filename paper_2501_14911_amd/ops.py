@@ -231,6 +231,88 @@ class P2OOperator:
         return phi, grad
 
 
+    # ------------------------------------------------------------------ offline / online phases
+    def data_dim(self) -> int:
+        """N = Nt * Nd, the data-space dimension."""
+        return self.Nt * self.Nd
+
+    def assemble_K(self, noise_var, prior_var: float = 1.0, K: Optional[torch.Tensor] = None,
+                   batch: Optional[int] = None) -> torch.Tensor:
+        """K = Gamma_noise + prior_var F F^* as a dense FP64 [N, N] tensor
+        (row j of the tensor is column j of K; K is symmetric), assembled in
+        batches of ``batch`` (default max_rhs) columns."""
+        N = self.data_dim()
+        if K is None:
+            K = torch.empty((N, N), dtype=torch.float64, device=self.device)
+        if K.dtype != torch.float64 or K.device != self.device or K.dim() != 2 or K.shape[1] != N or K.shape[0] != N \
+                or K.stride(1) != 1:
+            raise ValueError(f"K must be a contiguous float64 [{N}, {N}] tensor on {self.device}")
+        var = torch.as_tensor(noise_var, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+        b = int(batch or self.max_rhs)
+        self._stream()
+        for j0 in range(0, N, b):
+            check(lib.p2o_assemble_K(self._plan, float(prior_var), _ptr(var), var.numel(), _ptr(K), K.stride(0), j0,
+                                     min(b, N - j0)))
+        return K
+
+    def map_point(self, d_obs: torch.Tensor, L: torch.Tensor, noise_var, prior_var: float = 1.0) -> torch.Tensor:
+        """MAP point m_map = (I - G^* K^{-1} F) G^* Gamma_noise^{-1} d_obs,
+        G^* = prior_var F^*, from K's Cholesky factor L (``cholesky``)."""
+        db, sq = self._series(d_obs, self.Nd, "d_obs")
+        nrhs = db.shape[0]
+        _check_factor(L, self.data_dim(), self.device)
+        var = torch.as_tensor(noise_var, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+        m = torch.empty((nrhs, self.Nt, self.Nm), dtype=self.dtype, device=self.device)
+        self._stream()
+        check(lib.p2o_map_point(self._plan, float(prior_var), _ptr(var), var.numel(), _ptr(L), L.stride(0), _ptr(db),
+                                _ptr(m), nrhs))
+        return m[0] if sq else m
+
+    def posterior_cov_apply(self, v: torch.Tensor, L: torch.Tensor, prior_var: float = 1.0) -> torch.Tensor:
+        """Gamma_post v = (I - G^* K^{-1} F) Gamma_prior v with Gamma_prior =
+        prior_var I, from K's Cholesky factor L."""
+        vb, sq = self._series(v, self.Nm, "v")
+        nrhs = vb.shape[0]
+        _check_factor(L, self.data_dim(), self.device)
+        out = torch.empty_like(vb)
+        self._stream()
+        check(lib.p2o_posterior_cov_apply(self._plan, float(prior_var), _ptr(L), L.stride(0), _ptr(vb), _ptr(out), nrhs))
+        return out[0] if sq else out
+
+
+def _check_factor(L: torch.Tensor, N: int, device):
+    if L.dtype != torch.float64 or L.device != device or L.dim() != 2 or tuple(L.shape) != (N, N) or L.stride(1) != 1:
+        raise ValueError(f"L must be a contiguous float64 [{N}, {N}] tensor on {device}")
+
+
+def cholesky(K: torch.Tensor) -> torch.Tensor:
+    """In-place Cholesky factorisation of the symmetric positive definite FP64
+    [N, N] tensor K (row j = column j of K): on return its entries (j, i) with
+    i >= j, i.e. the lower triangle of the column-major matrix, hold L with
+    K = L L^T.  Raises when a pivot is not positive."""
+    if K.dtype != torch.float64 or K.dim() != 2 or K.shape[0] != K.shape[1] or K.stride(1) != 1:
+        raise ValueError("K must be a square float64 tensor with unit column stride")
+    info = torch.zeros(1, dtype=torch.int32, device=K.device)
+    check(lib.p2o_cholesky(_ptr(K), K.shape[0], K.stride(0), _ptr(info),
+                           c_void_p(torch.cuda.current_stream(K.device).cuda_stream)))
+    bad = int(info.item())
+    if bad:
+        raise ValueError(f"K is not positive definite (pivot {bad - 1} not positive)")
+    return K
+
+
+def cholesky_solve(L: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """X <- K^{-1} X in place for X of shape [nrhs, N] (each row one
+    right-hand side), from the factor of ``cholesky``."""
+    N = L.shape[0]
+    _check_factor(L, N, L.device)
+    if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != N or X.stride(1) != 1:
+        raise ValueError(f"X must be a float64 [nrhs, {N}] tensor with unit column stride")
+    check(lib.p2o_cholesky_solve(_ptr(L), N, L.stride(0), _ptr(X), X.shape[0], X.stride(0),
+                                 c_void_p(torch.cuda.current_stream(L.device).cuda_stream)))
+    return X
+
+
 # ---------------------------------------------------------------------- autograd
 class P2O(torch.autograd.Function):
     """d = F m with backward m_bar = F^* d_bar (the hand-written adjoint)."""

@@ -156,7 +156,8 @@ def test_python_operator_requires_a_gpu_device():
 def test_gemm_tile_table_and_autotune_checks():
     tiles = p2o.gemm_tiles()
     assert tiles == [(2, 4, 5, 64), (2, 2, 5, 64), (4, 2, 5, 32), (2, 2, 4, 64), (4, 2, 4, 32), (2, 2, 5, 64),
-                     (4, 2, 5, 64), (4, 2, 5, 64), (4, 2, 5, 32), (2, 2, 4, 64), (4, 2, 4, 32)]
+                     (4, 2, 5, 64), (4, 2, 5, 64), (4, 2, 5, 32), (2, 2, 4, 64), (4, 2, 4, 32), (2, 2, 1, 64),
+                     (4, 2, 1, 64)]
     assert lib.p2o_gemm_tile_info(len(tiles), None, None, None, None) == ARG
     assert lib.p2o_gemm_tile_info(-1, None, None, None, None) == ARG
     st, plan = create(Nd=4, Nm=64, Nt=16, prec=2, max_rhs=4)
@@ -170,8 +171,8 @@ def test_gemm_tile_table_and_autotune_checks():
 
 
 def test_matrix_core_option_needs_a_16_bit_spectrum():
-    """P2O_BATCHED_MFMA is accepted for BF16 and FP16 spectra (FP16 entries are
-    split into BF16 hi + lo on the matrix cores) and refused for FP32 / FP64."""
+    """P2O_BATCHED_MFMA is accepted for BF16 and FP16 spectra (FP16 spectra take
+    FP16 products with scaled FP16 right-hand sides) and refused for FP32 / FP64."""
     for prec, want in ((0, DTYPE), (1, DTYPE), (2, OK), (3, OK)):
         st, plan = create(Nd=4, Nm=64, Nt=16, prec=prec, max_rhs=4)
         assert st == OK

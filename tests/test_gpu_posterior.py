@@ -1,0 +1,118 @@
+"""GPU parity of the offline and online phases (data-space matrix K, its
+Cholesky factor and solves, MAP point, posterior-covariance actions) through
+the C ABI against the FP64 oracle (oracle/posterior.py), with the stand-in
+prior Gamma_prior = gamma I.
+
+Tolerances: K's columns carry the operator's own error (1e-12 FP64, 1e-5
+FP32, 2e-3 FP16 per column).  The factorisation and the solves are FP64 on
+both sides and are checked on the oracle's own K: backward error
+||L L^T - K|| / ||K|| <= 1e-14 (blocked Cholesky is backward stable), and the
+factor and solutions against numpy's within 1e-11 at the condition numbers
+used (K = Gamma_noise + gamma F F^T with the noise chosen to keep cond(K)
+below 1e3).  The MAP point and the posterior actions on an FP64 plan follow
+from these: 1e-10."""
+import numpy as np
+import pytest
+
+from conftest import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ensure_built()
+
+import oracle  # noqa: E402
+from oracle import posterior as OP  # noqa: E402
+import synth  # noqa: E402
+from paper_2501_14911_amd import P2OOperator, cholesky, cholesky_solve  # noqa: E402
+
+DEV = "cuda"
+SMALL = synth.Workload("post_small", Nd=8, Nm=512, Nt=63, tau=8.0)       # N = 504: ragged last 64-block
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def build(w, precision, max_rhs):
+    F = synth.operator_blocks(w)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, precision, max_rhs=max_rhs, device=DEV)
+    Ft = torch.from_numpy(F).to(DEV)
+    op.load(lambda c0, n: Ft[:, :, c0:c0 + n])
+    return op, F
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp16", 2e-3)])
+def test_assemble_K(precision, tol):
+    w = SMALL
+    rng = np.random.default_rng(1)
+    var = rng.uniform(0.5, 2.0, w.Nd) * 0.05
+    op, F = build(w, precision, max_rhs=40)               # 504 columns in batches of 40 (ragged last)
+    K = op.assemble_K(torch.from_numpy(var).to(DEV), prior_var=0.7)
+    Ko = OP.data_space_matrix(F, var, prior_var=0.7)
+    Kg = K.cpu().numpy().T                                # tensor row j = column j of K
+    errs = np.linalg.norm(Kg - Ko, axis=0) / np.linalg.norm(Ko, axis=0)
+    note(f"[posterior] K {precision}: worst column rel-L2 {errs.max():.3e}")
+    assert errs.max() <= tol
+
+
+def test_cholesky_and_solve_on_oracle_K():
+    w = SMALL
+    F = synth.operator_blocks(w)
+    Ko = OP.data_space_matrix(F, 0.05, prior_var=1.0)
+    N = Ko.shape[0]
+    note(f"[posterior] cond(K) {np.linalg.cond(Ko):.2e}")
+    K = torch.from_numpy(Ko.T.copy()).to(DEV)
+    L = cholesky(K)
+    Lg = np.tril(L.cpu().numpy().T)                       # lower triangle of the column-major factor
+    Lo = OP.cholesky_lower(Ko)
+    back = np.linalg.norm(Lg @ Lg.T - Ko) / np.linalg.norm(Ko)
+    fwd = np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo)
+    note(f"[posterior] Cholesky: backward error {back:.2e}, factor vs numpy {fwd:.2e}")
+    assert back <= 1e-14 and fwd <= 1e-11
+    # the strict upper triangle of the column-major matrix is left as it was
+    upper = np.triu(np.ones((N, N), dtype=bool), 1)
+    assert np.array_equal(L.cpu().numpy().T[upper], Ko[upper])
+    rng = np.random.default_rng(2)
+    B = rng.standard_normal((3, N))
+    X = cholesky_solve(L, torch.from_numpy(B).to(DEV)).cpu().numpy()
+    Xo = OP.solve_with_factor(Lo, B.T).T
+    err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    note(f"[posterior] solve vs oracle {err:.2e}")
+    assert err <= 1e-11
+
+
+def test_cholesky_reports_non_positive_pivot():
+    A = -torch.eye(70, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError, match="pivot 0"):
+        cholesky(A)
+    B = torch.eye(130, dtype=torch.float64, device=DEV)
+    B[100, 100] = -1.0                                   # in the third diagonal block
+    with pytest.raises(ValueError, match="pivot 100"):
+        cholesky(B)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_map_point_and_posterior_actions(precision, tol):
+    w = SMALL
+    rng = np.random.default_rng(3)
+    var = rng.uniform(0.5, 2.0, w.Nd * w.Nt) * 0.05
+    gam = 0.6
+    op, F = build(w, precision, max_rhs=64)
+    L = cholesky(op.assemble_K(torch.from_numpy(var).to(DEV), prior_var=gam))
+    Lo = OP.cholesky_lower(OP.data_space_matrix(F, var, gam))
+    d = synth.data_series(w, 2)
+    m = op.map_point(torch.from_numpy(d).to(DEV, op.dtype), L, torch.from_numpy(var).to(DEV), gam)
+    m = m.double().cpu().numpy()
+    for b in range(2):
+        mo = OP.map_point(F, d[b], var, gam, Lo)
+        e = oracle.rel_l2(m[b], mo)
+        note(f"[posterior] MAP {precision} rhs {b}: {e:.2e}")
+        assert e <= tol
+    v = synth.param_series(w, 2)
+    g = op.posterior_cov_apply(torch.from_numpy(v).to(DEV, op.dtype), L, gam).double().cpu().numpy()
+    for b in range(2):
+        go = OP.posterior_cov_apply(F, v[b], var, gam, Lo)
+        e = oracle.rel_l2(g[b], go)
+        note(f"[posterior] Gamma_post v {precision} rhs {b}: {e:.2e}")
+        assert e <= tol
