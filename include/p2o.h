@@ -234,6 +234,43 @@ p2o_status p2o_map_point(p2o_plan* plan, double prior_var, const double* noise_v
 p2o_status p2o_posterior_cov_apply(p2o_plan* plan, double prior_var, const double* L,
                                    int64_t ldl, const void* v, void* out, int64_t nrhs);
 
+/* h = F G^* e for two plans on the same parameter grid (same Nm, Nt,
+ * storage precision and stream, both loaded; nrhs at most both max_rhs):
+ * e is a data series of G ([nrhs][Nt / r_G][Nd_G]), h one of F
+ * ([nrhs][Nt / r_F][Nd_F]).  With G = F_q (the p2q map, equation p2q) this is
+ * the cross product F F_q^* of the QoI phases (section 4, Phase 3); G's
+ * adjoint pass and the truncate-and-re-pad run in G's workspace, F's forward
+ * pass in F's.  Asynchronous on the plans' stream. */
+p2o_status p2o_apply_FGt(p2o_plan* F, p2o_plan* G, const void* e, void* h, int64_t nrhs);
+
+/* Rows [r0, r0 + nrows) of the data-to-QoI map Q = F_q (I - G^* K^{-1} F) G^*
+ * Gamma_noise^{-1} (section 4, Phase 3, equation d2q-map; G^* = prior_var F^*)
+ * into Q (device FP64, row r at Q + r * ldq, ldq >= N = Nt * Nd): row r is
+ * Q^T e_r = prior_var Gamma_noise^{-1} (y - F F^* z) with y = F F_q^* e_r and
+ * z = prior_var K^{-1} y, all in data space (no parameter-sized buffer).
+ * F: the p2o plan (output stride 1), Fq: the p2q plan (any output stride;
+ * Q has Nq (Nt / r) rows, the QoI index being i * Nq + q).  L: K's Cholesky
+ * factor.  1 <= nrows <= max_rhs of both plans.  Uses both workspaces. */
+p2o_status p2o_d2q_rows(p2o_plan* F, p2o_plan* Fq, double prior_var, const double* noise_var,
+                        int64_t noise_var_len, const double* L, int64_t ldl, int64_t r0,
+                        int64_t nrows, double* Q, int64_t ldq);
+
+/* Columns [c0, c0 + ncols) of the QoI posterior covariance
+ * Gamma_post(q) = F_q (I - G^* K^{-1} F) G_q^* with G_q^* = prior_var F_q^*
+ * (section 4, Phase 3, equations qoi-covariance and fast-qoi-covariance),
+ * C device FP64, column c at C + c * ldc, ldc >= Nq (Nt / r): column c is
+ * prior_var (F_q F_q^* e_c - F_q G^* z) with z = K^{-1} F F_q^* e_c.  Plans
+ * and L as for p2o_d2q_rows. */
+p2o_status p2o_qoi_posterior_cov(p2o_plan* F, p2o_plan* Fq, double prior_var, const double* L,
+                                 int64_t ldl, int64_t c0, int64_t ncols, double* C, int64_t ldc);
+
+/* The online QoI prediction q = Q d (section 4, Phase 4, equation
+ * real-time-qoi, zero prior mean): q[b] = Q d[b] for nrhs data vectors of N
+ * values (device FP64, d[b] at d + b * N, q[b] at q + b * nq), Q as written
+ * by p2o_d2q_rows.  Asynchronous on `stream`. */
+p2o_status p2o_d2q_apply(const double* Q, int64_t nq, int64_t N, int64_t ldq, const double* d, double* q,
+                         int64_t nrhs, void* stream);
+
 /* Stages of the calls above, for per-stage timing. */
 typedef enum {
     P2O_STAGE_R2C = 0,       /* zero-padded real FFT along time              */
@@ -258,7 +295,16 @@ typedef enum {
     P2O_OPT_FFT_FIXED = 2    /* value: 1 (default) runs the time-axis FFTs (section 4's circulant
                                 embedding) with kernels compiled for the plan's transform length when
                                 the library has them (lengths L = 32, 256, 840), 0 always with the
-                                runtime-length kernels; both compute the same transforms */
+                                runtime-length kernels; both compute the same transforms */,
+    P2O_OPT_OUTPUT_STRIDE = 3  /* value r >= 1 dividing Nt (default 1): the plan's data series are
+                                  observed every r-th step, the multi-rate output of a p2q map whose
+                                  QoIs have a coarser time grid than its parameters (section 2, remark
+                                  on distinct temporal discretisations; section 5: QoIs at 1 Hz,
+                                  parameters at 10 Hz).  Data series then have Nt / r steps, step i
+                                  standing for step r (i + 1) - 1 of the parameter grid:
+                                  p2o_apply_F returns the outputs at those steps, p2o_apply_Ft and
+                                  p2o_apply_FFt take inputs there (zero between them).  Ragged
+                                  lengths, the misfit and the data-space calls need r = 1. */
 } p2o_option;
 
 /* How calls with several right-hand sides do the per-frequency products.

@@ -63,6 +63,10 @@ def _load():
         "p2o_cholesky_solve": [pv, c_int64, c_int64, pv, c_int64, c_int64, pv],
         "p2o_map_point": [pv, c_double, pv, c_int64, pv, c_int64, pv, pv, c_int64],
         "p2o_posterior_cov_apply": [pv, c_double, pv, c_int64, pv, pv, c_int64],
+        "p2o_apply_FGt": [pv, pv, pv, pv, c_int64],
+        "p2o_d2q_rows": [pv, pv, c_double, pv, c_int64, pv, c_int64, c_int64, c_int64, pv, c_int64],
+        "p2o_qoi_posterior_cov": [pv, pv, c_double, pv, c_int64, c_int64, c_int64, pv, c_int64],
+        "p2o_d2q_apply": [pv, c_int64, c_int64, c_int64, pv, pv, c_int64, pv],
         "p2o_profile_enable": [pv, c_int32],
         "p2o_set_option": [pv, c_int32, c_int64],
         "p2o_profile_read_nrhs": [pv, c_int32, c_int64, POINTER(c_double), POINTER(c_int64)],

@@ -93,6 +93,7 @@ struct p2o_plan {
     int c2r_nd_blocks = 1;
     int batched_mode = P2O_BATCHED_AUTO;
     int gemm_tile = -1;                     // forced matrix-core tile variant, -1: tuned or built-in
+    int qstride = 1;                        // data series observed every qstride-th step (multi-rate QoI maps)
     std::map<int64_t, int> tuned_fwd, tuned_adj;   // autotuned variant per right-hand-side count
     // bound memory
     char* fhat = nullptr;
@@ -332,12 +333,13 @@ int gemm_tile_for(const p2o_plan* p, const std::map<int64_t, int>& tuned, int64_
     return it == tuned.end() ? -1 : it->second;
 }
 
-// X (parameter spectra) -> Y partial products
-p2o_status enqueue_fwd_products(p2o_plan* p, const void* X, void* Y, int64_t nrhs) {
+// X (parameter spectra) -> Y partial products; xscale: the FP16 operand
+// scales written with X (this plan's own unless X comes from another plan)
+p2o_status enqueue_fwd_products(p2o_plan* p, const void* X, void* Y, int64_t nrhs, const float* xscale = nullptr) {
     if (mfma_on(p, nrhs))
         return staged(p, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores)", [&] {
             GemmArgs ga = gemm_args(p, nrhs);
-            ga.rhs_scale = scale_X(p);
+            ga.rhs_scale = xscale ? xscale : scale_X(p);
             return launch_gemm_fwd(ga, gemm_tile_for(p, p->tuned_fwd, nrhs), p->fhat, scales_of(p), X, Y, p->stream);
         });
     return staged(p, P2O_STAGE_GEMV_FWD, "forward per-frequency products", [&] {
@@ -446,6 +448,66 @@ p2o_status enqueue_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, co
         return launch_c2r(f64_plan(p), p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), p->ws + p->off_Y, d,
                           tw_of(p), nullptr, nullptr, 0, nullptr, p->stream);
     });
+}
+
+// h = F G^* e for two plans with the same parameter grid (Nm, Nt) and
+// storage: G's adjoint pass and the truncate-and-re-pad in G's workspace,
+// then F's forward products on G's parameter spectra and F's inverse FFT.
+// e and h are full-grid series (every step).
+p2o_status enqueue_cross(p2o_plan* F, p2o_plan* G, const void* e, void* h, int64_t nrhs) {
+    G->cur_nrhs = nrhs;
+    F->cur_nrhs = nrhs;
+    p2o_status s = enqueue_adjoint_to_X(G, e, nrhs, nullptr);
+    if (s) return s;
+    s = staged(G, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
+        return launch_project(f64_plan(G), G->fft, io_param_rhs(G, nrhs, nullptr, adj_parts(G, nrhs)),
+                              G->ws + G->off_X, tw_of(G), G->stream);
+    });
+    if (s) return s;
+    s = enqueue_fwd_products(F, G->ws + G->off_X, F->ws + F->off_Y, nrhs, scale_X(G));
+    if (s) return s;
+    return staged(F, P2O_STAGE_C2R, "c2r (data)", [&] {
+        return launch_c2r(f64_plan(F), F->fft, io_data(F, nrhs, nullptr, fwd_parts(F, nrhs)), F->ws + F->off_Y, h,
+                          tw_of(F), nullptr, nullptr, 0, nullptr, F->stream);
+    });
+}
+
+// Multi-rate plans exchange data series of Nt / qstride steps: expand one
+// to the full grid (zeros between its steps) in `full`, or sample a full one.
+p2o_status qoi_expand(p2o_plan* p, const void* q, void* full, int64_t nrhs) {
+    return check_hip(launch_qoi_scatter(f64_plan(p), q, full, (int)p->Nt, (int)p->Nd, p->qstride, (int)nrhs, p->stream),
+                     "series to the full grid");
+}
+p2o_status qoi_sample(p2o_plan* p, const void* full, void* q, int64_t nrhs) {
+    return check_hip(launch_qoi_gather(f64_plan(p), full, q, nullptr, 0, 0, 1.0, false, (int)p->Nt, (int)p->Nd,
+                                       p->qstride, (int)nrhs, p->stream), "series at the observed steps");
+}
+
+p2o_status every_step(const p2o_plan* p, const char* what) {
+    if (p->qstride != 1)
+        return fail(P2O_ERR_STATE, "%s needs data at every step (the plan observes every %d-th step)", what, p->qstride);
+    return P2O_OK;
+}
+
+// Two plans that share the parameter grid, storage and stream, ready for
+// nrhs right-hand sides.
+p2o_status compatible(const p2o_plan* F, const p2o_plan* G, int64_t nrhs) {
+    if (!F || !G) return fail(P2O_ERR_ARG, "plan is NULL");
+    if (F->Nm != G->Nm || F->Nt != G->Nt)
+        return fail(P2O_ERR_ARG, "plans differ in Nm (%lld, %lld) or Nt (%lld, %lld)", (long long)F->Nm,
+                    (long long)G->Nm, (long long)F->Nt, (long long)G->Nt);
+    if (F->prec != G->prec) return fail(P2O_ERR_DTYPE, "plans differ in storage precision");
+    if (F->stream != G->stream) return fail(P2O_ERR_ARG, "plans must use the same stream");
+    if (F->state != kReady || G->state != kReady)
+        return fail(P2O_ERR_STATE, "spectrum not loaded (call p2o_load_blocks and p2o_load_finalize)");
+    if (nrhs < 1 || nrhs > F->max_rhs || nrhs > G->max_rhs)
+        return fail(P2O_ERR_ARG, "nrhs=%lld outside [1, min(max_rhs)=%lld]", (long long)nrhs,
+                    (long long)std::min(F->max_rhs, G->max_rhs));
+    if (mfma_on(F, nrhs) != mfma_on(G, nrhs))
+        return fail(P2O_ERR_STATE, "the plans take different product paths for %lld right-hand sides (batched modes)",
+                    (long long)nrhs);
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return P2O_OK;
 }
 
 // ---------------------------------------------------------------- scratch of the allocation-free entry point
@@ -601,6 +663,12 @@ p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
     if (option == P2O_OPT_FFT_FIXED) {
         if (value != 0 && value != 1) return fail(P2O_ERR_ARG, "fixed-length FFT switch %lld is not 0 or 1", (long long)value);
         p->fft.fixed = (int)value;
+        return P2O_OK;
+    }
+    if (option == P2O_OPT_OUTPUT_STRIDE) {
+        if (value < 1 || value > p->Nt || p->Nt % value != 0)
+            return fail(P2O_ERR_ARG, "output stride %lld must divide Nt=%lld", (long long)value, (long long)p->Nt);
+        p->qstride = (int)value;
         return P2O_OK;
     }
     return fail(P2O_ERR_ARG, "unknown option %d", (int)option);
@@ -869,6 +937,11 @@ p2o_status p2o_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const 
     try {
         p2o_status s = ready_for_apply(p, m, d, nrhs);
         if (s) return s;
+        if (p->qstride > 1) {
+            if (nt_active) return fail(P2O_ERR_ARG, "ragged lengths are not defined with an output stride");
+            s = enqueue_apply_F(p, m, p->ws + p->off_D2, nrhs, nullptr);
+            return s ? s : qoi_sample(p, p->ws + p->off_D2, d, nrhs);
+        }
         return enqueue_apply_F(p, m, d, nrhs, nt_active);
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_apply_F");
@@ -878,6 +951,8 @@ p2o_status p2o_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, const 
 p2o_status p2o_apply_F_noalloc(p2o_plan* p, const void* m, void* d, int64_t nrhs, const int32_t* nt_active) {
     try {
         p2o_status s = ready_for_apply(p, m, d, nrhs);
+        if (s) return s;
+        s = every_step(p, "p2o_apply_F_noalloc");
         if (s) return s;
         // the workspace layout for exactly nrhs right-hand sides, carved from
         // this device's scratch array for the duration of the call
@@ -916,6 +991,11 @@ p2o_status p2o_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, const
     try {
         p2o_status s = ready_for_apply(p, d, m, nrhs);
         if (s) return s;
+        if (p->qstride > 1) {
+            if (nt_active) return fail(P2O_ERR_ARG, "ragged lengths are not defined with an output stride");
+            s = qoi_expand(p, d, p->ws + p->off_D, nrhs);
+            return s ? s : enqueue_apply_Ft(p, p->ws + p->off_D, m, nrhs, nullptr);
+        }
         return enqueue_apply_Ft(p, d, m, nrhs, nt_active);
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_apply_Ft");
@@ -926,6 +1006,12 @@ p2o_status p2o_apply_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, cons
     try {
         p2o_status s = ready_for_apply(p, e, h, nrhs);
         if (s) return s;
+        if (p->qstride > 1) {
+            if (nt_active) return fail(P2O_ERR_ARG, "ragged lengths are not defined with an output stride");
+            s = qoi_expand(p, e, p->ws + p->off_D, nrhs);
+            if (!s) s = enqueue_FFt(p, p->ws + p->off_D, p->ws + p->off_D2, nrhs, nullptr);
+            return s ? s : qoi_sample(p, p->ws + p->off_D2, h, nrhs);
+        }
         return enqueue_FFt(p, e, h, nrhs, nt_active);
     } catch (...) {
         return fail(P2O_ERR_ARG, "internal error in p2o_apply_FFt");
@@ -947,6 +1033,7 @@ p2o_status p2o_assemble_K(p2o_plan* p, double prior_var, const double* noise_var
             return fail(P2O_ERR_ARG, "columns [%lld, %lld) outside [0, %lld)", (long long)j0, (long long)(j0 + ncols),
                         (long long)N);
         s = ready_for_apply(p, K, K, ncols);
+        if (!s) s = every_step(p, "p2o_assemble_K");
         if (s) return s;
         p->cur_nrhs = ncols;
         void* E = p->ws + p->off_D;
@@ -994,6 +1081,7 @@ p2o_status p2o_map_point(p2o_plan* p, double prior_var, const double* noise_var,
         const int64_t N = p->Nt * p->Nd;
         if (ldl < N) return fail(P2O_ERR_ARG, "ldl=%lld < Nt*Nd=%lld", (long long)ldl, (long long)N);
         s = ready_for_apply(p, d_obs, m_map, nrhs);
+        if (!s) s = every_step(p, "p2o_map_point");
         if (s) return s;
         p->cur_nrhs = nrhs;
         const bool f64 = f64_plan(p);
@@ -1026,6 +1114,7 @@ p2o_status p2o_posterior_cov_apply(p2o_plan* p, double prior_var, const double* 
         const int64_t N = p->Nt * p->Nd;
         if (ldl < N) return fail(P2O_ERR_ARG, "ldl=%lld < Nt*Nd=%lld", (long long)ldl, (long long)N);
         p2o_status s = ready_for_apply(p, v, out, nrhs);
+        if (!s) s = every_step(p, "p2o_posterior_cov_apply");
         if (s) return s;
         if (v == out) return fail(P2O_ERR_ARG, "v and out must not be the same buffer");
         p->cur_nrhs = nrhs;
@@ -1049,6 +1138,121 @@ p2o_status p2o_posterior_cov_apply(p2o_plan* p, double prior_var, const double* 
     }
 }
 
+p2o_status p2o_apply_FGt(p2o_plan* F, p2o_plan* G, const void* e, void* h, int64_t nrhs) {
+    try {
+        p2o_status s = compatible(F, G, nrhs);
+        if (s) return s;
+        if (!e || !h) return fail(P2O_ERR_ARG, "input or output pointer is NULL");
+        const void* e_full = e;
+        if (G->qstride > 1) {
+            s = qoi_expand(G, e, G->ws + G->off_D, nrhs);
+            if (s) return s;
+            e_full = G->ws + G->off_D;
+        }
+        void* h_full = F->qstride > 1 ? F->ws + F->off_D2 : h;
+        s = enqueue_cross(F, G, e_full, h_full, nrhs);
+        if (s) return s;
+        return F->qstride > 1 ? qoi_sample(F, h_full, h, nrhs) : P2O_OK;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_apply_FGt");
+    }
+}
+
+p2o_status p2o_d2q_rows(p2o_plan* F, p2o_plan* Fq, double prior_var, const double* noise_var, int64_t noise_var_len,
+                        const double* L, int64_t ldl, int64_t r0, int64_t nrows, double* Q, int64_t ldq) {
+    try {
+        p2o_status s = compatible(F, Fq, nrows);
+        if (s) return s;
+        if (!L || !noise_var || !Q) return fail(P2O_ERR_ARG, "L, noise_var or Q is NULL");
+        int var_mode;
+        s = noise_mode(F, noise_var_len, &var_mode);
+        if (!s) s = every_step(F, "the data side of p2o_d2q_rows");
+        if (s) return s;
+        if (!(prior_var > 0.0) || prior_var > 1e300) return fail(P2O_ERR_ARG, "prior_var must be positive and finite");
+        const int64_t N = F->Nt * F->Nd, nq = (F->Nt / Fq->qstride) * Fq->Nd;
+        if (ldl < N || ldq < N) return fail(P2O_ERR_ARG, "ldl=%lld or ldq=%lld < Nt*Nd=%lld", (long long)ldl, (long long)ldq, (long long)N);
+        if (r0 < 0 || r0 + nrows > nq)
+            return fail(P2O_ERR_ARG, "rows [%lld, %lld) outside [0, %lld)", (long long)r0, (long long)(r0 + nrows), (long long)nq);
+        const bool f64 = f64_plan(F);
+        // unit QoI vectors -> y = F F_q^* e_r (Fq's series expanded in its own workspace)
+        void* E = Fq->ws + Fq->off_D2;
+        s = check_hip(launch_unit_vectors(f64, E, nq, r0, (int)nrows, 1.0, F->stream), "unit vectors");
+        const void* E_full = E;
+        if (!s && Fq->qstride > 1) {
+            s = qoi_expand(Fq, E, Fq->ws + Fq->off_D, nrows);
+            E_full = Fq->ws + Fq->off_D;
+        }
+        void* Y = F->ws + F->off_D;
+        void* H = F->ws + F->off_D2;
+        double* Z = reinterpret_cast<double*>(F->ws + F->off_Z);
+        if (!s) s = enqueue_cross(F, Fq, E_full, Y, nrows);
+        // z = gamma K^{-1} y; h = F F^* z (= F G^* K^{-1} y)
+        if (!s) s = check_hip(launch_to_f64(f64, Y, Z, N, (int)nrows, N, F->stream), "data vectors to FP64");
+        if (!s) s = check_hip(launch_cholesky_solve(L, N, ldl, Z, (int)nrows, N, F->stream), "K solve");
+        if (!s) s = check_hip(launch_combine(f64, H, Z, N, (int)nrows, N, 0.0, prior_var, F->stream), "gamma z");
+        if (!s) s = enqueue_FFt(F, H, H, nrows, nullptr);
+        // row = gamma Gamma_noise^{-1} (y - h)
+        if (!s) s = check_hip(launch_d2q_rows(f64, Y, H, N, (int)nrows, Q, ldq, r0, noise_var, var_mode, (int)F->Nd,
+                                              prior_var, F->stream), "d2q rows");
+        return s;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_d2q_rows");
+    }
+}
+
+p2o_status p2o_qoi_posterior_cov(p2o_plan* F, p2o_plan* Fq, double prior_var, const double* L, int64_t ldl,
+                                 int64_t c0, int64_t ncols, double* C, int64_t ldc) {
+    try {
+        p2o_status s = compatible(F, Fq, ncols);
+        if (s) return s;
+        if (!L || !C) return fail(P2O_ERR_ARG, "L or C is NULL");
+        s = every_step(F, "the data side of p2o_qoi_posterior_cov");
+        if (s) return s;
+        if (!(prior_var > 0.0) || prior_var > 1e300) return fail(P2O_ERR_ARG, "prior_var must be positive and finite");
+        const int64_t N = F->Nt * F->Nd, nq = (F->Nt / Fq->qstride) * Fq->Nd;
+        if (ldl < N) return fail(P2O_ERR_ARG, "ldl=%lld < Nt*Nd=%lld", (long long)ldl, (long long)N);
+        if (ldc < nq) return fail(P2O_ERR_ARG, "ldc=%lld < Nq*Ntq=%lld", (long long)ldc, (long long)nq);
+        if (c0 < 0 || c0 + ncols > nq)
+            return fail(P2O_ERR_ARG, "columns [%lld, %lld) outside [0, %lld)", (long long)c0, (long long)(c0 + ncols),
+                        (long long)nq);
+        const bool f64 = f64_plan(F);
+        const int rq = Fq->qstride;
+        void* E = Fq->ws + Fq->off_D2;
+        void* Efull = Fq->ws + Fq->off_D;
+        s = check_hip(launch_unit_vectors(f64, E, nq, c0, (int)ncols, 1.0, F->stream), "unit vectors");
+        if (!s) s = qoi_expand(Fq, E, Efull, ncols);           // stride 1: a copy
+        // y = F F_q^* e_c
+        void* Y = F->ws + F->off_D;
+        double* Z = reinterpret_cast<double*>(F->ws + F->off_Z);
+        if (!s) s = enqueue_cross(F, Fq, Efull, Y, ncols);
+        // C[:, c] = gamma F_q F_q^* e_c ...
+        if (!s) s = enqueue_FFt(Fq, Efull, Efull, ncols, nullptr);
+        if (!s) s = check_hip(launch_qoi_gather(f64, Efull, nullptr, C, ldc, c0, prior_var, false, (int)Fq->Nt,
+                                                (int)Fq->Nd, rq, (int)ncols, F->stream), "QoI columns");
+        // ... - gamma F_q G^* K^{-1} y, G^* = gamma F^*
+        if (!s) s = check_hip(launch_to_f64(f64, Y, Z, N, (int)ncols, N, F->stream), "data vectors to FP64");
+        if (!s) s = check_hip(launch_cholesky_solve(L, N, ldl, Z, (int)ncols, N, F->stream), "K solve");
+        void* W = F->ws + F->off_D2;
+        if (!s) s = check_hip(launch_combine(f64, W, Z, N, (int)ncols, N, 0.0, prior_var, F->stream), "gamma z");
+        if (!s) s = enqueue_cross(Fq, F, W, Efull, ncols);
+        if (!s) s = check_hip(launch_qoi_gather(f64, Efull, nullptr, C, ldc, c0, -prior_var, true, (int)Fq->Nt,
+                                                (int)Fq->Nd, rq, (int)ncols, F->stream), "QoI columns");
+        return s;
+    } catch (...) {
+        return fail(P2O_ERR_ARG, "internal error in p2o_qoi_posterior_cov");
+    }
+}
+
+p2o_status p2o_d2q_apply(const double* Q, int64_t nq, int64_t N, int64_t ldq, const double* d, double* q, int64_t nrhs,
+                         void* stream) {
+    if (!Q || !d || !q) return fail(P2O_ERR_ARG, "Q, d or q is NULL");
+    if (nq < 1 || N < 1 || ldq < N || nrhs < 1 || nrhs > 65535)
+        return fail(P2O_ERR_ARG, "nq=%lld, N=%lld, ldq=%lld or nrhs=%lld invalid", (long long)nq, (long long)N,
+                    (long long)ldq, (long long)nrhs);
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return check_hip(launch_d2q_apply(Q, nq, N, ldq, d, q, (int)nrhs, static_cast<hipStream_t>(stream)), "Q d");
+}
+
 p2o_status p2o_misfit_grad(p2o_plan* p, const void* m, const void* d_obs, const double* noise_var,
                            int64_t noise_var_len, void* grad, double* misfit, int64_t nrhs, const int32_t* nt_active) {
     try {
@@ -1058,6 +1262,7 @@ p2o_status p2o_misfit_grad(p2o_plan* p, const void* m, const void* d_obs, const 
         p2o_status s = noise_mode(p, noise_var_len, &var_mode);
         if (s) return s;
         s = ready_for_apply(p, m, grad, nrhs);
+        if (!s) s = every_step(p, "p2o_misfit_grad");
         if (s) return s;
         p->cur_nrhs = nrhs;
         s = enqueue_forward_to_Y(p, m, nrhs, nt_active);

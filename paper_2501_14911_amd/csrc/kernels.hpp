@@ -117,6 +117,13 @@ hipError_t launch_to_f64(bool f64, const void* Y, double* Z, long long N, int nr
 hipError_t launch_combine(bool f64, void* D, const double* Z, long long N, int nrhs, long long ldz, double a0, double a1,
                           hipStream_t st);
 hipError_t launch_axpby(bool f64, const void* v, void* out, long long n, double a0, double a1, hipStream_t st);
+hipError_t launch_qoi_scatter(bool f64, const void* q, void* Y, int Nt, int Nd, int r, int nrhs, hipStream_t st);
+hipError_t launch_qoi_gather(bool f64, const void* Y, void* q, double* C, long long ldc, long long c0, double alpha,
+                             bool accum, int Nt, int Nd, int r, int nrhs, hipStream_t st);
+hipError_t launch_d2q_rows(bool f64, const void* y, const void* h, long long N, int nrows, double* Q, long long ldq,
+                           long long r0, const double* var, int var_mode, int Nd, double gamma, hipStream_t st);
+hipError_t launch_d2q_apply(const double* Q, long long nq, long long N, long long ldq, const double* d, double* q,
+                            int nrhs, hipStream_t st);
 hipError_t launch_cholesky(double* A, long long n, long long lda, int* info, hipStream_t st);
 hipError_t launch_cholesky_solve(const double* L, long long n, long long lda, double* X, int nrhs, long long ldx,
                                  hipStream_t st);

@@ -97,6 +97,72 @@ __global__ void k_axpby(const T* __restrict__ v, T* __restrict__ out, long long 
     }
 }
 
+// ---------------------------------------------------------------- multi-rate (QoI) series
+// A plan observed every r-th step (QoI series, section 2 remark on distinct
+// temporal discretisations; section 5: QoIs at 1 Hz, parameters at 10 Hz)
+// exchanges series of Nt / r steps, step i standing for fine step r (i+1) - 1.
+// Y[b][t][s] = q[b][t / r][s] at those steps, 0 elsewhere.
+template <typename T>
+__global__ void k_qoi_scatter(const T* __restrict__ q, T* __restrict__ Y, int Nt, int Nd, int r, int nrhs) {
+    const long long n = (long long)nrhs * Nt * Nd;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / ((long long)Nt * Nd);
+        const int rem = (int)(e - b * Nt * Nd), t = rem / Nd, s = rem - t * Nd;
+        Y[e] = (t % r == r - 1) ? q[(b * (Nt / r) + t / r) * Nd + s] : T(0);
+    }
+}
+
+// q[b][i][s] = Y[b][r (i + 1) - 1][s]; with f64 output (C given), column
+// c0 + b of C (leading dimension ldc) receives alpha q[b] (added when accum).
+template <typename T>
+__global__ void k_qoi_gather(const T* __restrict__ Y, T* __restrict__ q, double* __restrict__ C, long long ldc,
+                             long long c0, double alpha, int accum, int Nt, int Nd, int r, int nrhs) {
+    const int Ntq = Nt / r;
+    const long long n = (long long)nrhs * Ntq * Nd;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / ((long long)Ntq * Nd);
+        const int rem = (int)(e - b * Ntq * Nd), i = rem / Nd, s = rem - i * Nd;
+        const T v = Y[(b * Nt + (long long)r * (i + 1) - 1) * Nd + s];
+        if (C) {
+            double* c = C + (c0 + b) * ldc + rem;
+            *c = accum ? *c + alpha * (double)v : alpha * (double)v;
+        } else {
+            q[e] = v;
+        }
+    }
+}
+
+// Rows r0 + b of the data-to-QoI map: Q[(r0 + b) ldq + i] =
+// gamma (y[b][i] - h[b][i]) / var_i.
+template <typename T>
+__global__ void k_d2q_rows(const T* __restrict__ y, const T* __restrict__ h, long long N, int nrows,
+                           double* __restrict__ Q, long long ldq, long long r0, const double* __restrict__ var,
+                           int var_mode, int Nd, double gamma) {
+    const long long n = N * nrows;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / N, i = e - b * N;
+        Q[(r0 + b) * ldq + i] = gamma * ((double)y[e] - (double)h[e]) / noise_var_at(var, var_mode, i, Nd);
+    }
+}
+
+// q[b][r] = sum_j Q[r ldq + j] d[b][j]: one wavefront per (row, right-hand
+// side), lanes striding over j (coalesced), fixed-order reduction.
+__global__ __launch_bounds__(256) void k_d2q_apply(const double* __restrict__ Q, long long nq, long long N,
+                                                   long long ldq, const double* __restrict__ d, double* __restrict__ q,
+                                                   int nrhs) {
+    const long long w = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= nq * nrhs) return;
+    const long long r = w % nq, b = w / nq;
+    const double* row = Q + r * ldq;
+    const double* x = d + b * N;
+    double acc = 0.0;
+    for (long long j = lane; j < N; j += 64) acc += row[j] * x[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) q[b * nq + r] = acc;
+}
+
 // ---------------------------------------------------------------- Cholesky
 // Factor the nb x nb diagonal block at (k, k) in place (nb <= kNB), one
 // workgroup: column j is scaled by 1 / sqrt(a_jj), then its outer product
@@ -377,6 +443,47 @@ hipError_t launch_axpby(bool f64, const void* v, void* out, long long n, double 
         hipLaunchKernelGGL(k_axpby<double>, grid_for(n), dim3(256), 0, st, (const double*)v, (double*)out, n, a0, a1);
     else
         hipLaunchKernelGGL(k_axpby<float>, grid_for(n), dim3(256), 0, st, (const float*)v, (float*)out, n, a0, a1);
+    return hipGetLastError();
+}
+
+hipError_t launch_qoi_scatter(bool f64, const void* q, void* Y, int Nt, int Nd, int r, int nrhs, hipStream_t st) {
+    const long long n = (long long)nrhs * Nt * Nd;
+    if (f64)
+        hipLaunchKernelGGL(k_qoi_scatter<double>, grid_for(n), dim3(256), 0, st, (const double*)q, (double*)Y, Nt, Nd, r,
+                           nrhs);
+    else
+        hipLaunchKernelGGL(k_qoi_scatter<float>, grid_for(n), dim3(256), 0, st, (const float*)q, (float*)Y, Nt, Nd, r,
+                           nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_qoi_gather(bool f64, const void* Y, void* q, double* C, long long ldc, long long c0, double alpha,
+                             bool accum, int Nt, int Nd, int r, int nrhs, hipStream_t st) {
+    const long long n = (long long)nrhs * (Nt / r) * Nd;
+    if (f64)
+        hipLaunchKernelGGL(k_qoi_gather<double>, grid_for(n), dim3(256), 0, st, (const double*)Y, (double*)q, C, ldc, c0,
+                           alpha, accum ? 1 : 0, Nt, Nd, r, nrhs);
+    else
+        hipLaunchKernelGGL(k_qoi_gather<float>, grid_for(n), dim3(256), 0, st, (const float*)Y, (float*)q, C, ldc, c0,
+                           alpha, accum ? 1 : 0, Nt, Nd, r, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_d2q_rows(bool f64, const void* y, const void* h, long long N, int nrows, double* Q, long long ldq,
+                           long long r0, const double* var, int var_mode, int Nd, double gamma, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_d2q_rows<double>, grid_for(N * nrows), dim3(256), 0, st, (const double*)y, (const double*)h,
+                           N, nrows, Q, ldq, r0, var, var_mode, Nd, gamma);
+    else
+        hipLaunchKernelGGL(k_d2q_rows<float>, grid_for(N * nrows), dim3(256), 0, st, (const float*)y, (const float*)h, N,
+                           nrows, Q, ldq, r0, var, var_mode, Nd, gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_d2q_apply(const double* Q, long long nq, long long N, long long ldq, const double* d, double* q,
+                            int nrhs, hipStream_t st) {
+    const long long waves = nq * nrhs;
+    hipLaunchKernelGGL(k_d2q_apply, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, Q, nq, N, ldq, d, q, nrhs);
     return hipGetLastError();
 }
 

@@ -56,6 +56,7 @@ class P2OOperator:
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         check(lib.p2o_bind_storage(plan, _ptr(self.fhat), self.fhat_bytes, _ptr(self.workspace), self.ws_bytes))
         self.ready = False
+        self.qstride = 1
 
     # ------------------------------------------------------------------ plumbing
     def _stream(self):
@@ -98,6 +99,18 @@ class P2OOperator:
         """Force matrix-core tile variant ``tile`` (see ``gemm_tiles()``) for
         both directions, or -1 for the autotuned or built-in choice."""
         check(lib.p2o_set_option(self._plan, 1, int(tile)))
+
+    def set_output_stride(self, r: int = 1):
+        """Observe the data series every r-th step (multi-rate output of a p2q
+        map): data series then have Nt / r steps, step i being parameter step
+        r (i + 1) - 1."""
+        check(lib.p2o_set_option(self._plan, 3, int(r)))
+        self.qstride = int(r)
+
+    @property
+    def Ntd(self) -> int:
+        """Steps of this operator's data series (Nt / output stride)."""
+        return self.Nt // self.qstride
 
     def set_fixed_fft(self, on: bool = True):
         """Use the FFT kernels compiled for this plan's transform length when
@@ -162,15 +175,16 @@ class P2OOperator:
         self.finalize()
 
     # ------------------------------------------------------------------ applies
-    def _series(self, x: torch.Tensor, last: int, name: str):
+    def _series(self, x: torch.Tensor, last: int, name: str, steps: Optional[int] = None):
+        steps = self.Nt if steps is None else steps
         if x.device != self.device:
             raise ValueError(f"{name} must be on {self.device}")
         if x.dtype != self.dtype:
             raise ValueError(f"{name} must be {self.dtype} for a {self.precision} operator")
         squeeze = x.dim() == 2
         xb = x.unsqueeze(0) if squeeze else x
-        if xb.dim() != 3 or xb.shape[1] != self.Nt or xb.shape[2] != last:
-            raise ValueError(f"{name} shape {tuple(x.shape)} must be [nrhs, {self.Nt}, {last}]")
+        if xb.dim() != 3 or xb.shape[1] != steps or xb.shape[2] != last:
+            raise ValueError(f"{name} shape {tuple(x.shape)} must be [nrhs, {steps}, {last}]")
         return xb.contiguous(), squeeze
 
     def _nt(self, nt_active, nrhs: int):
@@ -186,14 +200,14 @@ class P2OOperator:
         mb, sq = self._series(m, self.Nm, "m")
         nrhs = mb.shape[0]
         nt = self._nt(nt_active, nrhs)
-        d = out if out is not None else torch.empty((nrhs, self.Nt, self.Nd), dtype=self.dtype, device=self.device)
+        d = out if out is not None else torch.empty((nrhs, self.Ntd, self.Nd), dtype=self.dtype, device=self.device)
         self._stream()
         check(lib.p2o_apply_F(self._plan, _ptr(mb), _ptr(d), nrhs, _ptr(nt)))
         return d[0] if sq and out is None else d
 
     def apply_Ft(self, d: torch.Tensor, nt_active=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """m = F^* d."""
-        db, sq = self._series(d, self.Nd, "d")
+        db, sq = self._series(d, self.Nd, "d", self.Ntd)
         nrhs = db.shape[0]
         nt = self._nt(nt_active, nrhs)
         m = out if out is not None else torch.empty((nrhs, self.Nt, self.Nm), dtype=self.dtype, device=self.device)
@@ -203,10 +217,10 @@ class P2OOperator:
 
     def apply_FFt(self, e: torch.Tensor, nt_active=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """h = F F^* e (data-space operator columns)."""
-        eb, sq = self._series(e, self.Nd, "e")
+        eb, sq = self._series(e, self.Nd, "e", self.Ntd)
         nrhs = eb.shape[0]
         nt = self._nt(nt_active, nrhs)
-        h = out if out is not None else torch.empty((nrhs, self.Nt, self.Nd), dtype=self.dtype, device=self.device)
+        h = out if out is not None else torch.empty((nrhs, self.Ntd, self.Nd), dtype=self.dtype, device=self.device)
         self._stream()
         check(lib.p2o_apply_FFt(self._plan, _ptr(eb), _ptr(h), nrhs, _ptr(nt)))
         return h[0] if sq and out is None else h
@@ -278,6 +292,66 @@ class P2OOperator:
         self._stream()
         check(lib.p2o_posterior_cov_apply(self._plan, float(prior_var), _ptr(L), L.stride(0), _ptr(vb), _ptr(out), nrhs))
         return out[0] if sq else out
+
+
+    def apply_FGt(self, G: "P2OOperator", e: torch.Tensor) -> torch.Tensor:
+        """h = F G^* e for a second operator G on the same parameter grid
+        (e: G's data series, h: this operator's)."""
+        eb, sq = G._series(e, G.Nd, "e", G.Ntd)
+        nrhs = eb.shape[0]
+        h = torch.empty((nrhs, self.Ntd, self.Nd), dtype=self.dtype, device=self.device)
+        self._stream()
+        G._stream()
+        check(lib.p2o_apply_FGt(self._plan, G._plan, _ptr(eb), _ptr(h), nrhs))
+        return h[0] if sq else h
+
+    def d2q_map(self, Fq: "P2OOperator", L: torch.Tensor, noise_var, prior_var: float = 1.0,
+                batch: Optional[int] = None) -> torch.Tensor:
+        """Data-to-QoI map Q = F_q (I - G^* K^{-1} F) G^* Gamma_noise^{-1}
+        (G^* = prior_var F^*) as a dense FP64 [Nq Ntq, N] tensor (row r =
+        row r of Q), assembled ``batch`` rows per call."""
+        N = self.data_dim()
+        nq = Fq.Ntd * Fq.Nd
+        _check_factor(L, N, self.device)
+        var = torch.as_tensor(noise_var, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+        Q = torch.empty((nq, N), dtype=torch.float64, device=self.device)
+        b = int(batch or min(self.max_rhs, Fq.max_rhs))
+        self._stream()
+        Fq._stream()
+        for r0 in range(0, nq, b):
+            check(lib.p2o_d2q_rows(self._plan, Fq._plan, float(prior_var), _ptr(var), var.numel(), _ptr(L), L.stride(0),
+                                   r0, min(b, nq - r0), _ptr(Q), Q.stride(0)))
+        return Q
+
+    def qoi_posterior_cov(self, Fq: "P2OOperator", L: torch.Tensor, prior_var: float = 1.0,
+                          batch: Optional[int] = None) -> torch.Tensor:
+        """Gamma_post(q) = F_q (I - G^* K^{-1} F) G_q^* as a dense FP64
+        [Nq Ntq, Nq Ntq] tensor (tensor row c = column c; the matrix is
+        symmetric)."""
+        N = self.data_dim()
+        nq = Fq.Ntd * Fq.Nd
+        _check_factor(L, N, self.device)
+        C = torch.empty((nq, nq), dtype=torch.float64, device=self.device)
+        b = int(batch or min(self.max_rhs, Fq.max_rhs))
+        self._stream()
+        Fq._stream()
+        for c0 in range(0, nq, b):
+            check(lib.p2o_qoi_posterior_cov(self._plan, Fq._plan, float(prior_var), _ptr(L), L.stride(0), c0,
+                                            min(b, nq - c0), _ptr(C), C.stride(0)))
+        return C
+
+
+def d2q_apply(Q: torch.Tensor, d: torch.Tensor) -> torch.Tensor:
+    """q = Q d for data vectors d ([N] or [nrhs, N], float64), the online QoI
+    prediction."""
+    if Q.dtype != torch.float64 or Q.dim() != 2 or Q.stride(1) != 1:
+        raise ValueError("Q must be a float64 [nq, N] tensor with unit column stride")
+    nq, N = Q.shape
+    db = d.reshape(-1, N).to(torch.float64).contiguous()
+    q = torch.empty((db.shape[0], nq), dtype=torch.float64, device=Q.device)
+    check(lib.p2o_d2q_apply(_ptr(Q), nq, N, Q.stride(0), _ptr(db), _ptr(q), db.shape[0],
+                            c_void_p(torch.cuda.current_stream(Q.device).cuda_stream)))
+    return q[0] if d.dim() == 1 else q
 
 
 def _check_factor(L: torch.Tensor, N: int, device):
