@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-call-stats", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-largest", action="store_true")
+    ap.add_argument("--no-posterior", action="store_true")
     return ap.parse_args()
 
 
@@ -291,6 +292,8 @@ def main():
                                           args.no_accuracy, result)
     if not args.no_largest:
         result["largest"] = largest_leg(dev, torch, np, synth, P2OOperator, args.no_accuracy)
+    if not args.no_posterior:
+        result["posterior_paper_grid"] = posterior_leg(dev, torch, np, synth, P2OOperator, args.no_accuracy)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_cols, np)
     print(json.dumps(result), flush=True)
@@ -593,6 +596,83 @@ def fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var, no_acc, res
         f"speedup per matvec {out['batched_bf16_speedup_per_matvec']:.1f}x")
     op.close()
     del op
+    torch.cuda.empty_cache()
+    return out
+
+
+def posterior_leg(dev, torch, np, synth, P2OOperator, no_acc, batch=32, qstride=10, sigma=1e-2):
+    """The offline and online phases at the dimensions of the paper's
+    numerical example (section 5: Nd = 49, Nm = 513^2, Nt = 500; 16 QoIs every
+    10th step), FP16 spectra, stand-in prior Gamma_prior = I, Gamma_noise =
+    sigma^2 I: assembly of K (24,500 columns, `batch` per call), its Cholesky
+    factorisation, the MAP point (two adjoint and one forward application and
+    the two triangular solves), the d2q map Q (800 rows), the online
+    prediction Q d, and the QoI posterior covariance (800 columns).  Times
+    are HIP events on the stream; K is checked against the FP64 oracle on
+    sampled entries (blocks with time indices below 40, two sensors)."""
+    import oracle
+    from paper_2501_14911_amd import cholesky, d2q_apply
+    wf, wq = synth.CONFIGS["paper_grid"], synth.CONFIGS["paper_grid_qoi"]
+    t0 = time.perf_counter()
+    op = P2OOperator(wf.Nd, wf.Nm, wf.Nt, "fp16", max_rhs=batch, device=dev)
+    op.load(lambda c0, n: gpu_blocks(wf, c0, n, dev, torch, synth))
+    oq = P2OOperator(wq.Nd, wq.Nm, wq.Nt, "fp16", max_rhs=batch, device=dev)
+    oq.load(lambda c0, n: gpu_blocks(wq, c0, n, dev, torch, synth))
+    oq.set_output_stride(qstride)
+    log(f"[bench] posterior: FP16 spectra of F ({op.fhat_bytes / 1e9:.1f} GB) and F_q ({oq.fhat_bytes / 1e9:.1f} GB) "
+        f"loaded in {time.perf_counter() - t0:.1f} s")
+    var = torch.tensor([sigma ** 2], dtype=torch.float64, device=dev)
+    N, nq = op.data_dim(), oq.Ntd * oq.Nd
+
+    def timed(fn, reps=1):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return out, a.elapsed_time(b) / reps
+
+    out = {"workload": f"paper grid: Nd={wf.Nd} Nm={wf.Nm} Nt={wf.Nt}, Nq={wq.Nd} every {qstride}th step; FP16 spectra, "
+                       f"prior I, noise sigma={sigma}", "data_dim": N, "qoi_dim": nq}
+    K = torch.empty((N, N), dtype=torch.float64, device=dev)
+    _, out["assemble_K_ms"] = timed(lambda: op.assemble_K(var, 1.0, K=K))
+    out["assemble_K_ms_per_column"] = out["assemble_K_ms"] / N
+    if not no_acc:
+        # sampled entries of K: block (i, j), sensors (p, q): sum_k F_{i-k}[p] . F_{j-k}[q] + delta sigma^2
+        rng = np.random.default_rng(5)
+        sens = np.sort(rng.choice(wf.Nd, 2, replace=False))
+        Fr = synth.operator_rows_cols(wf, range(40), rows=sens, backend="torch").numpy()     # [40, 2, Nm]
+        Kh = K.cpu().numpy()
+        errs = []
+        for i, j in ((0, 0), (5, 3), (17, 17), (39, 20), (25, 38)):
+            for a in range(2):
+                for c in range(2):
+                    ref = sum(Fr[i - k, a] @ Fr[j - k, c] for k in range(min(i, j) + 1))
+                    if i == j and a == c:
+                        ref += sigma ** 2
+                    got = Kh[j * wf.Nd + sens[c], i * wf.Nd + sens[a]]      # tensor row = column of K
+                    errs.append(abs(got - ref) / abs(ref))
+        out["K_sampled_max_rel_err"] = float(max(errs))
+    L, out["cholesky_ms"] = timed(lambda: cholesky(K))
+    d_obs = synth.data_series(wf, 1, backend="torch", device=dev)[0].float() * 0.1
+    m_map, out["map_point_ms"] = timed(lambda: op.map_point(d_obs, L, var, 1.0), reps=5)
+    Q, out["d2q_map_ms"] = timed(lambda: op.d2q_map(oq, L, var, 1.0))
+    dvec = d_obs.double().reshape(1, -1)
+    q, out["d2q_apply_ms"] = timed(lambda: d2q_apply(Q, dvec), reps=20)
+    C, out["qoi_posterior_cov_ms"] = timed(lambda: op.qoi_posterior_cov(oq, L, 1.0))
+    if not no_acc:
+        # the online prediction Q d agrees with F_q applied to the MAP point (same operators)
+        qm = oq.apply_F(m_map.unsqueeze(0))[0].double().reshape(-1)
+        out["Qd_vs_Fq_map_rel"] = float((q[0] - qm).norm() / qm.norm())
+        Ch = C.cpu().numpy()
+        out["qoi_cov_symmetry_rel"] = float(np.linalg.norm(Ch - Ch.T) / np.linalg.norm(Ch))
+    log("[bench] posterior (paper grid): " + ", ".join(f"{k} {v:.3g}" for k, v in out.items()
+                                                      if isinstance(v, float)))
+    op.close()
+    oq.close()
+    del op, oq, K, L, Q, C
     torch.cuda.empty_cache()
     return out
 

@@ -106,7 +106,8 @@ p2o_status p2o_bind_storage(p2o_plan* plan, void* fhat, size_t fhat_bytes,
 p2o_status p2o_set_stream(p2o_plan* plan, void* stream);
 
 /* Transform and store columns [col0, col0+ncols) of the time-domain blocks
- * ("the DFT only needs to be done once for each matrix", section 4):
+ * (the blocks' DFT is computed once, offline, and reused by every matvec;
+ * section 4, paragraph on FFT-based p2o and p2q matvecs):
  * F_chunk is a device array [Nt][Nd][ncols] of element type src_dtype,
  * holding F_k[:, col0:col0+ncols] for k = 0..Nt-1.  For BF16/FP16 plans col0
  * must be a multiple of 4096 and ncols a multiple of 4096 unless the chunk
@@ -309,10 +310,11 @@ typedef enum {
 
 /* How calls with several right-hand sides do the per-frequency products.
  * AUTO: matrix cores (one launch for up to 64 right-hand sides per group,
- * BF16 spectrum x BF16 hi+lo split of the FP32 right-hand sides, FP32
- * accumulation; an FP16 spectrum enters as the exact sum of two BF16 parts)
- * when the spectrum is BF16 or FP16 and nrhs >= 2, otherwise one streaming
- * matrix-vector pass per right-hand side.  GEMV forces the latter; MFMA
+ * FP32 accumulation; a BF16 spectrum takes BF16 products with the BF16
+ * hi + lo split of the FP32 right-hand sides, an FP16 spectrum FP16 products
+ * with the right-hand sides rounded to FP16 after a per-right-hand-side
+ * power-of-two scale) when the spectrum is BF16 or FP16 and nrhs >= 2,
+ * otherwise one streaming matrix-vector pass per right-hand side.  GEMV forces the latter; MFMA
  * forces the former (BF16 plans, and FP16 plans whose one-frequency spectrum
  * is under 4 GiB; P2O_ERR_DTYPE otherwise).  FP16 plans use the LDS-ring
  * tile variants only (a forced other variant takes the built-in choice). */
@@ -344,9 +346,9 @@ p2o_status p2o_gemm_tile_info(int32_t tile, int32_t* row_groups, int32_t* subste
  * right-hand sides, and returns the choices and their mean launch times in
  * milliseconds (any output pointer may be NULL).  Uses the workspace as
  * operands (its contents are overwritten) and synchronises the stream.
- * Needs a loaded BF16 plan whose calls with nrhs right-hand sides use the
- * matrix cores (P2O_ERR_DTYPE otherwise), 1 <= nrhs <= max_rhs and
- * 1 <= reps <= 100. */
+ * Needs a loaded BF16 or FP16 plan whose calls with nrhs right-hand sides
+ * use the matrix cores (P2O_ERR_DTYPE otherwise; FP16 plans time the
+ * LDS-ring variants only), 1 <= nrhs <= max_rhs and 1 <= reps <= 100. */
 p2o_status p2o_autotune(p2o_plan* plan, int64_t nrhs, int32_t reps, int32_t* fwd_tile, int32_t* adj_tile,
                         double* fwd_ms, double* adj_ms);
 

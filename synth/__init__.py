@@ -148,6 +148,10 @@ CONFIGS = {
     "paper_time": Workload("paper_time", Nd=600, Nm=16384, Nt=420, tau=100.0, grid=128),
     # 600 x 65536 (256^2) x 420 steps: one GPU's column share
     "largest": Workload("largest", Nd=600, Nm=65536, Nt=420, tau=100.0, grid=256),
+    # the paper's numerical example's dimensions (section 5): 49 sensors, a 513^2 parameter grid,
+    # 500 steps, and its p2q map with 16 QoIs (observed every 10th step: 50 QoI steps)
+    "paper_grid": Workload("paper_grid", Nd=49, Nm=513 * 513, Nt=500, tau=100.0, grid=513),
+    "paper_grid_qoi": Workload("paper_grid_qoi", Nd=16, Nm=513 * 513, Nt=500, tau=100.0, grid=513, seed=SEED + 50),
 }
 
 
