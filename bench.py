@@ -2,24 +2,25 @@
 
 Workload: Nd = 600 sensors, Nm = 16384 parameters per step, Nt = 420 steps
 (circulant length 840), synthetic blocks F_k = exp(-k/100) N(0,1)/sqrt(Nm),
-half spectrum stored in 16 bits with FP32 accumulation.
+half spectrum stored in FP16 (per-block power-of-two scales) with FP32
+accumulation: the 16-bit storage whose every result, the data-space columns
+included, meets 2e-3 (with BF16 the columns of early spikes do not).
 
 One step is one pass over every use of the hot path:
   1. a data-misfit gradient on one right-hand side (r2c FFT of m, streaming
      forward products, inverse FFT fused with the residual and the FP64
      misfit reduction, r2c, streaming adjoint products, inverse FFT):
-     one F and one F^* matvec, BF16 spectrum;
+     one F and one F^* matvec;
   2. 64 data-space operator columns h_j = F F^* e_j in one call (batched
      adjoint and forward products on the matrix cores, truncate-and-repad
-     between them): 128 matvecs, FP16 spectrum -- the storage precision
-     whose columns meet 2e-3 on the whole output (with a BF16 spectrum the
-     columns of early spikes do not);
+     between them): 128 matvecs;
   3. F and F^* on 32 right-hand sides whose active lengths are drawn from
-     U{64..420} (batched, ragged): 64 matvecs, BF16 spectrum.
+     U{64..420} (batched, ragged): 64 matvecs.
 ``value`` = matvecs per second over the step (194 per step).  The plain FP64
 single-right-hand-side path on an FP64 spectrum of the same operator is timed
-beside it for the batched-mixed-precision speedup, and so are the FP32
-spectrum and the 600 x 65536 x 420 one-GPU share (BF16, 66 GB).
+beside it for the batched-mixed-precision speedup, and so are a BF16 spectrum
+(whole calls), the FP32 spectrum, the 600 x 65536 x 420 one-GPU share (BF16,
+66 GB) and the offline / online phases at the paper's dimensions.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build targets one
 GPU (the operator's column share on that GPU).
@@ -101,14 +102,14 @@ def main():
             f"{time.perf_counter() - t0:.1f} s (load kernels {ms:.1f} ms)")
         return o, ms
 
-    op, load_ms = loaded("bf16", N_HESS)        # gradient, ragged right-hand sides
-    op16, load16_ms = loaded("fp16", N_HESS)    # data-space columns
+    op16, load16_ms = loaded("fp16", N_HESS)    # the step
+    op, load_ms = loaded("bf16", N_HESS)        # BF16 comparison: whole calls and accuracy
 
     # matrix-core tile variants for the batched widths (autotuner, before timing)
     from paper_2501_14911_amd import gemm_tiles
     tiles = gemm_tiles()
     tuned = {}
-    for name, o, nr in (("bf16", op, N_RAGGED), ("bf16", op, N_HESS), ("fp16", op16, N_HESS)):
+    for name, o, nr in (("fp16", op16, N_RAGGED), ("fp16", op16, N_HESS), ("bf16", op, N_HESS)):
         r = o.autotune(nr, reps=2)
         tuned[f"{name}_{nr}"] = {d: {"tile": r[d][0], "shape": tiles[r[d][0]], "ms": r[d][1]} for d in ("fwd", "adj")}
         log(f"[bench] autotune {name} nrhs={nr}: fwd tile {r['fwd'][0]} {tiles[r['fwd'][0]]} {r['fwd'][1]:.3f} ms, "
@@ -131,21 +132,20 @@ def main():
     def step(evs=None):
         if evs:
             evs[0].record()
-        op.misfit_grad(m, d_obs, var)
+        op16.misfit_grad(m, d_obs, var)
         if evs:
             evs[1].record()
         op16.apply_FFt(E, out=H)
         if evs:
             evs[2].record()
-        op.apply_F(m_r, nt_active=nt_r_dev, out=Y_r)
-        op.apply_Ft(d_r, nt_active=nt_r_dev, out=S_r)
+        op16.apply_F(m_r, nt_active=nt_r_dev, out=Y_r)
+        op16.apply_Ft(d_r, nt_active=nt_r_dev, out=S_r)
         if evs:
             evs[3].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    op.profile(True)
     op16.profile(True)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -159,13 +159,12 @@ def main():
     wall = time.perf_counter() - wall0
     ms_step = ev0.elapsed_time(ev1) / args.steps
     part_ms = [sum(e[i].elapsed_time(e[i + 1]) for e in evs) / args.steps for i in range(3)]
-    st1, st32, st64 = op.stage_times(1), op.stage_times(N_RAGGED), op16.stage_times(N_HESS)
-    op.profile(False)
+    st1, st32, st64 = op16.stage_times(1), op16.stage_times(N_RAGGED), op16.stage_times(N_HESS)
     op16.profile(False)
     matvecs = 2 + 2 * N_HESS + 2 * N_RAGGED
     log(f"[bench] {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}): single-RHS gradient "
         f"{part_ms[0]:.3f} ms, 64 F F* columns {part_ms[1]:.3f} ms, 32 ragged F + F* {part_ms[2]:.3f} ms")
-    for label, st in (("bf16 nrhs= 1", st1), ("fp16 nrhs=64", st64), ("bf16 nrhs=32", st32)):
+    for label, st in (("nrhs= 1", st1), ("nrhs=64", st64), ("nrhs=32", st32)):
         for k, (tot, n) in st.items():
             if n:
                 log(f"[bench]   {label} {k:9s} {tot / n * 1e3:9.1f} us x {n / args.steps:.0f}/step")
@@ -175,7 +174,7 @@ def main():
     # is what a launch of the products must read whatever its right-hand-side
     # count; the right-hand-side and result spectra (8 bytes per bin and
     # series value) are reported beside it, not in it.
-    spec_bytes = op.nfreq * w.Nd * w.Nm * op.elem_bytes
+    spec_bytes = op16.nfreq * w.Nd * w.Nm * op16.elem_bytes
 
     def avg_us(st, k):
         tot, n = st[k]
@@ -187,12 +186,13 @@ def main():
     def gemm_flop(nrhs):        # real-equivalent flops of one pass
         return 2.0 * op.nfreq * w.Nd * (2 * w.Nm) * (2 * nrhs)
 
-    # kernel: (stage times, stage, spectrum precision, right-hand sides, products issued per real-equivalent flop)
+    # kernel: (stage times, stage, spectrum precision, right-hand sides, products issued per real-equivalent
+    # flop: one FP16 product per form)
     kdefs = {
-        "gemv_fwd": (st1, "gemv_fwd", "bf16", 1, None), "gemv_adj": (st1, "gemv_adj", "bf16", 1, None),
-        "gemm_fwd_64": (st64, "gemm_fwd", "fp16", N_HESS, 3), "gemm_adj_64": (st64, "gemm_adj", "fp16", N_HESS, 3),
+        "gemv_fwd": (st1, "gemv_fwd", "fp16", 1, None), "gemv_adj": (st1, "gemv_adj", "fp16", 1, None),
+        "gemm_fwd_64": (st64, "gemm_fwd", "fp16", N_HESS, 1), "gemm_adj_64": (st64, "gemm_adj", "fp16", N_HESS, 1),
         "project_64": (st64, "project", "fp16", N_HESS, None),
-        "gemm_fwd_32": (st32, "gemm_fwd", "bf16", N_RAGGED, 2), "gemm_adj_32": (st32, "gemm_adj", "bf16", N_RAGGED, 2),
+        "gemm_fwd_32": (st32, "gemm_fwd", "fp16", N_RAGGED, 1), "gemm_adj_32": (st32, "gemm_adj", "fp16", N_RAGGED, 1),
     }
     kern = {}
     for k, (st, stage, prec, nr, issue) in kdefs.items():
@@ -241,14 +241,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+fp16",
+        "dtype": "fp16",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt} L={op.L}; step = misfit gradient on 1 RHS "
-                               f"(BF16 spectrum) + 64 F F* columns (FP16 spectrum) + F and F* on 32 ragged RHS "
-                               f"(BF16 spectrum), FP32 accumulation ({matvecs} matvecs)",
-                   "Nd": w.Nd, "Nm": w.Nm, "Nt": w.Nt, "spectrum": {"gradient": "bf16", "hessian_columns": "fp16",
-                                                                   "ragged": "bf16"},
-                   "matvecs_per_step": matvecs},
+        "config": {"workload": f"{w.name}: Nd={w.Nd} Nm={w.Nm} Nt={w.Nt} L={op16.L}, FP16 spectrum, FP32 "
+                               f"accumulation; step = misfit gradient on 1 RHS + 64 F F* columns + F and F* on 32 "
+                               f"ragged RHS ({matvecs} matvecs)",
+                   "Nd": w.Nd, "Nm": w.Nm, "Nt": w.Nt, "spectrum": "fp16", "matvecs_per_step": matvecs},
         "roofline": roof,
         "parts_ms": {"single_rhs_gradient": part_ms[0], "hessian_64_columns": part_ms[1],
                      "ragged_32_F_and_Ft": part_ms[2]},
@@ -256,7 +254,7 @@ def main():
         "batched_matvecs_per_s": 2.0 * N_HESS / (part_ms[1] * 1e-3),
         "kernels": kern,
         "kernels_us": {lbl: {k: avg_us(st, k) for k in st if st[k][1]}
-                       for lbl, st in (("bf16_1", st1), ("fp16_64", st64), ("bf16_32", st32))},
+                       for lbl, st in (("nrhs_1", st1), ("nrhs_64", st64), ("nrhs_32", st32))},
         "load_ms": {"bf16": load_ms, "fp16": load16_ms},
         "autotune": tuned,
     }
@@ -456,7 +454,7 @@ def accuracy_sample(op, op16, w, m, H, hidx, m_r, Y_r, nt_r, dev, torch, np):
         out[f"fp16_hessian_column_t{t0}_spike_row"] = spike
     y = Y_r.double().cpu().numpy()
     mr = m_r.double().cpu().numpy()
-    out["bf16_ragged_F_4x_8rows"] = max(oracle.rel_l2(y[b][:, rows], oracle.apply_F(Fr, mr[b:b + 1], nt_r[b:b + 1])[0])
+    out["fp16_ragged_F_4x_8rows"] = max(oracle.rel_l2(y[b][:, rows], oracle.apply_F(Fr, mr[b:b + 1], nt_r[b:b + 1])[0])
                                         for b in range(4))
     log("[bench] rel-L2 vs FP64 oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
     out["tolerance"] = 2e-3
@@ -585,15 +583,15 @@ def fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var, no_acc, res
     out = {"ms_per_F_plus_Ft": ms, "matvecs_per_s": 2.0 / (ms * 1e-3),
            "gemv_fwd_us": st["gemv_fwd"][0] / max(1, st["gemv_fwd"][1]) * 1e3,
            "gemv_adj_us": st["gemv_adj"][0] / max(1, st["gemv_adj"][1]) * 1e3}
-    out["batched_bf16_speedup_per_matvec"] = result["batched_matvecs_per_s"] / out["matvecs_per_s"]
-    out["single_bf16_speedup"] = result["single_rhs_matvecs_per_s"] / out["matvecs_per_s"]
+    out["batched_fp16_speedup_per_matvec"] = result["batched_matvecs_per_s"] / out["matvecs_per_s"]
+    out["single_fp16_speedup"] = result["single_rhs_matvecs_per_s"] / out["matvecs_per_s"]
     if not no_acc:
         rows = np.sort(np.random.default_rng(1).choice(w.Nd, 8, replace=False))
         d = op.apply_F(m64).cpu().numpy()
         Fr = synth.operator_rows_cols(w, range(w.Nt), rows=rows, backend="torch").numpy()
         out["rel_l2_F_8rows"] = oracle.rel_l2(d[:, rows], oracle.apply_F(Fr, m64.cpu().numpy()))
-    log(f"[bench] FP64 plain: {ms:.3f} ms per F + F* ({out['matvecs_per_s']:.1f} matvecs/s); batched BF16 "
-        f"speedup per matvec {out['batched_bf16_speedup_per_matvec']:.1f}x")
+    log(f"[bench] FP64 plain: {ms:.3f} ms per F + F* ({out['matvecs_per_s']:.1f} matvecs/s); batched FP16 "
+        f"speedup per matvec {out['batched_fp16_speedup_per_matvec']:.1f}x")
     op.close()
     del op
     torch.cuda.empty_cache()

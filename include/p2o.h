@@ -201,7 +201,8 @@ p2o_status p2o_assemble_K(p2o_plan* plan, double prior_var, const double* noise_
 /* In-place Cholesky factorisation A = L L^T of a symmetric positive definite
  * n x n FP64 matrix on the device (column-major, lda >= n; section 4,
  * Phase 2: K is factorised offline): on return the lower triangle (i >= j)
- * holds L; the strict upper triangle is neither read nor written.  *info
+ * holds L and the strict upper triangle holds L^T (entry (i, j), i < j,
+ * equals L(j, i)); the input's upper triangle is not read.  *info
  * (device int32) receives 0, or k + 1 when the k-th pivot was not positive
  * (the factor is then not usable).  Blocked right-looking algorithm (blocks
  * of 64; trailing updates on the FP64 matrix cores).  Asynchronous on
@@ -211,7 +212,9 @@ p2o_status p2o_cholesky(double* A, int64_t n, int64_t lda, int32_t* info, void* 
 /* X <- K^{-1} X with K = L L^T from p2o_cholesky: the two triangular solves
  * of the online phase (section 4, Phase 4), L y = x then L^T x = y, for
  * nrhs right-hand sides, X column-major n x nrhs with leading dimension
- * ldx >= n (device FP64).  Asynchronous on `stream`. */
+ * ldx >= n (device FP64).  L is the matrix as p2o_cholesky leaves it: the
+ * forward solve reads its lower triangle, the backward solve its upper
+ * triangle (L^T).  Asynchronous on `stream`. */
 p2o_status p2o_cholesky_solve(const double* L, int64_t n, int64_t lda, double* X, int64_t nrhs,
                               int64_t ldx, void* stream);
 

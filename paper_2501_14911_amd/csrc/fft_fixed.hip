@@ -729,14 +729,17 @@ hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStrea
 }
 
 // Compiled (M, tile shift) pairs: the transform lengths of the common
-// workloads (Nt = 16, 128, 420), with the tile widths fft_tile_shift picks.
+// workloads (Nt = 16, 128, 420, and 500 of section 5's problem), with the
+// tile widths fft_tile_shift picks.
 #define P2O_FX_CASES(X) \
     X(float, 16, 5)     \
     X(float, 128, 4)    \
     X(float, 420, 3)    \
+    X(float, 500, 2)    \
     X(double, 16, 5)    \
     X(double, 128, 3)   \
-    X(double, 420, 2)
+    X(double, 420, 2)   \
+    X(double, 500, 1)
 
 // Lane offsets of `rows` rows of `stride` elements (plus a tile) fit the
 // 32-bit offsets the kernels use (rows: one sweep, 256 >> shift bins or

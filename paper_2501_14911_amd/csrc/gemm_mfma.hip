@@ -555,6 +555,168 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         }
 }
 
+// ---------------------------------------------------------------- forward, LDS ring, whole lines
+// Forward product as in k_gemm_fwd_ring, with steps of 32 complex columns:
+// each spectrum row contributes one whole 128-byte line per step (with
+// 16-column steps a row gives half a line, and streaming half lines from
+// many rows runs well below the rate of whole ones).  RG row groups x MB
+// blocks of 32 rows (320 rows for RG = 2, MB = 5: two tiles cover 600
+// sensors) x NH halves of 32 NH right-hand sides; four substeps per step.
+//   A: MROWS rows x 128 bytes in a 3-step ring; a load instruction fills 8
+//      rows; the 16-byte chunk c of row r sits in slot c ^ ((r / 2) mod 8),
+//      so that 16 lanes reading one chunk of 16 consecutive rows hit 16
+//      distinct bank groups.
+//   B: right-hand side b's 256 bytes of the step (8 groups x 2 parts) in a
+//      2-step ring, part p in slot p ^ (b mod 16); a load instruction moves
+//      4 right-hand sides.  B of step st + 1 is issued before A of step
+//      st + 2, so waiting for all but the last step's A loads covers both
+//      operands of the next step.
+template <int RG, int MB, int NH, bool F16>
+__global__ __launch_bounds__(64 * RG * NH) __attribute__((amdgpu_waves_per_eu(1)))
+void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
+                      float2* __restrict__ out_base, GemmArgs ga) {
+    constexpr int KU = 4;
+    constexpr int MROWS = RG * 32 * MB, RHS = 32 * NH, NW = RG * NH;
+    constexpr int AI = MROWS / 8 / NW;                    // A loads (8 rows each) per wavefront per step
+    static_assert(AI >= 1 && AI * 8 * NW == MROWS, "A rows per wavefront");
+    constexpr int BI = RHS / 4 / NW;                      // B loads (4 right-hand sides each) per wavefront per step
+    static_assert(BI >= 1 && 4 * BI * NW == RHS, "B loads per wavefront");
+    constexpr int A_STEP = MROWS * 128, B_STEP = RHS * 256;
+    __shared__ __align__(16) uint8_t ring_a[3][A_STEP];
+    __shared__ __align__(16) uint8_t ring_b[2][B_STEP];
+
+    const int q = xcd_item(blockIdx.x, ga.Q);
+    if (q >= ga.items) return;
+    int t = q;
+    const int mt = t % ga.n_mt; t /= ga.n_mt;
+    const int bg = t % ga.n_bg; t /= ga.n_bg;
+    const int kc = t % ga.n_kc; t /= ga.n_kc;
+    const int w = t;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rg = wave % RG, nh = wave / RG;
+    const int r = lane & 31, kg = lane >> 5;
+    const int b0 = bg * RHS;
+    const int nb_valid = min(RHS, ga.nrhs - b0);
+    const int m0 = mt * MROWS;
+    const int kbeg = kc * ga.kchunk;
+    const int kend = min((ga.ncols + 31) / 32 * 32, kbeg + ga.kchunk);
+    const int nst = (kend - kbeg) / 32;
+
+    // A instruction i of this wavefront fills tile rows 8 (AI wave + i) ..
+    // + 7; lane L takes row L / 8 of those and loads its chunk
+    // (L % 8) ^ ((row / 2) mod 8) into slot L % 8.
+    const uint8_t* const abase = fhat + ((long long)w * ga.Nd * ga.pitch + kbeg) * 4;
+    uint32_t aoff[AI];
+#pragma unroll
+    for (int i = 0; i < AI; ++i) {
+        const int row = 8 * (AI * wave + i) + (lane >> 3);
+        const int c = (lane & 7) ^ ((row >> 1) & 7);
+        const int sr = min(m0 + row, ga.Nd - 1);
+        aoff[i] = ((uint32_t)sr * (uint32_t)ga.pitch) * 4u + 16u * (uint32_t)c;
+    }
+    // B instruction i: right-hand sides 4 (BI wave + i) .. + 3; lane L moves
+    // part (L % 16) ^ (b mod 16) of b = 4 (BI wave + i) + L / 16 into slot L % 16
+    const uint8_t* const bbase = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8 + (long long)kbeg * 8;
+    uint32_t boff[BI];
+#pragma unroll
+    for (int i = 0; i < BI; ++i) {
+        const int b = 4 * (BI * wave + i) + (lane >> 4);
+        const int part = (lane & 15) ^ (b & 15);
+        boff[i] = (uint32_t)min(b, nb_valid - 1) * (uint32_t)ga.ldb * 8u + (uint32_t)part * 16u;
+    }
+    const uint32_t la = lds_addr(&ring_a[0][0]) + AI * wave * 1024, lb = lds_addr(&ring_b[0][0]) + BI * wave * 1024;
+    auto issue_a = [&](int st, int slot) {
+        const long long sa = st < nst ? st : nst - 1;       // past the end: repeat the last step (unused)
+#pragma unroll
+        for (int i = 0; i < AI; ++i) dma16(abase + sa * 128, aoff[i], la + slot * A_STEP + i * 1024);
+    };
+    auto issue_b = [&](int st, int slot) {
+        const long long sb = st < nst ? st : nst - 1;
+#pragma unroll
+        for (int i = 0; i < BI; ++i) dma16(bbase + sb * 256, boff[i], lb + slot * B_STEP + i * 1024);
+    };
+
+    f32x16 accr[MB], acci[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) accr[mb] = acci[mb] = f32x16{};
+
+    struct Frags {
+        uint4 a[MB], bh, bl;
+    };
+    const int rb = 32 * nh + r;
+    auto read = [&](Frags& f, int as, int bs, int u) {
+        const int g = 2 * u + kg;                         // this lane's group of 4 entries in the step
+        f.bh = *reinterpret_cast<const uint4*>(&ring_b[bs][rb * 256 + (((2 * g) ^ (rb & 15)) * 16)]);
+        f.bl = *reinterpret_cast<const uint4*>(&ring_b[bs][rb * 256 + (((2 * g + 1) ^ (rb & 15)) * 16)]);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int row = (rg * MB + mb) * 32 + r;
+            f.a[mb] = *reinterpret_cast<const uint4*>(&ring_a[as][row * 128 + ((g ^ ((row >> 1) & 7)) * 16)]);
+        }
+    };
+    float rs = 1.f;
+    if constexpr (F16) rs = ga.rhs_scale[min(b0 + rb, ga.nrhs - 1)];
+    auto mfmas = [&](const Frags& f) {
+        if constexpr (F16) {
+            const uint4 bx = f_rhs_f16(f.bh, f.bl, rs);
+            const uint4 b_r = f_conj(bx), b_i = f_swap(bx);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                accr[mb] = mfma32h(f.a[mb], b_r, accr[mb]);
+                acci[mb] = mfma32h(f.a[mb], b_i, acci[mb]);
+            }
+        } else {
+            const uint4 bh_r = f_conj(f.bh), bh_i = f_swap(f.bh), bl_r = f_conj(f.bl), bl_i = f_swap(f.bl);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                accr[mb] = mfma32(f.a[mb], bh_r, accr[mb]);
+                acci[mb] = mfma32(f.a[mb], bh_i, acci[mb]);
+                accr[mb] = mfma32(f.a[mb], bl_r, accr[mb]);
+                acci[mb] = mfma32(f.a[mb], bl_i, acci[mb]);
+            }
+        }
+    };
+
+    // Issue order B_0, A_0, A_1, then per step st: B_{st+1}, A_{st+2}.  At
+    // step st, waiting until at most AI loads are in flight leaves only
+    // A_{st+1} outstanding: A_st and B_st have landed.
+    issue_b(0, 0);
+    issue_a(0, 0);
+    issue_a(1, 1);
+    int as = 0, bs = 0;
+    for (int st = 0; st < nst; ++st) {
+        wait_vm_lgkm0<AI>();
+        bare_barrier();
+        Frags f;
+        read(f, as, bs, 0);
+        issue_b(st + 1, bs ^ 1);                          // the slot step st - 1 used
+        issue_a(st + 2, as == 0 ? 2 : as - 1);            // the slot step st - 1 used
+        mfmas(f);
+#pragma unroll
+        for (int u = 1; u < KU; ++u) {
+            read(f, as, bs, u);
+            mfmas(f);
+        }
+        as = as == 2 ? 0 : as + 1;
+        bs ^= 1;
+    }
+    wait_vm_lgkm0<0>();                                   // no load may land after the workgroup ends
+
+    const int b = b0 + rb;
+    if (b >= ga.nrhs) return;
+    const float sc = scales[(long long)w * ga.nblk + kbeg / kScaleBlock] / rs;
+    float2* out = out_base + (long long)kc * ga.part_stride + ((long long)w * ga.nrhs + b) * ga.Nd;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = m0 + (rg * MB + mb) * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
+            if (row < ga.Nd) out[row] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+        }
+}
+
 // ---------------------------------------------------------------- adjoint, LDS ring
 // Adjoint product with both operands streamed into a RING-step LDS ring by
 // direct-to-LDS loads, as in the forward ring.  RG NH wavefronts = RG column
@@ -830,8 +992,11 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
 // Variants 7 and 8 are the forward LDS-ring kernel (k_gemm_fwd_ring, pf = 0
 // marks a ring) with 640-row tiles for 64 and 32 right-hand sides per group,
 // 11 and 12 the same kernel with 64- and 128-row tiles (64 right-hand sides),
-// 9 and 10 the adjoint one (k_gemm_adj_ring) for 64 and 32; a direction a
-// variant lacks takes its built-in choice.
+// 13 and 14 the whole-line forward ring (k_gemm_fwd_ring2, 320-row tiles,
+// 32-column steps) for 64 and 32, 9 and 10 the adjoint one
+// (k_gemm_adj_ring) for 64 and 32, 15 and 16 the adjoint ring with 512
+// columns and 64 right-hand sides and with 256 columns and 32; a direction
+// a variant lacks takes its built-in choice.
 struct TileShape {
     int rg, ku, mb, wpe, pf, nw;
     int dirs;   // 1: forward, 2: adjoint, 3: both
@@ -840,7 +1005,8 @@ static const TileShape kTiles[] = {{2, 4, 5, 1, 2, 4, 3}, {2, 2, 5, 1, 2, 4, 3},
                                    {2, 2, 4, 2, 2, 4, 3}, {4, 2, 4, 2, 2, 4, 3}, {2, 2, 5, 2, 1, 4, 3},
                                    {4, 2, 5, 2, 1, 8, 3}, {4, 2, 5, 2, 0, 8, 1}, {4, 2, 5, 1, 0, 4, 1},
                                    {2, 2, 4, 2, 0, 4, 2}, {4, 2, 4, 1, 0, 4, 2}, {2, 2, 1, 2, 0, 4, 1},
-                                   {4, 2, 1, 2, 0, 8, 1}};
+                                   {4, 2, 1, 2, 0, 8, 1}, {2, 4, 5, 1, 0, 4, 1}, {2, 4, 5, 1, 0, 2, 1},
+                                   {4, 2, 4, 1, 0, 8, 2}, {2, 2, 4, 2, 0, 2, 2}};
 constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_tile_count() { return kTileCount; }
@@ -869,6 +1035,29 @@ static hipError_t launch_ring(GemmArgs ga, const void* fhat, const float* scales
                            (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     else
         hipLaunchKernelGGL((k_gemm_fwd_ring<RG, MB, NH, false>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                           (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
+    return hipGetLastError();
+}
+
+template <int RG, int MB, int NH>
+static hipError_t launch_ring2(GemmArgs ga, const void* fhat, const float* scales, const void* Bq, void* out,
+                               hipStream_t st) {
+    // 32-bit lane offsets, as in the 16-column ring
+    if ((long long)ga.Nd * ga.pitch * 4 >= (1LL << 32) || 32LL * NH * ga.ldb * 8 >= (1LL << 32) || ga.kchunk % 32 ||
+        ga.pitch % 32) {
+        if (ga.a_f16) return hipErrorInvalidValue;        // callers check gemm_f16_fits first
+        return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Bq, out, st);
+    }
+    constexpr int MROWS = 32 * RG * MB;
+    ga.n_mt = (ga.Nd + MROWS - 1) / MROWS;
+    ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
+    ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
+    ga.Q = (ga.items + 7) / 8;
+    if (ga.a_f16)
+        hipLaunchKernelGGL((k_gemm_fwd_ring2<RG, MB, NH, true>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                           (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
+    else
+        hipLaunchKernelGGL((k_gemm_fwd_ring2<RG, MB, NH, false>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
                            (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
 }
@@ -944,6 +1133,8 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
         case 8: return launch_ring<4, 5, 1>(ga, fhat, scales, Xq, Yp, st);
         case 11: return launch_ring<2, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 12: return launch_ring<4, 1, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 13: return launch_ring2<2, 5, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 14: return launch_ring2<2, 5, 1>(ga, fhat, scales, Xq, Yp, st);
         default: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
     }
 }
@@ -965,6 +1156,8 @@ hipError_t launch_gemm_adj(const GemmArgs& in, int tile, const void* fhat, const
         case 5: return launch_tile<false, 2, 2, 5, 2, 1>(ga, fhat, scales, Yq, Xp, st);
         case 6: return launch_tile<false, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Yq, Xp, st);
         case 9: return launch_adj_ring<2, 4, 2>(ga, fhat, scales, Yq, Xp, st);
+        case 15: return launch_adj_ring<4, 4, 2>(ga, fhat, scales, Yq, Xp, st);
+        case 16: return launch_adj_ring<2, 4, 1>(ga, fhat, scales, Yq, Xp, st);
         default: return launch_adj_ring<4, 4, 1>(ga, fhat, scales, Yq, Xp, st);
     }
 }

@@ -8,12 +8,20 @@
 // (i, j) at A[j * lda + i].  The data-space index is j = t * Nd + s (the
 // time-major order of the data series).
 //
-// Cholesky (right-looking, blocks of kNB = 64):
-//   for each diagonal block k: factor it in LDS (one workgroup); solve the
-//   panel below it against L_kk^T (one row per lane, L_kk in LDS); subtract
-//   P P^T from the lower tiles of the trailing matrix with
-//   v_mfma_f64_16x16x4f64 (64 x 64 tiles, panel columns staged in LDS).
-// The strict upper triangle is never read or written.
+// Cholesky (right-looking, panels of kNB2 = 256 columns made of blocks of
+// kNB = 64):
+//   for each 64-column block k of a panel: factor its diagonal block in
+//   registers (one wavefront, lane r holding row r); solve the rows below
+//   it against L_kk^T (one row per lane, L_kk in LDS); subtract its P P^T
+//   from the panel's remaining columns.  After the panel: subtract the
+//   panel's rank-256 product from the lower tiles of the trailing matrix.
+//   Both updates run on v_mfma_f64_16x16x4f64 (64 x 64 tiles, the panel
+//   columns staged in LDS 64 at a time, the tile accumulated in registers
+//   and written once).
+// The factor is also written transposed into the strict upper triangle
+// (entry (i, j), i < j, receives L(j, i)), so that both triangular solves
+// read whole contiguous column runs: the forward solve columns of L, the
+// backward solve columns of L^T.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -22,6 +30,7 @@ namespace p2o {
 namespace {
 
 constexpr int kNB = 64;                 // Cholesky / solve block size
+constexpr int kNB2 = 256;               // Cholesky panel width (trailing updates of rank kNB2)
 constexpr int kLP = kNB + 2;            // padded LDS row (doubles)
 
 __device__ __forceinline__ double noise_var_at(const double* var, int mode, long long i, int Nd) {
@@ -163,41 +172,50 @@ __global__ __launch_bounds__(256) void k_d2q_apply(const double* __restrict__ Q,
     if (lane == 0) q[b * nq + r] = acc;
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // ---------------------------------------------------------------- Cholesky
 // Factor the nb x nb diagonal block at (k, k) in place (nb <= kNB), one
-// workgroup: column j is scaled by 1 / sqrt(a_jj), then its outer product
-// leaves the trailing part of the block.  A pivot that is not positive (or
-// not a number) records k + j + 1 in *info if nothing was recorded before.
-__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, long long lda, int k, int nb,
-                                                    int* __restrict__ info) {
-    __shared__ double a[kNB][kLP];                     // a[col][row]
-    const int tid = threadIdx.x;
-    if (k == 0 && tid == 0 && info) *info = 0;        // read back only by this thread, in stream order
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int c = e / nb, r = e - c * nb;
-        if (r >= c) a[c][r] = A[(long long)(k + c) * lda + k + r];
-    }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-            const double d = a[j][j];
-            if (!(d > 0.0) && info && *info == 0) *info = k + j + 1;
-            a[j][j] = sqrt(d);
+// wavefront: lane r keeps row r of the block in registers; for each column
+// j the pivot is broadcast from lane j, the column is scaled, and its outer
+// product leaves the trailing part (row c of the column broadcast from lane
+// c).  Entries right of the diagonal in the registers are never stored.  A
+// pivot that is not positive (or not a number) records k + j + 1 in *info
+// if nothing was recorded before (*info is reset by the call with k = 0).
+// L is also written transposed into the upper triangle of the block.
+__global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ A, long long lda, int k, int nb,
+                                                   int* __restrict__ info) {
+    const int r = threadIdx.x;
+    const int prev = (info && k > 0) ? *info : 0;
+    double a[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) a[c] = (c <= r && r < nb) ? A[(long long)(k + c) * lda + k + r] : 0.0;
+    int bad = 0;                                       // first non-positive pivot of the block (1-based)
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) {
+        if (j < nb) {
+            const double d = readlane_f64(a[j], j);
+            if (!(d > 0.0) && bad == 0) bad = j + 1;
+            const double piv = sqrt(d), inv = 1.0 / piv;
+            a[j] = r == j ? piv : (r > j ? a[j] * inv : 0.0);
+#pragma unroll
+            for (int c = j + 1; c < kNB; ++c) a[c] -= a[j] * readlane_f64(a[j], c);
         }
-        __syncthreads();
-        const double dj = a[j][j];
-        for (int r = j + 1 + tid; r < nb; r += 256) a[j][r] /= dj;
-        __syncthreads();
-        const int m = nb - j - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            const int c = j + 1 + e / m, r = j + 1 + e % m;
-            if (r >= c) a[c][r] -= a[j][r] * a[j][c];
-        }
-        __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int c = e / nb, r = e - c * nb;
-        if (r >= c) A[(long long)(k + c) * lda + k + r] = a[c][r];
+    if (r < nb) {
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) {
+            if (c <= r) A[(long long)(k + c) * lda + k + r] = a[c];
+            if (c < r) A[(long long)(k + r) * lda + k + c] = a[c];    // L^T in the upper triangle
+        }
+    }
+    if (r == 0 && info) {
+        if (k == 0) *info = bad;
+        else if (prev == 0 && bad) *info = k + bad;
     }
 }
 
@@ -224,54 +242,70 @@ __global__ __launch_bounds__(256) void k_trsm_panel(double* __restrict__ A, long
     }
 #pragma unroll
     for (int c = 0; c < kNB; ++c) A[(long long)(k + c) * lda + r] = x[c];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) A[r * lda + k + c] = x[c];           // L^T: row k + c, column r
 }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Trailing update A[t0 + i, t0 + j] -= sum_c P[i, c] P[j, c] over the lower
-// 64 x 64 tiles (tile row >= tile column), P = A[t0:n, k:k + kNB], t0 =
-// k + kNB.  Workgroup = one tile, 4 wavefronts of 32 x 32 (2 x 2 blocks of
-// 16 x 16 on the matrix cores).  The products are taken as the transposed
-// block P_j P_i^T so that lane l of a block holds rows l % 16 of four
-// columns: stores cover 128 contiguous bytes per 16 lanes.
-__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, long long lda, int n, int k) {
+// Update A[t0 + i, t0 + j] -= sum_c P[i, c] P[j, c] over the 64 x 64 tiles
+// of rows [t0, n) and columns [t0, c_end) on or below the diagonal (tile
+// row >= tile column), P = A[t0:n, pk0:pk0 + kd].  Workgroup = one tile, 4
+// wavefronts of 32 x 32 (2 x 2 blocks of 16 x 16 on the matrix cores); the
+// panel columns are staged in LDS 64 at a time and the tile accumulates in
+// registers.  The products are taken as the transposed block P_j P_i^T so
+// that lane l of a block holds rows l % 16 of four columns: stores cover 128
+// contiguous bytes per 16 lanes.  Tiles are numbered column by column:
+// column tile tj has T - tj tiles (T row tiles).
+__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, long long lda, int n, int t0, int c_end,
+                                                     int pk0, int kd) {
     __shared__ double pi[kNB][kLP], pj[kNB][kLP];     // [panel column][tile row]
-    const int t0 = k + kNB;
-    const int m = n - t0;
-    // tile (ti, tj), tj <= ti, from the linear index ti (ti + 1) / 2 + tj
+    const int m = n - t0, mc = c_end - t0;
+    const int T = (m + 63) / 64;
+    // tile (ti, tj): tj is the largest column with S(tj) = tj (2T - tj + 1) / 2 <= q
     const long long q = blockIdx.x;
-    int ti = (int)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
-    while ((long long)(ti + 1) * (ti + 2) / 2 <= q) ++ti;
-    while ((long long)ti * (ti + 1) / 2 > q) --ti;
-    const int tj = (int)(q - (long long)ti * (ti + 1) / 2);
-    const int ri = ti * 64, rj = tj * 64;              // first rows (tile-local to t0)
-    for (int e = threadIdx.x; e < 64 * kNB; e += 256) {
-        const int c = e / 64, r = e % 64;
-        const double* col = A + (long long)(k + c) * lda + t0;
-        pi[c][r] = ri + r < m ? col[ri + r] : 0.0;
-        pj[c][r] = rj + r < m ? col[rj + r] : 0.0;
-    }
-    __syncthreads();
+    const double b2 = 2.0 * T + 1.0;
+    int tj = (int)((b2 - sqrt(b2 * b2 - 8.0 * (double)q)) * 0.5);
+    auto S = [&](long long c) { return c * (2LL * T - c + 1) / 2; };
+    while (tj > 0 && S(tj) > q) --tj;
+    while (S(tj + 1) <= q) ++tj;
+    const int ti = tj + (int)(q - S(tj));
+    const int ri = ti * 64, rj = tj * 64;              // first rows (relative to t0)
+    if (rj >= mc) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // sub-tile: rows wr (of i), columns wc (of j)
+    const int li = lane & 15, lk = lane >> 4;
     f64x4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const int li = lane & 15, lk = lane >> 4;
+    for (int k0 = 0; k0 < kd; k0 += kNB) {
+        const int kw = min(kNB, kd - k0);
+        if (k0 > 0) __syncthreads();                   // every wavefront is done with the previous columns
 #pragma unroll 4
-    for (int c0 = 0; c0 < kNB; c0 += 4) {
-        double vi[2], vj[2];
+        for (int e = threadIdx.x; e < 64 * kNB; e += 256) {
+            const int c = e / 64, r = e % 64;
+            const double* col = A + (long long)(pk0 + k0 + c) * lda + t0;
+            const bool cv = c < kw;
+            pi[c][r] = cv && ri + r < m ? col[ri + r] : 0.0;
+            pj[c][r] = cv && rj + r < m ? col[rj + r] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int c0 = 0; c0 < kNB; c0 += 4) {
+            double vi[2], vj[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) vi[a] = pi[c0 + lk][wr + 16 * a + li];
+            for (int a = 0; a < 2; ++a) vi[a] = pi[c0 + lk][wr + 16 * a + li];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) vj[b] = pj[c0 + lk][wc + 16 * b + li];
-        // block (a, b) of P_j P_i^T: rows = tile columns wc + 16 b + ., columns = tile rows wr + 16 a + .
+            for (int b = 0; b < 2; ++b) vj[b] = pj[c0 + lk][wc + 16 * b + li];
+            // block (a, b) of P_j P_i^T: rows = tile columns wc + 16 b + ., columns = tile rows wr + 16 a + .
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vj[b], vi[a], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vj[b], vi[a], acc[a][b], 0, 0, 0);
+        }
     }
     // lane l holds D[4 v + l / 16][l % 16] of each block in item v (measured
     // on gfx950 with an in-bounds probe): D row = j offset, D column = i offset
@@ -281,106 +315,84 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, lon
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gi = ri + wr + 16 * a + li;              // row of A (tile-local to t0)
+                const int gi = ri + wr + 16 * a + li;              // row of A (relative to t0)
                 const int gj = rj + wc + 16 * b + 4 * v + lk;      // column of A
-                if (gi < m && gj < m && gi >= gj) {
+                if (gi < m && gj < mc && gi >= gj) {
                     double* p = A + (long long)(t0 + gj) * lda + t0 + gi;
                     *p -= acc[a][b][v];
                 }
             }
 }
 
+static long long trapezoid_tiles(long long m, long long mc) {
+    const long long T = (m + 63) / 64, C = std::min(T, (mc + 63) / 64);
+    return C * (2 * T - C + 1) / 2;
+}
+
 // ---------------------------------------------------------------- triangular solves with L
-// Forward, diagonal block k (nb rows): X[b][k:k+nb] = L_kk^{-1} X[b][k:k+nb].
-// One wavefront per right-hand side; L_kk in LDS.
-__global__ __launch_bounds__(64) void k_trsv_fwd_diag(const double* __restrict__ L, long long lda, int k, int nb,
-                                                      double* __restrict__ X, long long ldx) {
-    __shared__ double l[kNB][kLP];
-    __shared__ double s[kNB];
+// Diagonal block k (nb rows) of the solves: X[b][k:k+nb] = L_kk^{-1} X[b][k:k+nb]
+// (forward) or L_kk^{-T} X[b][k:k+nb] (backward).  One workgroup per
+// right-hand side: all 256 lanes stage L_kk in LDS (16 independent loads
+// each; rows past nb get a unit diagonal), then the first wavefront keeps
+// lane i's row of L_kk (forward) or of L_kk^T (backward) in registers and
+// substitutes along the 64 rows, broadcasting each solved entry with
+// v_readlane.
+template <bool BWD>
+__global__ __launch_bounds__(256) void k_trsv_diag(const double* __restrict__ L, long long lda, int k, int nb,
+                                                   double* __restrict__ X, long long ldx) {
+    __shared__ double l[kNB][kLP];                     // l[col][row] = L_kk(row, col)
+#pragma unroll
+    for (int u = 0; u < kNB * kNB / 256; ++u) {
+        const int e = threadIdx.x + 256 * u, c = e / kNB, r = e % kNB;
+        l[c][r] = (r < nb && c < nb && r >= c) ? L[(long long)(k + c) * lda + k + r] : (r == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
     const int i = threadIdx.x;
-    for (int c = 0; c < nb; ++c) l[c][i] = (i < nb && i >= c) ? L[(long long)(k + c) * lda + k + i] : 0.0;
+    double row[kNB];                                   // strictly off-diagonal coefficients of lane i's row
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) row[c] = BWD ? (c > i ? l[i][c] : 0.0) : (c < i ? l[c][i] : 0.0);
+    const double inv = 1.0 / l[i][i];
     double* x = X + blockIdx.x * ldx + k;
     double xi = i < nb ? x[i] : 0.0;
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (i == j) {
-            xi /= l[j][j];
-            s[j] = xi;
-        }
-        __syncthreads();
-        if (i > j && i < nb) xi -= l[j][i] * s[j];
+#pragma unroll
+    for (int s = 0; s < kNB; ++s) {
+        const int j = BWD ? kNB - 1 - s : s;
+        if (i == j) xi *= inv;
+        xi -= row[j] * readlane_f64(xi, j);
     }
     if (i < nb) x[i] = xi;
 }
 
-// Forward, rows below block k: X[b][r] -= sum_c L[r, k + c] X[b][k + c]
-// for r in [k + nb, n); one row per lane, all right-hand sides per lane.
-__global__ __launch_bounds__(256) void k_trsv_fwd_update(const double* __restrict__ L, long long lda, int n, int k,
-                                                         double* __restrict__ X, long long ldx, int nrhs) {
+// Rows [row0, row0 + nrows) of the solves' updates with the nb columns of
+// block k: X[b][r] -= sum_c A[r, k + c] X[b][k + c].  Forward solve: rows
+// below the block, A = L.  Backward solve: rows above the block, where the
+// upper triangle holds L^T.  Either way column k + c is one contiguous run;
+// one row per lane, one wavefront per 64 rows.
+__global__ __launch_bounds__(64) void k_trsv_update(const double* __restrict__ A, long long lda, long long row0,
+                                                    long long nrows, int k, int nb, double* __restrict__ X,
+                                                    long long ldx, int nrhs) {
     __shared__ double xs[8][kNB];
-    const long long r = (long long)k + kNB + blockIdx.x * 256 + threadIdx.x;
-    double lr[kNB];
+    const long long r = blockIdx.x * 64 + threadIdx.x;
+    const bool live = r < nrows;
+    double a[kNB];
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) lr[c] = r < n ? L[(long long)(k + c) * lda + r] : 0.0;
+    for (int c = 0; c < kNB; ++c) a[c] = live && c < nb ? A[(long long)(k + c) * lda + row0 + r] : 0.0;
     for (int b0 = 0; b0 < nrhs; b0 += 8) {
-        const int nb = min(8, nrhs - b0);
+        const int m = min(8, nrhs - b0);
         __syncthreads();
-        for (int e = threadIdx.x; e < nb * kNB; e += 256) xs[e / kNB][e % kNB] = X[(long long)(b0 + e / kNB) * ldx + k + e % kNB];
+        for (int e = threadIdx.x; e < 8 * kNB; e += 64) {
+            const int b = e / kNB, c = e % kNB;
+            xs[b][c] = b < m && c < nb ? X[(long long)(b0 + b) * ldx + k + c] : 0.0;
+        }
         __syncthreads();
-        if (r < n) {
-            for (int b = 0; b < nb; ++b) {
+        if (live) {
+            for (int b = 0; b < m; ++b) {
                 double acc = 0.0;
 #pragma unroll
-                for (int c = 0; c < kNB; ++c) acc += lr[c] * xs[b][c];
-                X[(long long)(b0 + b) * ldx + r] -= acc;
+                for (int c = 0; c < kNB; ++c) acc += a[c] * xs[b][c];
+                X[(long long)(b0 + b) * ldx + row0 + r] -= acc;
             }
-        }
-    }
-}
-
-// Backward, diagonal block k: X[b][k:k+nb] = L_kk^{-T} X[b][k:k+nb].
-__global__ __launch_bounds__(64) void k_trsv_bwd_diag(const double* __restrict__ L, long long lda, int k, int nb,
-                                                      double* __restrict__ X, long long ldx) {
-    __shared__ double l[kNB][kLP];
-    __shared__ double s[kNB];
-    const int i = threadIdx.x;
-    for (int c = 0; c < nb; ++c) l[c][i] = (i < nb && i >= c) ? L[(long long)(k + c) * lda + k + i] : 0.0;
-    double* x = X + blockIdx.x * ldx + k;
-    double xi = i < nb ? x[i] : 0.0;
-    __syncthreads();
-    for (int j = nb - 1; j >= 0; --j) {
-        if (i == j) {
-            xi /= l[j][j];
-            s[j] = xi;
-        }
-        __syncthreads();
-        if (i < j) xi -= l[i][j] * s[j];                 // L^T(i, j) = L(j, i)
-    }
-    if (i < nb) x[i] = xi;
-}
-
-// Backward, columns left of block k: X[b][c] -= sum_{r in block} L[r, c] X[b][r]
-// for c < k; a workgroup stages 64 columns' rows of the block in LDS (whole
-// 512-byte runs per column) and each lane sums one column.
-__global__ __launch_bounds__(64) void k_trsv_bwd_update(const double* __restrict__ L, long long lda, int k, int nb,
-                                                        double* __restrict__ X, long long ldx, int nrhs) {
-    __shared__ double t[kNB][kLP];                     // t[col][row in block]
-    __shared__ double xs[kNB];
-    const int c0 = blockIdx.x * 64, lane = threadIdx.x;
-    for (int cc = 0; cc < 64; ++cc) {
-        const int c = c0 + cc;
-        t[cc][lane] = (c < k && lane < nb) ? L[(long long)c * lda + k + lane] : 0.0;
-    }
-    for (int b = 0; b < nrhs; ++b) {
-        __syncthreads();
-        xs[lane] = lane < nb ? X[(long long)b * ldx + k + lane] : 0.0;
-        __syncthreads();
-        const int c = c0 + lane;
-        if (c < k) {
-            double acc = 0.0;
-#pragma unroll 8
-            for (int r = 0; r < kNB; ++r) acc += t[lane][r] * xs[r];
-            X[(long long)b * ldx + c] -= acc;
         }
     }
 }
@@ -488,14 +500,24 @@ hipError_t launch_d2q_apply(const double* Q, long long nq, long long N, long lon
 }
 
 hipError_t launch_cholesky(double* A, long long n, long long lda, int* info, hipStream_t st) {
-    for (long long k = 0; k < n; k += kNB) {
-        const int nb = (int)std::min<long long>(kNB, n - k);
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, A, lda, (int)k, nb, info);
-        const long long below = n - k - nb;
-        if (below <= 0) break;
-        hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, st, A, lda, (int)n, (int)k);
-        const long long T = (below + 63) / 64;
-        hipLaunchKernelGGL(k_syrk_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, st, A, lda, (int)n, (int)k);
+    for (long long K0 = 0; K0 < n; K0 += kNB2) {
+        const long long pend = std::min<long long>(K0 + kNB2, n);      // end of the panel
+        for (long long k = K0; k < pend; k += kNB) {
+            const int nb = (int)std::min<long long>(kNB, n - k);
+            hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, st, A, lda, (int)k, nb, info);
+            const long long below = n - k - nb;
+            if (below <= 0) break;
+            hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, st, A, lda, (int)n,
+                               (int)k);
+            if (k + kNB < pend)                            // the panel's remaining columns, all rows below
+                hipLaunchKernelGGL(k_syrk_update, dim3((unsigned)trapezoid_tiles(below, pend - k - kNB)), dim3(256), 0,
+                                   st, A, lda, (int)n, (int)(k + kNB), (int)pend, (int)k, kNB);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (pend < n)                                       // trailing matrix, rank kNB2
+            hipLaunchKernelGGL(k_syrk_update, dim3((unsigned)trapezoid_tiles(n - pend, n - pend)), dim3(256), 0, st, A,
+                               lda, (int)n, (int)pend, (int)n, (int)K0, (int)(pend - K0));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -506,18 +528,18 @@ hipError_t launch_cholesky_solve(const double* L, long long n, long long lda, do
                                  hipStream_t st) {
     for (long long k = 0; k < n; k += kNB) {
         const int nb = (int)std::min<long long>(kNB, n - k);
-        hipLaunchKernelGGL(k_trsv_fwd_diag, dim3(nrhs), dim3(64), 0, st, L, lda, (int)k, nb, X, ldx);
+        hipLaunchKernelGGL(k_trsv_diag<false>, dim3(nrhs), dim3(256), 0, st, L, lda, (int)k, nb, X, ldx);
         const long long below = n - k - nb;
         if (below > 0)
-            hipLaunchKernelGGL(k_trsv_fwd_update, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, st, L, lda,
-                               (int)n, (int)k, X, ldx, nrhs);
+            hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((below + 63) / 64)), dim3(64), 0, st, L, lda, k + nb,
+                               below, (int)k, nb, X, ldx, nrhs);
     }
     for (long long k = (n - 1) / kNB * kNB; k >= 0; k -= kNB) {
         const int nb = (int)std::min<long long>(kNB, n - k);
-        hipLaunchKernelGGL(k_trsv_bwd_diag, dim3(nrhs), dim3(64), 0, st, L, lda, (int)k, nb, X, ldx);
+        hipLaunchKernelGGL(k_trsv_diag<true>, dim3(nrhs), dim3(256), 0, st, L, lda, (int)k, nb, X, ldx);
         if (k > 0)
-            hipLaunchKernelGGL(k_trsv_bwd_update, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, st, L, lda, (int)k, nb, X,
-                               ldx, nrhs);
+            hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, st, L, lda, 0LL, k,
+                               (int)k, nb, X, ldx, nrhs);
     }
     return hipGetLastError();
 }

@@ -363,7 +363,8 @@ def cholesky(K: torch.Tensor) -> torch.Tensor:
     """In-place Cholesky factorisation of the symmetric positive definite FP64
     [N, N] tensor K (row j = column j of K): on return its entries (j, i) with
     i >= j, i.e. the lower triangle of the column-major matrix, hold L with
-    K = L L^T.  Raises when a pivot is not positive."""
+    K = L L^T, and the strict upper triangle holds L^T (read by the backward
+    solve).  Raises when a pivot is not positive."""
     if K.dtype != torch.float64 or K.dim() != 2 or K.shape[0] != K.shape[1] or K.stride(1) != 1:
         raise ValueError("K must be a square float64 tensor with unit column stride")
     info = torch.zeros(1, dtype=torch.int32, device=K.device)
@@ -377,7 +378,8 @@ def cholesky(K: torch.Tensor) -> torch.Tensor:
 
 def cholesky_solve(L: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     """X <- K^{-1} X in place for X of shape [nrhs, N] (each row one
-    right-hand side), from the factor of ``cholesky``."""
+    right-hand side), from the factor as ``cholesky`` leaves it (both
+    triangles are read)."""
     N = L.shape[0]
     _check_factor(L, N, L.device)
     if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != N or X.stride(1) != 1:

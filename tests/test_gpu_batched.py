@@ -48,6 +48,8 @@ SHAPES = [
     synth.Workload("odd", Nd=70, Nm=1003, Nt=21, tau=6.0),        # 70 rows, pitch 1008 (partial column tiles)
     synth.Workload("blocks", Nd=37, Nm=9000, Nt=13, tau=5.0),     # three scale blocks / K chunks, ragged last
 ]
+# tile variants also on an operator with two 320-row forward tiles (the last ragged)
+TILE_SHAPES = SHAPES + [synth.Workload("tall", Nd=350, Nm=1003, Nt=21, tau=6.0)]
 
 
 @pytest.mark.parametrize("nrhs", [2, 9, 17, 40, 70])
@@ -122,7 +124,7 @@ def test_batched_misfit_gradient():
         assert oracle.rel_l2(g[b], g_o[b]) <= TOL_BF16
 
 
-@pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
+@pytest.mark.parametrize("w", TILE_SHAPES, ids=lambda w: w.name)
 def test_every_tile_variant(w):
     """Each matrix-core tile variant the autotuner can pick, forced, against
     the oracle (a full 64-wide group and a ragged one)."""
@@ -141,7 +143,7 @@ def test_every_tile_variant(w):
         assert worst <= TOL_BF16
 
 
-@pytest.mark.parametrize("w", SHAPES, ids=lambda w: w.name)
+@pytest.mark.parametrize("w", TILE_SHAPES, ids=lambda w: w.name)
 def test_fp16_spectrum_on_matrix_cores(w):
     """FP16-stored spectrum on the matrix cores (FP16 x FP16 products of the
     spectrum and the scaled right-hand sides, LDS-ring tiles): every ring

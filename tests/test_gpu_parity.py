@@ -140,16 +140,17 @@ def test_data_space_operator_columns(precision):
 # L = 840 (the paper's time shape): the length the library has compiled FFT
 # kernels for; 203 columns and 5 sensors leave ragged tiles on both sides.
 PAPER_T = synth.Workload("paper_t_small", Nd=5, Nm=203, Nt=420, tau=100.0)
+# section 5's number of time steps: L = 1000
+PAPER_T500 = synth.Workload("paper_t500_small", Nd=5, Nm=203, Nt=500, tau=100.0)
 
 
-def _l840_runs(precision):
+def _l840_runs(precision, w=PAPER_T):
     """F, F*, ragged F and F*, F F* (truncate-and-repad) with its spikes at
-    t = 0, 419, 347, 350, ragged F F* and the misfit epilogue at L = 840, on
-    both FFT paths (kernels compiled for L = 840 and the runtime-length ones),
-    with the oracle's results."""
-    w = PAPER_T
-    n = np.array([420, 301, 64, 0], dtype=np.int32)
-    nh = np.array([300, 420, 400, 351], dtype=np.int32)
+    t = 0, Nt - 1 and two more, ragged F F* and the misfit epilogue at
+    L = 2 Nt (840 by default), on both FFT paths (kernels compiled for that
+    length and the runtime-length ones), with the oracle's results."""
+    n = np.array([w.Nt, 301, 64, 0], dtype=np.int32)
+    nh = np.array([300, w.Nt, 400, 351], dtype=np.int32)
     op, F = build_op(w, precision, max_rhs=4)
     m = synth.param_series(w, 4)
     d = synth.data_series(w, 4)
@@ -212,6 +213,18 @@ def test_fixed_and_runtime_length_ffts(precision):
         # two) in the matrix-core operands: agreement to the operand rounding
         for key in got[True]:
             assert oracle.rel_l2(got[True][key], got[False][key]) <= 2.0 ** -11, key
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_fixed_and_runtime_length_ffts_at_L1000(precision):
+    """The same checks at L = 1000 (N_t = 500, the time steps of section 5's
+    problem; radices 4, 5, 5, 5)."""
+    note(f"[parity] fixed vs runtime-length FFTs, {PAPER_T500.name} {precision}")
+    ref, got, lens = _l840_runs(precision, PAPER_T500)
+    _check_l840(precision, ref, got, lens, ("F", "Ft", "F_ragged", "Ft_ragged", "FFt", "FFt_ragged"))
+    agree = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2.0 ** -11}[precision]
+    for key in got[True]:
+        assert oracle.rel_l2(got[True][key], got[False][key]) <= agree, key
 
 
 def test_bf16_spectrum_at_L840():

@@ -70,9 +70,9 @@ def test_cholesky_and_solve_on_oracle_K():
     fwd = np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo)
     note(f"[posterior] Cholesky: backward error {back:.2e}, factor vs numpy {fwd:.2e}")
     assert back <= 1e-14 and fwd <= 1e-11
-    # the strict upper triangle of the column-major matrix is left as it was
+    # the strict upper triangle of the column-major matrix holds L^T, bit for bit
     upper = np.triu(np.ones((N, N), dtype=bool), 1)
-    assert np.array_equal(L.cpu().numpy().T[upper], Ko[upper])
+    assert np.array_equal(L.cpu().numpy().T[upper], Lg.T[upper])
     rng = np.random.default_rng(2)
     B = rng.standard_normal((3, N))
     X = cholesky_solve(L, torch.from_numpy(B).to(DEV)).cpu().numpy()
