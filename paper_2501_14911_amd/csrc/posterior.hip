@@ -15,8 +15,8 @@
 //   it against L_kk^T (one row per lane, L_kk in LDS); subtract its P P^T
 //   from the panel's remaining columns.  After the panel: subtract the
 //   panel's rank-256 product from the lower tiles of the trailing matrix.
-//   Both updates run on v_mfma_f64_16x16x4f64 (64 x 64 tiles, the panel
-//   columns staged in LDS 64 at a time, the tile accumulated in registers
+//   Both updates run on v_mfma_f64_16x16x4f64 (128 x 128 tiles, the panel
+//   columns staged in LDS 16 at a time, the tile accumulated in registers
 //   and written once).
 // The factor is also written transposed into the strict upper triangle
 // (entry (i, j), i < j, receives L(j, i)), so that both triangular solves
@@ -248,20 +248,25 @@ __global__ __launch_bounds__(256) void k_trsm_panel(double* __restrict__ A, long
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Update A[t0 + i, t0 + j] -= sum_c P[i, c] P[j, c] over the 64 x 64 tiles
-// of rows [t0, n) and columns [t0, c_end) on or below the diagonal (tile
-// row >= tile column), P = A[t0:n, pk0:pk0 + kd].  Workgroup = one tile, 4
-// wavefronts of 32 x 32 (2 x 2 blocks of 16 x 16 on the matrix cores); the
-// panel columns are staged in LDS 64 at a time and the tile accumulates in
-// registers.  The products are taken as the transposed block P_j P_i^T so
-// that lane l of a block holds rows l % 16 of four columns: stores cover 128
-// contiguous bytes per 16 lanes.  Tiles are numbered column by column:
-// column tile tj has T - tj tiles (T row tiles).
-__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, long long lda, int n, int t0, int c_end,
+// Update A[t0 + i, t0 + j] -= sum_c P[i, c] P[j, c] over the 128 x 128
+// tiles of rows [t0, n) and columns [t0, c_end) on or below the diagonal
+// (tile row >= tile column), P = A[t0:n, pk0:pk0 + kd].  Workgroup = one
+// tile, 4 wavefronts of 64 x 64 (4 x 4 blocks of 16 x 16 on the matrix
+// cores), accumulated in registers and written once.  The panel columns
+// pass through LDS kKC at a time; the next columns are loaded into
+// registers while the matrix cores work on the current ones.  The products
+// are taken as the transposed block P_j P_i^T so that lane l of a block
+// holds rows l % 16 of four columns: stores cover 128 contiguous bytes per
+// 16 lanes.  Tiles are numbered column by column: column tile tj has T - tj
+// tiles (T row tiles).
+constexpr int kST = 128;                // update tile
+constexpr int kKC = 16;                 // panel columns per LDS stage
+constexpr int kSP = kST + 2;            // padded LDS row (doubles)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_syrk_update(double* __restrict__ A, long long lda, int n, int t0, int c_end,
                                                      int pk0, int kd) {
-    __shared__ double pi[kNB][kLP], pj[kNB][kLP];     // [panel column][tile row]
+    __shared__ double pi[kKC][kSP], pj[kKC][kSP];     // [panel column][tile row]
     const int m = n - t0, mc = c_end - t0;
-    const int T = (m + 63) / 64;
+    const int T = (m + kST - 1) / kST;
     // tile (ti, tj): tj is the largest column with S(tj) = tj (2T - tj + 1) / 2 <= q
     const long long q = blockIdx.x;
     const double b2 = 2.0 * T + 1.0;
@@ -270,49 +275,69 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, lon
     while (tj > 0 && S(tj) > q) --tj;
     while (S(tj + 1) <= q) ++tj;
     const int ti = tj + (int)(q - S(tj));
-    const int ri = ti * 64, rj = tj * 64;              // first rows (relative to t0)
+    const int ri = ti * kST, rj = tj * kST;            // first rows (relative to t0)
     if (rj >= mc) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // sub-tile: rows wr (of i), columns wc (of j)
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;   // sub-tile: rows wr (of i), columns wc (of j)
     const int li = lane & 15, lk = lane >> 4;
-    f64x4 acc[2][2];
+    f64x4 acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < kd; k0 += kNB) {
-        const int kw = min(kNB, kd - k0);
-        if (k0 > 0) __syncthreads();                   // every wavefront is done with the previous columns
-#pragma unroll 4
-        for (int e = threadIdx.x; e < 64 * kNB; e += 256) {
-            const int c = e / 64, r = e % 64;
+        for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // staging: thread t moves entries e = t + 256 u (column e / kST, row e % kST) of both panels
+    constexpr int NU = kKC * kST / 256;
+    double si[NU], sj[NU];
+    auto load = [&](int k0) {
+        const int kw = min(kKC, kd - k0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int e = threadIdx.x + 256 * u, c = e / kST, r = e % kST;
             const double* col = A + (long long)(pk0 + k0 + c) * lda + t0;
-            const bool cv = c < kw;
-            pi[c][r] = cv && ri + r < m ? col[ri + r] : 0.0;
-            pj[c][r] = cv && rj + r < m ? col[rj + r] : 0.0;
+            si[u] = c < kw && ri + r < m ? col[ri + r] : 0.0;
+            sj[u] = c < kw && rj + r < m ? col[rj + r] : 0.0;
         }
-        __syncthreads();
-#pragma unroll 4
-        for (int c0 = 0; c0 < kNB; c0 += 4) {
-            double vi[2], vj[2];
+    };
+    auto stage = [&]() {
 #pragma unroll
-            for (int a = 0; a < 2; ++a) vi[a] = pi[c0 + lk][wr + 16 * a + li];
+        for (int u = 0; u < NU; ++u) {
+            const int e = threadIdx.x + 256 * u, c = e / kST, r = e % kST;
+            pi[c][r] = si[u];
+            pj[c][r] = sj[u];
+        }
+    };
+    load(0);
+    stage();
+    __syncthreads();
+    for (int k0 = 0; k0 < kd; k0 += kKC) {
+        const bool more = k0 + kKC < kd;
+        if (more) load(k0 + kKC);                      // in flight during the products
+#pragma unroll 2
+        for (int c0 = 0; c0 < kKC; c0 += 4) {
+            double vi[4], vj[4];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) vj[b] = pj[c0 + lk][wc + 16 * b + li];
+            for (int a = 0; a < 4; ++a) vi[a] = pi[c0 + lk][wr + 16 * a + li];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vj[b] = pj[c0 + lk][wc + 16 * b + li];
             // block (a, b) of P_j P_i^T: rows = tile columns wc + 16 b + ., columns = tile rows wr + 16 a + .
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vj[b], vi[a], acc[a][b], 0, 0, 0);
+        }
+        if (more) {
+            __syncthreads();                           // every wavefront is done with these columns
+            stage();
+            __syncthreads();
         }
     }
     // lane l holds D[4 v + l / 16][l % 16] of each block in item v (measured
     // on gfx950 with an in-bounds probe): D row = j offset, D column = i offset
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gi = ri + wr + 16 * a + li;              // row of A (relative to t0)
@@ -325,7 +350,7 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, lon
 }
 
 static long long trapezoid_tiles(long long m, long long mc) {
-    const long long T = (m + 63) / 64, C = std::min(T, (mc + 63) / 64);
+    const long long T = (m + kST - 1) / kST, C = std::min(T, (mc + kST - 1) / kST);
     return C * (2 * T - C + 1) / 2;
 }
 

@@ -82,14 +82,44 @@ def test_cholesky_and_solve_on_oracle_K():
     assert err <= 1e-11
 
 
+def test_cholesky_panels_on_random_spd():
+    """Five 256-column panels (the last of 76 columns, its last 64-block of
+    12), 128-row update tiles with a ragged last row: factor against numpy's,
+    backward error, L^T in the upper triangle, solves against numpy's."""
+    n = 1100
+    rng = np.random.default_rng(5)
+    R = rng.standard_normal((n, n))
+    Ko = R @ R.T / n + np.eye(n)
+    L = cholesky(torch.from_numpy(Ko.T.copy()).to(DEV)).cpu().numpy().T
+    Lg = np.tril(L)
+    Ln = np.linalg.cholesky(Ko)
+    back = np.linalg.norm(Lg @ Lg.T - Ko) / np.linalg.norm(Ko)
+    fwd = np.linalg.norm(Lg - Ln) / np.linalg.norm(Ln)
+    note(f"[posterior] Cholesky n={n}: backward error {back:.2e}, factor vs numpy {fwd:.2e}")
+    assert back <= 1e-14 and fwd <= 1e-12
+    upper = np.triu(np.ones((n, n), dtype=bool), 1)
+    assert np.array_equal(L[upper], Lg.T[upper])
+    B = rng.standard_normal((5, n))
+    X = cholesky_solve(torch.from_numpy(L.T.copy()).to(DEV), torch.from_numpy(B).to(DEV)).cpu().numpy()
+    Xn = np.linalg.solve(Ko, B.T).T
+    assert np.linalg.norm(X - Xn) / np.linalg.norm(Xn) <= 1e-12
+
+
 def test_cholesky_reports_non_positive_pivot():
     A = -torch.eye(70, dtype=torch.float64, device=DEV)
     with pytest.raises(ValueError, match="pivot 0"):
         cholesky(A)
     B = torch.eye(130, dtype=torch.float64, device=DEV)
-    B[100, 100] = -1.0                                   # in the third diagonal block
+    B[100, 100] = -1.0                                   # in the second diagonal block
     with pytest.raises(ValueError, match="pivot 100"):
         cholesky(B)
+    C = torch.eye(600, dtype=torch.float64, device=DEV)
+    C[300, 300] = -1.0                                   # second panel; the first failure is reported
+    C[500, 500] = -2.0
+    with pytest.raises(ValueError, match="pivot 300"):
+        cholesky(C)
+    # a later call on a good matrix resets the report
+    cholesky(torch.eye(600, dtype=torch.float64, device=DEV))
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
