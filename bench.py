@@ -643,16 +643,18 @@ def posterior_leg(dev, torch, np, synth, P2OOperator, no_acc, batch=32, qstride=
         sens = np.sort(rng.choice(wf.Nd, 2, replace=False))
         Fr = synth.operator_rows_cols(wf, range(40), rows=sens, backend="torch").numpy()     # [40, 2, Nm]
         Kh = K.cpu().numpy()
+        def kref(i, j, a, c):
+            v = sum(Fr[i - k, a] @ Fr[j - k, c] for k in range(min(i, j) + 1))
+            return v + (sigma ** 2 if i == j and a == c else 0.0)
+
         errs = []
-        for i, j in ((0, 0), (5, 3), (17, 17), (39, 20), (25, 38)):
+        for i, j in ((0, 0), (1, 0), (5, 3), (17, 17), (39, 20), (25, 38)):
             for a in range(2):
                 for c in range(2):
-                    ref = sum(Fr[i - k, a] @ Fr[j - k, c] for k in range(min(i, j) + 1))
-                    if i == j and a == c:
-                        ref += sigma ** 2
                     got = Kh[j * wf.Nd + sens[c], i * wf.Nd + sens[a]]      # tensor row = column of K
-                    errs.append(abs(got - ref) / abs(ref))
-        out["K_sampled_max_rel_err"] = float(max(errs))
+                    # error against sqrt(K_pp K_qq), the bound of |K_pq| for an SPD K
+                    errs.append(abs(got - kref(i, j, a, c)) / np.sqrt(kref(i, i, a, a) * kref(j, j, c, c)))
+        out["K_sampled_max_err_vs_diag"] = float(max(errs))
     L, out["cholesky_ms"] = timed(lambda: cholesky(K))
     d_obs = synth.data_series(wf, 1, backend="torch", device=dev)[0].float() * 0.1
     m_map, out["map_point_ms"] = timed(lambda: op.map_point(d_obs, L, var, 1.0), reps=5)

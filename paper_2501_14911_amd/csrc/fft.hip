@@ -590,10 +590,19 @@ static hipError_t rhs_scales(const SeriesIO& io, int sh, hipError_t err, hipStre
 // series need at most (tiles of at least 4 series, 256-thread workgroups).
 int fft_amax_slots(int S_pad) { return (S_pad + 3) / 4 * (kFftThreads / 64); }
 
+// Wide tile shift for a transform of S series (when the compiled-length
+// kernels have one), else -1.  A transform that takes it reports the shift
+// it used, so that the per-tile maxima are read back with the same tiling.
+static int wide_shift(bool f64, const FftPlan& pl, int S) { return S >= kWideSeries ? fixed_wide_shift(f64, pl) : -1; }
+
 static hipError_t r2c_transform(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in,
-                                void* out, const void* tw, hipStream_t st) {
-    const int sh = fft_tile_shift(pl.M, f64);
+                                void* out, const void* tw, hipStream_t st, int* sh_used) {
     hipError_t err;
+    const int wsh = wide_shift(f64, pl, io.S_pad);
+    *sh_used = wsh;
+    if (wsh >= 0 && launch_fixed_r2c(f64, in_f64, pl, io, in, out, tw, wsh, st, &err)) return err;
+    const int sh = fft_tile_shift(pl.M, f64);
+    *sh_used = sh;
     if (launch_fixed_r2c(f64, in_f64, pl, io, in, out, tw, sh, st, &err)) return err;
     const ItemMap im = item_map(io.S_pad, sh, io.outer_count);
     if (io.amax_part && (long long)im.ntiles * (kFftThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
@@ -611,13 +620,19 @@ static hipError_t r2c_transform(bool f64, bool in_f64, const FftPlan& pl, const 
 
 hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
                       const void* tw, hipStream_t st) {
-    return rhs_scales(io, fft_tile_shift(pl.M, f64), r2c_transform(f64, in_f64, pl, io, in, out, tw, st), st);
+    int sh = 0;
+    const hipError_t err = r2c_transform(f64, in_f64, pl, io, in, out, tw, st, &sh);
+    return rhs_scales(io, sh, err, st);
 }
 
 hipError_t launch_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
                       const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st) {
-    const int sh = fft_tile_shift(pl.M, f64);
     hipError_t err;
+    // the misfit epilogue's partials are counted per tile of the runtime
+    // tile shift (c2r_grid_x), so it never takes wide tiles
+    const int wsh = d_obs ? -1 : wide_shift(f64, pl, io.S);
+    if (wsh >= 0 && launch_fixed_c2r(f64, pl, io, in, out, tw, wsh, d_obs, var, var_mode, partials, st, &err)) return err;
+    const int sh = fft_tile_shift(pl.M, f64);
     if (launch_fixed_c2r(f64, pl, io, in, out, tw, sh, d_obs, var, var_mode, partials, st, &err)) return err;
     const ItemMap im = item_map(io.S, sh, io.outer_count);
     dim3 grid(8 * im.Q);
@@ -643,9 +658,13 @@ int c2r_grid_x(const FftPlan& pl, bool f64, int S) {
 }
 
 static hipError_t project_transform(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
-                                    hipStream_t st) {
-    const int sh = fft_tile_shift(pl.M, f64);
+                                    hipStream_t st, int* sh_used) {
     hipError_t err;
+    const int wsh = wide_shift(f64, pl, io.S_pad);
+    *sh_used = wsh;
+    if (wsh >= 0 && launch_fixed_project(f64, pl, io, in_out, tw, wsh, st, &err)) return err;
+    const int sh = fft_tile_shift(pl.M, f64);
+    *sh_used = sh;
     if (launch_fixed_project(f64, pl, io, in_out, tw, sh, st, &err)) return err;
     const ItemMap im = item_map(io.S_pad, sh, io.outer_count);
     if (io.amax_part && (long long)im.ntiles * (kFftThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
@@ -657,7 +676,9 @@ static hipError_t project_transform(bool f64, const FftPlan& pl, const SeriesIO&
 
 hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
                           hipStream_t st) {
-    return rhs_scales(io, fft_tile_shift(pl.M, f64), project_transform(f64, pl, io, in_out, tw, st), st);
+    int sh = 0;
+    const hipError_t err = project_transform(f64, pl, io, in_out, tw, st, &sh);
+    return rhs_scales(io, sh, err, st);
 }
 
 hipError_t launch_misfit_reduce(const double* partials, int nper, double* misfit, int nrhs, hipStream_t st) {

@@ -730,25 +730,32 @@ hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStrea
 
 // Compiled (M, tile shift) pairs: the transform lengths of the common
 // workloads (Nt = 16, 128, 420, and 500 of section 5's problem), with the
-// tile widths fft_tile_shift picks.
+// tile widths fft_tile_shift picks, plus 16-series tiles for wide FP32
+// transforms of M = 500 (fixed_wide_shift): the runtime-length rule gives
+// M = 500 tiles of 4 series, whose bin rows are quarter lines of the
+// spectrum, while 16 series make each bin row of a tile one whole 128-byte
+// line.
 #define P2O_FX_CASES(X) \
     X(float, 16, 5)     \
     X(float, 128, 4)    \
     X(float, 420, 3)    \
     X(float, 500, 2)    \
+    X(float, 500, 4)    \
     X(double, 16, 5)    \
     X(double, 128, 3)   \
     X(double, 420, 2)   \
     X(double, 500, 1)
 
 // Lane offsets of `rows` rows of `stride` elements (plus a tile) fit the
-// 32-bit offsets the kernels use (rows: one sweep, 256 >> shift bins or
-// twice that many time steps).
+// unsigned 32-bit byte offsets the kernels add to their bases (ld, st;
+// rows: one sweep, 256 >> shift bins or twice that many time steps).
 bool fits32(long long rows, long long stride, size_t esz) {
-    return (rows * stride + 64) * (long long)esz < (1LL << 31);
+    return (rows * stride + 64) * (long long)esz < (1LL << 32);
 }
 
 }  // namespace
+
+int fixed_wide_shift(bool f64, const FftPlan& pl) { return !f64 && pl.fixed && pl.M == 500 ? 4 : -1; }
 
 bool launch_fixed_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
                       const void* tw, int sh, hipStream_t st, hipError_t* err) {

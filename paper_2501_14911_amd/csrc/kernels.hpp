@@ -51,6 +51,10 @@ struct LoadArgs {
 
 // fft.hip
 int fft_tile_shift(int M, bool f64);
+// Tile shift of the compiled-length kernels' wide tiles for this plan and
+// precision (used for transforms of at least kWideSeries series), or -1.
+int fixed_wide_shift(bool f64, const FftPlan& pl);
+constexpr int kWideSeries = 2048;
 int c2r_grid_x(const FftPlan& pl, bool f64, int S);
 hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st);
 hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,

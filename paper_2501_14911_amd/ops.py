@@ -251,10 +251,12 @@ class P2OOperator:
         return self.Nt * self.Nd
 
     def assemble_K(self, noise_var, prior_var: float = 1.0, K: Optional[torch.Tensor] = None,
-                   batch: Optional[int] = None) -> torch.Tensor:
+                   batch: Optional[int] = None, columns: Optional[tuple] = None) -> torch.Tensor:
         """K = Gamma_noise + prior_var F F^* as a dense FP64 [N, N] tensor
         (row j of the tensor is column j of K; K is symmetric), assembled in
-        batches of ``batch`` (default max_rhs) columns."""
+        batches of ``batch`` (default max_rhs) columns; ``columns`` = (j0, n)
+        assembles only columns j0 .. j0 + n - 1 (the rest of K is left as it
+        is)."""
         N = self.data_dim()
         if K is None:
             K = torch.empty((N, N), dtype=torch.float64, device=self.device)
@@ -263,10 +265,13 @@ class P2OOperator:
             raise ValueError(f"K must be a contiguous float64 [{N}, {N}] tensor on {self.device}")
         var = torch.as_tensor(noise_var, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
         b = int(batch or self.max_rhs)
+        c0, nc = (0, N) if columns is None else (int(columns[0]), int(columns[1]))
+        if c0 < 0 or nc < 0 or c0 + nc > N:
+            raise ValueError(f"columns ({c0}, {nc}) outside [0, {N})")
         self._stream()
-        for j0 in range(0, N, b):
+        for j0 in range(c0, c0 + nc, b):
             check(lib.p2o_assemble_K(self._plan, float(prior_var), _ptr(var), var.numel(), _ptr(K), K.stride(0), j0,
-                                     min(b, N - j0)))
+                                     min(b, c0 + nc - j0)))
         return K
 
     def map_point(self, d_obs: torch.Tensor, L: torch.Tensor, noise_var, prior_var: float = 1.0) -> torch.Tensor:

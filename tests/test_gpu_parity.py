@@ -142,6 +142,8 @@ def test_data_space_operator_columns(precision):
 PAPER_T = synth.Workload("paper_t_small", Nd=5, Nm=203, Nt=420, tau=100.0)
 # section 5's number of time steps: L = 1000
 PAPER_T500 = synth.Workload("paper_t500_small", Nd=5, Nm=203, Nt=500, tau=100.0)
+# at least 2048 parameter series: FP32 transforms of L = 1000 take 16-series tiles (the last one ragged)
+PAPER_T500_WIDE = synth.Workload("paper_t500_wide", Nd=3, Nm=2100, Nt=500, tau=100.0)
 
 
 def _l840_runs(precision, w=PAPER_T):
@@ -215,12 +217,16 @@ def test_fixed_and_runtime_length_ffts(precision):
             assert oracle.rel_l2(got[True][key], got[False][key]) <= 2.0 ** -11, key
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
-def test_fixed_and_runtime_length_ffts_at_L1000(precision):
+@pytest.mark.parametrize("precision,w", [("fp64", PAPER_T500), ("fp32", PAPER_T500), ("fp16", PAPER_T500),
+                                         ("fp32", PAPER_T500_WIDE), ("fp16", PAPER_T500_WIDE)],
+                         ids=["fp64", "fp32", "fp16", "fp32-wide", "fp16-wide"])
+def test_fixed_and_runtime_length_ffts_at_L1000(precision, w):
     """The same checks at L = 1000 (N_t = 500, the time steps of section 5's
-    problem; radices 4, 5, 5, 5)."""
-    note(f"[parity] fixed vs runtime-length FFTs, {PAPER_T500.name} {precision}")
-    ref, got, lens = _l840_runs(precision, PAPER_T500)
+    problem; radices 4, 5, 5, 5), with 4-series tiles and, for 2100
+    parameter series, 16-series tiles (compiled kernels only; the
+    runtime-length path keeps 4)."""
+    note(f"[parity] fixed vs runtime-length FFTs, {w.name} {precision}")
+    ref, got, lens = _l840_runs(precision, w)
     _check_l840(precision, ref, got, lens, ("F", "Ft", "F_ragged", "Ft_ragged", "FFt", "FFt_ragged"))
     agree = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2.0 ** -11}[precision]
     for key in got[True]:
