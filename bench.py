@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 N_HESS = 64
 N_RAGGED = 32
 
@@ -303,48 +304,57 @@ def main():
 # rows come from the autotuner's launches, which run every tile variant on the
 # benchmark's shapes.  Valid only for the kernel source it was measured on:
 # keyed by the SHA-1 of that file.
-_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "7199a5286c99f5aefcbeb78c705c380f0ce2cc96")
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "2f911a6b6be4d59d40b698f1b8e4ceda659b1751")
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
-# (kernel, tile): (fetch bytes, write bytes); GEMM rows from the autotuner's launches of every tile
+# (kernel, tile, spectrum precision): (fetch bytes, write bytes)
 _MEASURED = {
-    ('gemm_adj_32', 0): (16768916678, 1765821595),
-    ('gemm_adj_32', 1): (16800078712, 1765811099),
-    ('gemm_adj_32', 2): (16747575447, 1766837819),
-    ('gemm_adj_32', 3): (16721608483, 1765895067),
-    ('gemm_adj_32', 4): (16763789192, 1782897371),
-    ('gemm_adj_32', 5): (16814063237, 1810694459),
-    ('gemm_adj_32', 6): (16761001579, 1811694779),
-    ('gemm_adj_32', 9): (16737854099, 1765801979),
-    ('gemm_adj_32', 10): (16684835769, 1765801979),
-    ('gemm_adj_64', 0): (16952011041, 3537111734),
-    ('gemm_adj_64', 1): (17071207469, 3535810102),
-    ('gemm_adj_64', 2): (32457111877, 3534912246),
-    ('gemm_adj_64', 3): (16982867927, 3533839190),
-    ('gemm_adj_64', 4): (33574256827, 3566616630),
-    ('gemm_adj_64', 5): (17050211450, 3577760502),
-    ('gemm_adj_64', 6): (16932340573, 3670009462),
-    ('gemm_adj_64', 9): (16919524673, 3531603958),
-    ('gemm_adj_64', 10): (33353343939, 3531603958),
-    ('gemm_fwd_32', 0): (18397930027, 261020991),
-    ('gemm_fwd_32', 1): (18449910610, 261535935),
-    ('gemm_fwd_32', 2): (18759615643, 260724127),
-    ('gemm_fwd_32', 3): (20813418312, 260850847),
-    ('gemm_fwd_32', 4): (19964104051, 262083615),
-    ('gemm_fwd_32', 5): (19929158834, 260336255),
-    ('gemm_fwd_32', 6): (18581436609, 260754367),
-    ('gemm_fwd_32', 7): (18728610983, 260552511),
-    ('gemm_fwd_32', 8): (19034864092, 260919615),
-    ('gemm_fwd_64', 0): (20272753353, 522875903),
-    ('gemm_fwd_64', 1): (20711815515, 522553439),
-    ('gemm_fwd_64', 2): (20641582685, 524484831),
-    ('gemm_fwd_64', 3): (25466162858, 519329535),
-    ('gemm_fwd_64', 4): (24029962852, 522096895),
-    ('gemm_fwd_64', 5): (22905637899, 519834719),
-    ('gemm_fwd_64', 6): (20512511248, 534636383),
-    ('gemm_fwd_64', 7): (20722395220, 531308415),
-    ('gemm_fwd_64', 8): (20646713884, 524907615),
-    ('gemv_adj', None): (16586663286, 55188267),
-    ('gemv_fwd', None): (17107136589, 16166400),
+    ('gemm_adj_64', 1, 'bf16'): (17082032042, 3535705621),
+    ('gemm_adj_64', 2, 'bf16'): (31847052035, 3534823488),
+    ('gemm_adj_64', 3, 'bf16'): (17013299328, 3533744150),
+    ('gemm_adj_64', 4, 'bf16'): (33449310249, 3565478550),
+    ('gemm_adj_64', 5, 'bf16'): (17053242368, 3577802474),
+    ('gemm_adj_64', 6, 'bf16'): (16935612800, 3669371670),
+    ('gemm_adj_64', 9, 'bf16'): (16939654870, 3531603968),
+    ('gemm_adj_64', 10, 'bf16'): (33333909975, 3531603968),
+    ('gemm_adj_64', 15, 'bf16'): (16802764160, 3531603968),
+    ('gemm_adj_64', 16, 'bf16'): (33417260250, 3531603968),
+    ('gemm_fwd_64', 0, 'bf16'): (20244972587, 523023509),
+    ('gemm_fwd_64', 1, 'bf16'): (20338794752, 522562795),
+    ('gemm_fwd_64', 2, 'bf16'): (20641549776, 524581355),
+    ('gemm_fwd_64', 3, 'bf16'): (25084247081, 519237141),
+    ('gemm_fwd_64', 4, 'bf16'): (23961161346, 522095744),
+    ('gemm_fwd_64', 5, 'bf16'): (22625581309, 519619392),
+    ('gemm_fwd_64', 6, 'bf16'): (20503210755, 534626752),
+    ('gemm_fwd_64', 7, 'bf16'): (20567531520, 531692843),
+    ('gemm_fwd_64', 8, 'bf16'): (20643915346, 524817579),
+    ('gemm_fwd_64', 11, 'bf16'): (27314822021, 534802261),
+    ('gemm_fwd_64', 12, 'bf16'): (23765472256, 560254549),
+    ('gemm_fwd_64', 13, 'bf16'): (20203701846, 523361621),
+    ('gemm_fwd_64', 14, 'bf16'): (21224764075, 521022357),
+    ('gemv_adj', None, 'bf16'): (16586875904, 55188864),
+    ('gemv_fwd', None, 'bf16'): (17108026368, 16166400),
+    ('gemm_adj_32', 9, 'fp16'): (16706503211, 1765801984),
+    ('gemm_adj_32', 10, 'fp16'): (16713023061, 1765801984),
+    ('gemm_adj_32', 15, 'fp16'): (16703037696, 1765801984),
+    ('gemm_adj_32', 16, 'fp16'): (16710312404, 1765801984),
+    ('gemm_adj_64', 9, 'fp16'): (16902326699, 3531603968),
+    ('gemm_adj_64', 10, 'fp16'): (33488821596, 3531603968),
+    ('gemm_adj_64', 15, 'fp16'): (16802615594, 3531603968),
+    ('gemm_adj_64', 16, 'fp16'): (33430608131, 3531603968),
+    ('gemm_fwd_32', 7, 'fp16'): (18998609493, 260090709),
+    ('gemm_fwd_32', 8, 'fp16'): (19143526656, 260752640),
+    ('gemm_fwd_32', 11, 'fp16'): (21642715054, 262724416),
+    ('gemm_fwd_32', 12, 'fp16'): (20561256277, 267166891),
+    ('gemm_fwd_32', 13, 'fp16'): (18478076075, 261696939),
+    ('gemm_fwd_32', 14, 'fp16'): (18465922346, 261713429),
+    ('gemm_fwd_64', 7, 'fp16'): (21137234309, 526315627),
+    ('gemm_fwd_64', 8, 'fp16'): (20647867139, 524955285),
+    ('gemm_fwd_64', 11, 'fp16'): (28386387074, 531433344),
+    ('gemm_fwd_64', 12, 'fp16'): (23657384489, 537314645),
+    ('gemm_fwd_64', 13, 'fp16'): (20209269632, 523272448),
+    ('gemm_fwd_64', 14, 'fp16'): (24225048576, 525051179),
+    ('gemv_adj', None, 'fp16'): (16586877952, 55189120),
+    ('gemv_fwd', None, 'fp16'): (17108039295, 16166400),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
@@ -598,7 +608,7 @@ def fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var, no_acc, res
     return out
 
 
-def posterior_leg(dev, torch, np, synth, P2OOperator, no_acc, batch=32, qstride=10, sigma=1e-2):
+def posterior_leg(dev, torch, np, synth, P2OOperator, no_acc, batch=64, qstride=10, sigma=1e-2):
     """The offline and online phases at the dimensions of the paper's
     numerical example (section 5: Nd = 49, Nm = 513^2, Nt = 500; 16 QoIs every
     10th step), FP16 spectra, stand-in prior Gamma_prior = I, Gamma_noise =
@@ -668,8 +678,29 @@ def posterior_leg(dev, torch, np, synth, P2OOperator, no_acc, batch=32, qstride=
         out["Qd_vs_Fq_map_rel"] = float((q[0] - qm).norm() / qm.norm())
         Ch = C.cpu().numpy()
         out["qoi_cov_symmetry_rel"] = float(np.linalg.norm(Ch - Ch.T) / np.linalg.norm(Ch))
+    # Rooflines.  Each batched call reads the stored spectrum once per product
+    # whatever its right-hand-side count (<= batch); a triangular-solve pair
+    # reads the factor once (the forward solve its lower triangle, the
+    # backward solve its upper one: N^2 FP64 values).  Algorithmic bytes:
+    # spectrum passes x spectrum bytes + solves x 8 N^2.  The Cholesky
+    # factorisation is N^3 / 3 FP64 multiply-adds, x2 flops.
+    fb, fqb, lb = float(op.fhat_bytes), float(oq.fhat_bytes), 8.0 * N * N
+    nbk, nbq = -(-N // batch), -(-nq // batch)
+    phases = {"assemble_K": (nbk * 2 * fb, out["assemble_K_ms"]),
+              "map_point": (3 * fb + lb, out["map_point_ms"]),
+              "d2q_map": (nbq * (fqb + 3 * fb + lb), out["d2q_map_ms"]),
+              "qoi_posterior_cov": (nbq * (4 * fqb + 2 * fb + lb), out["qoi_posterior_cov_ms"])}
+    roof = {k: {"bound": "hbm", "algorithmic_bytes": b, "achieved": b / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS} for k, (b, ms) in phases.items()}
+    chol_flop = N ** 3 / 3.0 * 2.0
+    roof["cholesky"] = {"bound": "mfma", "algorithmic_flops": chol_flop,
+                        "achieved": chol_flop / (out["cholesky_ms"] * 1e-3) / 1e12, "peak": FP64_MFMA_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": chol_flop / (out["cholesky_ms"] * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS}
+    out["roofline"] = roof
     log("[bench] posterior (paper grid): " + ", ".join(f"{k} {v:.3g}" for k, v in out.items()
                                                       if isinstance(v, float)))
+    log("[bench] posterior rooflines: " + ", ".join(f"{k} {v['achieved']:.0f} {v['unit']} ({100 * v['frac']:.1f}%)"
+                                                  for k, v in roof.items()))
     op.close()
     oq.close()
     del op, oq, K, L, Q, C
