@@ -198,6 +198,33 @@ p2o_status p2o_assemble_K(p2o_plan* plan, double prior_var, const double* noise_
                           int64_t noise_var_len, double* K, int64_t ldk, int64_t j0,
                           int64_t ncols);
 
+/* K from the blocks themselves (section 4, Phase 2, when the caller holds
+ * the blocks F_k rather than only the loaded spectrum): since F is block
+ * lower-triangular Toeplitz, block (i, j) of F F^* is
+ * sum_{k <= min(i, j)} F_{i-k} F_{j-k}^T, i.e. for i >= j the prefix sum
+ * over l <= j of G(i - j + l, l) along a block diagonal of the Gram matrix
+ * G = A A^T of the stacked blocks A = [F_0; ...; F_{Nt-1}] (row t Nd + s is
+ * sensor s of F_t, the data-space order).  Exact up to FP64 rounding (no
+ * stored spectrum involved); FP64 matrix cores.  Two calls:
+ *
+ * p2o_gram_accumulate: G += A_c A_c^T on the lower triangle (i >= j) for a
+ * chunk A_c of A's columns: blocks[(t Nd + s) ldb + c] = F_t[s, c0 + c],
+ * c < ncols (device FP64; the layout a loader callback's [Nt][Nd][ncols]
+ * chunk has with ldb = ncols).  G: N x N, N = Nt Nd, column-major with
+ * leading dimension ldg >= N (device FP64), zeroed by the caller before the
+ * first chunk; chunks may come in any order.  Asynchronous on `stream`. */
+p2o_status p2o_gram_accumulate(const double* blocks, int64_t Nt, int64_t Nd, int64_t ncols, int64_t ldb, double* G,
+                               int64_t ldg, void* stream);
+
+/* p2o_gram_to_K: turns the accumulated G into K = Gamma_noise + prior_var
+ * F F^* in place (the block-diagonal prefix sums, the scaling, the noise
+ * variance on the diagonal, and the upper triangle mirrored from the lower
+ * one: the same matrix p2o_assemble_K assembles column by column).
+ * noise_var: device FP64 array of length 1, Nd or Nt Nd (as for
+ * p2o_assemble_K).  Asynchronous on `stream`. */
+p2o_status p2o_gram_to_K(double* G, int64_t ldg, int64_t Nt, int64_t Nd, double prior_var, const double* noise_var,
+                         int64_t noise_var_len, void* stream);
+
 /* In-place Cholesky factorisation A = L L^T of a symmetric positive definite
  * n x n FP64 matrix on the device (column-major, lda >= n; section 4,
  * Phase 2: K is factorised offline): on return the lower triangle (i >= j)

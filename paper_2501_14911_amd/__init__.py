@@ -9,7 +9,7 @@ package loads the library and fails if it has not been built.
 """
 from ._lib import P2OError, LIB_PATH, PRECISIONS, lib, status_name, last_error
 from .ops import (P2OOperator, P2O, P2OT, misfit, SCALE_BLOCK, bandwidth_probe, gemm_tiles, cholesky,
-                  cholesky_solve, d2q_apply)
+                  cholesky_solve, d2q_apply, assemble_K_from_blocks)
 
 __all__ = ["bandwidth_probe", "gemm_tiles", "P2OOperator", "P2O", "P2OT", "misfit", "cholesky", "cholesky_solve", "d2q_apply",
-           "P2OError", "PRECISIONS", "SCALE_BLOCK", "lib", "LIB_PATH", "status_name", "last_error"]
+           "assemble_K_from_blocks", "P2OError", "PRECISIONS", "SCALE_BLOCK", "lib", "LIB_PATH", "status_name", "last_error"]

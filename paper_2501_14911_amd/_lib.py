@@ -59,6 +59,8 @@ def _load():
         "p2o_apply_FFt": [pv, pv, pv, c_int64, pv],
         "p2o_misfit_grad": [pv, pv, pv, pv, c_int64, pv, pv, c_int64, pv],
         "p2o_assemble_K": [pv, c_double, pv, c_int64, pv, c_int64, c_int64, c_int64],
+        "p2o_gram_accumulate": [pv, c_int64, c_int64, c_int64, c_int64, pv, c_int64, pv],
+        "p2o_gram_to_K": [pv, c_int64, c_int64, c_int64, c_double, pv, c_int64, pv],
         "p2o_cholesky": [pv, c_int64, c_int64, pv, pv],
         "p2o_cholesky_solve": [pv, c_int64, c_int64, pv, c_int64, c_int64, pv],
         "p2o_map_point": [pv, c_double, pv, c_int64, pv, c_int64, pv, pv, c_int64],

@@ -1051,6 +1051,38 @@ p2o_status p2o_assemble_K(p2o_plan* p, double prior_var, const double* noise_var
     }
 }
 
+p2o_status p2o_gram_accumulate(const double* blocks, int64_t Nt, int64_t Nd, int64_t ncols, int64_t ldb, double* G,
+                               int64_t ldg, void* stream) {
+    if (!blocks || !G) return fail(P2O_ERR_ARG, "blocks or G is NULL");
+    if (Nt < 1 || Nd < 1 || Nt * Nd > (1LL << 31) - 1) return fail(P2O_ERR_ARG, "Nt=%lld, Nd=%lld invalid", (long long)Nt, (long long)Nd);
+    const int64_t N = Nt * Nd;
+    if (ncols < 1 || ncols > (1LL << 31) - 1 || ldb < ncols || ldg < N)
+        return fail(P2O_ERR_ARG, "ncols=%lld, ldb=%lld or ldg=%lld invalid", (long long)ncols, (long long)ldb,
+                    (long long)ldg);
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return check_hip(launch_gram_update(blocks, ldb, N, (int)ncols, G, ldg, static_cast<hipStream_t>(stream)),
+                     "Gram update");
+}
+
+p2o_status p2o_gram_to_K(double* G, int64_t ldg, int64_t Nt, int64_t Nd, double prior_var, const double* noise_var,
+                         int64_t noise_var_len, void* stream) {
+    if (!G || !noise_var) return fail(P2O_ERR_ARG, "G or noise_var is NULL");
+    if (Nt < 1 || Nd < 1 || Nt * Nd > (1LL << 31) - 1) return fail(P2O_ERR_ARG, "Nt=%lld, Nd=%lld invalid", (long long)Nt, (long long)Nd);
+    if (ldg < Nt * Nd) return fail(P2O_ERR_ARG, "ldg=%lld < Nt*Nd=%lld", (long long)ldg, (long long)(Nt * Nd));
+    if (!(prior_var > 0.0) || prior_var > 1e300) return fail(P2O_ERR_ARG, "prior_var must be positive and finite");
+    int var_mode;
+    if (noise_var_len == 1) var_mode = 0;
+    else if (noise_var_len == Nd) var_mode = 1;
+    else if (noise_var_len == Nd * Nt) var_mode = 2;
+    else
+        return fail(P2O_ERR_ARG, "noise_var_len=%lld must be 1, Nd=%lld or Nt*Nd=%lld", (long long)noise_var_len,
+                    (long long)Nd, (long long)(Nd * Nt));
+    if (!have_device()) return fail(P2O_ERR_NO_DEVICE, "no GPU available");
+    return check_hip(launch_gram_to_K(G, ldg, (int)Nt, (int)Nd, prior_var, noise_var, var_mode,
+                                      static_cast<hipStream_t>(stream)),
+                     "K from the Gram matrix");
+}
+
 p2o_status p2o_cholesky(double* A, int64_t n, int64_t lda, int32_t* info, void* stream) {
     if (!A || !info) return fail(P2O_ERR_ARG, "A or info is NULL");
     if (n < 1 || n > (1LL << 31) - 1 || lda < n) return fail(P2O_ERR_ARG, "n=%lld or lda=%lld invalid", (long long)n, (long long)lda);

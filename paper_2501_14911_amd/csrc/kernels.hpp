@@ -128,6 +128,12 @@ hipError_t launch_d2q_rows(bool f64, const void* y, const void* h, long long N, 
                            long long r0, const double* var, int var_mode, int Nd, double gamma, hipStream_t st);
 hipError_t launch_d2q_apply(const double* Q, long long nq, long long N, long long ldq, const double* d, double* q,
                             int nrhs, hipStream_t st);
+// G += B B^T (lower triangle; B: N rows of kc columns, row stride ldb), and
+// K = prior_var (block-diagonal prefix sums of G) + Gamma_noise, mirrored.
+hipError_t launch_gram_update(const double* B, long long ldb, long long N, int kc, double* G, long long ldg,
+                              hipStream_t st);
+hipError_t launch_gram_to_K(double* G, long long ldg, int Nt, int Nd, double prior_var, const double* var,
+                            int var_mode, hipStream_t st);
 hipError_t launch_cholesky(double* A, long long n, long long lda, int* info, hipStream_t st);
 hipError_t launch_cholesky_solve(const double* L, long long n, long long lda, double* X, int nrhs, long long ldx,
                                  hipStream_t st);

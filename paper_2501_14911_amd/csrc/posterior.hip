@@ -354,6 +354,146 @@ static long long trapezoid_tiles(long long m, long long mc) {
     return C * (2 * T - C + 1) / 2;
 }
 
+// ---------------------------------------------------------------- K from the blocks' Gram matrix
+// With the blocks F_k themselves at hand (not only their spectrum), the
+// (i, j) block of F F^* is sum_{k <= min(i, j)} F_{i-k} F_{j-k}^T (F is
+// block lower-triangular Toeplitz), i.e. for i >= j the sum over l <= j of
+// G(i - j + l, l), G(p, q) = F_p F_q^T: prefix sums along the block
+// diagonals of the Gram matrix G = A A^T of the stacked blocks
+// A = [F_0; ...; F_{Nt-1}] (row t Nd + s = sensor s of F_t).  G is summed
+// over column chunks of A as they are generated.
+
+// G += B B^T on the lower 128 x 128 tiles (tile row >= tile column) of the
+// N x N matrix G, B a chunk of A: N rows of kc columns, row r at B + r ldb.
+// Tiling, register prefetch of the next 16 columns and matrix-core products
+// as in k_syrk_update; the staging reads 16 consecutive columns (one 128-byte
+// line) of each row.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_gram_update(const double* __restrict__ B, long long ldb, int N, int kc, double* __restrict__ G, long long ldg) {
+    __shared__ double pi[kKC][kSP], pj[kKC][kSP];     // [chunk column][tile row]
+    const int T = (N + kST - 1) / kST;
+    const long long q = blockIdx.x;
+    const double b2 = 2.0 * T + 1.0;
+    int tj = (int)((b2 - sqrt(b2 * b2 - 8.0 * (double)q)) * 0.5);
+    auto S = [&](long long c) { return c * (2LL * T - c + 1) / 2; };
+    while (tj > 0 && S(tj) > q) --tj;
+    while (S(tj + 1) <= q) ++tj;
+    const int ti = tj + (int)(q - S(tj));
+    const int ri = ti * kST, rj = tj * kST;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int li = lane & 15, lk = lane >> 4;
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // staging: thread t moves row e / kKC, column e % kKC, e = t + 256 u
+    constexpr int NU = kKC * kST / 256;
+    double si[NU], sj[NU];
+    auto load = [&](int k0) {
+        const int kw = min(kKC, kc - k0);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int e = threadIdx.x + 256 * u, r = e / kKC, c = e % kKC;
+            si[u] = c < kw && ri + r < N ? B[(long long)(ri + r) * ldb + k0 + c] : 0.0;
+            sj[u] = c < kw && rj + r < N ? B[(long long)(rj + r) * ldb + k0 + c] : 0.0;
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int e = threadIdx.x + 256 * u, r = e / kKC, c = e % kKC;
+            pi[c][r] = si[u];
+            pj[c][r] = sj[u];
+        }
+    };
+    load(0);
+    stage();
+    __syncthreads();
+    for (int k0 = 0; k0 < kc; k0 += kKC) {
+        const bool more = k0 + kKC < kc;
+        if (more) load(k0 + kKC);
+#pragma unroll 2
+        for (int c0 = 0; c0 < kKC; c0 += 4) {
+            double vi[4], vj[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) vi[a] = pi[c0 + lk][wr + 16 * a + li];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vj[b] = pj[c0 + lk][wc + 16 * b + li];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vj[b], vi[a], acc[a][b], 0, 0, 0);
+        }
+        if (more) {
+            __syncthreads();
+            stage();
+            __syncthreads();
+        }
+    }
+    // lane l holds D[4 v + l / 16][l % 16]: D row = column offset of G, D column = row offset
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = ri + wr + 16 * a + li;
+                const int gj = rj + wc + 16 * b + 4 * v + lk;
+                if (gi < N && gj < N && gi >= gj) G[(long long)gj * ldg + gi] += acc[a][b][v];
+            }
+}
+
+// Prefix sums along the block diagonals of the lower triangle of G, in
+// place: thread (d, p, q) walks block (d + j, j), j = 0 .. Nt - 1 - d, entry
+// (p, q), keeping the running sum in a register (q <= p on the diagonal
+// blocks, whose upper parts are not computed).
+__global__ void k_gram_prefix(double* __restrict__ G, long long ldg, int Nt, int Nd) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long per = (long long)Nd * Nd;
+    if (t >= (long long)Nt * per) return;
+    const int d = (int)(t / per), e = (int)(t % per), q = e / Nd, p = e % Nd;
+    if (d == 0 && p < q) return;
+    double* g = G + (long long)q * ldg + (long long)d * Nd + p;    // block (d, 0), entry (p, q)
+    const long long step = (long long)Nd * ldg + Nd;                 // to block (d + j + 1, j + 1)
+    double sum = 0.0;
+    for (int j = 0; j < Nt - d; ++j) {
+        sum += *g;
+        *g = sum;
+        g += step;
+    }
+}
+
+// K from the prefix-summed G: K = prior_var G + Gamma_noise on and below the
+// diagonal, mirrored into the upper triangle (64 x 64 tiles through LDS;
+// tile (ti, tj), ti >= tj, writes its transpose to tile (tj, ti)).
+__global__ __launch_bounds__(256) void k_gram_finish(double* __restrict__ G, long long ldg, int N, double prior_var,
+                                                     const double* __restrict__ var, int var_mode, int Nd) {
+    __shared__ double t[64][65];
+    const long long qd = blockIdx.x;
+    int ti = (int)((sqrt(8.0 * (double)qd + 1.0) - 1.0) * 0.5);
+    while ((long long)(ti + 1) * (ti + 2) / 2 <= qd) ++ti;
+    while ((long long)ti * (ti + 1) / 2 > qd) --ti;
+    const int tj = (int)(qd - (long long)ti * (ti + 1) / 2);
+    const int r0 = ti * 64, c0 = tj * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int c = e / 64, r = e % 64, i = r0 + r, j = c0 + c;
+        if (i < N && j < N && i >= j) {
+            double v = prior_var * G[(long long)j * ldg + i];
+            if (i == j) v += noise_var_at(var, var_mode, i, Nd);
+            G[(long long)j * ldg + i] = v;
+            t[c][r] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e / 64, c = e % 64, i = r0 + r, j = c0 + c;      // write K(j, i) = K(i, j), i > j
+        if (i < N && j < N && i > j) G[(long long)i * ldg + j] = t[c][r];
+    }
+}
+
 // ---------------------------------------------------------------- triangular solves with L
 // Diagonal block k (nb rows) of the solves: X[b][k:k+nb] = L_kk^{-1} X[b][k:k+nb]
 // (forward) or L_kk^{-T} X[b][k:k+nb] (backward).  One workgroup per
@@ -521,6 +661,24 @@ hipError_t launch_d2q_apply(const double* Q, long long nq, long long N, long lon
                             int nrhs, hipStream_t st) {
     const long long waves = nq * nrhs;
     hipLaunchKernelGGL(k_d2q_apply, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, Q, nq, N, ldq, d, q, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_update(const double* B, long long ldb, long long N, int kc, double* G, long long ldg,
+                              hipStream_t st) {
+    if (N <= 0 || kc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_update, dim3((unsigned)trapezoid_tiles(N, N)), dim3(256), 0, st, B, ldb, (int)N, kc, G,
+                       ldg);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_to_K(double* G, long long ldg, int Nt, int Nd, double prior_var, const double* var,
+                            int var_mode, hipStream_t st) {
+    const long long N = (long long)Nt * Nd, nthr = (long long)Nt * Nd * Nd;
+    hipLaunchKernelGGL(k_gram_prefix, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st, G, ldg, Nt, Nd);
+    const long long T = (N + 63) / 64;
+    hipLaunchKernelGGL(k_gram_finish, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, st, G, ldg, (int)N, prior_var,
+                       var, var_mode, Nd);
     return hipGetLastError();
 }
 

@@ -364,6 +364,40 @@ def _check_factor(L: torch.Tensor, N: int, device):
         raise ValueError(f"L must be a contiguous float64 [{N}, {N}] tensor on {device}")
 
 
+def assemble_K_from_blocks(blocks: Callable[[int, int], torch.Tensor], Nd: int, Nm: int, Nt: int, noise_var,
+                           prior_var: float = 1.0, K: Optional[torch.Tensor] = None, chunk_cols: int = 2048,
+                           device="cuda") -> torch.Tensor:
+    """K = Gamma_noise + prior_var F F^* (dense FP64 [N, N], N = Nt Nd, row j
+    of the tensor = column j of K) from the blocks themselves:
+    ``blocks(c0, n)`` returns F_k[:, c0:c0+n] for all k as a [Nt, Nd, n]
+    tensor on the device (as for P2OOperator.load).  The Gram matrix of the
+    stacked blocks is accumulated chunk by chunk on the FP64 matrix cores and
+    turned into K by prefix sums along its block diagonals (no spectrum, no
+    FFT: exact up to FP64 rounding)."""
+    dev = torch.device(device)
+    if dev.type == "cuda" and dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    N = Nt * Nd
+    if K is None:
+        K = torch.empty((N, N), dtype=torch.float64, device=dev)
+    if K.dtype != torch.float64 or K.device != dev or K.dim() != 2 or K.shape[0] != N or K.shape[1] != N \
+            or K.stride(1) != 1:
+        raise ValueError(f"K must be a contiguous float64 [{N}, {N}] tensor on {dev}")
+    var = torch.as_tensor(noise_var, dtype=torch.float64, device=dev).reshape(-1).contiguous()
+    stream = c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    K.zero_()
+    for c0 in range(0, Nm, chunk_cols):
+        n = min(chunk_cols, Nm - c0)
+        B = blocks(c0, n)
+        if tuple(B.shape) != (Nt, Nd, n) or B.device != dev:
+            raise ValueError(f"blocks({c0}, {n}) must be a [{Nt}, {Nd}, {n}] tensor on {dev}")
+        B = B.to(torch.float64).contiguous()
+        check(lib.p2o_gram_accumulate(_ptr(B), Nt, Nd, n, n, _ptr(K), K.stride(0), stream))
+        del B
+    check(lib.p2o_gram_to_K(_ptr(K), K.stride(0), Nt, Nd, float(prior_var), _ptr(var), var.numel(), stream))
+    return K
+
+
 def cholesky(K: torch.Tensor) -> torch.Tensor:
     """In-place Cholesky factorisation of the symmetric positive definite FP64
     [N, N] tensor K (row j = column j of K): on return its entries (j, i) with
