@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-largest", action="store_true")
     ap.add_argument("--no-posterior", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     return ap.parse_args()
 
 
@@ -289,6 +290,8 @@ def main():
     if not args.no_fp64:
         result["fp64_plain"] = fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var,
                                           args.no_accuracy, result)
+    if not args.no_small:
+        result["small_configs"] = small_configs_leg(dev, torch, np, synth, P2OOperator, args.no_accuracy)
     if not args.no_largest:
         result["largest"] = largest_leg(dev, torch, np, synth, P2OOperator, args.no_accuracy)
     if not args.no_posterior:
@@ -604,6 +607,53 @@ def fp64_plain(w, dev, torch, np, synth, P2OOperator, m, d_obs, var, no_acc, res
         f"speedup per matvec {out['batched_fp16_speedup_per_matvec']:.1f}x")
     op.close()
     del op
+    torch.cuda.empty_cache()
+    return out
+
+
+def small_configs_leg(dev, torch, np, synth, P2OOperator, no_acc, calls=200):
+    """The two small configurations: 4 x 64 x 16 in FP64 and 64 x 4096 x 128
+    (L = 256) in FP64 and FP32.  Per call: mean microseconds of `calls`
+    back-to-back calls of F, F* and the misfit gradient on one right-hand side
+    (HIP events around the batch, so launch overhead is included), and the
+    error of F m and F* d against the FP64 oracle (the whole output)."""
+    import oracle
+    out = {}
+    for name, prec in (("tiny", "fp64"), ("medium", "fp64"), ("medium", "fp32")):
+        w = synth.CONFIGS[name]
+        F = synth.operator_blocks(w)
+        op = P2OOperator(w.Nd, w.Nm, w.Nt, prec, max_rhs=1, device=dev)
+        Ft = torch.from_numpy(F).to(dev)
+        op.load(lambda c0, n: Ft[:, :, c0:c0 + n])
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        m = synth.param_series(w, 1)
+        d = synth.data_series(w, 1)
+        d_obs = oracle.apply_F(F, synth.param_series(w, 1, seed_offset=11)) + synth.noise(w, 1)
+        mt, dtt, dot = (torch.from_numpy(x[0]).to(dev, dt) for x in (m, d, d_obs))
+        var = torch.tensor([w.sigma ** 2], dtype=torch.float64, device=dev)
+        res = {"shape": f"{w.Nd} x {w.Nm} x {w.Nt}", "L": op.L, "spectrum_bytes": op.fhat_bytes}
+        for key, fn in (("F", lambda: op.apply_F(mt)), ("Ft", lambda: op.apply_Ft(dtt)),
+                        ("misfit_grad", lambda: op.misfit_grad(mt, dot, var))):
+            for _ in range(10):
+                fn()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            for _ in range(calls):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            res[f"{key}_us"] = a.elapsed_time(b) / calls * 1e3
+        res["F_spectrum_GBs"] = op.fhat_bytes / (res["F_us"] * 1e-6) / 1e9
+        if not no_acc:
+            res["rel_l2_F"] = float(oracle.rel_l2(op.apply_F(mt).double().cpu().numpy(), oracle.apply_F(F, m)[0]))
+            res["rel_l2_Ft"] = float(oracle.rel_l2(op.apply_Ft(dtt).double().cpu().numpy(), oracle.apply_Ft(F, d)[0]))
+        out[f"{name}_{prec}"] = res
+        log(f"[bench] {name} {prec} ({res['shape']}): F {res['F_us']:.1f} us, F* {res['Ft_us']:.1f} us, "
+            f"misfit+gradient {res['misfit_grad_us']:.1f} us" +
+            (f"; rel-L2 F {res['rel_l2_F']:.1e}, F* {res['rel_l2_Ft']:.1e}" if not no_acc else ""))
+        op.close()
+        del op, Ft
     torch.cuda.empty_cache()
     return out
 
