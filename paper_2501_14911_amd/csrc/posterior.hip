@@ -562,6 +562,59 @@ __global__ __launch_bounds__(64) void k_trsv_update(const double* __restrict__ A
     }
 }
 
+// The same update for many right-hand sides as a product on the FP64 matrix
+// cores: workgroup = 64 rows x 64 right-hand sides, 4 wavefronts of 32 x 32
+// (2 x 2 blocks of 16 x 16), the block's 64 columns of A and the 64 x 64
+// right-hand-side values staged in LDS.  Taken as the transposed product
+// (right-hand side x row) so that 16 lanes update 16 consecutive rows of one
+// right-hand side (128 contiguous bytes).
+__global__ __launch_bounds__(256) void k_trsv_update_mfma(const double* __restrict__ A, long long lda, long long row0,
+                                                         long long nrows, int k, int nb, double* __restrict__ X,
+                                                         long long ldx, int nrhs) {
+    __shared__ double sa[kNB][kLP], sx[kNB][kLP];     // sa[c][r] = A(row0 + r0 + r, k + c), sx[c][b] = X[b0 + b][k + c]
+    const long long r0 = (long long)blockIdx.x * 64;
+    const int b0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * kNB; e += 256) {
+        const int c = e / 64, r = e % 64;
+        sa[c][r] = c < nb && r0 + r < nrows ? A[(long long)(k + c) * lda + row0 + r0 + r] : 0.0;
+        const int b = e / kNB, cc = e % kNB;
+        sx[cc][b] = cc < nb && b0 + b < nrhs ? X[(long long)(b0 + b) * ldx + k + cc] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wb = (wave & 1) * 32;   // rows wr.., right-hand sides wb..
+    const int li = lane & 15, lk = lane >> 4;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int c0 = 0; c0 < kNB; c0 += 4) {
+        double vr[2], vb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) vr[a] = sa[c0 + lk][wr + 16 * a + li];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) vb[b] = sx[c0 + lk][wb + 16 * b + li];
+        // block (a, b): rows of D = right-hand sides wb + 16 b + ., columns = rows wr + 16 a + .
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(vb[b], vr[a], acc[a][b], 0, 0, 0);
+    }
+    // lane l holds D[4 v + l / 16][l % 16] of each block in item v
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long long r = r0 + wr + 16 * a + li;
+                const int rb = b0 + wb + 16 * b + 4 * v + lk;
+                if (r < nrows && rb < nrhs) X[(long long)rb * ldx + row0 + r] -= acc[a][b][v];
+            }
+}
+
 dim3 grid_for(long long n) { return dim3((unsigned)std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256))); }
 
 }  // namespace
@@ -707,22 +760,31 @@ hipError_t launch_cholesky(double* A, long long n, long long lda, int* info, hip
     return hipGetLastError();
 }
 
+// Solve updates: one row per lane for few right-hand sides, the matrix-core
+// product from 16 on.
+constexpr int kTrsvMfmaRhs = 16;
+static void trsv_update(const double* L, long long lda, long long row0, long long nrows, int k, int nb, double* X,
+                        long long ldx, int nrhs, hipStream_t st) {
+    if (nrhs >= kTrsvMfmaRhs)
+        hipLaunchKernelGGL(k_trsv_update_mfma, dim3((unsigned)((nrows + 63) / 64), (unsigned)((nrhs + 63) / 64)),
+                           dim3(256), 0, st, L, lda, row0, nrows, k, nb, X, ldx, nrhs);
+    else
+        hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((nrows + 63) / 64)), dim3(64), 0, st, L, lda, row0, nrows, k,
+                           nb, X, ldx, nrhs);
+}
+
 hipError_t launch_cholesky_solve(const double* L, long long n, long long lda, double* X, int nrhs, long long ldx,
                                  hipStream_t st) {
     for (long long k = 0; k < n; k += kNB) {
         const int nb = (int)std::min<long long>(kNB, n - k);
         hipLaunchKernelGGL(k_trsv_diag<false>, dim3(nrhs), dim3(256), 0, st, L, lda, (int)k, nb, X, ldx);
         const long long below = n - k - nb;
-        if (below > 0)
-            hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((below + 63) / 64)), dim3(64), 0, st, L, lda, k + nb,
-                               below, (int)k, nb, X, ldx, nrhs);
+        if (below > 0) trsv_update(L, lda, k + nb, below, (int)k, nb, X, ldx, nrhs, st);
     }
     for (long long k = (n - 1) / kNB * kNB; k >= 0; k -= kNB) {
         const int nb = (int)std::min<long long>(kNB, n - k);
         hipLaunchKernelGGL(k_trsv_diag<true>, dim3(nrhs), dim3(256), 0, st, L, lda, (int)k, nb, X, ldx);
-        if (k > 0)
-            hipLaunchKernelGGL(k_trsv_update, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, st, L, lda, 0LL, k,
-                               (int)k, nb, X, ldx, nrhs);
+        if (k > 0) trsv_update(L, lda, 0, k, (int)k, nb, X, ldx, nrhs, st);
     }
     return hipGetLastError();
 }

@@ -125,10 +125,14 @@ def test_cholesky_panels_on_random_spd():
     assert back <= 1e-14 and fwd <= 1e-12
     upper = np.triu(np.ones((n, n), dtype=bool), 1)
     assert np.array_equal(L[upper], Lg.T[upper])
-    B = rng.standard_normal((5, n))
-    X = cholesky_solve(torch.from_numpy(L.T.copy()).to(DEV), torch.from_numpy(B).to(DEV)).cpu().numpy()
-    Xn = np.linalg.solve(Ko, B.T).T
-    assert np.linalg.norm(X - Xn) / np.linalg.norm(Xn) <= 1e-12
+    # 5 right-hand sides (one row per lane updates), 40 and 70 (matrix-core updates, ragged right-hand-side tiles)
+    for nrhs in (5, 40, 70):
+        B = rng.standard_normal((nrhs, n))
+        X = cholesky_solve(torch.from_numpy(L.T.copy()).to(DEV), torch.from_numpy(B).to(DEV)).cpu().numpy()
+        Xn = np.linalg.solve(Ko, B.T).T
+        err = np.linalg.norm(X - Xn) / np.linalg.norm(Xn)
+        note(f"[posterior] solve n={n} nrhs={nrhs}: {err:.2e}")
+        assert err <= 1e-12
 
 
 def test_cholesky_reports_non_positive_pivot():
