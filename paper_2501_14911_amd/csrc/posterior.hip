@@ -615,6 +615,78 @@ __global__ __launch_bounds__(256) void k_trsv_update_mfma(const double* __restri
             }
 }
 
+// Single-right-hand-side solves, one launch per 64-row block: kernel j
+// applies block j - 1's solved entries (forward; block j + 1's, backward) to
+// the rows of block j and solves block j (workgroup 0: one wavefront keeps
+// row i of the block in lane i, as in k_trsv_diag), while the other
+// workgroups apply the same entries to every row past block j (forward; above
+// it, backward), one row per lane.  Each row thus receives block m's entries
+// in the launch after block m was solved: from workgroup 0 if it belongs to
+// the next block, from the others otherwise.  The backward solve reads the
+// factor's transpose from the upper triangle, so every update reads
+// contiguous column runs.
+template <bool BWD>
+__global__ __launch_bounds__(256) void k_trsv_fused(const double* __restrict__ L, long long lda, int n, int j,
+                                                    double* __restrict__ X) {
+    const int nblk = (n + kNB - 1) / kNB;
+    const int k = j * kNB, nb = min(kNB, n - k);
+    const int src = BWD ? j + 1 : j - 1;               // block whose solved entries are applied
+    const bool apply = BWD ? src < nblk : src >= 0;
+    const int ks = src * kNB, nbs = apply ? min(kNB, n - ks) : 0;
+    __shared__ double xs[kNB];                         // the applied block's solved entries
+    __shared__ double l[kNB][kLP];                     // workgroup 0: l[col][row] = L_kk(row, col)
+    if (threadIdx.x < kNB) xs[threadIdx.x] = (int)threadIdx.x < nbs ? X[ks + threadIdx.x] : 0.0;
+    if (blockIdx.x > 0) {
+        // rows past block j (forward: [k + nb, n); backward: [0, k)); all 64 loads issued before the sum
+        const long long r = BWD ? (long long)(blockIdx.x - 1) * 256 + threadIdx.x
+                                : (long long)k + nb + (long long)(blockIdx.x - 1) * 256 + threadIdx.x;
+        const bool live = apply && (BWD ? r < k : r < n);
+        double a[kNB];
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) a[c] = live && c < nbs ? L[(long long)(ks + c) * lda + r] : 0.0;
+        __syncthreads();
+        if (!live) return;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) acc += a[c] * xs[c];
+        X[r] -= acc;
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < kNB * kNB / 256; ++u) {
+        const int e = threadIdx.x + 256 * u, c = e / kNB, r = e % kNB;
+        l[c][r] = (r < nb && c < nb && r >= c) ? L[(long long)(k + c) * lda + k + r] : (r == c ? 1.0 : 0.0);
+    }
+    const int i = threadIdx.x;
+    double xi = 0.0;
+    if (i < kNB) {
+        const bool live = apply && i < nb;
+        double a[kNB];
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) a[c] = live && c < nbs ? L[(long long)(ks + c) * lda + k + i] : 0.0;
+        xi = i < nb ? X[k + i] : 0.0;
+        __syncthreads();
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) acc += a[c] * xs[c];
+        xi -= acc;
+    } else {
+        __syncthreads();
+        return;
+    }
+    double row[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) row[c] = BWD ? (c > i ? l[i][c] : 0.0) : (c < i ? l[c][i] : 0.0);
+    const double inv = 1.0 / l[i][i];
+#pragma unroll
+    for (int s = 0; s < kNB; ++s) {
+        const int jj = BWD ? kNB - 1 - s : s;
+        if (i == jj) xi *= inv;
+        xi -= row[jj] * readlane_f64(xi, jj);
+    }
+    if (i < nb) X[k + i] = xi;
+}
+
 dim3 grid_for(long long n) { return dim3((unsigned)std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256))); }
 
 }  // namespace
@@ -775,6 +847,18 @@ static void trsv_update(const double* L, long long lda, long long row0, long lon
 
 hipError_t launch_cholesky_solve(const double* L, long long n, long long lda, double* X, int nrhs, long long ldx,
                                  hipStream_t st) {
+    if (nrhs == 1) {
+        const long long nblk = (n + kNB - 1) / kNB;
+        for (long long j = 0; j < nblk; ++j) {
+            const long long rest = n - std::min<long long>(n, (j + 1) * kNB);       // rows past block j
+            hipLaunchKernelGGL(k_trsv_fused<false>, dim3((unsigned)(1 + (rest + 255) / 256)), dim3(256), 0, st, L,
+                               lda, (int)n, (int)j, X);
+        }
+        for (long long j = nblk - 1; j >= 0; --j)
+            hipLaunchKernelGGL(k_trsv_fused<true>, dim3((unsigned)(1 + (j * kNB + 255) / 256)), dim3(256), 0, st, L,
+                               lda, (int)n, (int)j, X);
+        return hipGetLastError();
+    }
     for (long long k = 0; k < n; k += kNB) {
         const int nb = (int)std::min<long long>(kNB, n - k);
         hipLaunchKernelGGL(k_trsv_diag<false>, dim3(nrhs), dim3(256), 0, st, L, lda, (int)k, nb, X, ldx);

@@ -100,12 +100,13 @@ def test_cholesky_and_solve_on_oracle_K():
     upper = np.triu(np.ones((N, N), dtype=bool), 1)
     assert np.array_equal(L.cpu().numpy().T[upper], Lg.T[upper])
     rng = np.random.default_rng(2)
-    B = rng.standard_normal((3, N))
-    X = cholesky_solve(L, torch.from_numpy(B).to(DEV)).cpu().numpy()
-    Xo = OP.solve_with_factor(Lo, B.T).T
-    err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
-    note(f"[posterior] solve vs oracle {err:.2e}")
-    assert err <= 1e-11
+    for nrhs in (1, 3):
+        B = rng.standard_normal((nrhs, N))
+        X = cholesky_solve(L, torch.from_numpy(B).to(DEV)).cpu().numpy()
+        Xo = OP.solve_with_factor(Lo, B.T).T
+        err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+        note(f"[posterior] solve vs oracle ({nrhs} right-hand sides) {err:.2e}")
+        assert err <= 1e-11
 
 
 def test_cholesky_panels_on_random_spd():
@@ -125,8 +126,9 @@ def test_cholesky_panels_on_random_spd():
     assert back <= 1e-14 and fwd <= 1e-12
     upper = np.triu(np.ones((n, n), dtype=bool), 1)
     assert np.array_equal(L[upper], Lg.T[upper])
-    # 5 right-hand sides (one row per lane updates), 40 and 70 (matrix-core updates, ragged right-hand-side tiles)
-    for nrhs in (5, 40, 70):
+    # 1 right-hand side (one launch per block), 5 (one row per lane updates), 40 and 70 (matrix-core
+    # updates, ragged right-hand-side tiles)
+    for nrhs in (1, 5, 40, 70):
         B = rng.standard_normal((nrhs, n))
         X = cholesky_solve(torch.from_numpy(L.T.copy()).to(DEV), torch.from_numpy(B).to(DEV)).cpu().numpy()
         Xn = np.linalg.solve(Ko, B.T).T
@@ -169,6 +171,11 @@ def test_map_point_and_posterior_actions(precision, tol):
         e = oracle.rel_l2(m[b], mo)
         note(f"[posterior] MAP {precision} rhs {b}: {e:.2e}")
         assert e <= tol
+    # a single data vector takes the one-launch-per-block solves
+    m1 = op.map_point(torch.from_numpy(d[1]).to(DEV, op.dtype), L, torch.from_numpy(var).to(DEV), gam)
+    e1 = oracle.rel_l2(m1.double().cpu().numpy(), OP.map_point(F, d[1], var, gam, Lo))
+    note(f"[posterior] MAP {precision} single data vector: {e1:.2e}")
+    assert e1 <= tol
     v = synth.param_series(w, 2)
     g = op.posterior_cov_apply(torch.from_numpy(v).to(DEV, op.dtype), L, gam).double().cpu().numpy()
     for b in range(2):
