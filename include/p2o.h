@@ -325,8 +325,15 @@ typedef enum {
                                 built-in choice) */
     P2O_OPT_FFT_FIXED = 2    /* value: 1 (default) runs the time-axis FFTs (section 4's circulant
                                 embedding) with kernels compiled for the plan's transform length when
-                                the library has them (lengths L = 32, 256, 840), 0 always with the
+                                the library has them (lengths L = 32, 256, 840, 1000), 0 always with the
                                 runtime-length kernels; both compute the same transforms */,
+    P2O_OPT_FP16_OPERANDS = 4, /* value: 1 (default) lets p2o_apply_FFt and the calls built on it
+                                  (p2o_assemble_K, ...) keep the intermediate parameter-side spectra
+                                  of an FP16 plan as FP16 pairs with per-right-hand-side power-of-two
+                                  scales bounded a priori (half the bytes of complex FP32; the forward
+                                  products round their right-hand sides to FP16 either way), when the
+                                  plan has more than 128 sensors, calls use the matrix cores and a
+                                  compiled-length transform exists; 0 keeps them complex FP32 */
     P2O_OPT_OUTPUT_STRIDE = 3  /* value r >= 1 dividing Nt (default 1): the plan's data series are
                                   observed every r-th step, the multi-rate output of a p2q map whose
                                   QoIs have a coarser time grid than its parameters (section 2, remark

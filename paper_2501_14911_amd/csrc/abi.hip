@@ -94,6 +94,7 @@ struct p2o_plan {
     int batched_mode = P2O_BATCHED_AUTO;
     int gemm_tile = -1;                     // forced matrix-core tile variant, -1: tuned or built-in
     int qstride = 1;                        // data series observed every qstride-th step (multi-rate QoI maps)
+    int fp16_ops = 1;                       // FP16 intermediate operands of F F* calls where possible
     std::map<int64_t, int> tuned_fwd, tuned_adj;   // autotuned variant per right-hand-side count
     // bound memory
     char* fhat = nullptr;
@@ -206,7 +207,10 @@ void layout(p2o_plan* p) {
     if (p->prec == kFP16) {
         p->amax_slots = fft_amax_slots((int)std::max<int64_t>(p->pitch, gemm_data_pitch((int)p->Nd)));
         p->off_A = p->ws_total;
-        p->off_SX = align_up(p->off_A + R * (size_t)p->amax_slots * sizeof(float));
+        // A: the transforms' amax partials, or a data-space column call's
+        // FP16 operand scales (R) and row bounds (nfreq R)
+        const size_t alen = std::max<size_t>((size_t)p->amax_slots, nfreq + 1);
+        p->off_SX = align_up(p->off_A + R * alen * sizeof(float));
         p->off_SY = align_up(p->off_SX + R * sizeof(float));
         p->ws_total = align_up(p->off_SY + R * sizeof(float));
     }
@@ -423,8 +427,64 @@ p2o_status enqueue_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, c
     });
 }
 
+// The FP16-operand form of an F F* call is possible: FP16 spectrum on the
+// matrix cores, more than 128 sensors (the whole-line forward ring's 320-row
+// tiles), one adjoint partial and a compiled-length re-pad for the shape.
+bool fp16_operands_ok(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active) {
+    if (!p->fp16_ops || p->prec != kFP16 || p->Nd <= 128 || !mfma_on(p, nrhs) || adj_parts(p, nrhs) != 1) return false;
+    return launch_project_half(p->fft, io_param(p, nrhs, nt_active, 1), nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr);
+}
+
+// F F* with FP16 intermediate operands: the data-side r2c and the operand
+// scales (bounded from the data spectra and the spectrum's block
+// multipliers), adjoint products written as scaled FP16 pairs into X, the
+// re-pad in place on them, forward products reading them, data-side c2r.
+// sx lives in the wavefront-maximum region (free once the data-side scales
+// are taken), sy in the parameter-side scales read by the forward products.
+p2o_status enqueue_FFt_half(p2o_plan* p, const void* e, void* h, int64_t nrhs, const int32_t* nt_active) {
+    void* X = p->ws + p->off_X;
+    void* Y = p->ws + p->off_Y;
+    float* sx = reinterpret_cast<float*>(p->ws + p->off_A);
+    float* sy = scale_X(p);
+    const int ld = gemm_data_pitch((int)p->Nd);
+    p2o_status s = staged(p, P2O_STAGE_R2C, "r2c (data) and FP16 operand scales", [&] {
+        hipError_t err = launch_r2c(false, false, p->fft, io_data_rhs(p, nrhs, nt_active), e, Y, tw_of(p), p->stream);
+        if (err != hipSuccess) return err;
+        return launch_fp16_operand_scales(Y, ld, (int)nrhs, (int)p->nfreq, (int)p->Nd, scales_of(p), (int)p->nblk,
+                                          (int)p->Nt, sx + p->max_rhs, sx, sy, p->stream);
+    });
+    if (s) return s;
+    s = staged(p, P2O_STAGE_GEMM_ADJ, "adjoint per-frequency products (matrix cores, FP16 out)", [&] {
+        GemmArgs ga = gemm_args(p, nrhs);
+        ga.rhs_scale = scale_Y(p);
+        ga.out_scale = sx;
+        return launch_gemm_adj(ga, gemm_tile_for(p, p->tuned_adj, nrhs), p->fhat, scales_of(p), Y, X, p->stream);
+    });
+    if (s) return s;
+    s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad (FP16 operands)", [&] {
+        hipError_t err = hipErrorInvalidValue;
+        if (!launch_project_half(p->fft, io_param(p, nrhs, nt_active, 1), X, tw_of(p), sx, sy, p->stream, &err))
+            return hipErrorInvalidValue;
+        return err;
+    });
+    if (s) return s;
+    s = staged(p, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores, FP16 operands)", [&] {
+        GemmArgs ga = gemm_args(p, nrhs);
+        ga.rhs_scale = sy;
+        ga.b_f16 = 1;
+        return launch_gemm_fwd(ga, 13, p->fhat, scales_of(p), X, Y, p->stream);
+    });
+    if (s) return s;
+    return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
+        return launch_c2r(false, p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), Y, h, tw_of(p), nullptr,
+                          nullptr, 0, nullptr, p->stream);
+    });
+}
+
 p2o_status enqueue_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, const int32_t* nt_active) {
     p->cur_nrhs = nrhs;
+    if (fp16_operands_ok(p, nrhs, nt_active)) return enqueue_FFt_half(p, e, h, nrhs, nt_active);
     p2o_status s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
     if (s) return s;
     s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
@@ -663,6 +723,11 @@ p2o_status p2o_set_option(p2o_plan* p, int32_t option, int64_t value) {
     if (option == P2O_OPT_FFT_FIXED) {
         if (value != 0 && value != 1) return fail(P2O_ERR_ARG, "fixed-length FFT switch %lld is not 0 or 1", (long long)value);
         p->fft.fixed = (int)value;
+        return P2O_OK;
+    }
+    if (option == P2O_OPT_FP16_OPERANDS) {
+        if (value != 0 && value != 1) return fail(P2O_ERR_ARG, "FP16 operand switch %lld is not 0 or 1", (long long)value);
+        p->fp16_ops = (int)value;
         return P2O_OK;
     }
     if (option == P2O_OPT_OUTPUT_STRIDE) {

@@ -674,6 +674,13 @@ static hipError_t project_transform(bool f64, const FftPlan& pl, const SeriesIO&
     return hipGetLastError();
 }
 
+bool launch_project_half(const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, const float* sx,
+                         const float* sy, hipStream_t st, hipError_t* err) {
+    const int wsh = wide_shift(false, pl, io.S_pad);
+    if (wsh >= 0 && launch_fixed_project_h(pl, io, in_out, tw, wsh, sx, sy, st, err)) return true;
+    return launch_fixed_project_h(pl, io, in_out, tw, fft_tile_shift(pl.M, false), sx, sy, st, err);
+}
+
 hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw,
                           hipStream_t st) {
     int sh = 0;

@@ -648,6 +648,150 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>*
     }
 }
 
+// ---------------------------------------------------------------- FP16 operands of data-space columns
+// Truncate-and-repad on FP16 (re, im) pairs, in place: the adjoint products
+// arrive multiplied by sx[outer] and leave, re-padded, multiplied by
+// sy[outer] (the forward products' FP16 right-hand sides).  One partial sum;
+// the same transform as k_project_fx in FP32 between the conversions.
+__device__ __forceinline__ float2 f16pair(uint32_t w, float s) { return make_float2(f16lo(w) * s, f16hi(w) * s); }
+__device__ __forceinline__ uint32_t pair_f16(float re, float im, float s) {
+    return f32_to_f16_rne(re * s) | (f32_to_f16_rne(im * s) << 16);
+}
+
+template <int M, int SH>
+__device__ __forceinline__ void load_pre_h(float2* buf, const float2* twq, const uint32_t* __restrict__ src,
+                                           const SeriesIO& io, bool ok, int s, int j0, float inv) {
+    using Z = float2;
+    using G = Geo<M, SH>;
+    constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
+    static_assert(M - (JS - 1) - (NU - 1) * JS >= 0, "partner rows start inside the spectrum");
+    const uint32_t fs = (uint32_t)io.f_stride * 4u, so = (uint32_t)s * 4u;
+    uint32_t a0 = (uint32_t)j0 * fs + so, b0 = (uint32_t)(JS - 1 - j0) * fs + so;
+    asm volatile("" : "+v"(a0), "+v"(b0));
+    Z xa[NU], xb[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        if (u < NU - 1 || j0 + u * JS < G::NPAIR) {
+            if (ok) {
+                xa[u] = f16pair(ld(src + (long long)(u * JS) * io.f_stride, a0), inv);
+                xb[u] = f16pair(ld(src + (long long)(M - (JS - 1) - u * JS) * io.f_stride, b0), inv);
+            } else {
+                xa[u] = xb[u] = cmk<float>(0.f, 0.f);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int k = j0 + u * JS;
+        if (u < NU - 1 || k < G::NPAIR) {
+            Z a = xa[u], b = xb[u];
+            if (u == 0 && k == 0) { a.y = 0.f; b.y = 0.f; }
+            const Z w = twq[k];
+            buf[k * RS + s] = pre_one<float>(a, b, w);
+            if ((u > 0 || k > 0) && 2 * k != M) buf[(M - k) * RS + s] = pre_one<float>(b, a, cmk<float>(-w.x, w.y));
+        }
+    }
+    __syncthreads();
+}
+
+template <int M, int SH>
+__device__ __forceinline__ void post_store_h(float2* buf, const float2* twq, const SeriesIO& io, uint32_t* row, int s0,
+                                             int s, int j0, float sc) {
+    using Z = float2;
+    using G = Geo<M, SH>;
+    constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
+    static_assert(M - (JS - 1) - (NU - 1) * JS >= 0, "partner rows start inside the spectrum");
+    const bool ok = s0 + s < io.S_pad;
+    uint32_t* const rb = row + s0;
+    const uint32_t fs = (uint32_t)io.f_stride * 4u, lo_ = (uint32_t)s * 4u;
+    uint32_t oa = (uint32_t)j0 * fs + lo_, ob = (uint32_t)(JS - 1 - j0) * fs + lo_;
+    asm volatile("" : "+v"(oa), "+v"(ob));
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int k = j0 + u * JS;
+        if (u < NU - 1 || k < G::NPAIR) {
+            const int km = (u == 0 && k == 0) ? 0 : M - k;
+            const Z a = buf[k * RS + s], b = buf[km * RS + s];
+            const Z w = twq[k];
+            const Z xk = post_one<float>(a, b, w);
+            const Z xm = post_one<float>(b, a, cmk<float>(-w.x, w.y));
+            if (ok) {
+                st(rb + (long long)(u * JS) * io.f_stride, oa, pair_f16(xk.x, xk.y, sc));
+                if (2 * k != M) st(rb + (long long)(M - (JS - 1) - u * JS) * io.f_stride, ob, pair_f16(xm.x, xm.y, sc));
+            }
+        }
+    }
+}
+
+template <int M, int SH>
+__global__ __launch_bounds__(kFxThreads) void k_project_fx_h(SeriesIO io, uint32_t* in_out,
+                                                             const float2* __restrict__ twg, const float* __restrict__ sx,
+                                                             const float* __restrict__ sy, ItemMap im) {
+    using T = float;
+    using Z = float2;
+    using G = Geo<M, SH>;
+    using Pl = Pass<M, SH, true, G::NP - 1>;
+    using Pf = Pass<M, SH, false, 0>;
+    static_assert(Pl::R == Pf::R && Pl::NS == Pf::MR, "reversed order ends with the forward order's first radix");
+    constexpr int R = Pl::R, MR = Pl::MR, NU = Pl::NU, RS = G::RS, JS = G::JS;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Z* buf = reinterpret_cast<Z*>(smem_raw);
+    Z* twq = buf + G::TILE;
+    Z* twf = twq + G::NPAIR;
+    Z* twr = twf + (M - 1);
+    stage_pair_tw<T, M, SH>(twq, twg);
+    stage_pass_tw<T, M, SH, false>(twf, twg);
+    stage_pass_tw<T, M, SH, true>(twr, twg);
+    __syncthreads();
+    const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
+    const T inv = T(1) / T(M);
+    const int xq = (int)(blockIdx.x & 7) * im.Q, nper = (int)(gridDim.x >> 3);
+    for (int i = (int)(blockIdx.x >> 3); i < im.Q && xq + i < im.items; i += nper) {
+        const int outer = (xq + i) / im.ntiles, tile = xq + i - outer * im.ntiles;
+        int s = s_, j0 = j0_;
+        asm volatile("" : "+v"(s), "+v"(j0));
+        const int s0 = tile << SH;
+        const int nt_raw = active_raw(io, outer);
+        uint32_t* base = in_out + (long long)outer * io.f_outer;
+        load_pre_h<M, SH>(buf, twq, base + s0, io, s0 + s < io.S, s, j0, 1.f / sx[outer]);
+        const int nt = active_clamp(io, nt_raw);
+        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
+        Z v[NU][R];
+        const Z* rbp = buf + j0 * RS + s;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int j = j0 + u * JS;
+            if (Pl::live(u, j)) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) v[u][q] = rbp[(u * JS + q * MR) * RS];
+                apply_tw<T, R, true>(v[u], twr + Pl::TOFF + j * (R - 1));
+                dft_small<T, R, true>(v[u]);
+#pragma unroll
+                for (int p = 0; p < R; ++p) {
+                    const int n = j + p * MR;
+                    v[u][p].x = (2 * n < nt) ? v[u][p].x * inv : T(0);
+                    v[u][p].y = (2 * n + 1 < nt) ? v[u][p].y * inv : T(0);
+                }
+                dft_small<T, R, false>(v[u]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int j = j0 + u * JS;
+            if (Pl::live(u, j)) {
+                Z* wb = buf + j * R * RS + s;
+#pragma unroll
+                for (int p = 0; p < R; ++p) wb[p * RS] = v[u][p];
+            }
+        }
+        __syncthreads();
+        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
+        post_store_h<M, SH>(buf, twq, io, base, s0, s, j0, sy[outer]);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- host side
 template <int M, int SH>
 constexpr size_t fx_lds(size_t zbytes, int ntables) {
@@ -728,6 +872,18 @@ hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStrea
     return hipGetLastError();
 }
 
+template <int M, int SH>
+hipError_t fx_project_h(const SeriesIO& io, void* in_out, const void* tw, const float* sx, const float* sy,
+                        hipStream_t st) {
+    const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
+    if (im.items == 0) return hipSuccess;
+    const size_t lds = fx_lds<M, SH>(sizeof(float2), 2);
+    constexpr auto k = k_project_fx_h<M, SH>;
+    hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (uint32_t*)in_out, (const float2*)tw, sx, sy,
+                       im);
+    return hipGetLastError();
+}
+
 // Compiled (M, tile shift) pairs: the transform lengths of the common
 // workloads (Nt = 16, 128, 420, and 500 of section 5's problem), with the
 // tile widths fft_tile_shift picks, plus 16-series tiles for wide FP32
@@ -754,6 +910,21 @@ bool fits32(long long rows, long long stride, size_t esz) {
 }
 
 }  // namespace
+
+// FP16 operands of data-space columns: the FP32 lengths with compiled
+// kernels (the plan's tile shift for S_pad series); false if there is none.
+bool launch_fixed_project_h(const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,
+                            const float* sx, const float* sy, hipStream_t st, hipError_t* err) {
+    if (!pl.fixed || io.nparts != 1 || io.quad || !fits32(kFxThreads >> sh, io.f_stride, 4)) return false;
+#define X(T, M_, SH_)                                                                  \
+    if (sizeof(T) == 4 && pl.M == M_ && sh == SH_) {                                   \
+        if (err) *err = fx_project_h<M_, SH_>(io, in_out, tw, sx, sy, st);             \
+        return true;                                                                   \
+    }
+    P2O_FX_CASES(X)
+#undef X
+    return false;
+}
 
 int fixed_wide_shift(bool f64, const FftPlan& pl) { return !f64 && pl.fixed && pl.M == 500 ? 4 : -1; }
 

@@ -89,6 +89,10 @@ __device__ __forceinline__ uint32_t w_f16(uint32_t re, uint32_t im, float s) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{__uint_as_float(re) * s,
                                                                         __uint_as_float(im) * s}, f16x2));
 }
+// (re, im) FP32 times s as one word of two FP16 (nearest even).
+__device__ __forceinline__ uint32_t pack_f16(float re, float im, float s) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{re * s, im * s}, f16x2));
+}
 // Four consecutive complex FP32 values (two 16-byte parts) as an FP16 fragment.
 __device__ __forceinline__ uint4 f_rhs_f16(uint4 p0, uint4 p1, float s) {
     return make_uint4(w_f16(p0.x, p0.y, s), w_f16(p0.z, p0.w, s), w_f16(p1.x, p1.y, s), w_f16(p1.z, p1.w, s));
@@ -571,7 +575,7 @@ void k_gemm_fwd_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
 //      4 right-hand sides.  B of step st + 1 is issued before A of step
 //      st + 2, so waiting for all but the last step's A loads covers both
 //      operands of the next step.
-template <int RG, int MB, int NH, bool F16>
+template <int RG, int MB, int NH, bool F16, bool BH>
 __global__ __launch_bounds__(64 * RG * NH) __attribute__((amdgpu_waves_per_eu(1)))
 void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, const uint8_t* Bq,
                       float2* __restrict__ out_base, GemmArgs ga) {
@@ -579,9 +583,13 @@ void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, con
     constexpr int MROWS = RG * 32 * MB, RHS = 32 * NH, NW = RG * NH;
     constexpr int AI = MROWS / 8 / NW;                    // A loads (8 rows each) per wavefront per step
     static_assert(AI >= 1 && AI * 8 * NW == MROWS, "A rows per wavefront");
-    constexpr int BI = RHS / 4 / NW;                      // B loads (4 right-hand sides each) per wavefront per step
-    static_assert(BI >= 1 && 4 * BI * NW == RHS, "B loads per wavefront");
-    constexpr int A_STEP = MROWS * 128, B_STEP = RHS * 256;
+    // B bytes per right-hand side and step: 32 complex FP32 (or, BH, FP16 pairs)
+    constexpr int BRB = BH ? 128 : 256;
+    constexpr int BPI = 1024 / BRB;                       // right-hand sides per B load instruction
+    constexpr int BI = RHS / BPI / NW;                    // B loads per wavefront per step
+    static_assert(BI >= 1 && BPI * BI * NW == RHS, "B loads per wavefront");
+    static_assert(!BH || F16, "FP16 right-hand sides meet an FP16 spectrum");
+    constexpr int A_STEP = MROWS * 128, B_STEP = RHS * BRB;
     __shared__ __align__(16) uint8_t ring_a[3][A_STEP];
     __shared__ __align__(16) uint8_t ring_b[2][B_STEP];
 
@@ -617,14 +625,17 @@ void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, con
         aoff[i] = ((uint32_t)sr * (uint32_t)ga.pitch) * 4u + 16u * (uint32_t)c;
     }
     // B instruction i: right-hand sides 4 (BI wave + i) .. + 3; lane L moves
-    // part (L % 16) ^ (b mod 16) of b = 4 (BI wave + i) + L / 16 into slot L % 16
-    const uint8_t* const bbase = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * 8 + (long long)kbeg * 8;
+    // part (L % 16) ^ (b mod 16) of b = 4 (BI wave + i) + L / 16 into slot L % 16.
+    // BH: right-hand sides 8 (BI wave + i) .. + 7, part (L % 8) ^ ((b / 2) mod 8)
+    // of b = 8 (BI wave + i) + L / 8 into slot L % 8.
+    constexpr uint32_t EB = BH ? 4u : 8u;                 // bytes per complex right-hand-side value
+    const uint8_t* const bbase = Bq + ((long long)w * ga.nrhs + b0) * ga.ldb * EB + (long long)kbeg * EB;
     uint32_t boff[BI];
 #pragma unroll
     for (int i = 0; i < BI; ++i) {
-        const int b = 4 * (BI * wave + i) + (lane >> 4);
-        const int part = (lane & 15) ^ (b & 15);
-        boff[i] = (uint32_t)min(b, nb_valid - 1) * (uint32_t)ga.ldb * 8u + (uint32_t)part * 16u;
+        const int b = BH ? 8 * (BI * wave + i) + (lane >> 3) : 4 * (BI * wave + i) + (lane >> 4);
+        const int part = BH ? (lane & 7) ^ ((b >> 1) & 7) : (lane & 15) ^ (b & 15);
+        boff[i] = (uint32_t)min(b, nb_valid - 1) * (uint32_t)ga.ldb * EB + (uint32_t)part * 16u;
     }
     const uint32_t la = lds_addr(&ring_a[0][0]) + AI * wave * 1024, lb = lds_addr(&ring_b[0][0]) + BI * wave * 1024;
     auto issue_a = [&](int st, int slot) {
@@ -635,7 +646,7 @@ void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, con
     auto issue_b = [&](int st, int slot) {
         const long long sb = st < nst ? st : nst - 1;
 #pragma unroll
-        for (int i = 0; i < BI; ++i) dma16(bbase + sb * 256, boff[i], lb + slot * B_STEP + i * 1024);
+        for (int i = 0; i < BI; ++i) dma16(bbase + sb * BRB, boff[i], lb + slot * B_STEP + i * 1024);
     };
 
     f32x16 accr[MB], acci[MB];
@@ -648,8 +659,12 @@ void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, con
     const int rb = 32 * nh + r;
     auto read = [&](Frags& f, int as, int bs, int u) {
         const int g = 2 * u + kg;                         // this lane's group of 4 entries in the step
-        f.bh = *reinterpret_cast<const uint4*>(&ring_b[bs][rb * 256 + (((2 * g) ^ (rb & 15)) * 16)]);
-        f.bl = *reinterpret_cast<const uint4*>(&ring_b[bs][rb * 256 + (((2 * g + 1) ^ (rb & 15)) * 16)]);
+        if constexpr (BH) {
+            f.bh = *reinterpret_cast<const uint4*>(&ring_b[bs][rb * 128 + ((g ^ ((rb >> 1) & 7)) * 16)]);
+        } else {
+            f.bh = *reinterpret_cast<const uint4*>(&ring_b[bs][rb * 256 + (((2 * g) ^ (rb & 15)) * 16)]);
+            f.bl = *reinterpret_cast<const uint4*>(&ring_b[bs][rb * 256 + (((2 * g + 1) ^ (rb & 15)) * 16)]);
+        }
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const int row = (rg * MB + mb) * 32 + r;
@@ -660,7 +675,7 @@ void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, con
     if constexpr (F16) rs = ga.rhs_scale[min(b0 + rb, ga.nrhs - 1)];
     auto mfmas = [&](const Frags& f) {
         if constexpr (F16) {
-            const uint4 bx = f_rhs_f16(f.bh, f.bl, rs);
+            const uint4 bx = BH ? f.bh : f_rhs_f16(f.bh, f.bl, rs);
             const uint4 b_r = f_conj(bx), b_i = f_swap(bx);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
@@ -884,10 +899,14 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
             const int h = ch / (MROWS / CW), c0 = (ch % (MROWS / CW)) * CW;
             bare_barrier();                               // ring (or previous part) reads done
             if (nh == h && rg * MB * 32 / CW == c0 / CW) {
+                // FP16 output: this lane's right-hand side's scale folded in here
+                const int bo = b0 + 32 * nh + r;
+                const float os = F16 && ga.out_scale && bo < ga.nrhs ? ga.out_scale[bo] : 1.f;
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
                     const int cb = (rg * MB + mb) * 32;   // an m block lies in one 4096-column scale block
-                    const float sc = scales[(long long)w * ga.nblk + min(m0 + cb, ga.ncols - 1) / kScaleBlock] * irs;
+                    const float sc =
+                        scales[(long long)w * ga.nblk + min(m0 + cb, ga.ncols - 1) / kScaleBlock] * irs * os;
 #pragma unroll
                     for (int v = 0; v < 16; ++v) {
                         const int c = cb - c0 + 8 * (v >> 2) + 4 * kg + (v & 3);
@@ -904,11 +923,21 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
                 const int b = b0 + 32 * h + row, j = m0 + c0 + c;
                 const float4 v = *reinterpret_cast<const float4*>(&lds[row * OS_RS + c * 8]);
                 if (b < ga.nrhs && j < ga.ncols) {
-                    float2* o = out_base + ((long long)w * ga.nrhs + b) * ga.pitch + j;
-                    if (j + 1 < ga.ncols)
-                        *reinterpret_cast<float4*>(o) = v;
-                    else
-                        *o = make_float2(v.x, v.y);
+                    const long long at = ((long long)w * ga.nrhs + b) * ga.pitch + j;
+                    if (F16 && ga.out_scale) {
+                        // FP16 pairs (already scaled): the same index in a 4-byte array
+                        uint32_t* o = reinterpret_cast<uint32_t*>(out_base) + at;
+                        if (j + 1 < ga.ncols)
+                            *reinterpret_cast<uint2*>(o) = make_uint2(pack_f16(v.x, v.y, 1.f), pack_f16(v.z, v.w, 1.f));
+                        else
+                            *o = pack_f16(v.x, v.y, 1.f);
+                    } else {
+                        float2* o = out_base + at;
+                        if (j + 1 < ga.ncols)
+                            *reinterpret_cast<float4*>(o) = v;
+                        else
+                            *o = make_float2(v.x, v.y);
+                    }
                 }
             }
         }
@@ -916,6 +945,8 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
         const int b = b0 + 32 * nh + r;
         if (b >= ga.nrhs) return;
         float2* out = out_base + ((long long)w * ga.nrhs + b) * ga.pitch;
+        uint32_t* outh = reinterpret_cast<uint32_t*>(out_base) + ((long long)w * ga.nrhs + b) * ga.pitch;
+        const float os = F16 && ga.out_scale ? ga.out_scale[b] : 0.f;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const int jb = m0 + (rg * MB + mb) * 32;        // an m block lies in one 4096-column scale block
@@ -924,10 +955,81 @@ void k_gemm_adj_ring(const uint8_t* fhat, const float* __restrict__ scales, cons
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int j = jb + 8 * (v >> 2) + 4 * kg + (v & 3);
-                if (j < ga.ncols) out[j] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+                if (j < ga.ncols) {
+                    if (F16 && ga.out_scale)
+                        outh[j] = pack_f16(accr[mb][v] * sc, acci[mb][v] * sc, os);
+                    else
+                        out[j] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+                }
             }
         }
     }
+}
+
+// Scales of the FP16 operands of a data-space column call, per right-hand
+// side b, from the adjoint's input: every adjoint product of b satisfies
+// |sum_s conj(F_w[s, j]) y_w[s]| <= B = max_w (2^15 m_w sum_s (|re y| + |im y|)),
+// m_w the largest multiplier of frequency w's stored spectrum (stored values
+// are at most 2^15 in magnitude), and the truncate-and-repad maps a spectrum
+// bounded by B to one bounded by Nt B (each time value is at most B, each
+// output bin a sum of Nt of them).  sx[b] = the largest power of two with
+// B sx <= 2^14 (the adjoint's FP16 outputs), sy[b] the same for Nt B (the
+// re-padded FP16 right-hand sides of the forward products); 1 when B = 0.
+// First pass: a wavefront per (frequency, right-hand side) row writes
+// m_w sum_s (|re y| + |im y|) to part; second pass: the maximum over the
+// frequencies, one wavefront per right-hand side.
+__device__ __forceinline__ float pow2_at_most(float x) {
+    if (!(x > 0.f) || !(x < 3.0e38f)) return 1.f;
+    int e;
+    frexpf(x, &e);                                       // x = f 2^e, f in [1/2, 1)
+    return ldexpf(1.f, max(-126, min(126, e - 1)));
+}
+
+__global__ __launch_bounds__(1024) void k_fp16_operand_rows(const float2* __restrict__ Y, int ld, int nrhs, int nfreq,
+                                                            int Nd, const float* __restrict__ scales, int nblk,
+                                                            float* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 6);          // w nrhs + b
+    if (row >= nfreq * nrhs) return;
+    const int w = row / nrhs;
+    const float2* y = Y + (long long)row * ld;
+    float t = 0.f;
+    for (int s = lane; s < Nd; s += 64) {
+        const float2 v = y[s];
+        t += fabsf(v.x) + fabsf(v.y);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) {
+        float m = 0.f;
+        for (int k = 0; k < nblk; ++k) m = fmaxf(m, scales[(long long)w * nblk + k]);
+        part[row] = t * m;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_fp16_operand_scales(const float* __restrict__ part, int nrhs, int nfreq, int Nt,
+                                                            float* __restrict__ sx, float* __restrict__ sy) {
+    const int b = blockIdx.x;
+    float v = 0.f;
+    for (int w = threadIdx.x; w < nfreq; w += 64) v = fmaxf(v, part[(long long)w * nrhs + b]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if (threadIdx.x == 0) {
+        const float bound = v * 32768.f;
+        sx[b] = bound > 0.f ? pow2_at_most(16384.f / bound) : 1.f;
+        sy[b] = bound > 0.f ? pow2_at_most(16384.f / (bound * (float)Nt)) : 1.f;
+    }
+}
+
+hipError_t launch_fp16_operand_scales(const void* Y, int ld, int nrhs, int nfreq, int Nd, const float* scales, int nblk,
+                                      int Nt, float* part, float* sx, float* sy, hipStream_t st) {
+    const int rows = nfreq * nrhs;
+    hipLaunchKernelGGL(k_fp16_operand_rows, dim3((rows + 15) / 16), dim3(1024), 0, st, (const float2*)Y, ld, nrhs, nfreq,
+                       Nd, scales, nblk, part);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_fp16_operand_scales, dim3(nrhs), dim3(64), 0, st, (const float*)part, nrhs, nfreq, Nt, sx, sy);
+    return hipGetLastError();
 }
 
 // Operand filler for timing runs: words of two BF16 values with magnitudes in
@@ -1053,11 +1155,14 @@ static hipError_t launch_ring2(GemmArgs ga, const void* fhat, const float* scale
     ga.n_bg = (ga.nrhs + 32 * NH - 1) / (32 * NH);
     ga.items = ga.nfreq * ga.n_kc * ga.n_bg * ga.n_mt;
     ga.Q = (ga.items + 7) / 8;
-    if (ga.a_f16)
-        hipLaunchKernelGGL((k_gemm_fwd_ring2<RG, MB, NH, true>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+    if (ga.a_f16 && ga.b_f16)
+        hipLaunchKernelGGL((k_gemm_fwd_ring2<RG, MB, NH, true, true>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+                           (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
+    else if (ga.a_f16)
+        hipLaunchKernelGGL((k_gemm_fwd_ring2<RG, MB, NH, true, false>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
                            (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     else
-        hipLaunchKernelGGL((k_gemm_fwd_ring2<RG, MB, NH, false>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
+        hipLaunchKernelGGL((k_gemm_fwd_ring2<RG, MB, NH, false, false>), dim3(8 * ga.Q), dim3(64 * RG * NH), 0, st,
                            (const uint8_t*)fhat, scales, (const uint8_t*)Bq, (float2*)out, ga);
     return hipGetLastError();
 }
@@ -1121,6 +1226,10 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     ga.kchunk = kScaleBlock;
     ga.n_kc = gemm_fwd_kchunks(ga.ncols);
     if (!gemm_tile_has(tile, true) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, true, ga.Nd);
+    if (ga.b_f16) {                                    // FP16 right-hand sides: the whole-line ring only
+        if (!ga.a_f16) return hipErrorInvalidValue;
+        tile = ga.nrhs > 32 ? 13 : 14;
+    }
     switch (tile) {
         case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 1: return launch_tile<true, 2, 2, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);

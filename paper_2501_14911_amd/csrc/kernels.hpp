@@ -28,6 +28,12 @@ struct GemmArgs {
     long long part_stride;  // complex elements between forward partial outputs
     int a_f16;              // spectrum words are FP16 (re, im) pairs (BF16 otherwise); LDS-ring tiles only
     const float* rhs_scale; // FP16 spectra: per-right-hand-side power-of-two scales of the complex FP32 operand
+    // FP16 operands of the data-space columns (FP16 spectra, LDS-ring tiles):
+    // the adjoint writes its products as FP16 (re, im) pairs multiplied by
+    // out_scale[b] (when non-null); the forward reads such pairs as its
+    // right-hand sides (b_f16, already scaled by rhs_scale[b]; tiles 13, 14)
+    const float* out_scale;
+    int b_f16;
     // filled in by the launcher
     int ldb;                // complex values per right-hand-side row of the quad B operand
     int kchunk;             // complex columns per forward K chunk
@@ -54,6 +60,15 @@ int fft_tile_shift(int M, bool f64);
 // Tile shift of the compiled-length kernels' wide tiles for this plan and
 // precision (used for transforms of at least kWideSeries series), or -1.
 int fixed_wide_shift(bool f64, const FftPlan& pl);
+// Truncate-and-repad of FP16 operands (see launch_project_half), or false;
+// err == nullptr only reports whether a kernel exists.
+bool launch_fixed_project_h(const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,
+                            const float* sx, const float* sy, hipStream_t st, hipError_t* err);
+// In-place truncate-and-repad of FP16 (re, im) pairs: input multiplied by
+// sx[outer], output by sy[outer]; the compiled-length kernels only (false,
+// and nothing launched, without one; err == nullptr: availability only).
+bool launch_project_half(const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, const float* sx,
+                         const float* sy, hipStream_t st, hipError_t* err);
 constexpr int kWideSeries = 2048;
 int c2r_grid_x(const FftPlan& pl, bool f64, int S);
 hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st);
@@ -128,6 +143,12 @@ hipError_t launch_d2q_rows(bool f64, const void* y, const void* h, long long N, 
                            long long r0, const double* var, int var_mode, int Nd, double gamma, hipStream_t st);
 hipError_t launch_d2q_apply(const double* Q, long long nq, long long N, long long ldq, const double* d, double* q,
                             int nrhs, hipStream_t st);
+// Power-of-two scales of the FP16 operands of a data-space column call, from
+// its data-side spectra Y ([nfreq][nrhs][ld] complex FP32) and the spectrum's
+// block multipliers: sx[b] for the adjoint's outputs, sy[b] for the
+// re-padded right-hand sides; part holds nfreq nrhs floats of row bounds.
+hipError_t launch_fp16_operand_scales(const void* Y, int ld, int nrhs, int nfreq, int Nd, const float* scales, int nblk,
+                                      int Nt, float* part, float* sx, float* sy, hipStream_t st);
 // G += B B^T (lower triangle; B: N rows of kc columns, row stride ldb), and
 // K = prior_var (block-diagonal prefix sums of G) + Gamma_noise, mirrored.
 hipError_t launch_gram_update(const double* B, long long ldb, long long N, int kc, double* G, long long ldg,

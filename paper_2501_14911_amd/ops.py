@@ -117,6 +117,12 @@ class P2OOperator:
         the library has them (default), or always the runtime-length ones."""
         check(lib.p2o_set_option(self._plan, 2, 1 if on else 0))
 
+    def set_fp16_operands(self, on: bool = True):
+        """Let F F^* calls of an FP16 plan keep their intermediate
+        parameter-side spectra as scaled FP16 pairs where possible (default),
+        or always as complex FP32."""
+        check(lib.p2o_set_option(self._plan, 4, 1 if on else 0))
+
     def autotune(self, nrhs: int, reps: int = 3) -> dict:
         """Time every matrix-core tile variant for calls with ``nrhs``
         right-hand sides and keep the fastest (per direction) for later calls

@@ -254,3 +254,38 @@ def test_mfma_option_needs_a_16_bit_spectrum():
     from paper_2501_14911_amd import P2OError
     with pytest.raises(P2OError):
         op.set_batched("mfma")
+
+
+@pytest.mark.parametrize("w", [synth.Workload("tall16", Nd=330, Nm=1003, Nt=16, tau=4.0),
+                               synth.Workload("tall128", Nd=300, Nm=1003, Nt=128, tau=32.0)],
+                         ids=lambda w: w.name)
+def test_fp16_operand_data_space_columns(w):
+    """F F* e_j on an FP16 spectrum with FP16 intermediate operands (more than
+    128 sensors, compiled transform lengths L = 32 and 256; 64 columns, full and
+    ragged): every column against the oracle at 2e-3, and against the same
+    plan with complex FP32 intermediates, which differ only by the FP16
+    rounding of the adjoint products (2^-12 per value) and the scale of the
+    right-hand sides' rounding."""
+    F = synth.operator_blocks(w)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp16", max_rhs=64, device=DEV)
+    Ft = torch.from_numpy(F).to(DEV)
+    op.load(lambda c0, n: Ft[:, :, c0:c0 + n])
+    e = synth.unit_data_vectors(w, synth.hessian_column_indices(w, 64))
+    nt = synth.ragged_lengths(w, 64, lo=w.Nt // 4)
+    ref = oracle.data_space_hessian(F, e)
+    ref_r = oracle.data_space_hessian(F, e, nt)
+    got, got_r = {}, {}
+    for on in (True, False):
+        op.set_fp16_operands(on)
+        got[on] = host(op.apply_FFt(dev(e)))
+        got_r[on] = host(op.apply_FFt(dev(e), nt_active=nt))
+    for on in (True, False):
+        errs = [oracle.rel_l2(got[on][b], ref[b]) for b in range(64)]
+        errs_r = [oracle.rel_l2(got_r[on][b], ref_r[b]) for b in range(64) if np.any(ref_r[b])]
+        note(f"[batched] {w.name} FFt fp16 operands={on}: worst column {max(errs):.3e}, ragged {max(errs_r):.3e}")
+        assert max(errs) <= TOL_BF16 and max(errs_r) <= TOL_BF16
+        for b in range(64):
+            assert np.all(got_r[on][b, nt[b]:] == 0.0)
+    agree = oracle.rel_l2(got[True], got[False])
+    note(f"[batched] {w.name} FP16 vs FP32 intermediates: {agree:.3e}")
+    assert agree <= 2.0 ** -10
