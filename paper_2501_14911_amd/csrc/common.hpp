@@ -90,6 +90,21 @@ __device__ __forceinline__ Raw32 load32_split(const void* p, bool l0, bool l1) {
     return r;
 }
 
+// Streaming stores (non-temporal: written through without keeping the
+// lines), for outputs far larger than the caches.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4_nt __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_nt(float2* p, float2 v) {
+    __builtin_nontemporal_store((u32x2){__float_as_uint(v.x), __float_as_uint(v.y)}, reinterpret_cast<u32x2*>(p));
+}
+__device__ __forceinline__ void store_nt(float4* p, float4 v) {
+    __builtin_nontemporal_store((f32x4_nt){v.x, v.y, v.z, v.w}, reinterpret_cast<f32x4_nt*>(p));
+}
+__device__ __forceinline__ void store_nt(uint2* p, uint2 v) {
+    __builtin_nontemporal_store((u32x2){v.x, v.y}, reinterpret_cast<u32x2*>(p));
+}
+__device__ __forceinline__ void store_nt(uint32_t* p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ Raw32 load32(const void* p) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
     const u32x4 a = __builtin_nontemporal_load(q);
