@@ -196,13 +196,25 @@ def main():
         "project_64": (st64, "project", "fp16", N_HESS, None),
         "gemm_fwd_32": (st32, "gemm_fwd", "fp16", N_RAGGED, 1), "gemm_adj_32": (st32, "gemm_adj", "fp16", N_RAGGED, 1),
     }
+    # The 64 data-space columns run with FP16 intermediate operands (the
+    # library's default for an FP16 plan with more than 128 sensors, matrix-core
+    # products and a compiled transform length): the adjoint writes FP16 pairs,
+    # the re-pad reads and writes them, and the forward products take FP16
+    # right-hand sides in the whole-line ring (tile 13, not autotuned).
+    f16_ops = op16.fp16_operands and w.Nd > 128
+    variant = {"gemm_fwd_64": "fp16_rhs", "gemm_adj_64": "fp16_out"} if f16_ops else {}
     kern = {}
     for k, (st, stage, prec, nr, issue) in kdefs.items():
         us = avg_us(st, stage)
         v = {"us": us, "spectrum": prec, "nrhs": nr, "launches_per_step": st[stage][1] / args.steps}
+        if k in variant:
+            v["operands"] = variant[k]
         if k.startswith("project"):
-            # truncate-and-repad: reads the adjoint products and writes the forward operand, 8 B each per value
-            v["bytes"] = 2 * op.nfreq * nr * w.Nm * 8
+            # truncate-and-repad: reads the adjoint products and writes the
+            # forward operand, each a complex value per bin and series (8 B
+            # as complex FP32, 4 B as FP16 pairs)
+            v["operand_bytes"] = 4 if f16_ops else 8
+            v["bytes"] = 2 * op.nfreq * nr * w.Nm * v["operand_bytes"]
             v["GBs"] = v["bytes"] / (us * 1e-6) / 1e9 if us else 0.0
         else:
             v["spectrum_bytes"] = spec_bytes
@@ -219,12 +231,13 @@ def main():
     dom_tile = None
     if dom.startswith("gemm_"):
         nr = int(dom.rsplit("_", 1)[1])
-        dom_tile = tuned[f"{dk['spectrum']}_{nr}"][dom.split("_")[1]]["tile"]
-    traffic = measured_traffic(dom, dom_tile, dk["spectrum"], w)
+        dom_tile = 13 if variant.get(dom) == "fp16_rhs" else tuned[f"{dk['spectrum']}_{nr}"][dom.split("_")[1]]["tile"]
+    traffic = measured_traffic(dom, dom_tile, dk["spectrum"], w, variant.get(dom, ""))
     roof = {"bound": "hbm", "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dk["GBs"] / HBM_PEAK_GBS,
             "traffic": traffic["bytes"] if traffic else None, "traffic_unit": "bytes/launch",
             "traffic_detail": traffic, "kernel": dom, "tile": dom_tile, "spectrum": dk["spectrum"],
+            "operands": variant.get(dom, "complex_fp32"),
             "algorithmic_bytes_per_launch": spec_bytes, "avg_launch_us": dk["us"],
             "achieved_incl_rhs": dk.get("GBs_incl_rhs"), "frac_incl_rhs": (dk.get("GBs_incl_rhs") or 0) / HBM_PEAK_GBS,
             "rhs_bytes_per_launch": dk.get("rhs_bytes")}
@@ -309,62 +322,62 @@ def main():
 # keyed by the SHA-1 of that file.
 _GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "2f911a6b6be4d59d40b698f1b8e4ceda659b1751")
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
-# (kernel, tile, spectrum precision): (fetch bytes, write bytes)
+# (kernel, tile, spectrum precision, operand variant): (fetch bytes, write bytes)
 _MEASURED = {
-    ('gemm_adj_64', 1, 'bf16'): (17082032042, 3535705621),
-    ('gemm_adj_64', 2, 'bf16'): (31847052035, 3534823488),
-    ('gemm_adj_64', 3, 'bf16'): (17013299328, 3533744150),
-    ('gemm_adj_64', 4, 'bf16'): (33449310249, 3565478550),
-    ('gemm_adj_64', 5, 'bf16'): (17053242368, 3577802474),
-    ('gemm_adj_64', 6, 'bf16'): (16935612800, 3669371670),
-    ('gemm_adj_64', 9, 'bf16'): (16939654870, 3531603968),
-    ('gemm_adj_64', 10, 'bf16'): (33333909975, 3531603968),
-    ('gemm_adj_64', 15, 'bf16'): (16802764160, 3531603968),
-    ('gemm_adj_64', 16, 'bf16'): (33417260250, 3531603968),
-    ('gemm_fwd_64', 0, 'bf16'): (20244972587, 523023509),
-    ('gemm_fwd_64', 1, 'bf16'): (20338794752, 522562795),
-    ('gemm_fwd_64', 2, 'bf16'): (20641549776, 524581355),
-    ('gemm_fwd_64', 3, 'bf16'): (25084247081, 519237141),
-    ('gemm_fwd_64', 4, 'bf16'): (23961161346, 522095744),
-    ('gemm_fwd_64', 5, 'bf16'): (22625581309, 519619392),
-    ('gemm_fwd_64', 6, 'bf16'): (20503210755, 534626752),
-    ('gemm_fwd_64', 7, 'bf16'): (20567531520, 531692843),
-    ('gemm_fwd_64', 8, 'bf16'): (20643915346, 524817579),
-    ('gemm_fwd_64', 11, 'bf16'): (27314822021, 534802261),
-    ('gemm_fwd_64', 12, 'bf16'): (23765472256, 560254549),
-    ('gemm_fwd_64', 13, 'bf16'): (20203701846, 523361621),
-    ('gemm_fwd_64', 14, 'bf16'): (21224764075, 521022357),
-    ('gemv_adj', None, 'bf16'): (16586875904, 55188864),
-    ('gemv_fwd', None, 'bf16'): (17108026368, 16166400),
-    ('gemm_adj_32', 9, 'fp16'): (16706503211, 1765801984),
-    ('gemm_adj_32', 10, 'fp16'): (16713023061, 1765801984),
-    ('gemm_adj_32', 15, 'fp16'): (16703037696, 1765801984),
-    ('gemm_adj_32', 16, 'fp16'): (16710312404, 1765801984),
-    ('gemm_adj_64', 9, 'fp16'): (16902326699, 3531603968),
-    ('gemm_adj_64', 10, 'fp16'): (33488821596, 3531603968),
-    ('gemm_adj_64', 15, 'fp16'): (16802615594, 3531603968),
-    ('gemm_adj_64', 16, 'fp16'): (33430608131, 3531603968),
-    ('gemm_fwd_32', 7, 'fp16'): (18998609493, 260090709),
-    ('gemm_fwd_32', 8, 'fp16'): (19143526656, 260752640),
-    ('gemm_fwd_32', 11, 'fp16'): (21642715054, 262724416),
-    ('gemm_fwd_32', 12, 'fp16'): (20561256277, 267166891),
-    ('gemm_fwd_32', 13, 'fp16'): (18478076075, 261696939),
-    ('gemm_fwd_32', 14, 'fp16'): (18465922346, 261713429),
-    ('gemm_fwd_64', 7, 'fp16'): (21137234309, 526315627),
-    ('gemm_fwd_64', 8, 'fp16'): (20647867139, 524955285),
-    ('gemm_fwd_64', 11, 'fp16'): (28386387074, 531433344),
-    ('gemm_fwd_64', 12, 'fp16'): (23657384489, 537314645),
-    ('gemm_fwd_64', 13, 'fp16'): (20209269632, 523272448),
-    ('gemm_fwd_64', 14, 'fp16'): (24225048576, 525051179),
-    ('gemv_adj', None, 'fp16'): (16586877952, 55189120),
-    ('gemv_fwd', None, 'fp16'): (17108039295, 16166400),
+    ('gemm_adj_64', 1, 'bf16', ''): (17082032042, 3535705621),
+    ('gemm_adj_64', 2, 'bf16', ''): (31847052035, 3534823488),
+    ('gemm_adj_64', 3, 'bf16', ''): (17013299328, 3533744150),
+    ('gemm_adj_64', 4, 'bf16', ''): (33449310249, 3565478550),
+    ('gemm_adj_64', 5, 'bf16', ''): (17053242368, 3577802474),
+    ('gemm_adj_64', 6, 'bf16', ''): (16935612800, 3669371670),
+    ('gemm_adj_64', 9, 'bf16', ''): (16939654870, 3531603968),
+    ('gemm_adj_64', 10, 'bf16', ''): (33333909975, 3531603968),
+    ('gemm_adj_64', 15, 'bf16', ''): (16802764160, 3531603968),
+    ('gemm_adj_64', 16, 'bf16', ''): (33417260250, 3531603968),
+    ('gemm_fwd_64', 0, 'bf16', ''): (20244972587, 523023509),
+    ('gemm_fwd_64', 1, 'bf16', ''): (20338794752, 522562795),
+    ('gemm_fwd_64', 2, 'bf16', ''): (20641549776, 524581355),
+    ('gemm_fwd_64', 3, 'bf16', ''): (25084247081, 519237141),
+    ('gemm_fwd_64', 4, 'bf16', ''): (23961161346, 522095744),
+    ('gemm_fwd_64', 5, 'bf16', ''): (22625581309, 519619392),
+    ('gemm_fwd_64', 6, 'bf16', ''): (20503210755, 534626752),
+    ('gemm_fwd_64', 7, 'bf16', ''): (20567531520, 531692843),
+    ('gemm_fwd_64', 8, 'bf16', ''): (20643915346, 524817579),
+    ('gemm_fwd_64', 11, 'bf16', ''): (27314822021, 534802261),
+    ('gemm_fwd_64', 12, 'bf16', ''): (23765472256, 560254549),
+    ('gemm_fwd_64', 13, 'bf16', ''): (20203701846, 523361621),
+    ('gemm_fwd_64', 14, 'bf16', ''): (21224764075, 521022357),
+    ('gemv_adj', None, 'bf16', ''): (16586875904, 55188864),
+    ('gemv_fwd', None, 'bf16', ''): (17108026368, 16166400),
+    ('gemm_adj_32', 9, 'fp16', ''): (16706503211, 1765801984),
+    ('gemm_adj_32', 10, 'fp16', ''): (16713023061, 1765801984),
+    ('gemm_adj_32', 15, 'fp16', ''): (16703037696, 1765801984),
+    ('gemm_adj_32', 16, 'fp16', ''): (16710312404, 1765801984),
+    ('gemm_adj_64', 9, 'fp16', ''): (16902326699, 3531603968),
+    ('gemm_adj_64', 10, 'fp16', ''): (33488821596, 3531603968),
+    ('gemm_adj_64', 15, 'fp16', ''): (16802615594, 3531603968),
+    ('gemm_adj_64', 16, 'fp16', ''): (33430608131, 3531603968),
+    ('gemm_fwd_32', 7, 'fp16', ''): (18998609493, 260090709),
+    ('gemm_fwd_32', 8, 'fp16', ''): (19143526656, 260752640),
+    ('gemm_fwd_32', 11, 'fp16', ''): (21642715054, 262724416),
+    ('gemm_fwd_32', 12, 'fp16', ''): (20561256277, 267166891),
+    ('gemm_fwd_32', 13, 'fp16', ''): (18478076075, 261696939),
+    ('gemm_fwd_32', 14, 'fp16', ''): (18465922346, 261713429),
+    ('gemm_fwd_64', 7, 'fp16', ''): (21137234309, 526315627),
+    ('gemm_fwd_64', 8, 'fp16', ''): (20647867139, 524955285),
+    ('gemm_fwd_64', 11, 'fp16', ''): (28386387074, 531433344),
+    ('gemm_fwd_64', 12, 'fp16', ''): (23657384489, 537314645),
+    ('gemm_fwd_64', 13, 'fp16', ''): (20209269632, 523272448),
+    ('gemm_fwd_64', 14, 'fp16', ''): (24225048576, 525051179),
+    ('gemv_adj', None, 'fp16', ''): (16586877952, 55189120),
+    ('gemv_fwd', None, 'fp16', ''): (17108039295, 16166400),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
 
-def measured_traffic(kernel, tile, precision, w):
+def measured_traffic(kernel, tile, precision, w, variant=""):
     import hashlib
-    ent = TRAFFIC.get((kernel, tile, precision))
+    ent = TRAFFIC.get((kernel, tile, precision, variant))
     if not ent:
         return None
     src, sha, fetch, write, workload = ent

@@ -575,12 +575,13 @@ hipError_t launch_twiddle(void* tw64, void* tw32, int L, hipStream_t st) {
 }
 
 // After a transform that recorded wavefront maxima: the per-outer scales,
-// from the slots of its tiles (tile shift sh, four wavefronts per tile on
-// both the compiled-length and the runtime-length kernels).
-static hipError_t rhs_scales(const SeriesIO& io, int sh, hipError_t err, hipStream_t st) {
+// from the slots of its tiles (tile shift sh; four wavefronts per tile on
+// the runtime-length kernels, fixed_tile_waves on the compiled-length ones).
+static hipError_t rhs_scales(const FftPlan& pl, bool f64, const SeriesIO& io, int sh, hipError_t err,
+                             hipStream_t st) {
     if (err != hipSuccess || !io.amax_part || io.outer_count == 0) return err;
-    static_assert(kFftThreads == 256, "four wavefronts per tile");
-    const int used = ((io.S_pad + (1 << sh) - 1) >> sh) * 4;
+    static_assert(kFftThreads == 256, "four wavefronts per runtime-length tile");
+    const int used = ((io.S_pad + (1 << sh) - 1) >> sh) * fixed_tile_waves(f64, pl, sh);
     hipLaunchKernelGGL(k_rhs_scale, dim3(io.outer_count), dim3(256), 0, st, (const float*)io.amax_part, used,
                        io.amax_slots, io.rhs_scale);
     return hipGetLastError();
@@ -622,7 +623,7 @@ hipError_t launch_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& 
                       const void* tw, hipStream_t st) {
     int sh = 0;
     const hipError_t err = r2c_transform(f64, in_f64, pl, io, in, out, tw, st, &sh);
-    return rhs_scales(io, sh, err, st);
+    return rhs_scales(pl, f64, io, sh, err, st);
 }
 
 hipError_t launch_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out, const void* tw,
@@ -676,7 +677,10 @@ static hipError_t project_transform(bool f64, const FftPlan& pl, const SeriesIO&
 
 bool launch_project_half(const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, const float* sx,
                          const float* sy, hipStream_t st, hipError_t* err) {
-    const int wsh = wide_shift(false, pl, io.S_pad);
+    // FP16 pairs: a 16-series tile's bin rows are 64 bytes whichever the
+    // workgroup size; at M = 420 the re-pad on FP16 pairs measured 3 % slower
+    // on the wide tiles than on 8-series ones, so it keeps those there
+    const int wsh = pl.M == 420 ? -1 : wide_shift(false, pl, io.S_pad);
     if (wsh >= 0 && launch_fixed_project_h(pl, io, in_out, tw, wsh, sx, sy, st, err)) return true;
     return launch_fixed_project_h(pl, io, in_out, tw, fft_tile_shift(pl.M, false), sx, sy, st, err);
 }
@@ -685,7 +689,7 @@ hipError_t launch_project(bool f64, const FftPlan& pl, const SeriesIO& io, void*
                           hipStream_t st) {
     int sh = 0;
     const hipError_t err = project_transform(f64, pl, io, in_out, tw, st, &sh);
-    return rhs_scales(io, sh, err, st);
+    return rhs_scales(pl, f64, io, sh, err, st);
 }
 
 hipError_t launch_misfit_reduce(const double* partials, int nper, double* misfit, int nrhs, hipStream_t st) {

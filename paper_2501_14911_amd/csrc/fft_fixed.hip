@@ -33,7 +33,6 @@
 namespace p2o {
 namespace {
 
-constexpr int kFxThreads = 256;
 
 // M factored greedily over 8, 4, 2, 3, 5, 7 (as the plan does), in that order
 // or reversed.  ns: product of the radices of the earlier passes; toff: first
@@ -68,11 +67,11 @@ constexpr RadixSeq radix_seq(int M, bool reversed) {
     return f;
 }
 
-template <int M, int SH>
+template <int M, int SH, int NT>
 struct Geo {
     static constexpr int TW = 1 << SH;             // series per tile
     static constexpr int RS = TW + 1;              // LDS row stride in complex entries (odd: spreads banks)
-    static constexpr int JS = kFxThreads >> SH;    // bins (or butterflies) per sweep of the workgroup
+    static constexpr int JS = NT >> SH;            // bins (or butterflies) per sweep of the workgroup
     static constexpr RadixSeq FWD = radix_seq(M, false);
     static constexpr RadixSeq REV = radix_seq(M, true);
     static constexpr int NP = FWD.n;
@@ -85,9 +84,9 @@ struct Geo {
 // multiplies entry q by w[k][q] (k = j mod Ns), transforms, and writes
 // entry p to (j - k) R + k + p Ns.  A thread takes butterflies
 // j = j0 + u JS, u < NU (the last sweep may be partial).
-template <int M, int SH, bool REV, int P>
+template <int M, int SH, int NT, bool REV, int P>
 struct Pass {
-    using G = Geo<M, SH>;
+    using G = Geo<M, SH, NT>;
     static constexpr RadixSeq S = REV ? G::REV : G::FWD;
     static constexpr int R = S.r[P], NS = S.ns[P], TOFF = S.toff[P];
     static constexpr int MR = M / R;
@@ -146,17 +145,17 @@ __device__ __forceinline__ void st(E* base, uint32_t off, E v) {
 // twg: e^{-2 pi i n / L}, n < L = 2M.  Pair table: W^k, k <= M / 2.  Pass
 // table of a radix order: pass P's entry k (R - 1) + q - 1 is
 // e^{-2 pi i q k / (Ns R)} = twg[q k L / (Ns R)].
-template <typename T, int M, int SH>
+template <typename T, int M, int SH, int NT>
 __device__ __forceinline__ void stage_pair_tw(cplx<T>* twq, const cplx<T>* __restrict__ twg) {
-    for (int k = threadIdx.x; k < Geo<M, SH>::NPAIR; k += kFxThreads) twq[k] = twg[k];
+    for (int k = threadIdx.x; k < Geo<M, SH, NT>::NPAIR; k += NT) twq[k] = twg[k];
 }
 
-template <typename T, int M, int SH, bool REV>
+template <typename T, int M, int SH, int NT, bool REV>
 __device__ __forceinline__ void stage_pass_tw(cplx<T>* tab, const cplx<T>* __restrict__ twg) {
-    static_for<0, Geo<M, SH>::NP>([&](auto pc) {
-        using Ps = Pass<M, SH, REV, decltype(pc)::value>;
+    static_for<0, Geo<M, SH, NT>::NP>([&](auto pc) {
+        using Ps = Pass<M, SH, NT, REV, decltype(pc)::value>;
         constexpr int R = Ps::R, NS = Ps::NS, STEP = 2 * M / (NS * R);
-        for (int e = threadIdx.x; e < NS * (R - 1); e += kFxThreads) {
+        for (int e = threadIdx.x; e < NS * (R - 1); e += NT) {
             const int k = e / (R - 1), q = e - k * (R - 1) + 1;
             tab[Ps::TOFF + e] = twg[q * k * STEP];
         }
@@ -165,11 +164,11 @@ __device__ __forceinline__ void stage_pass_tw(cplx<T>* tab, const cplx<T>* __res
 
 // ---------------------------------------------------------------- passes
 // Pass P on the LDS tile (read, barrier, write, barrier).
-template <typename T, int M, int SH, bool REV, bool INV, int P>
+template <typename T, int M, int SH, int NT, bool REV, bool INV, int P>
 __device__ __forceinline__ void lds_pass(cplx<T>* buf, const cplx<T>* tab, int s, int j0) {
     using Z = cplx<T>;
-    using G = Geo<M, SH>;
-    using Ps = Pass<M, SH, REV, P>;
+    using G = Geo<M, SH, NT>;
+    using Ps = Pass<M, SH, NT, REV, P>;
     constexpr int R = Ps::R, NS = Ps::NS, MR = Ps::MR, NU = Ps::NU, RS = G::RS, JS = G::JS;
     Z v[NU][R];
     const Z* rb = buf + j0 * RS + s;
@@ -200,15 +199,15 @@ __device__ __forceinline__ void lds_pass(cplx<T>* buf, const cplx<T>* tab, int s
 // First forward pass fed by the time series (src: series s0 at t = 0; lane
 // s reads series s0 + s): z[n] = x[2n] + i x[2n+1], x[t] = 0 for t >= nt or
 // for a series past S (ok false).
-template <typename T, typename TIN, int M, int SH>
+template <typename T, typename TIN, int M, int SH, int NT>
 __device__ __forceinline__ void first_pass_from_time(cplx<T>* buf, const TIN* __restrict__ src, long long t_stride,
                                                      bool ok, int nt, int s, int j0) {
     const uint32_t ts = (uint32_t)t_stride * (uint32_t)sizeof(TIN);
     uint32_t o0 = 2u * (uint32_t)j0 * ts + (uint32_t)s * (uint32_t)sizeof(TIN);   // t = 2 j0 from the sweep base
     asm volatile("" : "+v"(o0));
     using Z = cplx<T>;
-    using G = Geo<M, SH>;
-    using Ps = Pass<M, SH, false, 0>;
+    using G = Geo<M, SH, NT>;
+    using Ps = Pass<M, SH, NT, false, 0>;
     constexpr int R = Ps::R, MR = Ps::MR, NU = Ps::NU, RS = G::RS, JS = G::JS;
     Z v[NU][R];
 #pragma unroll
@@ -262,11 +261,11 @@ __device__ __forceinline__ cplx<T> post_one(cplx<T> a, cplx<T> b, cplx<T> w) {
 // Half spectra X[0..M] (sum of nparts partials; zero for a series past S)
 // into Z[0..M-1] on the tile.  Bins 0 and M are taken as real.  src: series
 // s0 of bin 0 of partial 0; lane s reads series s0 + s.
-template <typename T, int M, int SH>
+template <typename T, int M, int SH, int NT>
 __device__ __forceinline__ void load_pre(cplx<T>* buf, const cplx<T>* twq, const cplx<T>* __restrict__ src,
                                          const SeriesIO& io, bool ok, int s, int j0) {
     using Z = cplx<T>;
-    using G = Geo<M, SH>;
+    using G = Geo<M, SH, NT>;
     constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
     // bin k = j0 + u JS: base row u JS, lane offset j0 rows; bin M - k: base
     // row M - (JS - 1) - u JS, lane offset JS - 1 - j0 rows
@@ -328,11 +327,11 @@ __device__ __forceinline__ void load_pre(cplx<T>* buf, const cplx<T>* twq, const
 // arithmetic, 1 % slower, so it stores per word).
 // With amax_slot (FP32 complex output only), each wavefront's largest |re|,
 // |im| of the values it stores goes to amax_slot[wavefront].
-template <typename T, int M, int SH, bool STAGED>
+template <typename T, int M, int SH, int NT, bool STAGED>
 __device__ __forceinline__ void post_store(cplx<T>* buf, const cplx<T>* twq, const SeriesIO& io, cplx<T>* row,
                                            int s0, int s, int j0, float* amax_slot) {
     using Z = cplx<T>;
-    using G = Geo<M, SH>;
+    using G = Geo<M, SH, NT>;
     constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
     if constexpr (sizeof(T) == sizeof(float) && STAGED) {
         if (io.quad) {
@@ -377,7 +376,7 @@ __device__ __forceinline__ void post_store(cplx<T>* buf, const cplx<T>* twq, con
             constexpr int CPB = RB / 16;                  // chunks per bin row
             uint8_t* const out = reinterpret_cast<uint8_t*>(row + s0);
             const long long fsb = (long long)io.f_stride * (long long)sizeof(Z);
-            for (int e = threadIdx.x; e < (M + 1) * CPB; e += kFxThreads) {
+            for (int e = threadIdx.x; e < (M + 1) * CPB; e += NT) {
                 const int bin = e / CPB, c = e % CPB;
                 if (s0 + 4 * (c >> 1) < io.S_pad)
                     *reinterpret_cast<uint4*>(out + bin * fsb + c * 16) =
@@ -433,11 +432,11 @@ __device__ __forceinline__ void post_store(cplx<T>* buf, const cplx<T>* twq, con
     }
 }
 
-static_assert(kFxThreads == 256, "four wavefront-maximum slots per tile, as in the runtime-length kernels");
-
-// Slots of this tile's wavefront maxima, or nullptr.
+// Slots of this tile's wavefront maxima (one per wavefront of an NT-thread
+// workgroup), or nullptr.
+template <int NT>
 __device__ __forceinline__ float* amax_slots_of(const SeriesIO& io, int outer, int tile) {
-    return io.amax_part ? io.amax_part + (long long)outer * io.amax_slots + tile * (kFxThreads / 64) : nullptr;
+    return io.amax_part ? io.amax_part + (long long)outer * io.amax_slots + tile * (NT / 64) : nullptr;
 }
 
 // ---------------------------------------------------------------- kernels
@@ -445,18 +444,18 @@ __device__ __forceinline__ float* amax_slots_of(const SeriesIO& io, int outer, i
 // x Q + i, i = b / 8, b / 8 + G / 8, ... of that XCD's share [x Q, (x + 1) Q)
 // (G = grid size, a multiple of 8): at any time the workgroups of one XCD
 // work on adjacent tiles.
-template <typename T, typename TIN, int M, int SH>
-__global__ __launch_bounds__(kFxThreads) void k_r2c_fx(SeriesIO io, const TIN* __restrict__ in,
+template <typename T, typename TIN, int M, int SH, int NT>
+__global__ __launch_bounds__(NT) void k_r2c_fx(SeriesIO io, const TIN* __restrict__ in,
                                                        cplx<T>* __restrict__ out, const cplx<T>* __restrict__ twg,
                                                        ItemMap im) {
     using Z = cplx<T>;
-    using G = Geo<M, SH>;
+    using G = Geo<M, SH, NT>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Z* buf = reinterpret_cast<Z*>(smem_raw);
     Z* twq = buf + G::TILE;
     Z* twf = twq + G::NPAIR;
-    stage_pair_tw<T, M, SH>(twq, twg);
-    stage_pass_tw<T, M, SH, false>(twf, twg);
+    stage_pair_tw<T, M, SH, NT>(twq, twg);
+    stage_pass_tw<T, M, SH, NT, false>(twf, twg);
     __syncthreads();
     const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
     const int xq = (int)(blockIdx.x & 7) * im.Q, nper = (int)(gridDim.x >> 3);
@@ -468,29 +467,29 @@ __global__ __launch_bounds__(kFxThreads) void k_r2c_fx(SeriesIO io, const TIN* _
         asm volatile("" : "+v"(s), "+v"(j0));
         const int s0 = tile << SH;
         const int nt = active_clamp(io, active_raw(io, outer));
-        first_pass_from_time<T, TIN, M, SH>(buf, in + (long long)outer * io.t_outer + s0, io.t_stride,
+        first_pass_from_time<T, TIN, M, SH, NT>(buf, in + (long long)outer * io.t_outer + s0, io.t_stride,
                                             s0 + s < io.S, nt, s, j0);
-        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
-        post_store<T, M, SH, true>(buf, twq, io, out + (long long)outer * io.f_outer, s0, s, j0,
-                                   amax_slots_of(io, outer, tile));
+        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, NT, false, false, decltype(pc)::value>(buf, twf, s, j0); });
+        post_store<T, M, SH, NT, true>(buf, twq, io, out + (long long)outer * io.f_outer, s0, s, j0,
+                                   amax_slots_of<NT>(io, outer, tile));
         __syncthreads();
     }
 }
 
-template <typename T, typename TOUT, int M, int SH, int EPI>
-__global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T>* __restrict__ in,
+template <typename T, typename TOUT, int M, int SH, int NT, int EPI>
+__global__ __launch_bounds__(NT) void k_c2r_fx(SeriesIO io, const cplx<T>* __restrict__ in,
                                                        TOUT* __restrict__ out, const cplx<T>* __restrict__ twg,
                                                        MisfitArgs ma, ItemMap im) {
     using Z = cplx<T>;
-    using G = Geo<M, SH>;
-    using Pl = Pass<M, SH, true, G::NP - 1>;
+    using G = Geo<M, SH, NT>;
+    using Pl = Pass<M, SH, NT, true, G::NP - 1>;
     constexpr int R = Pl::R, NS = Pl::NS, MR = Pl::MR, NU = Pl::NU, RS = G::RS, JS = G::JS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Z* buf = reinterpret_cast<Z*>(smem_raw);
     Z* twq = buf + G::TILE;
     Z* twr = twq + G::NPAIR;
-    stage_pair_tw<T, M, SH>(twq, twg);
-    stage_pass_tw<T, M, SH, true>(twr, twg);
+    stage_pair_tw<T, M, SH, NT>(twq, twg);
+    stage_pass_tw<T, M, SH, NT, true>(twr, twg);
     __syncthreads();
     const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
     const T inv = T(1) / T(M);
@@ -505,9 +504,9 @@ __global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T
         const int col = s0 + s;
         const bool ok = col < io.S;
         const int nt_raw = active_raw(io, outer);      // used after the transform
-        load_pre<T, M, SH>(buf, twq, in + (long long)outer * io.f_outer + s0, io, ok, s, j0);
+        load_pre<T, M, SH, NT>(buf, twq, in + (long long)outer * io.f_outer + s0, io, ok, s, j0);
         const int nt = active_clamp(io, nt_raw);
-        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
+        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, NT, true, true, decltype(pc)::value>(buf, twr, s, j0); });
         // last inverse pass: butterfly j (< MR = NS) writes z[j + p NS] straight to the time series
         Z v[NU][R];
         const Z* rb = buf + j0 * RS + s;
@@ -562,11 +561,11 @@ __global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T
         }
         __syncthreads();                       // tile reads done: the LDS is free
         if constexpr (EPI == EPI_MISFIT) {
-            static_assert(G::TILE * sizeof(Z) >= kFxThreads * sizeof(double), "reduction fits in the tile");
+            static_assert(G::TILE * sizeof(Z) >= NT * sizeof(double), "reduction fits in the tile");
             double* red = reinterpret_cast<double*>(smem_raw);
             red[threadIdx.x] = acc;
             __syncthreads();
-            for (int w = kFxThreads / 2; w > 0; w >>= 1) {
+            for (int w = NT / 2; w > 0; w >>= 1) {
                 if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
                 __syncthreads();
             }
@@ -577,13 +576,13 @@ __global__ __launch_bounds__(kFxThreads) void k_c2r_fx(SeriesIO io, const cplx<T
 }
 
 // Truncate-and-repad (see k_project in fft.hip), written over partial 0.
-template <typename T, int M, int SH>
-__global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>* in_out,
+template <typename T, int M, int SH, int NT>
+__global__ __launch_bounds__(NT) void k_project_fx(SeriesIO io, cplx<T>* in_out,
                                                            const cplx<T>* __restrict__ twg, ItemMap im) {
     using Z = cplx<T>;
-    using G = Geo<M, SH>;
-    using Pl = Pass<M, SH, true, G::NP - 1>;    // last inverse pass
-    using Pf = Pass<M, SH, false, 0>;           // first forward pass: same radix, same index sets
+    using G = Geo<M, SH, NT>;
+    using Pl = Pass<M, SH, NT, true, G::NP - 1>;    // last inverse pass
+    using Pf = Pass<M, SH, NT, false, 0>;           // first forward pass: same radix, same index sets
     static_assert(Pl::R == Pf::R && Pl::NS == Pf::MR, "reversed order ends with the forward order's first radix");
     constexpr int R = Pl::R, MR = Pl::MR, NU = Pl::NU, RS = G::RS, JS = G::JS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -591,9 +590,9 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>*
     Z* twq = buf + G::TILE;
     Z* twf = twq + G::NPAIR;
     Z* twr = twf + (M - 1);
-    stage_pair_tw<T, M, SH>(twq, twg);
-    stage_pass_tw<T, M, SH, false>(twf, twg);
-    stage_pass_tw<T, M, SH, true>(twr, twg);
+    stage_pair_tw<T, M, SH, NT>(twq, twg);
+    stage_pass_tw<T, M, SH, NT, false>(twf, twg);
+    stage_pass_tw<T, M, SH, NT, true>(twr, twg);
     __syncthreads();
     const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
     const T inv = T(1) / T(M);
@@ -607,9 +606,9 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>*
         const int s0 = tile << SH;
         const int nt_raw = active_raw(io, outer);      // used between the transforms
         Z* base = in_out + (long long)outer * io.f_outer;
-        load_pre<T, M, SH>(buf, twq, base + s0, io, s0 + s < io.S, s, j0);
+        load_pre<T, M, SH, NT>(buf, twq, base + s0, io, s0 + s < io.S, s, j0);
         const int nt = active_clamp(io, nt_raw);
-        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
+        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, NT, true, true, decltype(pc)::value>(buf, twr, s, j0); });
         // last inverse pass -> z[j + p MR]; keep t < nt (t = 2n, 2n + 1) and
         // scale by 1 / M; first forward pass on the same entries
         Z v[NU][R];
@@ -642,8 +641,8 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx(SeriesIO io, cplx<T>*
             }
         }
         __syncthreads();
-        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
-        post_store<T, M, SH, false>(buf, twq, io, base, s0, s, j0, amax_slots_of(io, outer, tile));
+        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, NT, false, false, decltype(pc)::value>(buf, twf, s, j0); });
+        post_store<T, M, SH, NT, false>(buf, twq, io, base, s0, s, j0, amax_slots_of<NT>(io, outer, tile));
         __syncthreads();
     }
 }
@@ -658,11 +657,11 @@ __device__ __forceinline__ uint32_t pair_f16(float re, float im, float s) {
     return f32_to_f16_rne(re * s) | (f32_to_f16_rne(im * s) << 16);
 }
 
-template <int M, int SH>
+template <int M, int SH, int NT>
 __device__ __forceinline__ void load_pre_h(float2* buf, const float2* twq, const uint32_t* __restrict__ src,
                                            const SeriesIO& io, bool ok, int s, int j0, float inv) {
     using Z = float2;
-    using G = Geo<M, SH>;
+    using G = Geo<M, SH, NT>;
     constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
     static_assert(M - (JS - 1) - (NU - 1) * JS >= 0, "partner rows start inside the spectrum");
     const uint32_t fs = (uint32_t)io.f_stride * 4u, so = (uint32_t)s * 4u;
@@ -694,11 +693,11 @@ __device__ __forceinline__ void load_pre_h(float2* buf, const float2* twq, const
     __syncthreads();
 }
 
-template <int M, int SH>
+template <int M, int SH, int NT>
 __device__ __forceinline__ void post_store_h(float2* buf, const float2* twq, const SeriesIO& io, uint32_t* row, int s0,
                                              int s, int j0, float sc) {
     using Z = float2;
-    using G = Geo<M, SH>;
+    using G = Geo<M, SH, NT>;
     constexpr int RS = G::RS, JS = G::JS, NU = (G::NPAIR + JS - 1) / JS;
     static_assert(M - (JS - 1) - (NU - 1) * JS >= 0, "partner rows start inside the spectrum");
     const bool ok = s0 + s < io.S_pad;
@@ -723,15 +722,15 @@ __device__ __forceinline__ void post_store_h(float2* buf, const float2* twq, con
     }
 }
 
-template <int M, int SH>
-__global__ __launch_bounds__(kFxThreads) void k_project_fx_h(SeriesIO io, uint32_t* in_out,
+template <int M, int SH, int NT>
+__global__ __launch_bounds__(NT) void k_project_fx_h(SeriesIO io, uint32_t* in_out,
                                                              const float2* __restrict__ twg, const float* __restrict__ sx,
                                                              const float* __restrict__ sy, ItemMap im) {
     using T = float;
     using Z = float2;
-    using G = Geo<M, SH>;
-    using Pl = Pass<M, SH, true, G::NP - 1>;
-    using Pf = Pass<M, SH, false, 0>;
+    using G = Geo<M, SH, NT>;
+    using Pl = Pass<M, SH, NT, true, G::NP - 1>;
+    using Pf = Pass<M, SH, NT, false, 0>;
     static_assert(Pl::R == Pf::R && Pl::NS == Pf::MR, "reversed order ends with the forward order's first radix");
     constexpr int R = Pl::R, MR = Pl::MR, NU = Pl::NU, RS = G::RS, JS = G::JS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -739,9 +738,9 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx_h(SeriesIO io, uint32
     Z* twq = buf + G::TILE;
     Z* twf = twq + G::NPAIR;
     Z* twr = twf + (M - 1);
-    stage_pair_tw<T, M, SH>(twq, twg);
-    stage_pass_tw<T, M, SH, false>(twf, twg);
-    stage_pass_tw<T, M, SH, true>(twr, twg);
+    stage_pair_tw<T, M, SH, NT>(twq, twg);
+    stage_pass_tw<T, M, SH, NT, false>(twf, twg);
+    stage_pass_tw<T, M, SH, NT, true>(twr, twg);
     __syncthreads();
     const int s_ = threadIdx.x & (G::TW - 1), j0_ = threadIdx.x >> SH;
     const T inv = T(1) / T(M);
@@ -753,9 +752,9 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx_h(SeriesIO io, uint32
         const int s0 = tile << SH;
         const int nt_raw = active_raw(io, outer);
         uint32_t* base = in_out + (long long)outer * io.f_outer;
-        load_pre_h<M, SH>(buf, twq, base + s0, io, s0 + s < io.S, s, j0, 1.f / sx[outer]);
+        load_pre_h<M, SH, NT>(buf, twq, base + s0, io, s0 + s < io.S, s, j0, 1.f / sx[outer]);
         const int nt = active_clamp(io, nt_raw);
-        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, true, true, decltype(pc)::value>(buf, twr, s, j0); });
+        static_for<0, G::NP - 1>([&](auto pc) { lds_pass<T, M, SH, NT, true, true, decltype(pc)::value>(buf, twr, s, j0); });
         Z v[NU][R];
         const Z* rbp = buf + j0 * RS + s;
 #pragma unroll
@@ -786,26 +785,26 @@ __global__ __launch_bounds__(kFxThreads) void k_project_fx_h(SeriesIO io, uint32
             }
         }
         __syncthreads();
-        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, false, false, decltype(pc)::value>(buf, twf, s, j0); });
-        post_store_h<M, SH>(buf, twq, io, base, s0, s, j0, sy[outer]);
+        static_for<1, G::NP>([&](auto pc) { lds_pass<T, M, SH, NT, false, false, decltype(pc)::value>(buf, twf, s, j0); });
+        post_store_h<M, SH, NT>(buf, twq, io, base, s0, s, j0, sy[outer]);
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------- host side
-template <int M, int SH>
+template <int M, int SH, int NT>
 constexpr size_t fx_lds(size_t zbytes, int ntables) {
-    return ((size_t)Geo<M, SH>::TILE + Geo<M, SH>::NPAIR + (size_t)ntables * (M - 1)) * zbytes;
+    return ((size_t)Geo<M, SH, NT>::TILE + Geo<M, SH, NT>::NPAIR + (size_t)ntables * (M - 1)) * zbytes;
 }
 
 // Grid of resident workgroups for kernel K (occupancy per CU cached per
 // kernel; the CU count is queried each time), at most 8 Q.
-template <auto K>
+template <auto K, int NT>
 dim3 fx_grid(size_t lds, const ItemMap& im) {
     static int occ = 0;
     if (occ == 0) {
         int o = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, K, kFxThreads, lds) != hipSuccess || o < 1) o = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, K, NT, lds) != hipSuccess || o < 1) o = 1;
         occ = o;
     }
     int dev = 0, ncu = 0;
@@ -824,87 +823,89 @@ ItemMap fx_items(int S, int sh, int outer) {
     return im;
 }
 
-template <typename T, int M, int SH>
+template <typename T, int M, int SH, int NT>
 hipError_t fx_r2c(bool in_f64, const SeriesIO& io, const void* in, void* out, const void* tw, hipStream_t st) {
     const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
-    if (io.amax_part && (long long)im.ntiles * (kFxThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
-    const size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 1);
+    if (io.amax_part && (long long)im.ntiles * (NT / 64) > io.amax_slots) return hipErrorInvalidValue;
+    const size_t lds = fx_lds<M, SH, NT>(sizeof(cplx<T>), 1);
     if (in_f64) {
-        constexpr auto k = k_r2c_fx<T, double, M, SH>;
-        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const double*)in, (cplx<T>*)out,
+        constexpr auto k = k_r2c_fx<T, double, M, SH, NT>;
+        hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (const double*)in, (cplx<T>*)out,
                            (const cplx<T>*)tw, im);
     } else {
-        constexpr auto k = k_r2c_fx<T, float, M, SH>;
-        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const float*)in, (cplx<T>*)out,
+        constexpr auto k = k_r2c_fx<T, float, M, SH, NT>;
+        hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (const float*)in, (cplx<T>*)out,
                            (const cplx<T>*)tw, im);
     }
     return hipGetLastError();
 }
 
-template <typename T, int M, int SH>
+template <typename T, int M, int SH, int NT>
 hipError_t fx_c2r(const SeriesIO& io, const void* in, void* out, const void* tw, const MisfitArgs& ma,
                   hipStream_t st) {
     const ItemMap im = fx_items(io.S, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
-    size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 1);
-    if (lds < kFxThreads * sizeof(double)) lds = kFxThreads * sizeof(double);
+    size_t lds = fx_lds<M, SH, NT>(sizeof(cplx<T>), 1);
+    if (lds < NT * sizeof(double)) lds = NT * sizeof(double);
     if (ma.d_obs) {
-        constexpr auto k = k_c2r_fx<T, T, M, SH, EPI_MISFIT>;
-        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const cplx<T>*)in, (T*)out,
+        constexpr auto k = k_c2r_fx<T, T, M, SH, NT, EPI_MISFIT>;
+        hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (const cplx<T>*)in, (T*)out,
                            (const cplx<T>*)tw, ma, im);
     } else {
-        constexpr auto k = k_c2r_fx<T, T, M, SH, EPI_PLAIN>;
-        hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (const cplx<T>*)in, (T*)out,
+        constexpr auto k = k_c2r_fx<T, T, M, SH, NT, EPI_PLAIN>;
+        hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (const cplx<T>*)in, (T*)out,
                            (const cplx<T>*)tw, ma, im);
     }
     return hipGetLastError();
 }
 
-template <typename T, int M, int SH>
+template <typename T, int M, int SH, int NT>
 hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStream_t st) {
     const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
-    if (io.amax_part && (long long)im.ntiles * (kFxThreads / 64) > io.amax_slots) return hipErrorInvalidValue;
-    const size_t lds = fx_lds<M, SH>(sizeof(cplx<T>), 2);
-    constexpr auto k = k_project_fx<T, M, SH>;
-    hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (cplx<T>*)in_out, (const cplx<T>*)tw, im);
+    if (io.amax_part && (long long)im.ntiles * (NT / 64) > io.amax_slots) return hipErrorInvalidValue;
+    const size_t lds = fx_lds<M, SH, NT>(sizeof(cplx<T>), 2);
+    constexpr auto k = k_project_fx<T, M, SH, NT>;
+    hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (cplx<T>*)in_out, (const cplx<T>*)tw, im);
     return hipGetLastError();
 }
 
-template <int M, int SH>
+template <int M, int SH, int NT>
 hipError_t fx_project_h(const SeriesIO& io, void* in_out, const void* tw, const float* sx, const float* sy,
                         hipStream_t st) {
     const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
-    const size_t lds = fx_lds<M, SH>(sizeof(float2), 2);
-    constexpr auto k = k_project_fx_h<M, SH>;
-    hipLaunchKernelGGL(k, fx_grid<k>(lds, im), dim3(kFxThreads), lds, st, io, (uint32_t*)in_out, (const float2*)tw, sx, sy,
+    const size_t lds = fx_lds<M, SH, NT>(sizeof(float2), 2);
+    constexpr auto k = k_project_fx_h<M, SH, NT>;
+    hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (uint32_t*)in_out, (const float2*)tw, sx, sy,
                        im);
     return hipGetLastError();
 }
 
-// Compiled (M, tile shift) pairs: the transform lengths of the common
-// workloads (Nt = 16, 128, 420, and 500 of section 5's problem), with the
-// tile widths fft_tile_shift picks, plus 16-series tiles for wide FP32
-// transforms of M = 500 (fixed_wide_shift): the runtime-length rule gives
-// M = 500 tiles of 4 series, whose bin rows are quarter lines of the
-// spectrum, while 16 series make each bin row of a tile one whole 128-byte
-// line.
-#define P2O_FX_CASES(X) \
-    X(float, 16, 5)     \
-    X(float, 128, 4)    \
-    X(float, 420, 3)    \
-    X(float, 500, 2)    \
-    X(float, 500, 4)    \
-    X(double, 16, 5)    \
-    X(double, 128, 3)   \
-    X(double, 420, 2)   \
-    X(double, 500, 1)
+// Compiled (M, tile shift, workgroup size) cases: the transform lengths of
+// the common workloads (Nt = 16, 128, 420, and 500 of section 5's problem),
+// with the tile widths fft_tile_shift picks on 256-thread workgroups, plus
+// wide FP32 tiles for transforms of many series (fixed_wide_shift): 16
+// series per tile, so that each bin row of a complex FP32 tile is one whole
+// 128-byte line (measured: stores of 64-byte rows run at 3.1 TB/s, of
+// 128-byte rows at 5.4 TB/s), on 512-thread workgroups for M = 420 (the
+// same work per thread as its 8-series tiles) and 256 for M = 500.
+#define P2O_FX_CASES(X)      \
+    X(float, 16, 5, 256)     \
+    X(float, 128, 4, 256)    \
+    X(float, 420, 3, 256)    \
+    X(float, 420, 4, 512)    \
+    X(float, 500, 2, 256)    \
+    X(float, 500, 4, 256)    \
+    X(double, 16, 5, 256)    \
+    X(double, 128, 3, 256)   \
+    X(double, 420, 2, 256)   \
+    X(double, 500, 1, 256)
 
 // Lane offsets of `rows` rows of `stride` elements (plus a tile) fit the
 // unsigned 32-bit byte offsets the kernels add to their bases (ld, st;
-// rows: one sweep, 256 >> shift bins or twice that many time steps).
+// rows: one sweep, NT >> shift bins or twice that many time steps).
 bool fits32(long long rows, long long stride, size_t esz) {
     return (rows * stride + 64) * (long long)esz < (1LL << 32);
 }
@@ -915,10 +916,11 @@ bool fits32(long long rows, long long stride, size_t esz) {
 // kernels (the plan's tile shift for S_pad series); false if there is none.
 bool launch_fixed_project_h(const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,
                             const float* sx, const float* sy, hipStream_t st, hipError_t* err) {
-    if (!pl.fixed || io.nparts != 1 || io.quad || !fits32(kFxThreads >> sh, io.f_stride, 4)) return false;
-#define X(T, M_, SH_)                                                                  \
+    if (!pl.fixed || io.nparts != 1 || io.quad) return false;
+#define X(T, M_, SH_, NT_)                                                             \
     if (sizeof(T) == 4 && pl.M == M_ && sh == SH_) {                                   \
-        if (err) *err = fx_project_h<M_, SH_>(io, in_out, tw, sx, sy, st);             \
+        if (!fits32(NT_ >> SH_, io.f_stride, 4)) return false;                         \
+        if (err) *err = fx_project_h<M_, SH_, NT_>(io, in_out, tw, sx, sy, st);        \
         return true;                                                                   \
     }
     P2O_FX_CASES(X)
@@ -926,16 +928,25 @@ bool launch_fixed_project_h(const FftPlan& pl, const SeriesIO& io, void* in_out,
     return false;
 }
 
-int fixed_wide_shift(bool f64, const FftPlan& pl) { return !f64 && pl.fixed && pl.M == 500 ? 4 : -1; }
+int fixed_wide_shift(bool f64, const FftPlan& pl) { return !f64 && pl.fixed && (pl.M == 500 || pl.M == 420) ? 4 : -1; }
+
+int fixed_tile_waves(bool f64, const FftPlan& pl, int sh) {
+#define X(T, M_, SH_, NT_) \
+    if ((sizeof(T) == 8) == f64 && pl.fixed && pl.M == M_ && sh == SH_) return NT_ / 64;
+    P2O_FX_CASES(X)
+#undef X
+    return 4;
+}
 
 bool launch_fixed_r2c(bool f64, bool in_f64, const FftPlan& pl, const SeriesIO& io, const void* in, void* out,
                       const void* tw, int sh, hipStream_t st, hipError_t* err) {
     const size_t z = f64 ? 16 : 8;
-    const int js = kFxThreads >> sh;
-    if (!pl.fixed || !fits32(2 * js, io.t_stride, in_f64 ? 8 : 4) || !fits32(js, io.f_stride, z)) return false;
-#define X(T, M_, SH_)                                                                  \
+    if (!pl.fixed) return false;
+#define X(T, M_, SH_, NT_)                                                             \
     if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
-        *err = fx_r2c<T, M_, SH_>(in_f64, io, in, out, tw, st);                        \
+        constexpr int js = NT_ >> SH_;                                                 \
+        if (!fits32(2 * js, io.t_stride, in_f64 ? 8 : 4) || !fits32(js, io.f_stride, z)) return false; \
+        *err = fx_r2c<T, M_, SH_, NT_>(in_f64, io, in, out, tw, st);                   \
         return true;                                                                   \
     }
     P2O_FX_CASES(X)
@@ -947,12 +958,13 @@ bool launch_fixed_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const voi
                       int sh, const void* d_obs, const double* var, int var_mode, double* partials, hipStream_t st,
                       hipError_t* err) {
     const size_t z = f64 ? 16 : 8;
-    const int js = kFxThreads >> sh;
-    if (!pl.fixed || !fits32(2 * js, io.t_stride, z / 2) || !fits32(js, io.f_stride, z)) return false;
+    if (!pl.fixed) return false;
     const MisfitArgs ma{d_obs, var, var_mode, partials};
-#define X(T, M_, SH_)                                                                  \
+#define X(T, M_, SH_, NT_)                                                             \
     if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
-        *err = fx_c2r<T, M_, SH_>(io, in, out, tw, ma, st);                            \
+        constexpr int js = NT_ >> SH_;                                                 \
+        if (!fits32(2 * js, io.t_stride, z / 2) || !fits32(js, io.f_stride, z)) return false; \
+        *err = fx_c2r<T, M_, SH_, NT_>(io, in, out, tw, ma, st);                       \
         return true;                                                                   \
     }
     P2O_FX_CASES(X)
@@ -962,10 +974,11 @@ bool launch_fixed_c2r(bool f64, const FftPlan& pl, const SeriesIO& io, const voi
 
 bool launch_fixed_project(bool f64, const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,
                           hipStream_t st, hipError_t* err) {
-    if (!pl.fixed || !fits32(kFxThreads >> sh, io.f_stride, f64 ? 16 : 8)) return false;
-#define X(T, M_, SH_)                                                                  \
+    if (!pl.fixed) return false;
+#define X(T, M_, SH_, NT_)                                                             \
     if ((sizeof(T) == 8) == f64 && pl.M == M_ && sh == SH_) {                          \
-        *err = fx_project<T, M_, SH_>(io, in_out, tw, st);                             \
+        if (!fits32(NT_ >> SH_, io.f_stride, f64 ? 16 : 8)) return false;              \
+        *err = fx_project<T, M_, SH_, NT_>(io, in_out, tw, st);                        \
         return true;                                                                   \
     }
     P2O_FX_CASES(X)

@@ -60,6 +60,9 @@ int fft_tile_shift(int M, bool f64);
 // Tile shift of the compiled-length kernels' wide tiles for this plan and
 // precision (used for transforms of at least kWideSeries series), or -1.
 int fixed_wide_shift(bool f64, const FftPlan& pl);
+// Wavefronts per workgroup of the compiled-length kernels for tile shift sh
+// (4 where no compiled case has that shift): one per-tile maximum slot each.
+int fixed_tile_waves(bool f64, const FftPlan& pl, int sh);
 // Truncate-and-repad of FP16 operands (see launch_project_half), or false;
 // err == nullptr only reports whether a kernel exists.
 bool launch_fixed_project_h(const FftPlan& pl, const SeriesIO& io, void* in_out, const void* tw, int sh,

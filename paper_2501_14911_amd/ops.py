@@ -122,6 +122,14 @@ class P2OOperator:
         parameter-side spectra as scaled FP16 pairs where possible (default),
         or always as complex FP32."""
         check(lib.p2o_set_option(self._plan, 4, 1 if on else 0))
+        self._fp16_operands = bool(on)
+
+    @property
+    def fp16_operands(self) -> bool:
+        """The setting of set_fp16_operands (True unless switched off); the
+        library applies it to FP16 plans with more than 128 sensors whose
+        products run on the matrix cores with a compiled transform length."""
+        return self.precision == "fp16" and getattr(self, "_fp16_operands", True)
 
     def autotune(self, nrhs: int, reps: int = 3) -> dict:
         """Time every matrix-core tile variant for calls with ``nrhs``

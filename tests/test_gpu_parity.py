@@ -140,6 +140,9 @@ def test_data_space_operator_columns(precision):
 # L = 840 (the paper's time shape): the length the library has compiled FFT
 # kernels for; 203 columns and 5 sensors leave ragged tiles on both sides.
 PAPER_T = synth.Workload("paper_t_small", Nd=5, Nm=203, Nt=420, tau=100.0)
+# at least 2048 parameter series: FP32 transforms of L = 840 take 16-series
+# tiles on 512-thread workgroups (the last tile ragged)
+PAPER_T_WIDE = synth.Workload("paper_t_wide", Nd=3, Nm=2100, Nt=420, tau=100.0)
 # section 5's number of time steps: L = 1000
 PAPER_T500 = synth.Workload("paper_t500_small", Nd=5, Nm=203, Nt=500, tau=100.0)
 # at least 2048 parameter series: FP32 transforms of L = 1000 take 16-series tiles (the last one ragged)
@@ -200,14 +203,17 @@ def _check_l840(precision, ref, got, lens, keys):
             assert oracle.rel_l2(r["grad"][b], ref["grad"][b]) <= TOL[precision]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
-def test_fixed_and_runtime_length_ffts(precision):
+@pytest.mark.parametrize("precision,w", [("fp64", PAPER_T), ("fp32", PAPER_T), ("fp16", PAPER_T),
+                                         ("fp32", PAPER_T_WIDE), ("fp16", PAPER_T_WIDE)],
+                         ids=["fp64", "fp32", "fp16", "fp32-wide", "fp16-wide"])
+def test_fixed_and_runtime_length_ffts(precision, w):
     """Both FFT paths against the oracle on every result at L = 840, each
     right-hand side (each F F* column) on its own; with an FP16 spectrum the
     batched calls take the matrix cores, and the two paths must then also
-    agree with each other to FP32 rounding."""
-    note(f"[parity] fixed vs runtime-length FFTs, {PAPER_T.name} {precision}")
-    ref, got, lens = _l840_runs(precision)
+    agree with each other to FP32 rounding.  2100 parameter series take the
+    wide tiles on the compiled path (the runtime-length path keeps 8)."""
+    note(f"[parity] fixed vs runtime-length FFTs, {w.name} {precision}")
+    ref, got, lens = _l840_runs(precision, w)
     _check_l840(precision, ref, got, lens, ("F", "Ft", "F_ragged", "Ft_ragged", "FFt", "FFt_ragged"))
     if precision == "fp16":
         # the two paths' FP32 rounding can move a right-hand side's value
