@@ -317,60 +317,65 @@ def main():
 # HBM traffic per launch of the timed kernels, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs of this benchmark (copy-kernel calibration: fetched KiB x 2,
 # written KiB x 1; see profiles/), on the paper_time workload.  The matrix-core
-# rows come from the autotuner's launches, which run every tile variant on the
-# benchmark's shapes.  Valid only for the kernel source it was measured on:
-# keyed by the SHA-1 of that file.
-_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "2f911a6b6be4d59d40b698f1b8e4ceda659b1751")
+# rows with an empty operand variant come from the autotuner's launches, which
+# run every tile variant on the benchmark's shapes (complex FP32 operands); the
+# fp16_out / fp16_rhs rows from the step's own 64-column F F* launches (FP16
+# intermediate operands).  Valid only for the kernel source it was measured
+# on: keyed by the SHA-1 of that file.
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "c8ad9369c70ef842fee0730af4f144596a9a54fc")
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile, spectrum precision, operand variant): (fetch bytes, write bytes)
 _MEASURED = {
-    ('gemm_adj_64', 1, 'bf16', ''): (17082032042, 3535705621),
-    ('gemm_adj_64', 2, 'bf16', ''): (31847052035, 3534823488),
-    ('gemm_adj_64', 3, 'bf16', ''): (17013299328, 3533744150),
-    ('gemm_adj_64', 4, 'bf16', ''): (33449310249, 3565478550),
-    ('gemm_adj_64', 5, 'bf16', ''): (17053242368, 3577802474),
-    ('gemm_adj_64', 6, 'bf16', ''): (16935612800, 3669371670),
-    ('gemm_adj_64', 9, 'bf16', ''): (16939654870, 3531603968),
-    ('gemm_adj_64', 10, 'bf16', ''): (33333909975, 3531603968),
-    ('gemm_adj_64', 15, 'bf16', ''): (16802764160, 3531603968),
-    ('gemm_adj_64', 16, 'bf16', ''): (33417260250, 3531603968),
-    ('gemm_fwd_64', 0, 'bf16', ''): (20244972587, 523023509),
-    ('gemm_fwd_64', 1, 'bf16', ''): (20338794752, 522562795),
-    ('gemm_fwd_64', 2, 'bf16', ''): (20641549776, 524581355),
-    ('gemm_fwd_64', 3, 'bf16', ''): (25084247081, 519237141),
-    ('gemm_fwd_64', 4, 'bf16', ''): (23961161346, 522095744),
-    ('gemm_fwd_64', 5, 'bf16', ''): (22625581309, 519619392),
-    ('gemm_fwd_64', 6, 'bf16', ''): (20503210755, 534626752),
-    ('gemm_fwd_64', 7, 'bf16', ''): (20567531520, 531692843),
-    ('gemm_fwd_64', 8, 'bf16', ''): (20643915346, 524817579),
-    ('gemm_fwd_64', 11, 'bf16', ''): (27314822021, 534802261),
-    ('gemm_fwd_64', 12, 'bf16', ''): (23765472256, 560254549),
-    ('gemm_fwd_64', 13, 'bf16', ''): (20203701846, 523361621),
-    ('gemm_fwd_64', 14, 'bf16', ''): (21224764075, 521022357),
-    ('gemv_adj', None, 'bf16', ''): (16586875904, 55188864),
-    ('gemv_fwd', None, 'bf16', ''): (17108026368, 16166400),
-    ('gemm_adj_32', 9, 'fp16', ''): (16706503211, 1765801984),
-    ('gemm_adj_32', 10, 'fp16', ''): (16713023061, 1765801984),
-    ('gemm_adj_32', 15, 'fp16', ''): (16703037696, 1765801984),
-    ('gemm_adj_32', 16, 'fp16', ''): (16710312404, 1765801984),
-    ('gemm_adj_64', 9, 'fp16', ''): (16902326699, 3531603968),
-    ('gemm_adj_64', 10, 'fp16', ''): (33488821596, 3531603968),
-    ('gemm_adj_64', 15, 'fp16', ''): (16802615594, 3531603968),
-    ('gemm_adj_64', 16, 'fp16', ''): (33430608131, 3531603968),
-    ('gemm_fwd_32', 7, 'fp16', ''): (18998609493, 260090709),
-    ('gemm_fwd_32', 8, 'fp16', ''): (19143526656, 260752640),
-    ('gemm_fwd_32', 11, 'fp16', ''): (21642715054, 262724416),
-    ('gemm_fwd_32', 12, 'fp16', ''): (20561256277, 267166891),
-    ('gemm_fwd_32', 13, 'fp16', ''): (18478076075, 261696939),
-    ('gemm_fwd_32', 14, 'fp16', ''): (18465922346, 261713429),
-    ('gemm_fwd_64', 7, 'fp16', ''): (21137234309, 526315627),
-    ('gemm_fwd_64', 8, 'fp16', ''): (20647867139, 524955285),
-    ('gemm_fwd_64', 11, 'fp16', ''): (28386387074, 531433344),
-    ('gemm_fwd_64', 12, 'fp16', ''): (23657384489, 537314645),
-    ('gemm_fwd_64', 13, 'fp16', ''): (20209269632, 523272448),
-    ('gemm_fwd_64', 14, 'fp16', ''): (24225048576, 525051179),
-    ('gemv_adj', None, 'fp16', ''): (16586877952, 55189120),
-    ('gemv_fwd', None, 'fp16', ''): (17108039295, 16166400),
+    ('gemm_adj_64', 0, 'bf16', ''): (16941290833, 3537093572),
+    ('gemm_adj_64', 1, 'bf16', ''): (17095697057, 3535364591),
+    ('gemm_adj_64', 2, 'bf16', ''): (32046607275, 3534498415),
+    ('gemm_adj_64', 3, 'bf16', ''): (17005613196, 3533943428),
+    ('gemm_adj_64', 4, 'bf16', ''): (33439840339, 3566382639),
+    ('gemm_adj_64', 5, 'bf16', ''): (17051067025, 3577756612),
+    ('gemm_adj_64', 6, 'bf16', ''): (16897432972, 3669987309),
+    ('gemm_adj_64', 9, 'bf16', ''): (16928408398, 3531608026),
+    ('gemm_adj_64', 10, 'bf16', ''): (33423971318, 3546223279),
+    ('gemm_adj_64', 15, 'bf16', ''): (16899095756, 3535467951),
+    ('gemm_adj_64', 16, 'bf16', ''): (33688563458, 3531803354),
+    ('gemm_fwd_64', 0, 'bf16', ''): (20247806159, 523068282),
+    ('gemm_fwd_64', 1, 'bf16', ''): (20259638068, 522436730),
+    ('gemm_fwd_64', 2, 'bf16', ''): (20641455605, 524478053),
+    ('gemm_fwd_64', 3, 'bf16', ''): (24992934690, 519382501),
+    ('gemm_fwd_64', 4, 'bf16', ''): (23988633443, 522059621),
+    ('gemm_fwd_64', 5, 'bf16', ''): (22510560142, 519700389),
+    ('gemm_fwd_64', 6, 'bf16', ''): (20494086987, 534636154),
+    ('gemm_fwd_64', 7, 'bf16', ''): (20592050508, 531578896),
+    ('gemm_fwd_64', 8, 'bf16', ''): (20641731009, 525033402),
+    ('gemm_fwd_64', 11, 'bf16', ''): (27018378522, 534337829),
+    ('gemm_fwd_64', 12, 'bf16', ''): (23929241234, 560087013),
+    ('gemm_fwd_64', 13, 'bf16', ''): (20203453540, 523605712),
+    ('gemm_fwd_64', 14, 'bf16', ''): (21232898015, 521011194),
+    ('gemv_adj', None, 'bf16', ''): (16586659931, 55185791),
+    ('gemv_fwd', None, 'bf16', ''): (17107806937, 16166400),
+    ('gemm_adj_32', 9, 'fp16', ''): (16922937921, 1765802136),
+    ('gemm_adj_32', 10, 'fp16', ''): (16875504725, 1773581890),
+    ('gemm_adj_32', 15, 'fp16', ''): (16844623761, 1766495384),
+    ('gemm_adj_32', 16, 'fp16', ''): (16918914762, 1765802477),
+    ('gemm_adj_64', 9, 'fp16', ''): (16999215881, 3531607514),
+    ('gemm_adj_64', 10, 'fp16', ''): (33748935316, 3535213487),
+    ('gemm_adj_64', 15, 'fp16', ''): (16901602604, 3536902447),
+    ('gemm_adj_64', 16, 'fp16', ''): (33795900594, 3531604911),
+    ('gemm_fwd_32', 7, 'fp16', ''): (18985184946, 260108669),
+    ('gemm_fwd_32', 8, 'fp16', ''): (19174015467, 260765352),
+    ('gemm_fwd_32', 11, 'fp16', ''): (21653953906, 262631293),
+    ('gemm_fwd_32', 12, 'fp16', ''): (20584128189, 266600018),
+    ('gemm_fwd_32', 13, 'fp16', ''): (18491927879, 261610088),
+    ('gemm_fwd_32', 14, 'fp16', ''): (18463356902, 261643026),
+    ('gemm_fwd_64', 7, 'fp16', ''): (21136366970, 526297317),
+    ('gemm_fwd_64', 8, 'fp16', ''): (20638632173, 524934458),
+    ('gemm_fwd_64', 11, 'fp16', ''): (28416415994, 531086970),
+    ('gemm_fwd_64', 12, 'fp16', ''): (23579282315, 536244880),
+    ('gemm_fwd_64', 13, 'fp16', ''): (20209174042, 523608165),
+    ('gemm_fwd_64', 14, 'fp16', ''): (25103778298, 524920698),
+    ('gemv_adj', None, 'fp16', ''): (16586662235, 55188991),
+    ('gemv_fwd', None, 'fp16', ''): (17107819608, 16166400),
+    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16886920501, 1768995725),
+    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18471146369, 523163034),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
