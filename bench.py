@@ -182,8 +182,8 @@ def main():
         tot, n = st[k]
         return tot / n * 1e3 if n else 0.0
 
-    def vec_bytes(nrhs):
-        return op.nfreq * nrhs * (w.Nm + w.Nd) * 8
+    def vec_bytes(nrhs, param_bytes=8):     # parameter-side values as complex FP32 (8 B) or FP16 pairs (4 B)
+        return op.nfreq * nrhs * (w.Nm * param_bytes + w.Nd * 8)
 
     def gemm_flop(nrhs):        # real-equivalent flops of one pass
         return 2.0 * op.nfreq * w.Nd * (2 * w.Nm) * (2 * nrhs)
@@ -218,9 +218,9 @@ def main():
             v["GBs"] = v["bytes"] / (us * 1e-6) / 1e9 if us else 0.0
         else:
             v["spectrum_bytes"] = spec_bytes
-            v["rhs_bytes"] = vec_bytes(nr)
+            v["rhs_bytes"] = vec_bytes(nr, 4 if k in variant else 8)
             v["GBs"] = spec_bytes / (us * 1e-6) / 1e9 if us else 0.0
-            v["GBs_incl_rhs"] = (spec_bytes + vec_bytes(nr)) / (us * 1e-6) / 1e9 if us else 0.0
+            v["GBs_incl_rhs"] = (spec_bytes + v["rhs_bytes"]) / (us * 1e-6) / 1e9 if us else 0.0
         if issue and us:
             v["TFLOPs_real_equiv"] = gemm_flop(nr) / (us * 1e-6) / 1e12
             v["TFLOPs_issued"] = issue * gemm_flop(nr) / (us * 1e-6) / 1e12
