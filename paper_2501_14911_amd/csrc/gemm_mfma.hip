@@ -725,17 +725,48 @@ void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, con
     }
     wait_vm_lgkm0<0>();                                   // no load may land after the workgroup ends
 
-    const int b = b0 + rb;
-    if (b >= ga.nrhs) return;
+    // Partial products, a half of the right-hand sides at a time, through
+    // the spectrum ring: the half's wavefronts write their scaled
+    // accumulators as [right-hand side][row] rows (OS_RS bytes apart), then
+    // the workgroup stores whole rows, 16 bytes per lane, non-temporal (the
+    // accumulator layout gives 8-byte pieces spread over 32 rows).
+    constexpr int OS_RS = MROWS * 8 + 16;
+    static_assert(32 * OS_RS <= 3 * A_STEP, "a half's products fit the spectrum ring");
+    uint8_t* const stg = &ring_a[0][0];
     const float sc = scales[(long long)w * ga.nblk + kbeg / kScaleBlock] / rs;
-    float2* out = out_base + (long long)kc * ga.part_stride + ((long long)w * ga.nrhs + b) * ga.Nd;
+    float2* const out_w = out_base + (long long)kc * ga.part_stride + (long long)w * ga.nrhs * ga.Nd;
+    const bool pairs = (ga.Nd & 1) == 0;                  // rows of even length: 16-byte aligned pairs
+    constexpr int CPR = MROWS / 2;                        // pairs per staged row
+#pragma unroll 1
+    for (int h = 0; h < NH; ++h) {
+        bare_barrier();                                   // ring reads (or the previous half's) done
+        if (nh == h) {
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int row = m0 + (rg * MB + mb) * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
-            if (row < ga.Nd) out[row] = make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+                for (int v = 0; v < 16; ++v) {
+                    const int row = (rg * MB + mb) * 32 + 8 * (v >> 2) + 4 * kg + (v & 3);
+                    *reinterpret_cast<float2*>(&stg[r * OS_RS + row * 8]) =
+                        make_float2(accr[mb][v] * sc, acci[mb][v] * sc);
+                }
         }
+        wait_vm_lgkm0<63>();                              // this wavefront's LDS writes done
+        bare_barrier();
+        for (int e = tid; e < 32 * CPR; e += 64 * NW) {
+            const int rr = e / CPR, c = 2 * (e - rr * CPR);
+            const int b = b0 + 32 * h + rr, row = m0 + c;
+            if (b < ga.nrhs && row < ga.Nd) {
+                const float4 v = *reinterpret_cast<const float4*>(&stg[rr * OS_RS + c * 8]);
+                float2* o = out_w + (long long)b * ga.Nd + row;
+                if (pairs && row + 1 < ga.Nd) {
+                    store_nt(reinterpret_cast<float4*>(o), v);
+                } else {
+                    o[0] = make_float2(v.x, v.y);
+                    if (row + 1 < ga.Nd) o[1] = make_float2(v.z, v.w);
+                }
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- adjoint, LDS ring
