@@ -322,60 +322,60 @@ def main():
 # fp16_out / fp16_rhs rows from the step's own 64-column F F* launches (FP16
 # intermediate operands).  Valid only for the kernel source it was measured
 # on: keyed by the SHA-1 of that file.
-_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "c8ad9369c70ef842fee0730af4f144596a9a54fc")
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "331c0cd285fcb8a3cb01505042b38a5a4e254199")
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile, spectrum precision, operand variant): (fetch bytes, write bytes)
 _MEASURED = {
-    ('gemm_adj_64', 0, 'bf16', ''): (16941290833, 3537093572),
-    ('gemm_adj_64', 1, 'bf16', ''): (17095697057, 3535364591),
-    ('gemm_adj_64', 2, 'bf16', ''): (32046607275, 3534498415),
-    ('gemm_adj_64', 3, 'bf16', ''): (17005613196, 3533943428),
-    ('gemm_adj_64', 4, 'bf16', ''): (33439840339, 3566382639),
-    ('gemm_adj_64', 5, 'bf16', ''): (17051067025, 3577756612),
-    ('gemm_adj_64', 6, 'bf16', ''): (16897432972, 3669987309),
-    ('gemm_adj_64', 9, 'bf16', ''): (16928408398, 3531608026),
-    ('gemm_adj_64', 10, 'bf16', ''): (33423971318, 3546223279),
-    ('gemm_adj_64', 15, 'bf16', ''): (16899095756, 3535467951),
-    ('gemm_adj_64', 16, 'bf16', ''): (33688563458, 3531803354),
-    ('gemm_fwd_64', 0, 'bf16', ''): (20247806159, 523068282),
-    ('gemm_fwd_64', 1, 'bf16', ''): (20259638068, 522436730),
-    ('gemm_fwd_64', 2, 'bf16', ''): (20641455605, 524478053),
-    ('gemm_fwd_64', 3, 'bf16', ''): (24992934690, 519382501),
-    ('gemm_fwd_64', 4, 'bf16', ''): (23988633443, 522059621),
-    ('gemm_fwd_64', 5, 'bf16', ''): (22510560142, 519700389),
-    ('gemm_fwd_64', 6, 'bf16', ''): (20494086987, 534636154),
-    ('gemm_fwd_64', 7, 'bf16', ''): (20592050508, 531578896),
-    ('gemm_fwd_64', 8, 'bf16', ''): (20641731009, 525033402),
-    ('gemm_fwd_64', 11, 'bf16', ''): (27018378522, 534337829),
-    ('gemm_fwd_64', 12, 'bf16', ''): (23929241234, 560087013),
-    ('gemm_fwd_64', 13, 'bf16', ''): (20203453540, 523605712),
-    ('gemm_fwd_64', 14, 'bf16', ''): (21232898015, 521011194),
-    ('gemv_adj', None, 'bf16', ''): (16586659931, 55185791),
-    ('gemv_fwd', None, 'bf16', ''): (17107806937, 16166400),
-    ('gemm_adj_32', 9, 'fp16', ''): (16922937921, 1765802136),
-    ('gemm_adj_32', 10, 'fp16', ''): (16875504725, 1773581890),
-    ('gemm_adj_32', 15, 'fp16', ''): (16844623761, 1766495384),
-    ('gemm_adj_32', 16, 'fp16', ''): (16918914762, 1765802477),
-    ('gemm_adj_64', 9, 'fp16', ''): (16999215881, 3531607514),
-    ('gemm_adj_64', 10, 'fp16', ''): (33748935316, 3535213487),
-    ('gemm_adj_64', 15, 'fp16', ''): (16901602604, 3536902447),
-    ('gemm_adj_64', 16, 'fp16', ''): (33795900594, 3531604911),
-    ('gemm_fwd_32', 7, 'fp16', ''): (18985184946, 260108669),
-    ('gemm_fwd_32', 8, 'fp16', ''): (19174015467, 260765352),
-    ('gemm_fwd_32', 11, 'fp16', ''): (21653953906, 262631293),
-    ('gemm_fwd_32', 12, 'fp16', ''): (20584128189, 266600018),
-    ('gemm_fwd_32', 13, 'fp16', ''): (18491927879, 261610088),
-    ('gemm_fwd_32', 14, 'fp16', ''): (18463356902, 261643026),
-    ('gemm_fwd_64', 7, 'fp16', ''): (21136366970, 526297317),
-    ('gemm_fwd_64', 8, 'fp16', ''): (20638632173, 524934458),
-    ('gemm_fwd_64', 11, 'fp16', ''): (28416415994, 531086970),
-    ('gemm_fwd_64', 12, 'fp16', ''): (23579282315, 536244880),
-    ('gemm_fwd_64', 13, 'fp16', ''): (20209174042, 523608165),
-    ('gemm_fwd_64', 14, 'fp16', ''): (25103778298, 524920698),
-    ('gemv_adj', None, 'fp16', ''): (16586662235, 55188991),
-    ('gemv_fwd', None, 'fp16', ''): (17107819608, 16166400),
-    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16886920501, 1768995725),
-    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18471146369, 523163034),
+    ('gemm_adj_64', 0, 'bf16', ''): (16942869743, 3536747949),
+    ('gemm_adj_64', 1, 'bf16', ''): (17088510044, 3535604397),
+    ('gemm_adj_64', 2, 'bf16', ''): (32026837729, 3534742957),
+    ('gemm_adj_64', 3, 'bf16', ''): (16996156046, 3533922456),
+    ('gemm_adj_64', 4, 'bf16', ''): (33470726261, 3566492034),
+    ('gemm_adj_64', 5, 'bf16', ''): (17063729396, 3577795543),
+    ('gemm_adj_64', 6, 'bf16', ''): (16921393115, 3669345026),
+    ('gemm_adj_64', 9, 'bf16', ''): (16923680061, 3531607362),
+    ('gemm_adj_64', 10, 'bf16', ''): (33417433011, 3549440621),
+    ('gemm_adj_64', 15, 'bf16', ''): (16898372999, 3534425666),
+    ('gemm_adj_64', 16, 'bf16', ''): (33681628010, 3531731778),
+    ('gemm_fwd_64', 0, 'bf16', ''): (20246481230, 523046632),
+    ('gemm_fwd_64', 1, 'bf16', ''): (20314463918, 522302760),
+    ('gemm_fwd_64', 2, 'bf16', ''): (20641392483, 524934248),
+    ('gemm_fwd_64', 3, 'bf16', ''): (25049396762, 519556733),
+    ('gemm_fwd_64', 4, 'bf16', ''): (23993157288, 522080957),
+    ('gemm_fwd_64', 5, 'bf16', ''): (22450504641, 519779795),
+    ('gemm_fwd_64', 6, 'bf16', ''): (20493067208, 534640040),
+    ('gemm_fwd_64', 7, 'bf16', ''): (20628401635, 531632808),
+    ('gemm_fwd_64', 8, 'bf16', ''): (20643604424, 525220669),
+    ('gemm_fwd_64', 11, 'bf16', ''): (26989780428, 533529832),
+    ('gemm_fwd_64', 12, 'bf16', ''): (24204795577, 554645885),
+    ('gemm_fwd_64', 13, 'bf16', ''): (20203387263, 528180413),
+    ('gemm_fwd_64', 14, 'bf16', ''): (21274103137, 528971965),
+    ('gemv_adj', None, 'bf16', ''): (16586660021, 55187968),
+    ('gemv_fwd', None, 'bf16', ''): (17107804726, 16166400),
+    ('gemm_adj_32', 9, 'fp16', ''): (16921010955, 1765803382),
+    ('gemm_adj_32', 10, 'fp16', ''): (16860758940, 1768522700),
+    ('gemm_adj_32', 15, 'fp16', ''): (16844641048, 1766495905),
+    ('gemm_adj_32', 16, 'fp16', ''): (16918354477, 1765849249),
+    ('gemm_adj_64', 9, 'fp16', ''): (16998596548, 3531644568),
+    ('gemm_adj_64', 10, 'fp16', ''): (33730257608, 3534418925),
+    ('gemm_adj_64', 15, 'fp16', ''): (16900492566, 3535468269),
+    ('gemm_adj_64', 16, 'fp16', ''): (33796092660, 3531639405),
+    ('gemm_fwd_32', 7, 'fp16', ''): (19076941593, 260074431),
+    ('gemm_fwd_32', 8, 'fp16', ''): (19198079557, 260818729),
+    ('gemm_fwd_32', 11, 'fp16', ''): (21639147177, 262696724),
+    ('gemm_fwd_32', 12, 'fp16', ''): (20554382246, 266369833),
+    ('gemm_fwd_32', 13, 'fp16', ''): (18468540210, 262649705),
+    ('gemm_fwd_32', 14, 'fp16', ''): (18414534257, 263868351),
+    ('gemm_fwd_64', 7, 'fp16', ''): (21148451316, 526595048),
+    ('gemm_fwd_64', 8, 'fp16', ''): (20640185885, 525129085),
+    ('gemm_fwd_64', 11, 'fp16', ''): (27963272700, 530850770),
+    ('gemm_fwd_64', 12, 'fp16', ''): (23637874272, 535474557),
+    ('gemm_fwd_64', 13, 'fp16', ''): (20207566836, 527628989),
+    ('gemm_fwd_64', 14, 'fp16', ''): (25683143732, 527964050),
+    ('gemv_adj', None, 'fp16', ''): (16586662325, 55186688),
+    ('gemv_fwd', None, 'fp16', ''): (17107817782, 16166400),
+    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16890729504, 1768663862),
+    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18405076673, 528897149),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
