@@ -197,11 +197,11 @@ def main():
         "gemm_fwd_32": (st32, "gemm_fwd", "fp16", N_RAGGED, 1), "gemm_adj_32": (st32, "gemm_adj", "fp16", N_RAGGED, 1),
     }
     # The 64 data-space columns run with FP16 intermediate operands (the
-    # library's default for an FP16 plan with more than 128 sensors, matrix-core
-    # products and a compiled transform length): the adjoint writes FP16 pairs,
-    # the re-pad reads and writes them, and the forward products take FP16
-    # right-hand sides in the whole-line ring (tile 13, not autotuned).
-    f16_ops = op16.fp16_operands and w.Nd > 128
+    # library's default for an FP16 plan with matrix-core products and a
+    # compiled transform length): the adjoint writes FP16 pairs, the re-pad
+    # reads and writes them, and the forward products take FP16 right-hand
+    # sides in the whole-line ring (tile 13 above 128 sensors, not autotuned).
+    f16_ops = op16.fp16_operands
     variant = {"gemm_fwd_64": "fp16_rhs", "gemm_adj_64": "fp16_out"} if f16_ops else {}
     kern = {}
     for k, (st, stage, prec, nr, issue) in kdefs.items():

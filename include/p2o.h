@@ -332,8 +332,8 @@ typedef enum {
                                   of an FP16 plan as FP16 pairs with per-right-hand-side power-of-two
                                   scales bounded a priori (half the bytes of complex FP32; the forward
                                   products round their right-hand sides to FP16 either way), when the
-                                  plan has more than 128 sensors, calls use the matrix cores and a
-                                  compiled-length transform exists; 0 keeps them complex FP32 */
+                                  call uses the matrix cores and a compiled-length transform exists;
+                                  0 keeps them complex FP32 */
     P2O_OPT_OUTPUT_STRIDE = 3  /* value r >= 1 dividing Nt (default 1): the plan's data series are
                                   observed every r-th step, the multi-rate output of a p2q map whose
                                   QoIs have a coarser time grid than its parameters (section 2, remark

@@ -428,63 +428,67 @@ p2o_status enqueue_apply_Ft(p2o_plan* p, const void* d, void* m, int64_t nrhs, c
 }
 
 // The FP16-operand form of an F F* call is possible: FP16 spectrum on the
-// matrix cores, more than 128 sensors (the whole-line forward ring's 320-row
-// tiles), one adjoint partial and a compiled-length re-pad for the shape.
+// matrix cores, one adjoint partial and a compiled-length re-pad for the
+// shape (the forward products take the whole-line ring: 64- or 128-row tiles
+// for at most 64 or 128 sensors, 320-row ones above).
 bool fp16_operands_ok(const p2o_plan* p, int64_t nrhs, const int32_t* nt_active) {
-    if (!p->fp16_ops || p->prec != kFP16 || p->Nd <= 128 || !mfma_on(p, nrhs) || adj_parts(p, nrhs) != 1) return false;
+    if (!p->fp16_ops || p->prec != kFP16 || !mfma_on(p, nrhs) || adj_parts(p, nrhs) != 1) return false;
     return launch_project_half(p->fft, io_param(p, nrhs, nt_active, 1), nullptr, nullptr, nullptr, nullptr, nullptr,
                                nullptr);
 }
 
-// F F* with FP16 intermediate operands: the data-side r2c and the operand
-// scales (bounded from the data spectra and the spectrum's block
-// multipliers), adjoint products written as scaled FP16 pairs into X, the
-// re-pad in place on them, forward products reading them, data-side c2r.
-// sx lives in the wavefront-maximum region (free once the data-side scales
-// are taken), sy in the parameter-side scales read by the forward products.
-p2o_status enqueue_FFt_half(p2o_plan* p, const void* e, void* h, int64_t nrhs, const int32_t* nt_active) {
-    void* X = p->ws + p->off_X;
-    void* Y = p->ws + p->off_Y;
-    float* sx = reinterpret_cast<float*>(p->ws + p->off_A);
-    float* sy = scale_X(p);
-    const int ld = gemm_data_pitch((int)p->Nd);
-    p2o_status s = staged(p, P2O_STAGE_R2C, "r2c (data) and FP16 operand scales", [&] {
-        hipError_t err = launch_r2c(false, false, p->fft, io_data_rhs(p, nrhs, nt_active), e, Y, tw_of(p), p->stream);
+// F G* with FP16 intermediate operands (F G* = F F* when F and G are the
+// same plan): G's data-side r2c and the operand scales (bounded from the data
+// spectra and G's block multipliers), G's adjoint products written as scaled
+// FP16 pairs into G's X, the re-pad in place on them, F's forward products
+// reading them as FP16 right-hand sides, F's data-side c2r.  sx lives in G's
+// wavefront-maximum region (free once the data-side scales are taken), sy in
+// G's parameter-side scales.
+p2o_status enqueue_cross_half(p2o_plan* F, p2o_plan* G, const void* e, void* h, int64_t nrhs,
+                              const int32_t* nt_active) {
+    void* X = G->ws + G->off_X;
+    void* YG = G->ws + G->off_Y;
+    void* YF = F->ws + F->off_Y;
+    float* sx = reinterpret_cast<float*>(G->ws + G->off_A);
+    float* sy = scale_X(G);
+    const int ld = gemm_data_pitch((int)G->Nd);
+    p2o_status s = staged(G, P2O_STAGE_R2C, "r2c (data) and FP16 operand scales", [&] {
+        hipError_t err = launch_r2c(false, false, G->fft, io_data_rhs(G, nrhs, nt_active), e, YG, tw_of(G), G->stream);
         if (err != hipSuccess) return err;
-        return launch_fp16_operand_scales(Y, ld, (int)nrhs, (int)p->nfreq, (int)p->Nd, scales_of(p), (int)p->nblk,
-                                          (int)p->Nt, sx + p->max_rhs, sx, sy, p->stream);
+        return launch_fp16_operand_scales(YG, ld, (int)nrhs, (int)G->nfreq, (int)G->Nd, scales_of(G), (int)G->nblk,
+                                          (int)G->Nt, sx + G->max_rhs, sx, sy, G->stream);
     });
     if (s) return s;
-    s = staged(p, P2O_STAGE_GEMM_ADJ, "adjoint per-frequency products (matrix cores, FP16 out)", [&] {
-        GemmArgs ga = gemm_args(p, nrhs);
-        ga.rhs_scale = scale_Y(p);
+    s = staged(G, P2O_STAGE_GEMM_ADJ, "adjoint per-frequency products (matrix cores, FP16 out)", [&] {
+        GemmArgs ga = gemm_args(G, nrhs);
+        ga.rhs_scale = scale_Y(G);
         ga.out_scale = sx;
-        return launch_gemm_adj(ga, gemm_tile_for(p, p->tuned_adj, nrhs), p->fhat, scales_of(p), Y, X, p->stream);
+        return launch_gemm_adj(ga, gemm_tile_for(G, G->tuned_adj, nrhs), G->fhat, scales_of(G), YG, X, G->stream);
     });
     if (s) return s;
-    s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad (FP16 operands)", [&] {
+    s = staged(G, P2O_STAGE_PROJECT, "truncate and re-pad (FP16 operands)", [&] {
         hipError_t err = hipErrorInvalidValue;
-        if (!launch_project_half(p->fft, io_param(p, nrhs, nt_active, 1), X, tw_of(p), sx, sy, p->stream, &err))
+        if (!launch_project_half(G->fft, io_param(G, nrhs, nt_active, 1), X, tw_of(G), sx, sy, G->stream, &err))
             return hipErrorInvalidValue;
         return err;
     });
     if (s) return s;
-    s = staged(p, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores, FP16 operands)", [&] {
-        GemmArgs ga = gemm_args(p, nrhs);
+    s = staged(F, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores, FP16 operands)", [&] {
+        GemmArgs ga = gemm_args(F, nrhs);
         ga.rhs_scale = sy;
         ga.b_f16 = 1;
-        return launch_gemm_fwd(ga, 13, p->fhat, scales_of(p), X, Y, p->stream);
+        return launch_gemm_fwd(ga, 13, F->fhat, scales_of(F), X, YF, F->stream);
     });
     if (s) return s;
-    return staged(p, P2O_STAGE_C2R, "c2r (data)", [&] {
-        return launch_c2r(false, p->fft, io_data(p, nrhs, nt_active, fwd_parts(p, nrhs)), Y, h, tw_of(p), nullptr,
-                          nullptr, 0, nullptr, p->stream);
+    return staged(F, P2O_STAGE_C2R, "c2r (data)", [&] {
+        return launch_c2r(false, F->fft, io_data(F, nrhs, nt_active, fwd_parts(F, nrhs)), YF, h, tw_of(F), nullptr,
+                          nullptr, 0, nullptr, F->stream);
     });
 }
 
 p2o_status enqueue_FFt(p2o_plan* p, const void* e, void* h, int64_t nrhs, const int32_t* nt_active) {
     p->cur_nrhs = nrhs;
-    if (fp16_operands_ok(p, nrhs, nt_active)) return enqueue_FFt_half(p, e, h, nrhs, nt_active);
+    if (fp16_operands_ok(p, nrhs, nt_active)) return enqueue_cross_half(p, p, e, h, nrhs, nt_active);
     p2o_status s = enqueue_adjoint_to_X(p, e, nrhs, nt_active);
     if (s) return s;
     s = staged(p, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {
@@ -517,6 +521,8 @@ p2o_status enqueue_apply_F(p2o_plan* p, const void* m, void* d, int64_t nrhs, co
 p2o_status enqueue_cross(p2o_plan* F, p2o_plan* G, const void* e, void* h, int64_t nrhs) {
     G->cur_nrhs = nrhs;
     F->cur_nrhs = nrhs;
+    if (fp16_operands_ok(G, nrhs, nullptr) && F->fp16_ops && F->prec == kFP16 && mfma_on(F, nrhs))
+        return enqueue_cross_half(F, G, e, h, nrhs, nullptr);
     p2o_status s = enqueue_adjoint_to_X(G, e, nrhs, nullptr);
     if (s) return s;
     s = staged(G, P2O_STAGE_PROJECT, "truncate and re-pad", [&] {

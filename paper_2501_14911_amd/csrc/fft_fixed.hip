@@ -903,6 +903,17 @@ hipError_t fx_project_h(const SeriesIO& io, void* in_out, const void* tw, const 
     X(double, 420, 2, 256)   \
     X(double, 500, 1, 256)
 
+// The re-pad on FP16 pairs (data-space columns): the FP32 cases, with
+// 512-thread workgroups on the 16-series tiles of M = 500 (at the paper's
+// dimensions 56.8 -> 42.8 ms per 64-column call, where the FP32 re-pad ran
+// 50.6 -> 106 ms with them: it keeps 256); M = 420 keeps 8-series tiles.
+#define P2O_FX_CASES_H(X)    \
+    X(float, 16, 5, 256)     \
+    X(float, 128, 4, 256)    \
+    X(float, 420, 3, 256)    \
+    X(float, 500, 2, 256)    \
+    X(float, 500, 4, 512)
+
 // Lane offsets of `rows` rows of `stride` elements (plus a tile) fit the
 // unsigned 32-bit byte offsets the kernels add to their bases (ld, st;
 // rows: one sweep, NT >> shift bins or twice that many time steps).
@@ -923,7 +934,7 @@ bool launch_fixed_project_h(const FftPlan& pl, const SeriesIO& io, void* in_out,
         if (err) *err = fx_project_h<M_, SH_, NT_>(io, in_out, tw, sx, sy, st);        \
         return true;                                                                   \
     }
-    P2O_FX_CASES(X)
+    P2O_FX_CASES_H(X)
 #undef X
     return false;
 }

@@ -1134,8 +1134,10 @@ static hipError_t launch_tile(GemmArgs ga, const void* fhat, const float* scales
 // 13 and 14 the whole-line forward ring (k_gemm_fwd_ring2, 320-row tiles,
 // 32-column steps) for 64 and 32, 9 and 10 the adjoint one
 // (k_gemm_adj_ring) for 64 and 32, 15 and 16 the adjoint ring with 512
-// columns and 64 right-hand sides and with 256 columns and 32; a direction
-// a variant lacks takes its built-in choice.
+// columns and 64 right-hand sides and with 256 columns and 32, 17 and 18 the
+// whole-line forward ring with 64- and 128-row tiles (64 right-hand sides:
+// operators with few sensors, also on FP16 right-hand sides); a direction a
+// variant lacks takes its built-in choice.
 struct TileShape {
     int rg, ku, mb, wpe, pf, nw;
     int dirs;   // 1: forward, 2: adjoint, 3: both
@@ -1145,7 +1147,8 @@ static const TileShape kTiles[] = {{2, 4, 5, 1, 2, 4, 3}, {2, 2, 5, 1, 2, 4, 3},
                                    {4, 2, 5, 2, 1, 8, 3}, {4, 2, 5, 2, 0, 8, 1}, {4, 2, 5, 1, 0, 4, 1},
                                    {2, 2, 4, 2, 0, 4, 2}, {4, 2, 4, 1, 0, 4, 2}, {2, 2, 1, 2, 0, 4, 1},
                                    {4, 2, 1, 2, 0, 8, 1}, {2, 4, 5, 1, 0, 4, 1}, {2, 4, 5, 1, 0, 2, 1},
-                                   {4, 2, 4, 1, 0, 8, 2}, {2, 2, 4, 2, 0, 2, 2}};
+                                   {4, 2, 4, 1, 0, 8, 2}, {2, 2, 4, 2, 0, 2, 2}, {2, 4, 1, 2, 0, 4, 1},
+                                   {4, 4, 1, 2, 0, 8, 1}};
 constexpr int kTileCount = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_tile_count() { return kTileCount; }
@@ -1265,7 +1268,7 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
     if (!gemm_tile_has(tile, true) || (ga.a_f16 && !gemm_tile_is_ring(tile))) tile = gemm_default_tile(ga.nrhs, true, ga.Nd);
     if (ga.b_f16) {                                    // FP16 right-hand sides: the whole-line ring only
         if (!ga.a_f16) return hipErrorInvalidValue;
-        tile = ga.nrhs > 32 ? 13 : 14;
+        tile = ga.Nd <= 64 ? 17 : ga.Nd <= 128 ? 18 : ga.nrhs > 32 ? 13 : 14;
     }
     switch (tile) {
         case 0: return launch_tile<true, 2, 4, 5, 1, 2>(ga, fhat, scales, Xq, Yp, st);
@@ -1281,6 +1284,8 @@ hipError_t launch_gemm_fwd(const GemmArgs& in, int tile, const void* fhat, const
         case 12: return launch_ring<4, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         case 13: return launch_ring2<2, 5, 2>(ga, fhat, scales, Xq, Yp, st);
         case 14: return launch_ring2<2, 5, 1>(ga, fhat, scales, Xq, Yp, st);
+        case 17: return launch_ring2<2, 1, 2>(ga, fhat, scales, Xq, Yp, st);
+        case 18: return launch_ring2<4, 1, 2>(ga, fhat, scales, Xq, Yp, st);
         default: return launch_tile<true, 4, 2, 5, 2, 1, 8>(ga, fhat, scales, Xq, Yp, st);
     }
 }

@@ -127,8 +127,8 @@ class P2OOperator:
     @property
     def fp16_operands(self) -> bool:
         """The setting of set_fp16_operands (True unless switched off); the
-        library applies it to FP16 plans with more than 128 sensors whose
-        products run on the matrix cores with a compiled transform length."""
+        library applies it to FP16 plans whose products run on the matrix
+        cores with a compiled transform length."""
         return self.precision == "fp16" and getattr(self, "_fp16_operands", True)
 
     def autotune(self, nrhs: int, reps: int = 3) -> dict:

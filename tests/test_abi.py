@@ -157,7 +157,8 @@ def test_gemm_tile_table_and_autotune_checks():
     tiles = p2o.gemm_tiles()
     assert tiles == [(2, 4, 5, 64), (2, 2, 5, 64), (4, 2, 5, 32), (2, 2, 4, 64), (4, 2, 4, 32), (2, 2, 5, 64),
                      (4, 2, 5, 64), (4, 2, 5, 64), (4, 2, 5, 32), (2, 2, 4, 64), (4, 2, 4, 32), (2, 2, 1, 64),
-                     (4, 2, 1, 64), (2, 4, 5, 64), (2, 4, 5, 32), (4, 2, 4, 64), (2, 2, 4, 32)]
+                     (4, 2, 1, 64), (2, 4, 5, 64), (2, 4, 5, 32), (4, 2, 4, 64), (2, 2, 4, 32), (2, 4, 1, 64),
+                     (4, 4, 1, 64)]
     assert lib.p2o_gemm_tile_info(len(tiles), None, None, None, None) == ARG
     assert lib.p2o_gemm_tile_info(-1, None, None, None, None) == ARG
     st, plan = create(Nd=4, Nm=64, Nt=16, prec=2, max_rhs=4)

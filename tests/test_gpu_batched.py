@@ -257,12 +257,15 @@ def test_mfma_option_needs_a_16_bit_spectrum():
 
 
 @pytest.mark.parametrize("w", [synth.Workload("tall16", Nd=330, Nm=1003, Nt=16, tau=4.0),
-                               synth.Workload("tall128", Nd=300, Nm=1003, Nt=128, tau=32.0)],
+                               synth.Workload("tall128", Nd=300, Nm=1003, Nt=128, tau=32.0),
+                               synth.Workload("few49", Nd=49, Nm=1003, Nt=128, tau=32.0),
+                               synth.Workload("few100", Nd=100, Nm=2100, Nt=16, tau=4.0)],
                          ids=lambda w: w.name)
 def test_fp16_operand_data_space_columns(w):
-    """F F* e_j on an FP16 spectrum with FP16 intermediate operands (more than
-    128 sensors, compiled transform lengths L = 32 and 256; 64 columns, full and
-    ragged): every column against the oracle at 2e-3, and against the same
+    """F F* e_j on an FP16 spectrum with FP16 intermediate operands (forward
+    products in the whole-line ring's 320-, 64- and 128-row tiles; compiled
+    transform lengths L = 32 and 256; 64 columns, full and ragged): every
+    column against the oracle at 2e-3, and against the same
     plan with complex FP32 intermediates, which differ only by the FP16
     rounding of the adjoint products (2^-12 per value) and the scale of the
     right-hand sides' rounding."""
