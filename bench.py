@@ -322,60 +322,60 @@ def main():
 # fp16_out / fp16_rhs rows from the step's own 64-column F F* launches (FP16
 # intermediate operands).  Valid only for the kernel source it was measured
 # on: keyed by the SHA-1 of that file.
-_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "331c0cd285fcb8a3cb01505042b38a5a4e254199")
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "32c778cff5b0f0511dcc8da6dac25ee1f5a6e0ae")
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile, spectrum precision, operand variant): (fetch bytes, write bytes)
 _MEASURED = {
-    ('gemm_adj_64', 0, 'bf16', ''): (16942869743, 3536747949),
-    ('gemm_adj_64', 1, 'bf16', ''): (17088510044, 3535604397),
-    ('gemm_adj_64', 2, 'bf16', ''): (32026837729, 3534742957),
-    ('gemm_adj_64', 3, 'bf16', ''): (16996156046, 3533922456),
-    ('gemm_adj_64', 4, 'bf16', ''): (33470726261, 3566492034),
-    ('gemm_adj_64', 5, 'bf16', ''): (17063729396, 3577795543),
-    ('gemm_adj_64', 6, 'bf16', ''): (16921393115, 3669345026),
-    ('gemm_adj_64', 9, 'bf16', ''): (16923680061, 3531607362),
-    ('gemm_adj_64', 10, 'bf16', ''): (33417433011, 3549440621),
-    ('gemm_adj_64', 15, 'bf16', ''): (16898372999, 3534425666),
-    ('gemm_adj_64', 16, 'bf16', ''): (33681628010, 3531731778),
-    ('gemm_fwd_64', 0, 'bf16', ''): (20246481230, 523046632),
-    ('gemm_fwd_64', 1, 'bf16', ''): (20314463918, 522302760),
-    ('gemm_fwd_64', 2, 'bf16', ''): (20641392483, 524934248),
-    ('gemm_fwd_64', 3, 'bf16', ''): (25049396762, 519556733),
-    ('gemm_fwd_64', 4, 'bf16', ''): (23993157288, 522080957),
-    ('gemm_fwd_64', 5, 'bf16', ''): (22450504641, 519779795),
-    ('gemm_fwd_64', 6, 'bf16', ''): (20493067208, 534640040),
-    ('gemm_fwd_64', 7, 'bf16', ''): (20628401635, 531632808),
-    ('gemm_fwd_64', 8, 'bf16', ''): (20643604424, 525220669),
-    ('gemm_fwd_64', 11, 'bf16', ''): (26989780428, 533529832),
-    ('gemm_fwd_64', 12, 'bf16', ''): (24204795577, 554645885),
-    ('gemm_fwd_64', 13, 'bf16', ''): (20203387263, 528180413),
-    ('gemm_fwd_64', 14, 'bf16', ''): (21274103137, 528971965),
-    ('gemv_adj', None, 'bf16', ''): (16586660021, 55187968),
-    ('gemv_fwd', None, 'bf16', ''): (17107804726, 16166400),
-    ('gemm_adj_32', 9, 'fp16', ''): (16921010955, 1765803382),
-    ('gemm_adj_32', 10, 'fp16', ''): (16860758940, 1768522700),
-    ('gemm_adj_32', 15, 'fp16', ''): (16844641048, 1766495905),
-    ('gemm_adj_32', 16, 'fp16', ''): (16918354477, 1765849249),
-    ('gemm_adj_64', 9, 'fp16', ''): (16998596548, 3531644568),
-    ('gemm_adj_64', 10, 'fp16', ''): (33730257608, 3534418925),
-    ('gemm_adj_64', 15, 'fp16', ''): (16900492566, 3535468269),
-    ('gemm_adj_64', 16, 'fp16', ''): (33796092660, 3531639405),
-    ('gemm_fwd_32', 7, 'fp16', ''): (19076941593, 260074431),
-    ('gemm_fwd_32', 8, 'fp16', ''): (19198079557, 260818729),
-    ('gemm_fwd_32', 11, 'fp16', ''): (21639147177, 262696724),
-    ('gemm_fwd_32', 12, 'fp16', ''): (20554382246, 266369833),
-    ('gemm_fwd_32', 13, 'fp16', ''): (18468540210, 262649705),
-    ('gemm_fwd_32', 14, 'fp16', ''): (18414534257, 263868351),
-    ('gemm_fwd_64', 7, 'fp16', ''): (21148451316, 526595048),
-    ('gemm_fwd_64', 8, 'fp16', ''): (20640185885, 525129085),
-    ('gemm_fwd_64', 11, 'fp16', ''): (27963272700, 530850770),
-    ('gemm_fwd_64', 12, 'fp16', ''): (23637874272, 535474557),
-    ('gemm_fwd_64', 13, 'fp16', ''): (20207566836, 527628989),
-    ('gemm_fwd_64', 14, 'fp16', ''): (25683143732, 527964050),
-    ('gemv_adj', None, 'fp16', ''): (16586662325, 55186688),
-    ('gemv_fwd', None, 'fp16', ''): (17107817782, 16166400),
-    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16890729504, 1768663862),
-    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18405076673, 528897149),
+    ('gemm_adj_64', 0, 'bf16', ''): (16944175739, 3536929216),
+    ('gemm_adj_64', 1, 'bf16', ''): (17108730915, 3535299222),
+    ('gemm_adj_64', 2, 'bf16', ''): (31923806887, 3534514901),
+    ('gemm_adj_64', 3, 'bf16', ''): (16984682008, 3533813163),
+    ('gemm_adj_64', 4, 'bf16', ''): (33459397563, 3566458816),
+    ('gemm_adj_64', 5, 'bf16', ''): (17066194037, 3577857429),
+    ('gemm_adj_64', 6, 'bf16', ''): (16900460765, 3669414357),
+    ('gemm_adj_64', 9, 'bf16', ''): (16922977296, 3531608619),
+    ('gemm_adj_64', 10, 'bf16', ''): (33425991737, 3542391339),
+    ('gemm_adj_64', 15, 'bf16', ''): (16894224004, 3534345984),
+    ('gemm_adj_64', 16, 'bf16', ''): (33670081290, 3531848235),
+    ('gemm_fwd_64', 0, 'bf16', ''): (20253427477, 523061227),
+    ('gemm_fwd_64', 1, 'bf16', ''): (20365828663, 522339563),
+    ('gemm_fwd_64', 2, 'bf16', ''): (20641472234, 524648747),
+    ('gemm_fwd_64', 3, 'bf16', ''): (25028789582, 519388309),
+    ('gemm_fwd_64', 4, 'bf16', ''): (23988440770, 522097131),
+    ('gemm_fwd_64', 5, 'bf16', ''): (22522291274, 519880555),
+    ('gemm_fwd_64', 6, 'bf16', ''): (20498014258, 534638635),
+    ('gemm_fwd_64', 7, 'bf16', ''): (20620915319, 531571051),
+    ('gemm_fwd_64', 8, 'bf16', ''): (20646006434, 524994283),
+    ('gemm_fwd_64', 11, 'bf16', ''): (27427399833, 533915093),
+    ('gemm_fwd_64', 12, 'bf16', ''): (23775289494, 555891051),
+    ('gemm_fwd_64', 13, 'bf16', ''): (20203381152, 528155179),
+    ('gemm_fwd_64', 14, 'bf16', ''): (21230186545, 529020864),
+    ('gemv_adj', None, 'bf16', ''): (16586660468, 55188224),
+    ('gemv_fwd', None, 'bf16', ''): (17107806597, 16166400),
+    ('gemm_adj_32', 9, 'fp16', ''): (16922342124, 1765837355),
+    ('gemm_adj_32', 10, 'fp16', ''): (16866079303, 1776357973),
+    ('gemm_adj_32', 15, 'fp16', ''): (16835177219, 1766107648),
+    ('gemm_adj_32', 16, 'fp16', ''): (16919045826, 1765819435),
+    ('gemm_adj_64', 9, 'fp16', ''): (16998355815, 3531633280),
+    ('gemm_adj_64', 10, 'fp16', ''): (33708911501, 3536656299),
+    ('gemm_adj_64', 15, 'fp16', ''): (16893402340, 3537487701),
+    ('gemm_adj_64', 16, 'fp16', ''): (33795043848, 3531604053),
+    ('gemm_fwd_32', 7, 'fp16', ''): (19035730098, 260070933),
+    ('gemm_fwd_32', 8, 'fp16', ''): (19164248323, 260735275),
+    ('gemm_fwd_32', 11, 'fp16', ''): (21642116004, 262625365),
+    ('gemm_fwd_32', 12, 'fp16', ''): (20567240066, 266561877),
+    ('gemm_fwd_32', 13, 'fp16', ''): (18457982041, 262667200),
+    ('gemm_fwd_32', 14, 'fp16', ''): (18413800939, 263871531),
+    ('gemm_fwd_64', 7, 'fp16', ''): (21149458683, 526237995),
+    ('gemm_fwd_64', 8, 'fp16', ''): (20642500140, 524970091),
+    ('gemm_fwd_64', 11, 'fp16', ''): (27830176598, 531101120),
+    ('gemm_fwd_64', 12, 'fp16', ''): (23537103688, 535528469),
+    ('gemm_fwd_64', 13, 'fp16', ''): (20205913769, 527497493),
+    ('gemm_fwd_64', 14, 'fp16', ''): (25310714707, 528059627),
+    ('gemv_adj', None, 'fp16', ''): (16586662131, 55186304),
+    ('gemv_fwd', None, 'fp16', ''): (17107821315, 16166400),
+    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16889483544, 1767263520),
+    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18405435277, 528702752),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
