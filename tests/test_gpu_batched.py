@@ -292,3 +292,27 @@ def test_fp16_operand_data_space_columns(w):
     agree = oracle.rel_l2(got[True], got[False])
     note(f"[batched] {w.name} FP16 vs FP32 intermediates: {agree:.3e}")
     assert agree <= 2.0 ** -10
+
+def test_fp16_operand_scales_span_magnitudes():
+    """FP16 intermediate operands with right-hand sides from 1e-20 to 1e20 and
+    an all-zero one in one call: the a-priori power-of-two scales follow each
+    right-hand side, so every column matches the complex FP32 intermediates
+    to the FP16 rounding (relative per column), and the zero one stays zero."""
+    w = synth.Workload("tall16", Nd=330, Nm=1003, Nt=16, tau=4.0)
+    F = synth.operator_blocks(w)
+    op = P2OOperator(w.Nd, w.Nm, w.Nt, "fp16", max_rhs=64, device=DEV)
+    Ft = torch.from_numpy(F).to(DEV)
+    op.load(lambda c0, n: Ft[:, :, c0:c0 + n])
+    d = synth.data_series(w, 41)
+    mags = 10.0 ** np.arange(-20, 21)
+    x = d * mags[:, None, None]
+    x[20] = 0.0
+    got = {}
+    for on in (True, False):
+        op.set_fp16_operands(on)
+        got[on] = host(op.apply_FFt(torch.from_numpy(x).to(DEV, torch.float32)))
+    assert np.all(got[True][20] == 0.0) and np.all(got[False][20] == 0.0)
+    worst = max(oracle.rel_l2(got[True][b], got[False][b]) for b in range(41) if b != 20)
+    note(f"[batched] FP16 operands over 1e-20 .. 1e20: worst column vs FP32 intermediates {worst:.3e}")
+    assert worst <= 2.0 ** -10
+    assert np.all(np.isfinite(got[True]))
