@@ -439,6 +439,43 @@ __device__ __forceinline__ float* amax_slots_of(const SeriesIO& io, int outer, i
     return io.amax_part ? io.amax_part + (long long)outer * io.amax_slots + tile * (NT / 64) : nullptr;
 }
 
+// The re-pad's merged pass on one butterfly (after its inverse twiddles):
+// inverse radix-R DFT to z[j + p MR], p < R; keep the time values of the
+// active length (t = 2n, 2n + 1 < nt) scaled by 1 / M; forward radix-R DFT
+// of the result.  With R = 4 the outputs p = 2, 3 are time indices
+// n >= 2 MR = M / 2, i.e. t >= M >= Nt >= nt (M = L / 2 is at least Nt), so
+// they are zero for every active length: the inverse forms outputs 0 and 1
+// only (12 additions instead of 16) and the forward takes (z0, z1, 0, 0)
+// (8 instead of 16); other radices take the general form.
+template <typename T, int R, int MR>
+__device__ __forceinline__ void truncate_repad_pass(cplx<T>* a, int j, int nt, T inv) {
+    using Z = cplx<T>;
+    if constexpr (R == 4) {
+        const Z t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        const Z t2 = cadd(a[1], a[3]), t3 = csub(a[1], a[3]);
+        Z z0 = cadd(t0, t2);
+        Z z1 = cmk<T>(t1.x - t3.y, t1.y + t3.x);              // t1 + i t3
+        const int n0 = j, n1 = j + MR;
+        z0.x = (2 * n0 < nt) ? z0.x * inv : T(0);
+        z0.y = (2 * n0 + 1 < nt) ? z0.y * inv : T(0);
+        z1.x = (2 * n1 < nt) ? z1.x * inv : T(0);
+        z1.y = (2 * n1 + 1 < nt) ? z1.y * inv : T(0);
+        a[0] = cadd(z0, z1);
+        a[2] = csub(z0, z1);
+        a[1] = cmk<T>(z0.x + z1.y, z0.y - z1.x);               // z0 - i z1
+        a[3] = cmk<T>(z0.x - z1.y, z0.y + z1.x);               // z0 + i z1
+    } else {
+        dft_small<T, R, true>(a);
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            const int n = j + p * MR;
+            a[p].x = (2 * n < nt) ? a[p].x * inv : T(0);
+            a[p].y = (2 * n + 1 < nt) ? a[p].y * inv : T(0);
+        }
+        dft_small<T, R, false>(a);
+    }
+}
+
 // ---------------------------------------------------------------- kernels
 // Persistent item loop: workgroup b runs on XCD b % 8 and takes the items
 // x Q + i, i = b / 8, b / 8 + G / 8, ... of that XCD's share [x Q, (x + 1) Q)
@@ -620,14 +657,7 @@ __global__ __launch_bounds__(NT) void k_project_fx(SeriesIO io, cplx<T>* in_out,
 #pragma unroll
                 for (int q = 0; q < R; ++q) v[u][q] = rb[(u * JS + q * MR) * RS];
                 apply_tw<T, R, true>(v[u], twr + Pl::TOFF + j * (R - 1));
-                dft_small<T, R, true>(v[u]);
-#pragma unroll
-                for (int p = 0; p < R; ++p) {
-                    const int n = j + p * MR;
-                    v[u][p].x = (2 * n < nt) ? v[u][p].x * inv : T(0);
-                    v[u][p].y = (2 * n + 1 < nt) ? v[u][p].y * inv : T(0);
-                }
-                dft_small<T, R, false>(v[u]);
+                truncate_repad_pass<T, R, MR>(v[u], j, nt, inv);
             }
         }
         __syncthreads();
@@ -764,14 +794,7 @@ __global__ __launch_bounds__(NT) void k_project_fx_h(SeriesIO io, uint32_t* in_o
 #pragma unroll
                 for (int q = 0; q < R; ++q) v[u][q] = rbp[(u * JS + q * MR) * RS];
                 apply_tw<T, R, true>(v[u], twr + Pl::TOFF + j * (R - 1));
-                dft_small<T, R, true>(v[u]);
-#pragma unroll
-                for (int p = 0; p < R; ++p) {
-                    const int n = j + p * MR;
-                    v[u][p].x = (2 * n < nt) ? v[u][p].x * inv : T(0);
-                    v[u][p].y = (2 * n + 1 < nt) ? v[u][p].y * inv : T(0);
-                }
-                dft_small<T, R, false>(v[u]);
+                truncate_repad_pass<T, R, MR>(v[u], j, nt, inv);
             }
         }
         __syncthreads();
@@ -865,6 +888,7 @@ hipError_t fx_project(const SeriesIO& io, void* in_out, const void* tw, hipStrea
     const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
     if (io.amax_part && (long long)im.ntiles * (NT / 64) > io.amax_slots) return hipErrorInvalidValue;
+    if (io.Nt > M) return hipErrorInvalidValue;         // the merged pass drops time indices >= M
     const size_t lds = fx_lds<M, SH, NT>(sizeof(cplx<T>), 2);
     constexpr auto k = k_project_fx<T, M, SH, NT>;
     hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (cplx<T>*)in_out, (const cplx<T>*)tw, im);
@@ -876,6 +900,7 @@ hipError_t fx_project_h(const SeriesIO& io, void* in_out, const void* tw, const 
                         hipStream_t st) {
     const ItemMap im = fx_items(io.S_pad, SH, io.outer_count);
     if (im.items == 0) return hipSuccess;
+    if (io.Nt > M) return hipErrorInvalidValue;         // the merged pass drops time indices >= M
     const size_t lds = fx_lds<M, SH, NT>(sizeof(float2), 2);
     constexpr auto k = k_project_fx_h<M, SH, NT>;
     hipLaunchKernelGGL(k, (fx_grid<k, NT>(lds, im)), dim3(NT), lds, st, io, (uint32_t*)in_out, (const float2*)tw, sx, sy,
