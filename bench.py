@@ -200,7 +200,8 @@ def main():
     # library's default for an FP16 plan with matrix-core products and a
     # compiled transform length): the adjoint writes FP16 pairs, the re-pad
     # reads and writes them, and the forward products take FP16 right-hand
-    # sides in the whole-line ring (tile 13 above 128 sensors, not autotuned).
+    # sides in the whole-line ring (tile 13 above 128 sensors, 17 / 18 below;
+    # not autotuned).
     f16_ops = op16.fp16_operands
     variant = {"gemm_fwd_64": "fp16_rhs", "gemm_adj_64": "fp16_out"} if f16_ops else {}
     kern = {}
@@ -231,7 +232,10 @@ def main():
     dom_tile = None
     if dom.startswith("gemm_"):
         nr = int(dom.rsplit("_", 1)[1])
-        dom_tile = 13 if variant.get(dom) == "fp16_rhs" else tuned[f"{dk['spectrum']}_{nr}"][dom.split("_")[1]]["tile"]
+        if variant.get(dom) == "fp16_rhs":       # the library's whole-line tile for the sensor count
+            dom_tile = 17 if w.Nd <= 64 else 18 if w.Nd <= 128 else 13
+        else:
+            dom_tile = tuned[f"{dk['spectrum']}_{nr}"][dom.split("_")[1]]["tile"]
     traffic = measured_traffic(dom, dom_tile, dk["spectrum"], w, variant.get(dom, ""))
     roof = {"bound": "hbm", "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dk["GBs"] / HBM_PEAK_GBS,

@@ -476,8 +476,8 @@ p2o_status enqueue_cross_half(p2o_plan* F, p2o_plan* G, const void* e, void* h, 
     s = staged(F, P2O_STAGE_GEMM_FWD, "forward per-frequency products (matrix cores, FP16 operands)", [&] {
         GemmArgs ga = gemm_args(F, nrhs);
         ga.rhs_scale = sy;
-        ga.b_f16 = 1;
-        return launch_gemm_fwd(ga, 13, F->fhat, scales_of(F), X, YF, F->stream);
+        ga.b_f16 = 1;                                     // the whole-line tile for F's sensor count
+        return launch_gemm_fwd(ga, -1, F->fhat, scales_of(F), X, YF, F->stream);
     });
     if (s) return s;
     return staged(F, P2O_STAGE_C2R, "c2r (data)", [&] {
