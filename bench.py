@@ -330,56 +330,56 @@ _GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "32c778cff5b0f0511dcc8da6dac
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile, spectrum precision, operand variant): (fetch bytes, write bytes)
 _MEASURED = {
-    ('gemm_adj_64', 0, 'bf16', ''): (16944175739, 3536929216),
-    ('gemm_adj_64', 1, 'bf16', ''): (17108730915, 3535299222),
-    ('gemm_adj_64', 2, 'bf16', ''): (31923806887, 3534514901),
-    ('gemm_adj_64', 3, 'bf16', ''): (16984682008, 3533813163),
-    ('gemm_adj_64', 4, 'bf16', ''): (33459397563, 3566458816),
-    ('gemm_adj_64', 5, 'bf16', ''): (17066194037, 3577857429),
-    ('gemm_adj_64', 6, 'bf16', ''): (16900460765, 3669414357),
-    ('gemm_adj_64', 9, 'bf16', ''): (16922977296, 3531608619),
-    ('gemm_adj_64', 10, 'bf16', ''): (33425991737, 3542391339),
-    ('gemm_adj_64', 15, 'bf16', ''): (16894224004, 3534345984),
-    ('gemm_adj_64', 16, 'bf16', ''): (33670081290, 3531848235),
-    ('gemm_fwd_64', 0, 'bf16', ''): (20253427477, 523061227),
-    ('gemm_fwd_64', 1, 'bf16', ''): (20365828663, 522339563),
-    ('gemm_fwd_64', 2, 'bf16', ''): (20641472234, 524648747),
-    ('gemm_fwd_64', 3, 'bf16', ''): (25028789582, 519388309),
-    ('gemm_fwd_64', 4, 'bf16', ''): (23988440770, 522097131),
-    ('gemm_fwd_64', 5, 'bf16', ''): (22522291274, 519880555),
-    ('gemm_fwd_64', 6, 'bf16', ''): (20498014258, 534638635),
-    ('gemm_fwd_64', 7, 'bf16', ''): (20620915319, 531571051),
-    ('gemm_fwd_64', 8, 'bf16', ''): (20646006434, 524994283),
-    ('gemm_fwd_64', 11, 'bf16', ''): (27427399833, 533915093),
-    ('gemm_fwd_64', 12, 'bf16', ''): (23775289494, 555891051),
-    ('gemm_fwd_64', 13, 'bf16', ''): (20203381152, 528155179),
-    ('gemm_fwd_64', 14, 'bf16', ''): (21230186545, 529020864),
-    ('gemv_adj', None, 'bf16', ''): (16586660468, 55188224),
-    ('gemv_fwd', None, 'bf16', ''): (17107806597, 16166400),
-    ('gemm_adj_32', 9, 'fp16', ''): (16922342124, 1765837355),
-    ('gemm_adj_32', 10, 'fp16', ''): (16866079303, 1776357973),
-    ('gemm_adj_32', 15, 'fp16', ''): (16835177219, 1766107648),
-    ('gemm_adj_32', 16, 'fp16', ''): (16919045826, 1765819435),
-    ('gemm_adj_64', 9, 'fp16', ''): (16998355815, 3531633280),
-    ('gemm_adj_64', 10, 'fp16', ''): (33708911501, 3536656299),
-    ('gemm_adj_64', 15, 'fp16', ''): (16893402340, 3537487701),
-    ('gemm_adj_64', 16, 'fp16', ''): (33795043848, 3531604053),
-    ('gemm_fwd_32', 7, 'fp16', ''): (19035730098, 260070933),
-    ('gemm_fwd_32', 8, 'fp16', ''): (19164248323, 260735275),
-    ('gemm_fwd_32', 11, 'fp16', ''): (21642116004, 262625365),
-    ('gemm_fwd_32', 12, 'fp16', ''): (20567240066, 266561877),
-    ('gemm_fwd_32', 13, 'fp16', ''): (18457982041, 262667200),
-    ('gemm_fwd_32', 14, 'fp16', ''): (18413800939, 263871531),
-    ('gemm_fwd_64', 7, 'fp16', ''): (21149458683, 526237995),
-    ('gemm_fwd_64', 8, 'fp16', ''): (20642500140, 524970091),
-    ('gemm_fwd_64', 11, 'fp16', ''): (27830176598, 531101120),
-    ('gemm_fwd_64', 12, 'fp16', ''): (23537103688, 535528469),
-    ('gemm_fwd_64', 13, 'fp16', ''): (20205913769, 527497493),
-    ('gemm_fwd_64', 14, 'fp16', ''): (25310714707, 528059627),
-    ('gemv_adj', None, 'fp16', ''): (16586662131, 55186304),
-    ('gemv_fwd', None, 'fp16', ''): (17107821315, 16166400),
-    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16889483544, 1767263520),
-    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18405435277, 528702752),
+    ('gemm_adj_64', 0, 'bf16', ''): (16942949681, 3536911267),
+    ('gemm_adj_64', 1, 'bf16', ''): (17070906206, 3535580601),
+    ('gemm_adj_64', 2, 'bf16', ''): (32081993540, 3534407779),
+    ('gemm_adj_64', 3, 'bf16', ''): (16990893804, 3533909689),
+    ('gemm_adj_64', 4, 'bf16', ''): (33446696365, 3566553059),
+    ('gemm_adj_64', 5, 'bf16', ''): (17057559990, 3577783566),
+    ('gemm_adj_64', 6, 'bf16', ''): (16921288778, 3669995021),
+    ('gemm_adj_64', 9, 'bf16', ''): (16928389785, 3531605859),
+    ('gemm_adj_64', 10, 'bf16', ''): (33434118566, 3539753187),
+    ('gemm_adj_64', 15, 'bf16', ''): (16904243838, 3534847033),
+    ('gemm_adj_64', 16, 'bf16', ''): (33685088912, 3533436857),
+    ('gemm_fwd_64', 0, 'bf16', ''): (20252195385, 523076646),
+    ('gemm_fwd_64', 1, 'bf16', ''): (20410894379, 522452646),
+    ('gemm_fwd_64', 2, 'bf16', ''): (20641580619, 525209916),
+    ('gemm_fwd_64', 3, 'bf16', ''): (25075976804, 519530833),
+    ('gemm_fwd_64', 4, 'bf16', ''): (24007707115, 522086716),
+    ('gemm_fwd_64', 5, 'bf16', ''): (22723129679, 519806972),
+    ('gemm_fwd_64', 6, 'bf16', ''): (20504000962, 534590524),
+    ('gemm_fwd_64', 7, 'bf16', ''): (20643789823, 531614801),
+    ('gemm_fwd_64', 8, 'bf16', ''): (20642278295, 525302694),
+    ('gemm_fwd_64', 11, 'bf16', ''): (27034573043, 533674918),
+    ('gemm_fwd_64', 12, 'bf16', ''): (24017643759, 553552806),
+    ('gemm_fwd_64', 13, 'bf16', ''): (20203383944, 528259452),
+    ('gemm_fwd_64', 14, 'bf16', ''): (21229617048, 529032337),
+    ('gemv_adj', None, 'bf16', ''): (16586660380, 55190016),
+    ('gemv_fwd', None, 'bf16', ''): (17107806120, 16166400),
+    ('gemm_adj_32', 9, 'fp16', ''): (16922437435, 1765805938),
+    ('gemm_adj_32', 10, 'fp16', ''): (16856807142, 1773822450),
+    ('gemm_adj_32', 15, 'fp16', ''): (16841958097, 1766752071),
+    ('gemm_adj_32', 16, 'fp16', ''): (16918570563, 1765815794),
+    ('gemm_adj_64', 9, 'fp16', ''): (16998758107, 3531618062),
+    ('gemm_adj_64', 10, 'fp16', ''): (33736503079, 3540007779),
+    ('gemm_adj_64', 15, 'fp16', ''): (16895445275, 3536854926),
+    ('gemm_adj_64', 16, 'fp16', ''): (33795606014, 3531621347),
+    ('gemm_fwd_32', 7, 'fp16', ''): (19018770772, 260196691),
+    ('gemm_fwd_32', 8, 'fp16', ''): (19175178212, 260920403),
+    ('gemm_fwd_32', 11, 'fp16', ''): (21649197521, 262631443),
+    ('gemm_fwd_32', 12, 'fp16', ''): (20565848570, 266402771),
+    ('gemm_fwd_32', 13, 'fp16', ''): (18460444971, 262664403),
+    ('gemm_fwd_32', 14, 'fp16', ''): (18416959627, 263894078),
+    ('gemm_fwd_64', 7, 'fp16', ''): (21147144996, 526691494),
+    ('gemm_fwd_64', 8, 'fp16', ''): (20621899595, 525038076),
+    ('gemm_fwd_64', 11, 'fp16', ''): (28285430482, 531058833),
+    ('gemm_fwd_64', 12, 'fp16', ''): (23682865645, 535783526),
+    ('gemm_fwd_64', 13, 'fp16', ''): (20205825513, 529156220),
+    ('gemm_fwd_64', 14, 'fp16', ''): (25988741641, 528014353),
+    ('gemv_adj', None, 'fp16', ''): (16586662301, 55187456),
+    ('gemv_fwd', None, 'fp16', ''): (17107820583, 16166400),
+    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16890091510, 1767810066),
+    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18416265854, 528159868),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
