@@ -157,7 +157,8 @@ p2o_status p2o_apply_Ft(p2o_plan* plan, const void* d, void* m, int64_t nrhs,
  * products that assemble K = Gamma_noise + F Gamma_prior F^* column by
  * column, section 4, Phase 2).  e, h: [nrhs][Nt][Nd].  The intermediate
  * parameter series is truncated to Nt steps between the two passes and never
- * leaves the workspace.  nt_active as for p2o_apply_F. */
+ * leaves the workspace (on an FP16 plan as FP16 pairs with a-priori scales
+ * unless P2O_OPT_FP16_OPERANDS is 0).  nt_active as for p2o_apply_F. */
 p2o_status p2o_apply_FFt(p2o_plan* plan, const void* e, void* h, int64_t nrhs,
                          const int32_t* nt_active);
 
