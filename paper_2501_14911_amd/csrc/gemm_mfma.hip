@@ -400,7 +400,9 @@ __device__ __forceinline__ void dma16(const uint8_t* base, uint32_t off, uint32_
 }
 // The same load marked non-temporal, for the spectrum: each of its bytes is
 // read once per launch, so its lines need not displace the right-hand sides'
-// (measured on a load-only ring over a 16.6 GB spectrum: 6.5 -> 7.0 TB/s).
+// (measured on load-only rings over a 16.6 GB spectrum: 6.5 -> 7.0 TB/s with
+// the adjoint's 2 KB row pieces, 6.1 -> 6.8 TB/s with the whole-line forward
+// ring's 128-byte ones).
 __device__ __forceinline__ void dma16_stream(const uint8_t* base, uint32_t off, uint32_t lds) {
     asm volatile("global_load_lds_dwordx4 %0, %1 nt" : : "v"(off), "s"(base), "{m0}"(lds) : "memory");
 }
@@ -647,7 +649,7 @@ void k_gemm_fwd_ring2(const uint8_t* fhat, const float* __restrict__ scales, con
     auto issue_a = [&](int st, int slot) {
         const long long sa = st < nst ? st : nst - 1;       // past the end: repeat the last step (unused)
 #pragma unroll
-        for (int i = 0; i < AI; ++i) dma16(abase + sa * 128, aoff[i], la + slot * A_STEP + i * 1024);
+        for (int i = 0; i < AI; ++i) dma16_stream(abase + sa * 128, aoff[i], la + slot * A_STEP + i * 1024);
     };
     auto issue_b = [&](int st, int slot) {
         const long long sb = st < nst ? st : nst - 1;
