@@ -326,60 +326,58 @@ def main():
 # fp16_out / fp16_rhs rows from the step's own 64-column F F* launches (FP16
 # intermediate operands).  Valid only for the kernel source it was measured
 # on: keyed by the SHA-1 of that file.
-_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "32c778cff5b0f0511dcc8da6dac25ee1f5a6e0ae")
+_GEMM = ("paper_2501_14911_amd/csrc/gemm_mfma.hip", "500f3eee6e4788c3c66404861889c195fa1fa646")
 _GEMV = ("paper_2501_14911_amd/csrc/gemv.hip", "c9f87c34e4ec54f35d4392f5aa3152c315a2e18b")
 # (kernel, tile, spectrum precision, operand variant): (fetch bytes, write bytes)
 _MEASURED = {
-    ('gemm_adj_64', 0, 'bf16', ''): (16942949681, 3536911267),
-    ('gemm_adj_64', 1, 'bf16', ''): (17070906206, 3535580601),
-    ('gemm_adj_64', 2, 'bf16', ''): (32081993540, 3534407779),
-    ('gemm_adj_64', 3, 'bf16', ''): (16990893804, 3533909689),
-    ('gemm_adj_64', 4, 'bf16', ''): (33446696365, 3566553059),
-    ('gemm_adj_64', 5, 'bf16', ''): (17057559990, 3577783566),
-    ('gemm_adj_64', 6, 'bf16', ''): (16921288778, 3669995021),
-    ('gemm_adj_64', 9, 'bf16', ''): (16928389785, 3531605859),
-    ('gemm_adj_64', 10, 'bf16', ''): (33434118566, 3539753187),
-    ('gemm_adj_64', 15, 'bf16', ''): (16904243838, 3534847033),
-    ('gemm_adj_64', 16, 'bf16', ''): (33685088912, 3533436857),
-    ('gemm_fwd_64', 0, 'bf16', ''): (20252195385, 523076646),
-    ('gemm_fwd_64', 1, 'bf16', ''): (20410894379, 522452646),
-    ('gemm_fwd_64', 2, 'bf16', ''): (20641580619, 525209916),
-    ('gemm_fwd_64', 3, 'bf16', ''): (25075976804, 519530833),
-    ('gemm_fwd_64', 4, 'bf16', ''): (24007707115, 522086716),
-    ('gemm_fwd_64', 5, 'bf16', ''): (22723129679, 519806972),
-    ('gemm_fwd_64', 6, 'bf16', ''): (20504000962, 534590524),
-    ('gemm_fwd_64', 7, 'bf16', ''): (20643789823, 531614801),
-    ('gemm_fwd_64', 8, 'bf16', ''): (20642278295, 525302694),
-    ('gemm_fwd_64', 11, 'bf16', ''): (27034573043, 533674918),
-    ('gemm_fwd_64', 12, 'bf16', ''): (24017643759, 553552806),
-    ('gemm_fwd_64', 13, 'bf16', ''): (20203383944, 528259452),
-    ('gemm_fwd_64', 14, 'bf16', ''): (21229617048, 529032337),
-    ('gemv_adj', None, 'bf16', ''): (16586660380, 55190016),
-    ('gemv_fwd', None, 'bf16', ''): (17107806120, 16166400),
-    ('gemm_adj_32', 9, 'fp16', ''): (16922437435, 1765805938),
-    ('gemm_adj_32', 10, 'fp16', ''): (16856807142, 1773822450),
-    ('gemm_adj_32', 15, 'fp16', ''): (16841958097, 1766752071),
-    ('gemm_adj_32', 16, 'fp16', ''): (16918570563, 1765815794),
-    ('gemm_adj_64', 9, 'fp16', ''): (16998758107, 3531618062),
-    ('gemm_adj_64', 10, 'fp16', ''): (33736503079, 3540007779),
-    ('gemm_adj_64', 15, 'fp16', ''): (16895445275, 3536854926),
-    ('gemm_adj_64', 16, 'fp16', ''): (33795606014, 3531621347),
-    ('gemm_fwd_32', 7, 'fp16', ''): (19018770772, 260196691),
-    ('gemm_fwd_32', 8, 'fp16', ''): (19175178212, 260920403),
-    ('gemm_fwd_32', 11, 'fp16', ''): (21649197521, 262631443),
-    ('gemm_fwd_32', 12, 'fp16', ''): (20565848570, 266402771),
-    ('gemm_fwd_32', 13, 'fp16', ''): (18460444971, 262664403),
-    ('gemm_fwd_32', 14, 'fp16', ''): (18416959627, 263894078),
-    ('gemm_fwd_64', 7, 'fp16', ''): (21147144996, 526691494),
-    ('gemm_fwd_64', 8, 'fp16', ''): (20621899595, 525038076),
-    ('gemm_fwd_64', 11, 'fp16', ''): (28285430482, 531058833),
-    ('gemm_fwd_64', 12, 'fp16', ''): (23682865645, 535783526),
-    ('gemm_fwd_64', 13, 'fp16', ''): (20205825513, 529156220),
-    ('gemm_fwd_64', 14, 'fp16', ''): (25988741641, 528014353),
-    ('gemv_adj', None, 'fp16', ''): (16586662301, 55187456),
-    ('gemv_fwd', None, 'fp16', ''): (17107820583, 16166400),
-    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16890091510, 1767810066),
-    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18416265854, 528159868),
+    ('gemm_adj_64', 0, 'bf16', ''): (16942853753, 3537489346),
+    ('gemm_adj_64', 1, 'bf16', ''): (17104500028, 3534946371),
+    ('gemm_adj_64', 2, 'bf16', ''): (31768355830, 3534329218),
+    ('gemm_adj_64', 3, 'bf16', ''): (16983260948, 3533991704),
+    ('gemm_adj_64', 4, 'bf16', ''): (33554990155, 3566467287),
+    ('gemm_adj_64', 5, 'bf16', ''): (17063562877, 3577773911),
+    ('gemm_adj_64', 6, 'bf16', ''): (16942112813, 3669423276),
+    ('gemm_adj_64', 9, 'bf16', ''): (16938900097, 3531606765),
+    ('gemm_adj_64', 10, 'bf16', ''): (33539370174, 3544518295),
+    ('gemm_adj_64', 15, 'bf16', ''): (16901021082, 3534618477),
+    ('gemm_adj_64', 16, 'bf16', ''): (33664828213, 3531677762),
+    ('gemm_fwd_64', 0, 'bf16', ''): (20323290132, 523066045),
+    ('gemm_fwd_64', 1, 'bf16', ''): (20719164951, 522427112),
+    ('gemm_fwd_64', 2, 'bf16', ''): (20641849215, 524829544),
+    ('gemm_fwd_64', 3, 'bf16', ''): (25562691581, 519522387),
+    ('gemm_fwd_64', 4, 'bf16', ''): (24013753316, 522089533),
+    ('gemm_fwd_64', 5, 'bf16', ''): (22932785187, 519748648),
+    ('gemm_fwd_64', 6, 'bf16', ''): (20514379486, 534824466),
+    ('gemm_fwd_64', 7, 'bf16', ''): (20777059613, 531616786),
+    ('gemm_fwd_64', 8, 'bf16', ''): (20645856334, 525254589),
+    ('gemm_fwd_64', 11, 'bf16', ''): (29230050768, 533705213),
+    ('gemm_fwd_64', 12, 'bf16', ''): (24999208790, 555568296),
+    ('gemm_fwd_64', 13, 'bf16', ''): (20388694676, 528415954),
+    ('gemm_fwd_64', 14, 'bf16', ''): (29962048433, 529273704),
+    ('gemm_adj_32', 9, 'fp16', ''): (16922849448, 1765827702),
+    ('gemm_adj_32', 10, 'fp16', ''): (16851931162, 1775968801),
+    ('gemm_adj_32', 15, 'fp16', ''): (16839668069, 1765926476),
+    ('gemm_adj_32', 16, 'fp16', ''): (16917589911, 1765803084),
+    ('gemm_adj_64', 9, 'fp16', ''): (16996708068, 3531649432),
+    ('gemm_adj_64', 10, 'fp16', ''): (33744490742, 3554068077),
+    ('gemm_adj_64', 15, 'fp16', ''): (16887236772, 3534404077),
+    ('gemm_adj_64', 16, 'fp16', ''): (33796669647, 3531618242),
+    ('gemm_fwd_32', 7, 'fp16', ''): (19039659940, 260075263),
+    ('gemm_fwd_32', 8, 'fp16', ''): (19138077045, 260911529),
+    ('gemm_fwd_32', 11, 'fp16', ''): (21691994840, 262634537),
+    ('gemm_fwd_32', 12, 'fp16', ''): (20537077202, 266294591),
+    ('gemm_fwd_32', 13, 'fp16', ''): (18543777981, 262786303),
+    ('gemm_fwd_32', 14, 'fp16', ''): (18541415644, 263958569),
+    ('gemm_fwd_64', 7, 'fp16', ''): (21117670687, 526445053),
+    ('gemm_fwd_64', 8, 'fp16', ''): (20645911622, 525184957),
+    ('gemm_fwd_64', 11, 'fp16', ''): (27885444225, 531038546),
+    ('gemm_fwd_64', 12, 'fp16', ''): (23608629043, 535116136),
+    ('gemm_fwd_64', 13, 'fp16', ''): (20385855376, 527147069),
+    ('gemm_fwd_64', 14, 'fp16', ''): (32336739755, 527812818),
+    ('gemv_adj', None, 'fp16', ''): (16586661619, 55188224),
+    ('gemv_fwd', None, 'fp16', ''): (17107815270, 16166400),
+    ('gemm_adj_64', 15, 'fp16', 'fp16_out'): (16892934072, 1767214934),
+    ('gemm_fwd_64', 13, 'fp16', 'fp16_rhs'): (18530538730, 529057821),
 }
 TRAFFIC = {k: ((_GEMV if k[0].startswith("gemv") else _GEMM) + v + ("paper_time",)) for k, v in _MEASURED.items()}
 
