@@ -190,8 +190,22 @@ def test_fixed_length_fft_switch():
         assert lib.p2o_set_option(plan, 2, v) == OK
     for v in (-1, 2):
         assert lib.p2o_set_option(plan, 2, v) == ARG
-    assert lib.p2o_set_option(plan, 3, 0) == ARG          # no such option
+    assert lib.p2o_set_option(plan, 3, 0) == ARG          # output stride 0
+    assert lib.p2o_set_option(plan, 99, 0) == ARG         # no such option
     lib.p2o_destroy(plan)
+
+
+def test_fp16_operand_switch():
+    """P2O_OPT_FP16_OPERANDS takes 0 or 1 on any plan (it only acts on FP16
+    plans whose products run on the matrix cores)."""
+    for prec in (0, 3):
+        st, plan = create(Nd=4, Nm=64, Nt=420, prec=prec, max_rhs=2)
+        assert st == OK
+        for v in (0, 1):
+            assert lib.p2o_set_option(plan, 4, v) == OK
+        for v in (-1, 2):
+            assert lib.p2o_set_option(plan, 4, v) == ARG
+        lib.p2o_destroy(plan)
 
 
 def test_bandwidth_probe_argument_checks():
